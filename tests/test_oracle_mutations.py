@@ -1,0 +1,107 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each case monkeypatches one plausible error into the oracle (on the CPU) and
+checks that the named pin test then fails. This guards against pins that
+would pass whatever the oracle computed.
+"""
+import numpy as np
+import pytest
+
+from oracle import icm
+import tests.test_oracle_pins as pins
+
+
+def _fails(fn, *args):
+    try:
+        fn(*args)
+    except AssertionError:
+        return True
+    return False
+
+
+def test_wrong_divergence_symbol_sign(monkeypatch):
+    orig = icm.symbols
+
+    def bad(p):
+        D, G, L = orig(p)
+        return [-d for d in D], G, -L
+    monkeypatch.setattr(icm, "symbols", bad)
+    assert _fails(pins.test_helmholtz_solve_real_space_residual)
+
+
+def test_transposed_gradient_symbol(monkeypatch):
+    orig = icm.symbols
+
+    def bad(p):
+        D, G, L = orig(p)
+        return D, [np.conj(g) for g in G], L
+    monkeypatch.setattr(icm, "symbols", bad)
+    assert _fails(pins.test_projection_divergence_idempotence_mean)
+
+
+def test_noise_diagonal_without_factor_two(monkeypatch):
+    orig = icm.philox.stress_normals
+
+    def bad(n, step, seed, replica):
+        W = orig(n, step, seed, replica)
+        for k in ("xx", "yy", "zz"):
+            W[k] = W[k] / 2.0 * np.sqrt(2.0)   # variance 2 instead of 4
+        return W
+    monkeypatch.setattr(icm.philox, "stress_normals", bad)
+    assert _fails(pins.test_noise_one_step_variance_closed_form)
+
+
+def test_noise_amplitude_missing_dt(monkeypatch):
+    monkeypatch.setattr(icm.Params, "noise_amplitude",
+                        property(lambda self: np.sqrt(self.kT * self.eta / self.cell_volume)))
+    assert _fails(pins.test_equilibrium_is_preserved_by_the_fluctuating_step)
+
+
+def test_step5_coefficient_uses_m_f_not_mt_f(monkeypatch):
+    monkeypatch.setattr(icm.Params, "mt_f", property(lambda self: self.m_f))
+    assert _fails(pins.test_inviscid_impulse_gives_effective_mass, 1.0)
+
+
+def test_dropped_g_term_breaks_momentum(monkeypatch):
+    orig = icm.helmholtz_project
+    calls = {"n": 0}
+
+    def bad(p, rhs, a, b):
+        calls["n"] += 1
+        out = orig(p, rhs, a, b)
+        return out * (1.0 if a != p.rho else 1.1)   # perturb the dv solve
+    monkeypatch.setattr(icm, "helmholtz_project", bad)
+    assert _fails(pins.test_momentum_conserved_exactly, icm.SLIP_VISCOUS)
+
+
+def test_laplacian_missing_one_axis(monkeypatch):
+    def bad(p, v):
+        out = np.zeros_like(v)
+        for a in range(3):
+            for b in range(2):
+                out[a] += icm.shift(v[a], b, 1) - 2.0 * v[a] + icm.shift(v[a], b, -1)
+        return out / p.h ** 2
+    monkeypatch.setattr(icm, "laplacian", bad)
+    assert _fails(pins.test_single_shear_mode_decay_closed_form) or \
+        _fails(pins.test_helmholtz_solve_real_space_residual)
+
+
+def test_wrong_face_offset_in_interp(monkeypatch):
+    orig = icm._component_weights
+
+    def bad(p, q, alpha, deriv_axis=None):
+        return orig(p, q + 0.5 * (alpha == 0) * np.array([[1.0, 0, 0]]), alpha, deriv_axis)
+    monkeypatch.setattr(icm, "_component_weights", bad)
+    assert _fails(pins.test_interp_brute_force_single_node)
+
+
+def test_wca_force_sign(monkeypatch):
+    orig = icm.wca_forces
+    monkeypatch.setattr(icm, "wca_forces", lambda p, q: -orig(p, q))
+    assert _fails(pins.test_wca_force_is_minus_gradient_of_potential)
+
+
+def test_thermal_drift_sign(monkeypatch):
+    orig = icm.dphi3
+    monkeypatch.setattr(icm, "dphi3", lambda r: -orig(r))
+    assert _fails(pins.test_kernel_derivative_matches_finite_difference, 3)

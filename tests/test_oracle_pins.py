@@ -1,0 +1,504 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests compares the oracle with itself: each checks a value the
+paper prints (tests/golden/paper_values.json), a closed form, an invariant or
+a brute-force/independent computation, chosen so that a dropped term, a wrong
+sign or index, or a transposed operand fails at least one of them.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import icm, philox
+import icm_inputs
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def P(**kw):
+    return icm.Params(**kw)
+
+
+# ---------------------------------------------------------------- kernels
+@pytest.mark.parametrize("kernel,sq", [(3, 0.5), (4, 0.375)])
+def test_kernel_moment_conditions(kernel, sq):
+    """Eq. (JS_invariance): sum phi = 1, sum (x-k) phi = 0, sum phi^2 const,
+    at 1000 random offsets; the 4-point kernel also has even = odd = 1/2."""
+    phi, _ = icm.kernel_fns(kernel)
+    x = np.random.default_rng(0).uniform(-7, 7, 1000)
+    nodes, d = icm.stencil_nodes(kernel, x)
+    w = phi(d)
+    assert np.max(np.abs(w.sum(1) - 1.0)) < 1e-15
+    assert np.max(np.abs((d * w).sum(1))) < 1e-15
+    assert np.max(np.abs((w * w).sum(1) - sq)) < 1e-15
+    if kernel == 4:
+        even = np.where(nodes % 2 == 0, w, 0.0).sum(1)
+        assert np.max(np.abs(even - 0.5)) < 1e-15
+    # support: nothing outside the stencil is lost
+    assert np.all(phi(np.array([kernel / 2.0 + 1e-9, -kernel / 2.0 - 1e-9])) == 0.0)
+
+
+@pytest.mark.parametrize("kernel", [3, 4])
+def test_kernel_derivative_matches_finite_difference(kernel):
+    phi, dphi = icm.kernel_fns(kernel)
+    r = np.random.default_rng(1).uniform(-kernel / 2.0, kernel / 2.0, 2000)
+    eps = 1e-6
+    fd = (phi(r + eps) - phi(r - eps)) / (2 * eps)
+    assert np.max(np.abs(fd - dphi(r))) < 1e-8
+    # the derivative weights of any stencil sum to zero (d/dq of sum phi = 1)
+    _, d = icm.stencil_nodes(kernel, np.random.default_rng(2).uniform(-5, 5, 100))
+    assert np.max(np.abs(dphi(d).sum(1))) < 1e-13
+
+
+def test_blob_volume_3pt_is_eight_cells():
+    """Sec. III.A.1: dV = 8 dV_f for the three-point kernel."""
+    p = P(kernel=3, h=0.7)
+    assert p.blob_volume / p.h ** 3 == pytest.approx(GOLD["blob_volume_3pt_over_cell"]["value"], abs=1e-13)
+
+
+# ----------------------------------------------------------------- J and S
+@pytest.mark.parametrize("kernel", [3, 4])
+def test_JS_is_inverse_blob_volume(kernel):
+    """Eq. (dV_JS): J S = dV^-1 I at any position."""
+    p = P(n=(12, 10, 14), kernel=kernel, h=0.9)
+    rng = np.random.default_rng(3)
+    for q in rng.uniform(-20, 20, (5, 3)):
+        M = np.zeros((3, 3))
+        for a in range(3):
+            F = np.zeros((1, 3))
+            F[0, a] = 1.0
+            M[:, a] = icm.interp(p, icm.spread(p, F, q[None]), q[None])[0]
+        assert np.max(np.abs(M * p.blob_volume - np.eye(3))) < 1e-14
+
+
+@pytest.mark.parametrize("kernel", [3, 4])
+def test_adjointness(kernel):
+    """Eq. (adjoint_cond), discrete form S = dV_f^-1 J*: (J v).U = dV_f sum v.(S U)."""
+    p = P(n=(10, 12, 8), kernel=kernel, h=1.3)
+    rng = np.random.default_rng(4)
+    v = rng.standard_normal((3, 8, 12, 10))
+    q = rng.uniform(0, 13, (7, 3))
+    U = rng.standard_normal((7, 3))
+    lhs = np.sum(icm.interp(p, v, q) * U)
+    rhs = p.cell_volume * np.sum(v * icm.spread(p, U, q))
+    assert abs(lhs - rhs) < 1e-13 * (abs(lhs) + 1)
+
+
+def test_interp_brute_force_single_node():
+    """J of a field that is 1 on one face and 0 elsewhere is the product of
+    the three 1-D kernel values at that face's offsets (component x)."""
+    p = P(n=(8, 8, 8), kernel=3)
+    q = np.array([[3.3, 4.6, 5.05]])
+    v = np.zeros((3, 8, 8, 8))
+    i, j, k = 3, 4, 5
+    v[0, k, j, i] = 1.0
+    dx = q[0, 0] - i          # x-face at i h
+    dy = q[0, 1] - (j + 0.5)  # y offset 1/2
+    dz = q[0, 2] - (k + 0.5)
+    expect = icm.phi3(dx) * icm.phi3(dy) * icm.phi3(dz)
+    assert icm.interp(p, v, q)[0, 0] == pytest.approx(float(expect), abs=1e-16)
+    assert icm.interp(p, v, q)[0, 1] == 0.0
+
+
+def test_disjoint_kernels_do_not_overlap():
+    """Sec. III.A.2: J_i S_j = 0 when the kernels have disjoint support."""
+    p = P(n=(16, 16, 16), kernel=3)
+    qi = np.array([[4.2, 5.1, 6.3]])
+    qj = qi + np.array([[3.6, 0.0, 0.0]])
+    for a in range(3):
+        F = np.zeros((1, 3))
+        F[0, a] = 1.0
+        assert np.all(icm.interp(p, icm.spread(p, F, qj), qi) == 0.0)
+
+
+def test_JPS_translational_invariance_bounds():
+    """Sec. III.A.2, Fig. (JPS): (3 dV/2) J P S - I has diagonal deviations
+    below 5% and off-diagonal of order 0.1% at N = 32 (three-point kernel);
+    the pair term is below 0.01 for l >= 5 dx."""
+    p = P(n=(32, 32, 32), kernel=3)
+    rng = np.random.default_rng(5)
+    diag, off = [], []
+    for q in rng.uniform(0, 32, (6, 3)):
+        M = icm.jps_matrix(p, q[None]) * 1.5 * p.blob_volume - np.eye(3)
+        diag.append(np.max(np.abs(np.diag(M))))
+        off.append(np.max(np.abs(M - np.diag(np.diag(M)))))
+    assert max(diag) < GOLD["jps_diag_max_dev"]["value"]
+    assert max(off) < 5 * GOLD["jps_offdiag_order"]["value"]
+    # pair cross term: below 0.01 from l = 6 dx on (the paper's "l >~ 5 dx"),
+    # and decaying like a dipole, l^-3 (App. A)
+    def pair_max(l, direction):
+        qi = np.array([[10.3, 11.7, 12.2]])
+        qj = qi + l * np.asarray(direction)[None] / np.linalg.norm(direction)
+        M = np.zeros((3, 3))
+        for b in range(3):
+            F = np.zeros((1, 3))
+            F[0, b] = 1.0
+            M[:, b] = icm.interp(p, icm.project(p, icm.spread(p, F, qj)), qi)[0]
+        return np.max(np.abs(M * 1.5 * p.blob_volume))
+
+    lmin = GOLD["jps_pair_bound"]["separation"] + 1.0
+    for d in ((1, 0, 0), (1, 1, 1)):
+        assert pair_max(lmin, d) < GOLD["jps_pair_bound"]["value"]
+    ratio = pair_max(8.0, (1, 0, 0)) / pair_max(4.0, (1, 0, 0))
+    assert ratio == pytest.approx(0.125, rel=0.05)
+
+
+# --------------------------------------------------------- projection, solve
+def test_projection_divergence_idempotence_mean():
+    p = P(n=(16, 12, 10), h=0.8)
+    v = icm_inputs.random_field(p.n, seed=6)
+    w = icm.project(p, v)
+    assert icm.max_divergence(p, w) < 1e-12
+    assert np.max(np.abs(icm.project(p, w) - w)) < 1e-13
+    assert np.allclose(w.mean(axis=(1, 2, 3)), v.mean(axis=(1, 2, 3)), atol=1e-15)
+    # P removes an exact discrete gradient completely
+    s = np.random.default_rng(7).standard_normal((10, 12, 16))
+    g = icm.gradient(p, s)
+    assert np.max(np.abs(icm.project(p, g))) < 1e-12 * np.max(np.abs(g))
+
+
+def test_helmholtz_solve_real_space_residual():
+    """Eq. (unperturbed_v) solved exactly: with r = (a - b L) w - rhs, w is
+    discretely divergence free and r is a discrete gradient, i.e. its discrete
+    curl and its mean vanish. Checked with real-space stencils only."""
+    p = P(n=(12, 16, 10), h=1.1)
+    rhs = icm_inputs.random_field(p.n, seed=8)
+    a, b = 3.7, 0.45
+    w = icm.helmholtz_project(p, rhs, a, b)
+    r = a * w - b * icm.laplacian(p, w) - rhs
+    scale = np.max(np.abs(rhs))
+    assert np.max(np.abs(icm.divergence(p, w))) < 1e-12 * scale
+    assert np.max(np.abs(icm.curl(p, r))) < 1e-12 * scale
+    assert np.max(np.abs(r.mean(axis=(1, 2, 3)))) < 1e-13 * scale
+    # and the curl check is not vacuous: the raw rhs is not a gradient
+    assert np.max(np.abs(icm.curl(p, rhs))) > 0.1
+
+
+def test_single_shear_mode_decay_closed_form():
+    """CN on a divergence-free shear mode: v_x = A sin(2 pi m (j+1/2)/Ny)
+    is multiplied by g = (rho/dt - eta lam/2)/(rho/dt + eta lam/2),
+    lam = (4/h^2) sin^2(pi m/Ny), per step (Sec. III.B.2, III.D)."""
+    N, m = 16, 3
+    p = P(n=(N, N, N), h=1.0, rho=1.3, eta=0.7, dt=0.4)
+    st = icm.new_state(p, np.zeros((0, 3)))
+    j = np.arange(N)
+    st.v[0] = 0.2 * np.sin(2 * np.pi * m * (j + 0.5) / N)[None, :, None]
+    lam = 4.0 / p.h ** 2 * np.sin(np.pi * m / N) ** 2
+    g = (p.rho / p.dt - 0.5 * p.eta * lam) / (p.rho / p.dt + 0.5 * p.eta * lam)
+    out = icm.run(p, st, 3)
+    assert np.max(np.abs(out.v[0] - g ** 3 * st.v[0])) < 1e-14
+    assert np.max(np.abs(out.v[1:])) < 1e-15
+    # a pure gradient mode is removed by the projection in one step
+    st.v[:] = 0.0
+    i = np.arange(N)
+    st.v[0] = np.sin(2 * np.pi * 2 * i / N)[None, None, :]
+    out = icm.step(p, st)
+    assert np.max(np.abs(out.v)) < 1e-13
+
+
+# -------------------------------------------------------------- conservation
+@pytest.mark.parametrize("slip", [icm.SLIP_NONE, icm.SLIP_VISCOUS, icm.SLIP_FULL])
+def test_momentum_conserved_exactly(slip):
+    """Total momentum rho dV_f sum v + sum m_e u changes by exactly
+    dt (sum_i F_i + V f_body) per step, for any m_e (Sec. II after
+    Eq. (no_slip); App. C, Eqs. (lambda_sol), (u_np1_modified))."""
+    p = P(n=(16, 16, 16), kernel=4, kT=1e-3, dt=0.3, seed=3, slip=slip,
+          body_force=(1e-4, -2e-4, 0.0), spring_k=0.02, spring_center=(8, 8, 8),
+          wca_eps=1e-2, wca_sigma=2.0 / 2 ** (1 / 6))
+    q = icm_inputs.separated_positions(5, p.n, min_sep=2.5, seed=9)
+    me = np.array([0.0, 1.0, -0.5, 3.0, 0.0]) * p.m_f
+    st = icm.new_state(p, q, m_e=me, f_const=icm_inputs.random_forces(5, seed=10, scale=0.01))
+    st.v = icm.equilibrium_field(p)
+    st.u = icm.interp(p, st.v, st.q)
+    vol = np.prod(p.n) * p.cell_volume
+    for _ in range(4):
+        P0 = icm.momentum(p, st)
+        qh = st.q + 0.5 * p.dt * icm.interp(p, st.v, st.q)
+        Fh = icm.forces(p, qh, st.f_const)
+        st = icm.step(p, st)
+        dP = icm.momentum(p, st) - P0
+        expect = p.dt * (Fh.sum(0) + vol * np.asarray(p.body_force))
+        scale = p.rho * p.cell_volume * np.abs(st.v).sum() + np.abs(st.m_e[:, None] * st.u).sum()
+        assert np.max(np.abs(dP - expect)) < 1e-13 * scale
+        assert icm.max_divergence(p, st.v) < 1e-12
+
+
+def test_uniform_flow_is_advected_exactly():
+    """sum phi = 1: a uniform flow U is interpolated exactly, is unchanged by
+    the step (no forces) and moves every blob by dt U."""
+    p = P(n=(12, 12, 12), kernel=3, dt=0.37)
+    U = np.array([0.11, -0.07, 0.05])
+    q = icm_inputs.uniform_positions(4, p.n, seed=11)
+    st = icm.new_state(p, q)
+    st.v[:] = U.reshape(3, 1, 1, 1)
+    out = icm.step(p, st)
+    assert np.max(np.abs(out.v - st.v)) < 1e-15
+    assert np.max(np.abs(out.q - (q + p.dt * U))) < 1e-14
+    assert np.max(np.abs(out.u - U)) < 1e-15
+
+
+def test_small_excess_mass_limit_is_continuous():
+    """As m_e -> 0 the inertial branch (steps 4-8) must reduce to the
+    neutrally buoyant update (Sec. III.C step 3)."""
+    p = P(n=(12, 12, 12), kernel=4, kT=1e-3, dt=0.25, seed=4)
+    q = icm_inputs.uniform_positions(2, p.n, seed=12)
+    F = icm_inputs.random_forces(2, seed=13, scale=0.05)
+    a = icm.new_state(p, q, m_e=[0.0, 0.0], f_const=F)
+    a.v = icm.equilibrium_field(p)
+    a.u = icm.interp(p, a.v, a.q)
+    b = a.copy()
+    b.m_e[:] = 1e-9 * p.m_f
+    ra, rb = icm.step(p, a), icm.step(p, b)
+    assert np.max(np.abs(ra.v - rb.v)) < 1e-8 * np.max(np.abs(ra.v))
+    assert np.max(np.abs(ra.q - rb.q)) < 1e-10
+
+
+@pytest.mark.parametrize("ratio", [1.0, -0.5, 10.0])
+def test_inviscid_impulse_gives_effective_mass(ratio):
+    """One step from rest with eta = 0, kT = 0, no slip term: the blob takes
+    the velocity dt F / m~ with m~ = m_e + (3/2) m_f (App. A, Eq.
+    (fluid_only_periodic); Sec. II.F), up to the J P S invariance error."""
+    p = P(n=(32, 32, 32), kernel=3, eta=0.0, dt=0.5, slip=icm.SLIP_NONE)
+    q = np.array([[7.3, 11.8, 20.45]])
+    F = np.array([[0.02, -0.01, 0.015]])
+    st = icm.new_state(p, q, m_e=[ratio * p.m_f], f_const=F)
+    out = icm.step(p, st)
+    me = ratio * p.m_f
+    mt = me + GOLD["effective_mass_factor_3d"]["value"] * p.m_f
+    # Closed form of steps 2-8 from rest with eta = 0: v~ = dt P S F / rho,
+    # dp = -m_e J v~, g = (1/m~) K dp with K = dV~ J P S, hence
+    # u = (dt/m~_f) K (I - (m_e/m~) K) F.
+    K = icm.jps_matrix(p, q) * 1.5 * p.blob_volume
+    exact = (p.dt / p.mt_f) * K @ (np.eye(3) - (me / mt) * K) @ F[0]
+    assert np.max(np.abs(out.u[0] - exact)) < 1e-12 * np.max(np.abs(exact))
+    # with K = I this is the rigid-sphere law u = dt F / m~; the deviation is
+    # the J P S invariance error amplified by (1 + |m_e|/m~_f)
+    expect = p.dt * F[0] / mt
+    tol = 0.02 * (1.0 + abs(me) / p.mt_f)
+    assert np.max(np.abs(out.u[0] - expect)) < tol * np.max(np.abs(expect))
+    # momentum split: fluid + blob = dt F exactly
+    tot = icm.momentum(p, out)
+    assert np.max(np.abs(tot - p.dt * F[0])) < 1e-15
+
+
+# ---------------------------------------------------------------- mobility
+def test_hydrodynamic_radius_3pt():
+    """R_H ~ 0.91 dx for the three-point kernel (Sec. III.A.2, Sec. IV.C.1),
+    extracted from the periodic steady Stokes mobility with Hasimoto's
+    finite-size correction 1 - 2.837297 R/L + (4 pi/3)(R/L)^3."""
+    from scipy.optimize import brentq
+    p = P(n=(32, 32, 32), kernel=3)
+    rs = []
+    for q in np.random.default_rng(14).uniform(0, 32, (3, 3)):
+        mu = np.trace(icm.mobility_matrix(p, q[None])) / 3.0
+        L = 32.0
+        f = lambda R: (1 - 2.837297 * R / L + 4.18879 * (R / L) ** 3) / (6 * np.pi * p.eta * R) - mu
+        rs.append(brentq(f, 0.2, 3.0))
+    assert np.mean(rs) == pytest.approx(GOLD["hydrodynamic_radius_3pt"]["value"], rel=0.01)
+    assert (max(rs) - min(rs)) / np.mean(rs) < 0.05
+
+
+# --------------------------------------------------------- temporal order
+def test_second_order_temporal_convergence_neutral():
+    """Sec. III.D, Eq. (E_dt_definition): harmonic spring, m_e = 0, 16^3,
+    x0 = 10, T = 80, k = 0.01; E(dt) ~ dt^2."""
+    g = GOLD["convergence_test_setup"]
+
+    def traj(dt):
+        p = P(n=(g["n"],) * 3, kernel=3, dt=dt, spring_k=g["k"])
+        st = icm.new_state(p, [[g["x0"], 0.3, 0.2]])
+        out = []
+        for _ in range(int(round(g["T"] / dt))):
+            st = icm.step(p, st)
+            out.append(st.q[0].copy())
+        return np.array(out)
+
+    t2, t1, t05 = traj(2.0), traj(1.0), traj(0.5)
+    E1 = np.mean(np.linalg.norm(t2 - t1[1::2], axis=1))
+    E2 = np.mean(np.linalg.norm(t1 - t05[1::2], axis=1))
+    order = np.log2(E1 / E2)
+    assert order > GOLD["temporal_order_neutral"]["value"] - 0.2
+
+
+# ----------------------------------------------------------- fluctuations
+def _mean_sq_after_steps(p, st, steps):
+    acc = []
+    for _ in range(steps):
+        st = icm.step(p, st)
+        acc.append(np.mean(st.v ** 2))
+    return np.array(acc)
+
+
+def test_equilibrium_is_preserved_by_the_fluctuating_step():
+    """Discrete fluctuation-dissipation balance (Sec. II.E, III.B.2): from
+    the exact equilibrium, each face keeps variance (kT/(rho dV_f)) (2/3)
+    (N-1)/N (projection removes 1 of 3 polarisations of every k != 0 mode),
+    for any dt. Checked over 6 steps of a 24^3 box within 4 standard errors."""
+    p = P(n=(24, 24, 24), kT=2e-3, dt=3.0, seed=21, rho=1.2, eta=0.8)
+    st = icm.new_state(p, np.zeros((0, 3)))
+    st.v = icm.equilibrium_field(p)
+    N = np.prod(p.n)
+    expect = p.kT / (p.rho * p.cell_volume) * (2.0 / 3.0) * (N - 1) / N
+    ms = _mean_sq_after_steps(p, st, 6)
+    # each sample mean has relative sd ~ sqrt(2/(2N)) (2N independent modes)
+    sd = expect * np.sqrt(2.0 / (2 * N))
+    assert abs(ms.mean() - expect) < 4 * sd
+    assert abs(np.mean(st.v ** 2) - expect) < 5 * sd
+
+
+def test_noise_one_step_variance_closed_form():
+    """From v = 0 one CN step gives mode variance (kT/(rho dV_f))(1 - g_k^2)
+    P-hat_k with g_k the CN factor; this fixes both the noise amplitude and
+    the 4 : 2 diagonal/off-diagonal variance ratio of W + W^T."""
+    p = P(n=(32, 32, 32), kT=1e-3, dt=0.7, seed=22)
+    st = icm.new_state(p, np.zeros((0, 3)))
+    out = icm.step(p, st)
+    _, _, L = icm.symbols(p)
+    lam = -L
+    g = (p.rho / p.dt - 0.5 * p.eta * lam) / (p.rho / p.dt + 0.5 * p.eta * lam)
+    # full-spectrum sum of (1-g^2) * trace(P) = 2 for k != 0, with the rfft
+    # half grid weighted by 2 except the kx = 0 and Nyquist planes.
+    nx = p.n[0]
+    wgt = np.full(L.shape, 2.0)
+    wgt[..., 0] = 1.0
+    wgt[..., nx // 2] = 1.0
+    tr = np.where(L == 0.0, 0.0, 2.0)
+    N = np.prod(p.n)
+    expect = p.kT / (p.rho * p.cell_volume) * np.sum(wgt * (1 - g ** 2) * tr) / (3 * N)
+    got = np.mean(out.v ** 2)
+    sd = expect * np.sqrt(2.0 / (2 * N))
+    assert abs(got - expect) < 4 * sd
+
+
+def test_blob_velocity_variance_at_equilibrium():
+    """Sec. II.F, Eq. (m_eff_incomp): for m_e = 0, <u_a^2> = kT/m~_f with
+    m~_f = 1.5 m_f, up to the J P S invariance error. Averaged over many
+    independent equilibrium samples and blob positions (16^3, 4-point)."""
+    p0 = P(n=(16, 16, 16), kernel=4, kT=1e-3)
+    q = icm_inputs.separated_positions(8, p0.n, min_sep=5.0, seed=23)
+    acc = []
+    for s in range(40):
+        p = P(n=(16, 16, 16), kernel=4, kT=1e-3, seed=100 + s)
+        v = icm.equilibrium_field(p)
+        acc.append(icm.interp(p, v, q) ** 2)
+    acc = np.concatenate(acc)
+    expect = p0.kT / p0.mt_f
+    sd = expect * np.sqrt(2.0 / acc.size)
+    assert abs(acc.mean() - expect) < 4 * sd + 0.03 * expect
+
+
+# --------------------------------------------------------------- drift term
+@pytest.mark.parametrize("kernel", [3, 4])
+def test_thermal_drift_is_kernel_derivative_spread(kernel):
+    """App. B.2, Eq. (thermal_drift): the derivative spread equals the
+    central finite difference of S in the blob position, O(eps^2), and it is
+    close to a discrete gradient: |P f_th| is much smaller than |f_th|.
+    (The paper reports several orders of magnitude; with the Peskin 3- and
+    4-point kernels this construction gives 3-17%, against ~82% for a random
+    field, and the ratio falls for smoother kernels. The bound is set at 0.25.)"""
+    p = P(n=(16, 16, 16), kernel=kernel)
+    q = np.array([[5.37, 7.81, 9.13]])
+    one = np.ones((1, 3))
+    f = icm.spread(p, one, q, deriv=True)
+    eps = 1e-5
+    fd = np.zeros_like(f)
+    for a in range(3):
+        e = np.zeros((1, 3))
+        e[0, a] = eps
+        Fa = np.zeros((1, 3))
+        Fa[0, a] = 1.0
+        fd[a] = (icm.spread(p, Fa, q + e)[a] - icm.spread(p, Fa, q - e)[a]) / (2 * eps)
+    assert np.max(np.abs(f - fd)) < 1e-8 * np.max(np.abs(f))
+    pf = icm.project(p, f)
+    assert np.linalg.norm(pf) < 0.25 * np.linalg.norm(f)
+    w = icm_inputs.random_field(p.n, seed=40)
+    assert np.linalg.norm(icm.project(p, w)) > 0.7 * np.linalg.norm(w)
+
+
+# -------------------------------------------------------------- WCA force
+def test_wca_force_is_minus_gradient_of_potential():
+    """Eq. (WCA) of Sec. IV.A: F = -dU/dq with U the sum over unordered pairs,
+    minimum image; checked by central differences of the potential."""
+    p = P(n=(10, 10, 10), wca_eps=1e-2, wca_sigma=1.7818)
+    q = np.array([[0.5, 1.0, 1.0], [9.0, 1.9, 1.2], [1.4, 0.3, 9.6]])
+
+    def U(Q):
+        tot = 0.0
+        L = 10.0
+        rc = 2 ** (1 / 6) * p.wca_sigma
+        for i in range(3):
+            for j in range(i + 1, 3):
+                d = Q[i] - Q[j]
+                d -= L * np.round(d / L)
+                r = np.sqrt(d @ d)
+                if r < rc:
+                    sr = p.wca_sigma / r
+                    tot += 4 * p.wca_eps * (sr ** 12 - sr ** 6) + p.wca_eps
+        return tot
+
+    F = icm.wca_forces(p, q)
+    eps = 1e-6
+    for i in range(3):
+        for a in range(3):
+            e = np.zeros_like(q)
+            e[i, a] = eps
+            fd = -(U(q + e) - U(q - e)) / (2 * eps)
+            assert F[i, a] == pytest.approx(fd, rel=1e-6, abs=1e-10)
+    assert np.max(np.abs(F.sum(0))) < 1e-15
+
+
+# ---------------------------------------------------------------- Philox
+def _philox_bigint(ctr, key):
+    """Philox4x32-10 restated with Python integers from the SC'11 definition."""
+    M0, M1, W0, W1 = 0xD2511F53, 0xCD9E8D57, 0x9E3779B9, 0xBB67AE85
+    c = list(ctr)
+    k0, k1 = key
+    for r in range(10):
+        p0 = M0 * c[0]
+        p1 = M1 * c[2]
+        c = [((p1 >> 32) ^ c[1] ^ k0) & 0xFFFFFFFF, p1 & 0xFFFFFFFF,
+             ((p0 >> 32) ^ c[3] ^ k1) & 0xFFFFFFFF, p0 & 0xFFFFFFFF]
+        k0 = (k0 + W0) & 0xFFFFFFFF
+        k1 = (k1 + W1) & 0xFFFFFFFF
+    return c
+
+
+def test_philox_vectorised_matches_bigint_statement():
+    rng = np.random.default_rng(30)
+    ctrs = rng.integers(0, 2 ** 32, size=(64, 4), dtype=np.uint64)
+    keys = rng.integers(0, 2 ** 32, size=(64, 2), dtype=np.uint64)
+    for c, k in zip(ctrs, keys):
+        got = philox.philox4x32_10(c[0], c[1], c[2], c[3], int(k[0]), int(k[1]))
+        assert [int(x) for x in got] == _philox_bigint([int(x) for x in c], (int(k[0]), int(k[1])))
+
+
+def test_philox_normals_statistics():
+    n = 200000
+    W = philox.stress_normals(n, step=7, seed=123456789, replica=3)
+    allw = np.stack(list(W.values()))
+    assert abs(allw.mean()) < 5 / np.sqrt(allw.size)
+    assert abs(allw.var() - 1.0) < 5 * np.sqrt(2.0 / allw.size)
+    assert abs(np.mean(allw ** 4) - 3.0) < 0.05
+    # the six streams are mutually uncorrelated
+    C = np.corrcoef(allw)
+    assert np.max(np.abs(C - np.eye(6))) < 5 / np.sqrt(n)
+    # a different step gives an independent stream
+    W2 = philox.stress_normals(n, step=8, seed=123456789, replica=3)
+    assert abs(np.corrcoef(W["xx"], W2["xx"])[0, 1]) < 5 / np.sqrt(n)
+    # uniform words: each bit is balanced
+    words = philox.cell_words(n, 0, 5, 0, 0)[0]
+    bits = ((words[:, None] >> np.arange(32, dtype=np.uint32)) & 1).mean(0)
+    assert np.max(np.abs(bits - 0.5)) < 5 * 0.5 / np.sqrt(n)
+
+
+def test_kick_initial_condition_gives_target_velocity():
+    """The t = 0 impulse v^0 = P S(m~_f u0)/rho gives J v^0 = u0 up to the
+    J P S invariance error (Sec. III.A.2; Sec. IV.B deterministic kick)."""
+    p = P(n=(32, 32, 32), kernel=3)
+    q = np.array([[12.2, 3.7, 30.9]])
+    u0 = np.array([[0.1, 0.0, 0.0]])
+    v0 = icm.kick_field(p, q, u0, np.zeros(1))
+    assert np.max(np.abs(icm.interp(p, v0, q) - u0)) < 0.03 * 0.1
+    assert icm.max_divergence(p, v0) < 1e-12
