@@ -1,0 +1,203 @@
+/*
+ * icm.h - C ABI of the MI355X (gfx950) incompressible Inertial Coupling
+ * Method step.
+ *
+ * The library advances blob particles coupled to a fluctuating incompressible
+ * fluid on a periodic staggered (MAC) grid by the second-order semi-implicit
+ * step of Balboa Usabiaga, Delgado-Buscalioni, Griffith and Donev, "Inertial
+ * coupling method for particles in an incompressible fluctuating fluid",
+ * Sec. III.C (Summary of Algorithm, steps 1-9) with the inertial velocity
+ * correction of App. C and the thermal drift of App. B.2. Every step of the
+ * method runs in hand-written HIP kernels on the device; the host only
+ * validates arguments, uploads/downloads state and enqueues work.
+ *
+ * Conventions shared by every entry point
+ *  - Grid: Nx x Ny x Nz cells of side h (h = dx = dy = dz, Sec. III.A). Each
+ *    N must be even, between 4 and 512, and have no prime factor other than 2
+ *    and 3. A face field is three arrays (x, y, z components) of Nx*Ny*Nz
+ *    values each, x fastest; v_x[k][j][i] sits at (i h, (j+1/2) h, (k+1/2) h),
+ *    v_y at ((i+1/2) h, j h, (k+1/2) h), v_z at ((i+1/2) h, (j+1/2) h, k h).
+ *  - Field values are double (ICM_FP64) or float (ICM_FP32_GRID); blob
+ *    positions, velocities, masses and forces are always double, laid out as
+ *    n_blobs x 3 (x,y,z interleaved). Positions are unwrapped: the library
+ *    never folds them into the box, it wraps only when indexing the grid.
+ *  - Host pointers are read or written only during the call. With
+ *    ICM_PTRS_DEVICE the pointers must be device memory on the context's
+ *    device; the copies are then enqueued on the context stream.
+ *  - All device work is ordered on the stream given to icm_create. Calls that
+ *    return data to host memory synchronise that stream first.
+ *  - Every call returns an icm_status; on a negative status icm_last_error
+ *    describes the problem. ICM_E_INVALID and ICM_E_UNSUPPORTED leave the
+ *    context unchanged and usable. ICM_E_DEVICE and ICM_E_NUMERIC put it in an
+ *    error state in which icm_step refuses to run until icm_set_state
+ *    installs a new state.
+ *  - One context must not be used from two host threads at once.
+ */
+#ifndef ICM_H
+#define ICM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct icm_ctx icm_ctx;
+
+typedef enum {
+    ICM_OK = 0,
+    ICM_E_INVALID = -1,     /* bad argument or parameter                    */
+    ICM_E_UNSUPPORTED = -2, /* valid request this build does not handle     */
+    ICM_E_NOMEM = -3,       /* workspace too small or device allocation failed */
+    ICM_E_DEVICE = -4,      /* a HIP call failed                            */
+    ICM_E_STATE = -5,       /* context in error state / call out of order   */
+    ICM_E_NUMERIC = -6      /* NaN/Inf or a blob moved more than h in a step */
+} icm_status;
+
+enum { ICM_FP64 = 0, ICM_FP32_GRID = 1 };
+
+/* No-slip centring correction delta-u of step 4 (Sec. III.C):
+ * NONE: delta-u = 0 (first order, most stable for very large dt);
+ * VISCOUS: the lagged viscous term of Eq. (delta_u_nph_visc) (the paper's
+ *          default for small Reynolds numbers);
+ * FULL: Eq. (delta_u_nph), adding (J^{n+1/2} - J^n) v^n.                */
+enum { ICM_SLIP_NONE = 0, ICM_SLIP_VISCOUS = 1, ICM_SLIP_FULL = 2 };
+
+/* flags of icm_set_blobs / icm_set_state / icm_get_state */
+enum {
+    ICM_PTRS_DEVICE = 1u,   /* pointer arguments are device memory          */
+    ICM_BLOBS_KICK = 2u,    /* icm_set_blobs: add to the fluid the impulse
+                               v += P S(m~_f u) / rho that gives each blob the
+                               velocity u at t = 0                           */
+    ICM_STATE_PROJECT = 4u, /* icm_set_state: project the uploaded v onto
+                               discretely divergence-free fields             */
+    ICM_STATE_EQUILIBRIUM = 8u /* icm_set_state: replace v by a sample of the
+                               discrete equilibrium N(0, kT/(rho h^3)) P drawn
+                               from Philox block 2 of (seed, replica_id)     */
+};
+
+/* Physical and numerical parameters of one replica (one periodic box). */
+typedef struct {
+    int32_t n[3];            /* Nx, Ny, Nz                                   */
+    int32_t kernel;          /* 3 or 4: Peskin 3-point or 4-point kernel     */
+    double h;                /* grid spacing (> 0)                           */
+    double rho;              /* fluid density (> 0)                          */
+    double eta;              /* shear viscosity (>= 0)                       */
+    double kT;               /* temperature k_B T (>= 0; 0 = deterministic)  */
+    double dt;               /* time step (> 0)                              */
+    int32_t slip;            /* ICM_SLIP_*                                   */
+    int32_t thermal_drift;   /* 1: spread the thermal drift of App. B.2 when
+                                kT > 0; 0: omit it                           */
+    uint64_t seed;           /* Philox key of the stochastic stress          */
+    uint32_t replica_id;     /* Philox counter word distinguishing replicas  */
+    uint32_t reserved;       /* must be 0                                    */
+    double body_force[3];    /* uniform force density on the fluid           */
+    double wca_eps;          /* WCA pair potential of Sec. IV.A (0 = off)    */
+    double wca_sigma;        /* WCA diameter; cutoff 2^(1/6) sigma < N h / 2 */
+    double spring_k;         /* tether spring -k (q - c) per blob (0 = off)  */
+    double spring_center[3];
+} icm_replica_params;
+
+/* FP64 diagnostics of one replica. */
+typedef struct {
+    double momentum[3];  /* rho h^3 sum v + sum m_e u (Sec. II)                 */
+    double ke_fluid;     /* rho h^3 sum v^2 / 2                                 */
+    double ke_blob;      /* sum m_e u^2 / 2                                     */
+    double max_div;      /* max |D v| h / max |v| (0 for v = 0)                 */
+    int64_t step;        /* steps taken since the state was set                */
+} icm_diag;
+
+/* Bytes of device workspace icm_create needs for these replicas.
+ * p: n_rep parameter blocks; max_blobs: n_rep capacities (>= 0).           */
+icm_status icm_workspace_bytes(int32_t n_rep, const icm_replica_params* p,
+                               const int32_t* max_blobs, int32_t precision,
+                               size_t* bytes);
+
+/* Create a context of n_rep independent replicas (uneven grids allowed) that
+ * are stepped together. precision: ICM_FP64 or ICM_FP32_GRID (blob state is
+ * FP64 in both). workspace/bytes: device memory of at least
+ * icm_workspace_bytes, owned by the caller and kept alive until
+ * icm_destroy; NULL makes the library allocate (and free) it. stream: a
+ * hipStream_t, or NULL for the null stream. On success *out receives the
+ * context; the fluid starts at rest with no blobs.                          */
+icm_status icm_create(int32_t n_rep, const icm_replica_params* p,
+                      const int32_t* max_blobs, int32_t precision,
+                      void* workspace, size_t bytes, void* stream,
+                      icm_ctx** out);
+
+/* Install n_blobs blobs in a replica (replacing any previous ones).
+ * q: positions (required); u: velocities (NULL = 0); m_e: excess masses
+ * (NULL = 0, each must exceed -m_f = -rho dV, Sec. I.A); f_const: constant
+ * external forces (NULL = 0). Clears the lagged slip term.
+ * Flags: ICM_PTRS_DEVICE, ICM_BLOBS_KICK.                                  */
+icm_status icm_set_blobs(icm_ctx* ctx, int32_t replica, int32_t n_blobs,
+                         const double* q, const double* u, const double* m_e,
+                         const double* f_const, uint32_t flags);
+
+/* Overwrite parts of a replica's state (checkpoint restore / test input).
+ * v: face field in the context precision (NULL = keep); q, u, lag_c:
+ * n_blobs x 3 blob arrays for the installed blobs (NULL = keep); step: the
+ * step counter n that feeds the Philox counter (negative = keep).
+ * Flags: ICM_PTRS_DEVICE, ICM_STATE_PROJECT, ICM_STATE_EQUILIBRIUM.
+ * Clears the error state.                                                  */
+icm_status icm_set_state(icm_ctx* ctx, int32_t replica, const void* v,
+                         const double* q, const double* u,
+                         const double* lag_c, int64_t step, uint32_t flags);
+
+/* Advance every replica by n_steps steps (Sec. III.C). Work is enqueued on
+ * the context stream; the call then synchronises once to check the numeric
+ * flag (NaN/Inf in a blob, or a blob displacement above h in one step, which
+ * breaks the advective CFL condition alpha < 1 of Sec. III.D) and returns
+ * ICM_E_NUMERIC if it was raised.                                          */
+icm_status icm_step(icm_ctx* ctx, int64_t n_steps, uint32_t flags);
+
+/* Read a replica's state. Any output may be NULL. v: face field in the
+ * context precision; q, u, lag_c: n_blobs x 3; diag: FP64 diagnostics.     */
+icm_status icm_get_state(icm_ctx* ctx, int32_t replica, void* v, double* q,
+                         double* u, double* lag_c, icm_diag* diag,
+                         uint32_t flags);
+
+/* Per-kernel timing of icm_step. With timing enabled, icm_step records a
+ * pair of HIP events on the context stream around every kernel launch and
+ * accumulates the elapsed time per phase (a fixed kernel family), so that a
+ * kernel's average launch duration is ms[phase] / launches[phase]. Timing
+ * adds a small host cost per launch; leave it off for throughput runs.     */
+enum {
+    ICM_PHASE_GATHER = 0,    /* J: interpolation of a face field at blobs    */
+    ICM_PHASE_BLOB = 1,      /* per-blob FP64 updates (steps 1, 4, 8, 9)     */
+    ICM_PHASE_FORCES = 2,    /* tether spring + WCA pair forces              */
+    ICM_PHASE_RHS = 3,       /* step-2 right-hand side with Philox noise     */
+    ICM_PHASE_SPREAD = 4,    /* S: spreading of forces / drift / momentum    */
+    ICM_PHASE_FFT_X_FWD = 5, /* real-to-complex transform along x            */
+    ICM_PHASE_FFT_Y_FWD = 6, /* complex transform along y                    */
+    ICM_PHASE_FFT_Z_SOLVE = 7, /* z transform, Helmholtz + projection, inverse z */
+    ICM_PHASE_FFT_Y_INV = 8, /* inverse transform along y                    */
+    ICM_PHASE_FFT_X_INV = 9, /* complex-to-real transform along x            */
+    ICM_PHASE_FIELD_OPS = 10, /* field clears and additions                  */
+    ICM_NUM_PHASES = 11
+};
+typedef struct {
+    double ms[16];         /* accumulated GPU time per phase (milliseconds) */
+    int64_t launches[16];  /* number of timed launches per phase            */
+} icm_timing;
+
+icm_status icm_set_timing(icm_ctx* ctx, int32_t enable);
+/* Copy the accumulated timing into *out; reset != 0 clears it afterwards.  */
+icm_status icm_get_timing(icm_ctx* ctx, icm_timing* out, int32_t reset);
+
+/* Number of blobs currently installed in a replica (or -1 on a bad call). */
+int32_t icm_num_blobs(const icm_ctx* ctx, int32_t replica);
+
+/* Release the context and any memory the library allocated. NULL is a no-op. */
+void icm_destroy(icm_ctx* ctx);
+
+/* Message of the last failing call on ctx (or of the last failing
+ * icm_create / icm_workspace_bytes when ctx is NULL). Never NULL.          */
+const char* icm_last_error(const icm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ICM_H */

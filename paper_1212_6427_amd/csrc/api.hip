@@ -1,0 +1,720 @@
+// Context and C ABI of the ICM library (declared in include/icm.h).
+//
+// A context owns one HIP stream binding and a device workspace carved into
+// per-replica field buffers (v, rhs, aux, spectrum), FFT twiddles, difference
+// symbols and FP64 blob arrays. icm_step enqueues, for every replica, the
+// nine steps of the Summary of Algorithm (Sec. III.C) as a fixed sequence of
+// kernels; no host synchronisation happens inside a step.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/icm.h"
+#include "icm_internal.h"
+
+using icm::cplx;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+struct Replica {
+    icm_replica_params p;
+    int max_nb = 0;
+    int nb = 0;
+    int64_t step = 0;
+    bool any_me = false;
+    double m_f = 0, mt_f = 0;
+    icm::GridDesc<float> gf{};
+    icm::GridDesc<double> gd{};
+    icm::BlobBufs bb{};
+    double* diag = nullptr;  // 16 doubles
+};
+
+}  // namespace
+
+struct icm_ctx {
+    // per-phase kernel timing (icm_set_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    double phase_ms[16] = {0};
+    int64_t phase_n[16] = {0};
+    int32_t precision = ICM_FP64;
+    hipStream_t stream = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool owns_ws = false;
+    bool error_state = false;
+    std::vector<Replica> reps;
+    std::string err = "no error";
+};
+
+namespace {
+
+icm_status fail(icm_ctx* c, icm_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(ctx, call)                                                                      \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) {                                                                 \
+            if (ctx) (ctx)->error_state = true;                                                 \
+            return fail(ctx, ICM_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));      \
+        }                                                                                       \
+    } while (0)
+
+// ------------------------------------------------------------ validation
+bool factor_plan(int n, icm::FFTPlan& pl) {
+    pl.n = n;
+    pl.nst = 0;
+    int m = n;
+    while (m % 8 == 0 && pl.nst < icm::kMaxStages) { pl.radix[pl.nst++] = 8; m /= 8; }
+    while (m % 4 == 0 && pl.nst < icm::kMaxStages) { pl.radix[pl.nst++] = 4; m /= 4; }
+    while (m % 2 == 0 && pl.nst < icm::kMaxStages) { pl.radix[pl.nst++] = 2; m /= 2; }
+    while (m % 3 == 0 && pl.nst < icm::kMaxStages) { pl.radix[pl.nst++] = 3; m /= 3; }
+    return m == 1;
+}
+
+double sum_phi_sq(int kernel) { return kernel == 3 ? 0.5 : 0.375; }
+
+icm_status validate(int32_t n_rep, const icm_replica_params* p, const int32_t* max_blobs, int32_t precision) {
+    if (n_rep < 1) return fail(nullptr, ICM_E_INVALID, "n_rep must be >= 1 (got %d)", n_rep);
+    if (!p || !max_blobs) return fail(nullptr, ICM_E_INVALID, "params and max_blobs must not be NULL");
+    if (precision != ICM_FP64 && precision != ICM_FP32_GRID)
+        return fail(nullptr, ICM_E_INVALID, "precision must be ICM_FP64 or ICM_FP32_GRID");
+    for (int r = 0; r < n_rep; ++r) {
+        const icm_replica_params& q = p[r];
+        for (int a = 0; a < 3; ++a) {
+            icm::FFTPlan pl;
+            const int n = q.n[a];
+            if (n < 4 || n > 512 || (n & 1) || !factor_plan(n, pl))
+                return fail(nullptr, ICM_E_INVALID,
+                            "replica %d: N[%d] = %d must be even, in [4, 512], with prime factors 2 and 3 only", r,
+                            a, n);
+        }
+        if (q.kernel != 3 && q.kernel != 4) return fail(nullptr, ICM_E_INVALID, "replica %d: kernel must be 3 or 4", r);
+        if (!(q.h > 0) || !(q.rho > 0) || !(q.eta >= 0) || !(q.kT >= 0) || !(q.dt > 0))
+            return fail(nullptr, ICM_E_INVALID, "replica %d: need h > 0, rho > 0, eta >= 0, kT >= 0, dt > 0", r);
+        if (q.slip < ICM_SLIP_NONE || q.slip > ICM_SLIP_FULL)
+            return fail(nullptr, ICM_E_INVALID, "replica %d: slip must be ICM_SLIP_NONE/VISCOUS/FULL", r);
+        if (q.thermal_drift != 0 && q.thermal_drift != 1)
+            return fail(nullptr, ICM_E_INVALID, "replica %d: thermal_drift must be 0 or 1", r);
+        if (q.reserved != 0) return fail(nullptr, ICM_E_INVALID, "replica %d: reserved must be 0", r);
+        if (!(q.wca_eps >= 0)) return fail(nullptr, ICM_E_INVALID, "replica %d: wca_eps must be >= 0", r);
+        if (q.wca_eps > 0) {
+            const double rc = std::pow(2.0, 1.0 / 6.0) * q.wca_sigma;
+            const double lmin = q.h * std::min(q.n[0], std::min(q.n[1], q.n[2]));
+            if (!(q.wca_sigma > 0) || !(rc < 0.5 * lmin))
+                return fail(nullptr, ICM_E_INVALID, "replica %d: need wca_sigma > 0 and cutoff < half the box", r);
+        }
+        if (max_blobs[r] < 0) return fail(nullptr, ICM_E_INVALID, "replica %d: max_blobs must be >= 0", r);
+    }
+    return ICM_OK;
+}
+
+// ------------------------------------------------------- workspace carving
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+    template <typename U>
+    U* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        U* r = base ? reinterpret_cast<U*>(base + off) : nullptr;
+        off += std::max<size_t>(count, 1) * sizeof(U);
+        return r;
+    }
+};
+
+template <typename T>
+void carve_grid(Carver& cv, const icm_replica_params& p, icm::GridDesc<T>& g) {
+    g.nx = p.n[0];
+    g.ny = p.n[1];
+    g.nz = p.n[2];
+    g.W = g.nx / 2 + 1;
+    g.ncell = (long long)g.nx * g.ny * g.nz;
+    g.nspec = (long long)g.nz * g.ny * g.W;
+    g.h = p.h;
+    g.v = cv.take<T>(3 * g.ncell);
+    g.rhs = cv.take<T>(3 * g.ncell);
+    g.aux = cv.take<T>(3 * g.ncell);
+    g.spec = cv.take<cplx<T>>(3 * g.nspec);
+    factor_plan(g.nx, g.px);
+    factor_plan(g.ny, g.py);
+    factor_plan(g.nz, g.pz);
+    g.twx = cv.take<cplx<T>>(g.nx);
+    g.twy = cv.take<cplx<T>>(g.ny);
+    g.twz = cv.take<cplx<T>>(g.nz);
+    g.dx_hat = cv.take<cplx<T>>(g.W);
+    g.dy_hat = cv.take<cplx<T>>(g.ny);
+    g.dz_hat = cv.take<cplx<T>>(g.nz);
+    g.lx = cv.take<T>(g.W);
+    g.ly = cv.take<T>(g.ny);
+    g.lz = cv.take<T>(g.nz);
+}
+
+void carve_blobs(Carver& cv, int max_nb, icm::BlobBufs& b, double*& diag) {
+    const size_t n3 = 3 * (size_t)max_nb;
+    b.q = cv.take<double>(n3);
+    b.u = cv.take<double>(n3);
+    b.fconst = cv.take<double>(n3);
+    b.lag = cv.take<double>(n3);
+    b.qh = cv.take<double>(n3);
+    b.F = cv.take<double>(n3);
+    b.Jn = cv.take<double>(n3);
+    b.Jhvn = cv.take<double>(n3);
+    b.Jhvt = cv.take<double>(n3);
+    b.du = cv.take<double>(n3);
+    b.dp = cv.take<double>(n3);
+    b.dp2 = cv.take<double>(n3);
+    b.g = cv.take<double>(n3);
+    b.Jhvnew = cv.take<double>(n3);
+    b.me = cv.take<double>(max_nb);
+    b.c5 = cv.take<double>(max_nb);
+    b.cdrift = cv.take<double>(max_nb);
+    b.flag = cv.take<unsigned int>(1);
+    diag = cv.take<double>(16);
+}
+
+size_t layout(int32_t n_rep, const icm_replica_params* p, const int32_t* max_blobs, int32_t precision, void* base,
+              std::vector<Replica>* reps) {
+    Carver cv(base);
+    for (int r = 0; r < n_rep; ++r) {
+        Replica tmp;
+        Replica& R = reps ? (*reps)[r] : tmp;
+        if (precision == ICM_FP64)
+            carve_grid(cv, p[r], R.gd);
+        else
+            carve_grid(cv, p[r], R.gf);
+        carve_blobs(cv, max_blobs[r], R.bb, R.diag);
+    }
+    return (cv.off + 255) & ~size_t(255);
+}
+
+// ---------------------------------------------------------- host tables
+template <typename T>
+icm_status upload_tables(icm_ctx* c, const icm::GridDesc<T>& g) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    auto tw = [&](int n) {
+        std::vector<cplx<T>> t(n);
+        for (int m = 0; m < n; ++m) {
+            const long double th = 2.0L * pi * (long double)m / (long double)n;
+            t[m] = {(T)cosl(th), (T)(-sinl(th))};
+        }
+        return t;
+    };
+    // Dhat = (e^{i theta} - 1)/h = (-2 sin^2(theta/2) + i sin theta)/h,
+    // lambda = 4 sin^2(theta/2) / h^2.
+    auto sym = [&](int n, int count, std::vector<cplx<T>>& d, std::vector<T>& l) {
+        d.resize(count);
+        l.resize(count);
+        for (int m = 0; m < count; ++m) {
+            const long double th = 2.0L * pi * (long double)m / (long double)n;
+            const long double s2 = sinl(0.5L * th);
+            d[m] = {(T)(-2.0L * s2 * s2 / g.h), (T)(sinl(th) / g.h)};
+            l[m] = (T)(4.0L * s2 * s2 / ((long double)g.h * g.h));
+        }
+    };
+    const hipStream_t s = c->stream;
+    auto tx = tw(g.nx), ty = tw(g.ny), tz = tw(g.nz);
+    std::vector<cplx<T>> dx, dy, dz;
+    std::vector<T> lx, ly, lz;
+    sym(g.nx, g.W, dx, lx);
+    sym(g.ny, g.ny, dy, ly);
+    sym(g.nz, g.nz, dz, lz);
+    HIP_TRY(c, hipMemcpyAsync((void*)g.twx, tx.data(), tx.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync((void*)g.twy, ty.data(), ty.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync((void*)g.twz, tz.data(), tz.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync((void*)g.dx_hat, dx.data(), dx.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync((void*)g.dy_hat, dy.data(), dy.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync((void*)g.dz_hat, dz.data(), dz.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync((void*)g.lx, lx.data(), lx.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync((void*)g.ly, ly.data(), ly.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync((void*)g.lz, lz.data(), lz.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipStreamSynchronize(s));  // host vectors go out of scope
+    return ICM_OK;
+}
+
+icm::BlobParams blob_params(const Replica& R) {
+    icm::BlobParams bp;
+    bp.nb = R.nb;
+    bp.dt = R.p.dt;
+    bp.rho = R.p.rho;
+    bp.eta = R.p.eta;
+    bp.kT = R.p.kT;
+    for (int a = 0; a < 3; ++a) {
+        bp.box[a] = R.p.n[a] * R.p.h;
+        bp.spring_c[a] = R.p.spring_center[a];
+    }
+    bp.wca_eps = R.p.wca_eps;
+    bp.wca_sigma = R.p.wca_sigma;
+    bp.spring_k = R.p.spring_k;
+    bp.slip = R.p.slip;
+    return bp;
+}
+
+icm::NoiseKey noise_key(const Replica& R, int64_t step) {
+    icm::NoiseKey k;
+    k.k0 = (uint32_t)(R.p.seed & 0xffffffffu);
+    k.k1 = (uint32_t)(R.p.seed >> 32);
+    k.step_lo = (uint32_t)((uint64_t)step & 0xffffffffu);
+    k.step_hi = (uint32_t)((uint64_t)step >> 32);
+    k.rep_tag = R.p.replica_id << 4;
+    return k;
+}
+
+template <typename T>
+icm::GridDesc<T>& grid_of(Replica& R);
+template <>
+icm::GridDesc<float>& grid_of<float>(Replica& R) { return R.gf; }
+template <>
+icm::GridDesc<double>& grid_of<double>(Replica& R) { return R.gd; }
+
+hipEvent_t take_event(icm_ctx* c) {
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+}
+
+// Run f (which enqueues kernels on s); with timing on, bracket it by events.
+template <class F>
+void timed(icm_ctx* c, int phase, hipStream_t s, F&& f) {
+    if (!c || !c->timing) {
+        f();
+        return;
+    }
+    hipEvent_t a = take_event(c), b = take_event(c);
+    if (!a || !b) {
+        f();
+        return;
+    }
+    (void)hipEventRecord(a, s);
+    f();
+    (void)hipEventRecord(b, s);
+    c->pending.push_back({phase, {a, b}});
+}
+
+// Fold finished event pairs into the per-phase totals (stream synchronised).
+void harvest_timing(icm_ctx* c) {
+    for (auto& p : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            c->phase_ms[p.first] += ms;
+            c->phase_n[p.first] += 1;
+        }
+    }
+    c->pending.clear();
+    c->ev_used = 0;
+}
+
+template <typename T>
+void enqueue_fft_solve(icm_ctx* c, const icm::GridDesc<T>& g, const T* in, T* out, bool accumulate,
+                       icm::SolveCoef sc, hipStream_t s) {
+    timed(c, ICM_PHASE_FFT_X_FWD, s, [&] { icm::launch_fft_x_forward(g, in, s); });
+    timed(c, ICM_PHASE_FFT_Y_FWD, s, [&] { icm::launch_fft_y(g, -1, s); });
+    timed(c, ICM_PHASE_FFT_Z_SOLVE, s, [&] { icm::launch_fft_z_solve(g, sc, true, s); });
+    timed(c, ICM_PHASE_FFT_Y_INV, s, [&] { icm::launch_fft_y(g, 1, s); });
+    timed(c, ICM_PHASE_FFT_X_INV, s, [&] { icm::launch_fft_x_inverse(g, out, accumulate, s); });
+}
+
+// One step of Sec. III.C for one replica, enqueued on stream s.
+template <typename T>
+void enqueue_step(icm_ctx* c, Replica& R, hipStream_t s) {
+    icm::GridDesc<T>& g = grid_of<T>(R);
+    icm::BlobBufs& b = R.bb;
+    const icm::BlobParams bp = blob_params(R);
+    const int P = R.p.kernel, nb = R.nb;
+    const double inv_n = 1.0 / (double)g.ncell;
+    // Step 1: midpoint predictor, forces, and J^{n+1/2} v^n for step 9.
+    timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather(g, g.v, P, nb, b.q, b.Jn, false, s); });
+    timed(c, ICM_PHASE_BLOB, s, [&] { icm::launch_predict(bp, b, s); });
+    timed(c, ICM_PHASE_FORCES, s, [&] { icm::launch_forces(bp, b, s); });
+    timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather(g, g.v, P, nb, b.qh, b.Jhvn, false, s); });
+    // Step 2: unperturbed fluid solve.
+    icm::RhsCoef rc;
+    rc.rho_dt = R.p.rho / R.p.dt;
+    rc.half_eta_h2 = 0.5 * R.p.eta / (R.p.h * R.p.h);
+    rc.noise = R.p.kT > 0 ? std::sqrt(R.p.kT * R.p.eta / (R.p.h * R.p.h * R.p.h * R.p.dt)) / R.p.h : 0.0;
+    for (int a = 0; a < 3; ++a) rc.body[a] = R.p.body_force[a];
+    rc.key = noise_key(R, R.step);
+    timed(c, ICM_PHASE_RHS, s, [&] { icm::launch_rhs(g, rc, s); });
+    timed(c, ICM_PHASE_SPREAD, s, [&] { icm::launch_spread(g, g.rhs, P, nb, b.qh, b.F, nullptr, false, s); });
+    if (R.p.kT > 0 && R.p.thermal_drift)
+        timed(c, ICM_PHASE_SPREAD, s, [&] { icm::launch_spread(g, g.rhs, P, nb, b.qh, nullptr, b.cdrift, true, s); });
+    enqueue_fft_solve(c, g, g.rhs, g.v, false, icm::SolveCoef{R.p.rho / R.p.dt, 0.5 * R.p.eta, inv_n}, s);
+    if (R.any_me) {
+        // Step 4: slip correction and excess-momentum change.
+        timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather(g, g.v, P, nb, b.qh, b.Jhvt, false, s); });
+        timed(c, ICM_PHASE_BLOB, s, [&] { icm::launch_inertial_dp(bp, b, s); });
+        // Step 5: dv~ = m~_f/(rho m~) P S dp.
+        timed(c, ICM_PHASE_FIELD_OPS, s, [&] { icm::launch_zero(g.rhs, 3 * g.ncell, s); });
+        timed(c, ICM_PHASE_SPREAD, s, [&] { icm::launch_spread(g, g.rhs, P, nb, b.qh, b.dp, b.c5, false, s); });
+        enqueue_fft_solve(c, g, g.rhs, g.aux, false, icm::SolveCoef{1.0, 0.0, inv_n}, s);
+        timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather(g, g.aux, P, nb, b.qh, b.g, false, s); });
+        // Step 6: (rho - dt/2 eta L) dv + dt G dpi = S (dp - m_e J dv~).
+        timed(c, ICM_PHASE_BLOB, s, [&] { icm::launch_inertial_dp2(bp, b, s); });
+        timed(c, ICM_PHASE_FIELD_OPS, s, [&] { icm::launch_zero(g.rhs, 3 * g.ncell, s); });
+        timed(c, ICM_PHASE_SPREAD, s, [&] { icm::launch_spread(g, g.rhs, P, nb, b.qh, b.dp2, nullptr, false, s); });
+        enqueue_fft_solve(c, g, g.rhs, g.aux, false, icm::SolveCoef{R.p.rho, 0.5 * R.p.dt * R.p.eta, inv_n}, s);
+        // Step 7, lagged J L dv, step 8.
+        timed(c, ICM_PHASE_FIELD_OPS, s, [&] { icm::launch_axpy(g.v, g.aux, 3 * g.ncell, s); });
+        timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather(g, g.aux, P, nb, b.qh, b.lag, true, s); });
+        timed(c, ICM_PHASE_BLOB, s, [&] { icm::launch_inertial_u(bp, b, s); });
+    }
+    // Step 9.
+    timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather(g, g.v, P, nb, b.qh, b.Jhvnew, false, s); });
+    timed(c, ICM_PHASE_BLOB, s, [&] { icm::launch_final(bp, b, R.p.h, s); });
+    R.step += 1;
+}
+
+template <typename T>
+void enqueue_project(Replica& R, const T* in, bool accumulate, hipStream_t s) {
+    icm::GridDesc<T>& g = grid_of<T>(R);
+    icm::launch_fft_forward_solve_inverse(g, in, g.v, accumulate, icm::SolveCoef{1.0, 0.0, 1.0 / (double)g.ncell},
+                                          true, s);
+}
+
+icm_status check_replica(icm_ctx* c, int32_t replica) {
+    if (!c) return fail(nullptr, ICM_E_INVALID, "NULL context");
+    if (replica < 0 || replica >= (int32_t)c->reps.size())
+        return fail(c, ICM_E_INVALID, "replica %d out of range [0, %d)", replica, (int)c->reps.size());
+    return ICM_OK;
+}
+
+size_t field_bytes(const icm_ctx* c, const Replica& R) {
+    const long long ncell = (long long)R.p.n[0] * R.p.n[1] * R.p.n[2];
+    return 3 * (size_t)ncell * (c->precision == ICM_FP64 ? sizeof(double) : sizeof(float));
+}
+
+void* field_ptr(icm_ctx* c, Replica& R) {
+    return c->precision == ICM_FP64 ? (void*)R.gd.v : (void*)R.gf.v;
+}
+void* rhs_ptr(icm_ctx* c, Replica& R) {
+    return c->precision == ICM_FP64 ? (void*)R.gd.rhs : (void*)R.gf.rhs;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+icm_status icm_workspace_bytes(int32_t n_rep, const icm_replica_params* p, const int32_t* max_blobs,
+                               int32_t precision, size_t* bytes) {
+    icm_status st = validate(n_rep, p, max_blobs, precision);
+    if (st != ICM_OK) return st;
+    if (!bytes) return fail(nullptr, ICM_E_INVALID, "bytes must not be NULL");
+    *bytes = layout(n_rep, p, max_blobs, precision, nullptr, nullptr);
+    return ICM_OK;
+}
+
+icm_status icm_create(int32_t n_rep, const icm_replica_params* p, const int32_t* max_blobs, int32_t precision,
+                      void* workspace, size_t bytes, void* stream, icm_ctx** out) {
+    if (!out) return fail(nullptr, ICM_E_INVALID, "out must not be NULL");
+    *out = nullptr;
+    icm_status st = validate(n_rep, p, max_blobs, precision);
+    if (st != ICM_OK) return st;
+    const size_t need = layout(n_rep, p, max_blobs, precision, nullptr, nullptr);
+    icm_ctx* c = new icm_ctx();
+    c->precision = precision;
+    c->stream = static_cast<hipStream_t>(stream);
+    if (workspace) {
+        if (bytes < need) {
+            delete c;
+            return fail(nullptr, ICM_E_NOMEM, "workspace of %zu bytes is smaller than the %zu required", bytes, need);
+        }
+        if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) {
+            delete c;
+            return fail(nullptr, ICM_E_INVALID, "workspace must be 256-byte aligned");
+        }
+        c->ws = workspace;
+        c->ws_bytes = bytes;
+    } else {
+        hipError_t e = hipMalloc(&c->ws, need);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(nullptr, ICM_E_NOMEM, "hipMalloc of %zu bytes failed: %s", need, hipGetErrorString(e));
+        }
+        c->owns_ws = true;
+        c->ws_bytes = need;
+    }
+    c->reps.resize(n_rep);
+    layout(n_rep, p, max_blobs, precision, c->ws, &c->reps);
+    for (int r = 0; r < n_rep; ++r) {
+        Replica& R = c->reps[r];
+        R.p = p[r];
+        R.max_nb = max_blobs[r];
+        R.nb = 0;
+        R.step = 0;
+        R.m_f = p[r].rho * std::pow(p[r].h, 3) / std::pow(sum_phi_sq(p[r].kernel), 3);
+        R.mt_f = 1.5 * R.m_f;
+        st = (precision == ICM_FP64) ? upload_tables(c, R.gd) : upload_tables(c, R.gf);
+        if (st != ICM_OK) {
+            g_last_error = c->err;
+            icm_destroy(c);
+            return st;
+        }
+        const size_t fb = field_bytes(c, R);
+        hipError_t e = hipMemsetAsync(field_ptr(c, R), 0, fb, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(R.bb.flag, 0, sizeof(unsigned int), c->stream);
+        if (e != hipSuccess) {
+            g_last_error = std::string("hipMemsetAsync failed: ") + hipGetErrorString(e);
+            icm_destroy(c);
+            return ICM_E_DEVICE;
+        }
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+        g_last_error = "stream synchronisation failed after create";
+        icm_destroy(c);
+        return ICM_E_DEVICE;
+    }
+    *out = c;
+    return ICM_OK;
+}
+
+icm_status icm_set_blobs(icm_ctx* c, int32_t replica, int32_t n_blobs, const double* q, const double* u,
+                         const double* m_e, const double* f_const, uint32_t flags) {
+    icm_status st = check_replica(c, replica);
+    if (st != ICM_OK) return st;
+    Replica& R = c->reps[replica];
+    if (n_blobs < 0 || n_blobs > R.max_nb)
+        return fail(c, ICM_E_INVALID, "n_blobs = %d outside [0, max_blobs = %d]", n_blobs, R.max_nb);
+    if (n_blobs > 0 && !q) return fail(c, ICM_E_INVALID, "q must not be NULL");
+    const bool dev = (flags & ICM_PTRS_DEVICE) != 0;
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const size_t n3 = 3 * (size_t)n_blobs;
+    hipStream_t s = c->stream;
+    // masses are needed on the host for validation and coefficients
+    std::vector<double> me(n_blobs, 0.0);
+    if (m_e && n_blobs) {
+        if (dev) {
+            HIP_TRY(c, hipMemcpyAsync(me.data(), m_e, n_blobs * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_TRY(c, hipStreamSynchronize(s));
+        } else {
+            std::memcpy(me.data(), m_e, n_blobs * sizeof(double));
+        }
+    }
+    for (int i = 0; i < n_blobs; ++i)
+        if (!(me[i] > -R.m_f) || !std::isfinite(me[i]))
+            return fail(c, ICM_E_INVALID, "blob %d: m_e = %g must exceed -m_f = %g", i, me[i], -R.m_f);
+    std::vector<double> c5(n_blobs), cd(n_blobs);
+    bool any = false;
+    for (int i = 0; i < n_blobs; ++i) {
+        c5[i] = R.mt_f / (R.p.rho * (me[i] + R.mt_f));
+        cd[i] = R.p.kT * R.mt_f / (me[i] + R.mt_f);
+        any = any || me[i] != 0.0;
+    }
+    if (n_blobs) {
+        HIP_TRY(c, hipMemcpyAsync(R.bb.q, q, n3 * sizeof(double), kind, s));
+        if (u)
+            HIP_TRY(c, hipMemcpyAsync(R.bb.u, u, n3 * sizeof(double), kind, s));
+        else
+            HIP_TRY(c, hipMemsetAsync(R.bb.u, 0, n3 * sizeof(double), s));
+        if (f_const)
+            HIP_TRY(c, hipMemcpyAsync(R.bb.fconst, f_const, n3 * sizeof(double), kind, s));
+        else
+            HIP_TRY(c, hipMemsetAsync(R.bb.fconst, 0, n3 * sizeof(double), s));
+        HIP_TRY(c, hipMemcpyAsync(R.bb.me, me.data(), n_blobs * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_TRY(c, hipMemcpyAsync(R.bb.c5, c5.data(), n_blobs * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_TRY(c, hipMemcpyAsync(R.bb.cdrift, cd.data(), n_blobs * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_TRY(c, hipMemsetAsync(R.bb.lag, 0, n3 * sizeof(double), s));
+    }
+    R.nb = n_blobs;
+    R.any_me = any;
+    if ((flags & ICM_BLOBS_KICK) && n_blobs) {
+        // v += P S (m~_f u0) / rho
+        std::vector<double> imp(n3, 0.0);
+        if (u) {
+            if (dev) {
+                HIP_TRY(c, hipMemcpyAsync(imp.data(), u, n3 * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIP_TRY(c, hipStreamSynchronize(s));
+            } else {
+                std::memcpy(imp.data(), u, n3 * sizeof(double));
+            }
+        }
+        for (auto& x : imp) x *= R.mt_f / R.p.rho;
+        HIP_TRY(c, hipMemcpyAsync(R.bb.dp, imp.data(), n3 * sizeof(double), hipMemcpyHostToDevice, s));
+        if (c->precision == ICM_FP64) {
+            icm::launch_zero(R.gd.rhs, 3 * R.gd.ncell, s);
+            icm::launch_spread(R.gd, R.gd.rhs, R.p.kernel, n_blobs, R.bb.q, R.bb.dp, nullptr, false, s);
+            enqueue_project<double>(R, R.gd.rhs, true, s);
+        } else {
+            icm::launch_zero(R.gf.rhs, 3 * R.gf.ncell, s);
+            icm::launch_spread(R.gf, R.gf.rhs, R.p.kernel, n_blobs, R.bb.q, R.bb.dp, nullptr, false, s);
+            enqueue_project<float>(R, R.gf.rhs, true, s);
+        }
+        HIP_TRY(c, hipGetLastError());
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return ICM_OK;
+}
+
+icm_status icm_set_state(icm_ctx* c, int32_t replica, const void* v, const double* q, const double* u,
+                         const double* lag_c, int64_t step, uint32_t flags) {
+    icm_status st = check_replica(c, replica);
+    if (st != ICM_OK) return st;
+    Replica& R = c->reps[replica];
+    const bool dev = (flags & ICM_PTRS_DEVICE) != 0;
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const size_t n3 = 3 * (size_t)R.nb;
+    hipStream_t s = c->stream;
+    const size_t fb = field_bytes(c, R);
+    if (flags & ICM_STATE_EQUILIBRIUM) {
+        const double sd = std::sqrt(R.p.kT / (R.p.rho * R.p.h * R.p.h * R.p.h));
+        const icm::NoiseKey nk = noise_key(R, 0);
+        if (c->precision == ICM_FP64) {
+            icm::launch_equilibrium_noise(R.gd, sd, nk, s);
+            enqueue_project<double>(R, R.gd.rhs, false, s);
+        } else {
+            icm::launch_equilibrium_noise(R.gf, sd, nk, s);
+            enqueue_project<float>(R, R.gf.rhs, false, s);
+        }
+        HIP_TRY(c, hipGetLastError());
+    } else if (v) {
+        if (flags & ICM_STATE_PROJECT) {
+            HIP_TRY(c, hipMemcpyAsync(rhs_ptr(c, R), v, fb, kind, s));
+            if (c->precision == ICM_FP64)
+                enqueue_project<double>(R, R.gd.rhs, false, s);
+            else
+                enqueue_project<float>(R, R.gf.rhs, false, s);
+            HIP_TRY(c, hipGetLastError());
+        } else {
+            HIP_TRY(c, hipMemcpyAsync(field_ptr(c, R), v, fb, kind, s));
+        }
+    }
+    if (q && n3) HIP_TRY(c, hipMemcpyAsync(R.bb.q, q, n3 * sizeof(double), kind, s));
+    if (u && n3) HIP_TRY(c, hipMemcpyAsync(R.bb.u, u, n3 * sizeof(double), kind, s));
+    if (lag_c && n3) {
+        if (R.any_me)
+            HIP_TRY(c, hipMemcpyAsync(R.bb.lag, lag_c, n3 * sizeof(double), kind, s));
+        else
+            HIP_TRY(c, hipMemsetAsync(R.bb.lag, 0, n3 * sizeof(double), s));
+    }
+    if (step >= 0) R.step = step;
+    HIP_TRY(c, hipMemsetAsync(R.bb.flag, 0, sizeof(unsigned int), s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->error_state = false;
+    return ICM_OK;
+}
+
+icm_status icm_step(icm_ctx* c, int64_t n_steps, uint32_t flags) {
+    (void)flags;
+    if (!c) return fail(nullptr, ICM_E_INVALID, "NULL context");
+    if (c->error_state) return fail(c, ICM_E_STATE, "context is in an error state; call icm_set_state first");
+    if (n_steps < 0) return fail(c, ICM_E_INVALID, "n_steps must be >= 0");
+    hipStream_t s = c->stream;
+    for (int64_t n = 0; n < n_steps; ++n) {
+        for (Replica& R : c->reps) {
+            if (c->precision == ICM_FP64)
+                enqueue_step<double>(c, R, s);
+            else
+                enqueue_step<float>(c, R, s);
+        }
+    }
+    HIP_TRY(c, hipGetLastError());
+    unsigned int flag = 0;
+    for (Replica& R : c->reps) {
+        unsigned int f = 0;
+        HIP_TRY(c, hipMemcpyAsync(&f, R.bb.flag, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        flag |= f;
+    }
+    if (c->timing) harvest_timing(c);
+    if (flag) {
+        c->error_state = true;
+        return fail(c, ICM_E_NUMERIC, "numeric failure flag 0x%x (1: non-finite blob state, 2: blob moved > h)",
+                    flag);
+    }
+    return ICM_OK;
+}
+
+icm_status icm_get_state(icm_ctx* c, int32_t replica, void* v, double* q, double* u, double* lag_c, icm_diag* d,
+                         uint32_t flags) {
+    icm_status st = check_replica(c, replica);
+    if (st != ICM_OK) return st;
+    Replica& R = c->reps[replica];
+    const bool dev = (flags & ICM_PTRS_DEVICE) != 0;
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const size_t n3 = 3 * (size_t)R.nb;
+    hipStream_t s = c->stream;
+    if (v) HIP_TRY(c, hipMemcpyAsync(v, field_ptr(c, R), field_bytes(c, R), kind, s));
+    if (q && n3) HIP_TRY(c, hipMemcpyAsync(q, R.bb.q, n3 * sizeof(double), kind, s));
+    if (u && n3) HIP_TRY(c, hipMemcpyAsync(u, R.bb.u, n3 * sizeof(double), kind, s));
+    if (lag_c && n3) HIP_TRY(c, hipMemcpyAsync(lag_c, R.bb.lag, n3 * sizeof(double), kind, s));
+    if (d) {
+        double acc[16];
+        HIP_TRY(c, hipMemsetAsync(R.diag, 0, 16 * sizeof(double), s));
+        if (c->precision == ICM_FP64)
+            icm::launch_field_diag(R.gd, R.p.rho, R.diag, s);
+        else
+            icm::launch_field_diag(R.gf, R.p.rho, R.diag, s);
+        icm::launch_blob_diag(R.nb, R.bb.me, R.bb.u, R.diag + 8, s);
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipMemcpyAsync(acc, R.diag, sizeof(acc), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        for (int a = 0; a < 3; ++a) d->momentum[a] = acc[a] + acc[8 + a];
+        d->ke_fluid = acc[3];
+        d->ke_blob = acc[11];
+        d->max_div = acc[4] > 0 ? acc[5] / acc[4] : 0.0;
+        d->step = R.step;
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return ICM_OK;
+}
+
+icm_status icm_set_timing(icm_ctx* c, int32_t enable) {
+    if (!c) return fail(nullptr, ICM_E_INVALID, "NULL context");
+    c->timing = enable != 0;
+    return ICM_OK;
+}
+
+icm_status icm_get_timing(icm_ctx* c, icm_timing* out, int32_t reset) {
+    if (!c || !out) return fail(c, ICM_E_INVALID, "NULL argument");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    harvest_timing(c);
+    for (int i = 0; i < 16; ++i) {
+        out->ms[i] = c->phase_ms[i];
+        out->launches[i] = c->phase_n[i];
+    }
+    if (reset)
+        for (int i = 0; i < 16; ++i) {
+            c->phase_ms[i] = 0;
+            c->phase_n[i] = 0;
+        }
+    return ICM_OK;
+}
+
+int32_t icm_num_blobs(const icm_ctx* c, int32_t replica) {
+    if (!c || replica < 0 || replica >= (int32_t)c->reps.size()) return -1;
+    return c->reps[replica].nb;
+}
+
+void icm_destroy(icm_ctx* c) {
+    if (!c) return;
+    if (c->stream || c->owns_ws) (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->owns_ws && c->ws) (void)hipFree(c->ws);
+    delete c;
+}
+
+const char* icm_last_error(const icm_ctx* c) { return c ? c->err.c_str() : g_last_error.c_str(); }
+
+}  // extern "C"

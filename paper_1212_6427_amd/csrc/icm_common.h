@@ -1,0 +1,161 @@
+// Shared device helpers of the gfx950 ICM library: complex type, Philox
+// counter-based generator, Box-Muller normals and the Peskin kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace icm {
+
+template <typename T>
+struct cplx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.x, -a.y}; }
+// multiply by i (s = +1) or -i (s = -1)
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul_i(cplx<T> a, int s) {
+    return s > 0 ? cplx<T>{-a.y, a.x} : cplx<T>{a.y, -a.x};
+}
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11): each round
+// multiplies counter words 0 and 2 by fixed odd constants, and mixes the
+// high/low halves of the products with words 1 and 3 and the round key; the
+// key advances by the Weyl constants between rounds.
+struct u32x4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = u32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Counter layout: (cell, step mod 2^32, (replica << 4) | block, step >> 32),
+// key (seed mod 2^32, seed >> 32).
+struct NoiseKey {
+    uint32_t k0, k1;      // seed words
+    uint32_t step_lo, step_hi;
+    uint32_t rep_tag;     // replica << 4
+};
+
+__device__ __forceinline__ u32x4 noise_words(const NoiseKey& nk, uint32_t cell, uint32_t block) {
+    return philox4x32_10(u32x4{cell, nk.step_lo, nk.rep_tag | block, nk.step_hi}, nk.k0, nk.k1);
+}
+
+// Box-Muller: first word -> radius via u1 = (w+1) 2^-32 in (0,1], second word
+// -> angle 2 pi u2 with u2 = w 2^-32 in [0,1).
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& z0, double& z1) {
+    const double u1 = ((double)wa + 1.0) * 2.3283064365386963e-10;
+    const double u2 = (double)wb * 2.3283064365386963e-10;
+    const double r = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z0, float& z1) {
+    const float u1 = fmaf((float)wa, 2.3283064365386963e-10f, 2.3283064365386963e-10f);
+    const float u2 = (float)wb * 2.3283064365386963e-10f;
+    const float r = sqrtf(-2.0f * logf(u1));
+    float s, c;
+    sincospif(2.0f * u2, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+// ---------------------------------------------------------- Peskin kernels
+// Three-point kernel: minimal support with sum phi = 1, zero first moment and
+// sum phi^2 = 1/2 (Sec. III.A.1); four-point kernel of Peskin (2002): support 4
+// with the even/odd sums 1/2, zero first moment and sum phi^2 = 3/8.
+__device__ __forceinline__ double phi3(double r) {
+    const double s = fabs(r);
+    if (s <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * s * s)) / 3.0;
+    if (s <= 1.5) {
+        const double t = 1.0 - s;
+        return (5.0 - 3.0 * s - sqrt(fmax(1.0 - 3.0 * t * t, 0.0))) / 6.0;
+    }
+    return 0.0;
+}
+__device__ __forceinline__ double dphi3(double r) {
+    const double s = fabs(r);
+    if (s <= 0.5) return -r / sqrt(1.0 - 3.0 * r * r);
+    if (s <= 1.5) {
+        const double t = 1.0 - s;
+        const double v = -0.5 - t / (2.0 * sqrt(fmax(1.0 - 3.0 * t * t, 1e-300)));
+        return r >= 0.0 ? v : -v;
+    }
+    return 0.0;
+}
+__device__ __forceinline__ double phi4(double r) {
+    const double s = fabs(r);
+    if (s <= 1.0) return (3.0 - 2.0 * s + sqrt(1.0 + 4.0 * s - 4.0 * s * s)) * 0.125;
+    if (s <= 2.0) return (5.0 - 2.0 * s - sqrt(fmax(-7.0 + 12.0 * s - 4.0 * s * s, 0.0))) * 0.125;
+    return 0.0;
+}
+__device__ __forceinline__ double dphi4(double r) {
+    const double s = fabs(r);
+    double v;
+    if (s <= 1.0)
+        v = (-2.0 + (4.0 - 8.0 * s) / (2.0 * sqrt(1.0 + 4.0 * s - 4.0 * s * s))) * 0.125;
+    else if (s <= 2.0)
+        v = (-2.0 - (12.0 - 8.0 * s) / (2.0 * sqrt(fmax(-7.0 + 12.0 * s - 4.0 * s * s, 1e-300)))) * 0.125;
+    else
+        return 0.0;
+    return r >= 0.0 ? v : -v;
+}
+
+// Nodes and weights of one axis. x: blob coordinate in grid units measured
+// from node 0 of the component grid. 3-point: nodes round(x) + {-1,0,1};
+// 4-point: floor(x) + {-1,0,1,2}. Node indices are wrapped into [0, n).
+template <int P>
+struct AxisStencil {
+    int node[P];
+    double w[P];
+};
+
+template <int P>
+__device__ __forceinline__ void axis_stencil(double x, int n, bool deriv, double inv_h, AxisStencil<P>& st) {
+    const double m0 = (P == 3) ? floor(x + 0.5) : floor(x);
+    const long long mi = (long long)m0;
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+        const long long node = mi - 1 + a;
+        const double d = x - (double)node;
+        long long wn = node % n;
+        if (wn < 0) wn += n;
+        st.node[a] = (int)wn;
+        if (P == 3)
+            st.w[a] = deriv ? dphi3(d) * inv_h : phi3(d);
+        else
+            st.w[a] = deriv ? dphi4(d) * inv_h : phi4(d);
+    }
+}
+
+__host__ __device__ __forceinline__ int wrap(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+}  // namespace icm

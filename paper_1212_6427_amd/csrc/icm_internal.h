@@ -1,0 +1,128 @@
+// Internal interfaces between the ICM context (api.hip) and the kernel
+// launchers (fft.hip, grid.hip, blobs.hip). Everything here works on raw
+// device pointers and one HIP stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "icm_common.h"
+
+namespace icm {
+
+constexpr int kMaxStages = 16;
+
+// Mixed-radix (2, 3, 4, 8) Stockham plan of one FFT length.
+struct FFTPlan {
+    int n;
+    int nst;
+    int radix[kMaxStages];
+};
+
+// Field buffers of one replica. Real face fields hold 3 components of
+// ncell values (x fastest); the spectrum holds 3 components of
+// nz * ny * W complex values with W = nx/2 + 1 (kx fastest).
+template <typename T>
+struct GridDesc {
+    int nx, ny, nz, W;
+    long long ncell;   // nx * ny * nz
+    long long nspec;   // nz * ny * W
+    double h;
+    T* v;              // fluid velocity v^n / v^{n+1}
+    T* rhs;            // right-hand side / spread scratch field
+    T* aux;            // inertial-correction field (dv~, dv)
+    cplx<T>* spec;     // spectral work buffer
+    // FFT plans and twiddles exp(-2 pi i m / N), m < N, per axis
+    FFTPlan px, py, pz;
+    const cplx<T>* twx;
+    const cplx<T>* twy;
+    const cplx<T>* twz;
+    // difference symbols: Dhat_a = (e^{i theta} - 1)/h, lam_a = |Dhat_a|^2
+    const cplx<T>* dx_hat;  // W entries
+    const cplx<T>* dy_hat;  // ny entries
+    const cplx<T>* dz_hat;  // nz entries
+    const T* lx;
+    const T* ly;
+    const T* lz;
+};
+
+// Spectral multiplier applied between the forward and inverse transforms:
+// w = P-hat( R-hat * scale / (a + b lambda) ), lambda = -L-hat >= 0.
+struct SolveCoef {
+    double a, b, scale;
+};
+
+// Physical constants of the right-hand side of step 2 (Sec. III.C).
+struct RhsCoef {
+    double rho_dt;      // rho / dt
+    double half_eta_h2; // (eta / 2) / h^2
+    double noise;       // (kT eta / (h^3 dt))^(1/2) / h, 0 = deterministic
+    double body[3];
+    NoiseKey key;
+};
+
+// ------------------------------------------------------------------- FFT
+template <typename T>
+void launch_fft_x_forward(const GridDesc<T>& g, const T* in, hipStream_t s);
+template <typename T>
+void launch_fft_y(const GridDesc<T>& g, int dir, hipStream_t s);
+template <typename T>
+void launch_fft_z_solve(const GridDesc<T>& g, SolveCoef sc, bool project, hipStream_t s);
+template <typename T>
+void launch_fft_x_inverse(const GridDesc<T>& g, T* out, bool accumulate, hipStream_t s);
+template <typename T>
+void launch_fft_forward_solve_inverse(const GridDesc<T>& g, const T* in, T* out, bool accumulate,
+                                      SolveCoef sc, bool project, hipStream_t s);
+
+// ------------------------------------------------------------ grid kernels
+template <typename T>
+void launch_rhs(const GridDesc<T>& g, const RhsCoef& c, hipStream_t s);
+template <typename T>
+void launch_equilibrium_noise(const GridDesc<T>& g, double sd, NoiseKey key, hipStream_t s);
+template <typename T>
+void launch_zero(T* p, long long n, hipStream_t s);
+template <typename T>
+void launch_axpy(T* y, const T* x, long long n, hipStream_t s);
+
+// spread: field += h^-3 * prod(phi) * val, val_a = (F ? F[b][a] : 1) * (coef ? coef[b] : 1);
+// deriv: the a-axis weight of component a is phi'(d)/h (thermal drift).
+template <typename T>
+void launch_spread(const GridDesc<T>& g, T* field, int kernel, int nb, const double* q,
+                   const double* F, const double* coef, bool deriv, hipStream_t s);
+// gather: out[b][a] = sum prod(phi) f_a (or of (L f)_a with laplacian = true)
+template <typename T>
+void launch_gather(const GridDesc<T>& g, const T* field, int kernel, int nb, const double* q,
+                   double* out, bool laplacian, hipStream_t s);
+
+// ------------------------------------------------------------ reductions
+// acc[0..2] += rho h^3 sum v; acc[3] += rho h^3 sum v^2 / 2;
+// acc[4] = max |v| (as bits), acc[5] = max |Dv| (as bits)
+template <typename T>
+void launch_field_diag(const GridDesc<T>& g, double rho, double* acc, hipStream_t s);
+
+// ----------------------------------------------------------- blob kernels
+struct BlobParams {
+    int nb;
+    double dt, rho, eta, kT;
+    double box[3];
+    double wca_eps, wca_sigma;
+    double spring_k, spring_c[3];
+    int slip;
+};
+
+struct BlobBufs {
+    double *q, *u, *me, *fconst, *lag;     // state
+    double *qh, *F, *Jn, *Jhvn, *Jhvt, *du, *dp, *dp2, *g, *Jhvnew;  // per step
+    double *c5, *cdrift;                   // per-blob coefficients
+    unsigned int* flag;                    // numeric error flag
+};
+
+void launch_predict(const BlobParams& bp, const BlobBufs& b, hipStream_t s);
+void launch_forces(const BlobParams& bp, const BlobBufs& b, hipStream_t s);
+void launch_inertial_dp(const BlobParams& bp, const BlobBufs& b, hipStream_t s);
+void launch_inertial_dp2(const BlobParams& bp, const BlobBufs& b, hipStream_t s);
+void launch_inertial_u(const BlobParams& bp, const BlobBufs& b, hipStream_t s);
+void launch_final(const BlobParams& bp, const BlobBufs& b, double h, hipStream_t s);
+void launch_blob_diag(int nb, const double* me, const double* u, double* acc, hipStream_t s);
+
+}  // namespace icm

@@ -1,0 +1,276 @@
+"""Thin ctypes binding of the gfx950 ICM library (include/icm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of libicm.so. Importing this module fails loudly if the library has not been
+built (python -m paper_1212_6427_amd.build); there is no fallback.
+
+Host arrays are numpy arrays; device arrays may be passed as torch tensors
+together with PTRS_DEVICE. PyTorch is used only for device memory (the
+optional workspace) and streams.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libicm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libicm.so is not built; run `python -m paper_1212_6427_amd.build` "
+                      "(the ICM step has no non-HIP implementation)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# status codes and flags (mirrors include/icm.h)
+OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_STATE, E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32_GRID = 0, 1
+SLIP_NONE, SLIP_VISCOUS, SLIP_FULL = 0, 1, 2
+PTRS_DEVICE, BLOBS_KICK, STATE_PROJECT, STATE_EQUILIBRIUM = 1, 2, 4, 8
+
+_STATUS_NAMES = {OK: "ICM_OK", E_INVALID: "ICM_E_INVALID", E_UNSUPPORTED: "ICM_E_UNSUPPORTED",
+                 E_NOMEM: "ICM_E_NOMEM", E_DEVICE: "ICM_E_DEVICE", E_STATE: "ICM_E_STATE",
+                 E_NUMERIC: "ICM_E_NUMERIC"}
+
+
+class icm_replica_params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32 * 3),
+        ("kernel", ctypes.c_int32),
+        ("h", ctypes.c_double),
+        ("rho", ctypes.c_double),
+        ("eta", ctypes.c_double),
+        ("kT", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("slip", ctypes.c_int32),
+        ("thermal_drift", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("replica_id", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("body_force", ctypes.c_double * 3),
+        ("wca_eps", ctypes.c_double),
+        ("wca_sigma", ctypes.c_double),
+        ("spring_k", ctypes.c_double),
+        ("spring_center", ctypes.c_double * 3),
+    ]
+
+
+class icm_diag(ctypes.Structure):
+    _fields_ = [
+        ("momentum", ctypes.c_double * 3),
+        ("ke_fluid", ctypes.c_double),
+        ("ke_blob", ctypes.c_double),
+        ("max_div", ctypes.c_double),
+        ("step", ctypes.c_int64),
+    ]
+
+
+class icm_timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 16), ("launches", ctypes.c_int64 * 16)]
+
+
+PHASES = ["gather", "blob", "forces", "rhs", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_solve", "fft_y_inv",
+          "fft_x_inv", "field_ops"]
+
+_p = ctypes.c_void_p
+_lib.icm_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(icm_replica_params),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_size_t)]
+_lib.icm_workspace_bytes.restype = ctypes.c_int
+_lib.icm_create.argtypes = [ctypes.c_int32, ctypes.POINTER(icm_replica_params), ctypes.POINTER(ctypes.c_int32),
+                            ctypes.c_int32, _p, ctypes.c_size_t, _p, ctypes.POINTER(_p)]
+_lib.icm_create.restype = ctypes.c_int
+_lib.icm_set_blobs.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _p, _p, _p, ctypes.c_uint32]
+_lib.icm_set_blobs.restype = ctypes.c_int
+_lib.icm_set_state.argtypes = [_p, ctypes.c_int32, _p, _p, _p, _p, ctypes.c_int64, ctypes.c_uint32]
+_lib.icm_set_state.restype = ctypes.c_int
+_lib.icm_step.argtypes = [_p, ctypes.c_int64, ctypes.c_uint32]
+_lib.icm_step.restype = ctypes.c_int
+_lib.icm_get_state.argtypes = [_p, ctypes.c_int32, _p, _p, _p, _p, ctypes.POINTER(icm_diag), ctypes.c_uint32]
+_lib.icm_get_state.restype = ctypes.c_int
+_lib.icm_num_blobs.argtypes = [_p, ctypes.c_int32]
+_lib.icm_num_blobs.restype = ctypes.c_int32
+_lib.icm_set_timing.argtypes = [_p, ctypes.c_int32]
+_lib.icm_set_timing.restype = ctypes.c_int
+_lib.icm_get_timing.argtypes = [_p, ctypes.POINTER(icm_timing), ctypes.c_int32]
+_lib.icm_get_timing.restype = ctypes.c_int
+_lib.icm_destroy.argtypes = [_p]
+_lib.icm_destroy.restype = None
+_lib.icm_last_error.argtypes = [_p]
+_lib.icm_last_error.restype = ctypes.c_char_p
+
+
+class ICMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def _check(status, ctx=None):
+    if status != OK:
+        raise ICMError(status, _lib.icm_last_error(ctx).decode())
+
+
+def make_params(n, h=1.0, rho=1.0, eta=1.0, kT=0.0, dt=0.1, kernel=3, slip=SLIP_VISCOUS, thermal_drift=True,
+                seed=0, replica_id=0, body_force=(0.0, 0.0, 0.0), wca_eps=0.0, wca_sigma=0.0, spring_k=0.0,
+                spring_center=(0.0, 0.0, 0.0)):
+    p = icm_replica_params()
+    p.n[:] = [int(x) for x in n]
+    p.kernel = int(kernel)
+    p.h, p.rho, p.eta, p.kT, p.dt = float(h), float(rho), float(eta), float(kT), float(dt)
+    p.slip = int(slip)
+    p.thermal_drift = 1 if thermal_drift else 0
+    p.seed = int(seed)
+    p.replica_id = int(replica_id)
+    p.reserved = 0
+    p.body_force[:] = [float(x) for x in body_force]
+    p.wca_eps, p.wca_sigma = float(wca_eps), float(wca_sigma)
+    p.spring_k = float(spring_k)
+    p.spring_center[:] = [float(x) for x in spring_center]
+    return p
+
+
+def _params_array(params):
+    arr = (icm_replica_params * len(params))()
+    for i, p in enumerate(params):
+        arr[i] = p
+    return arr
+
+
+def _ptr(x, dtype):
+    """ctypes pointer of a host array (made contiguous with the right dtype)
+    or of a device tensor; returns (pointer, keepalive)."""
+    if x is None:
+        return None, None
+    if hasattr(x, "data_ptr"):          # torch tensor (device or host)
+        return ctypes.c_void_p(x.data_ptr()), x
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return a.ctypes.data_as(ctypes.c_void_p), a
+
+
+def icm_workspace_bytes(params, max_blobs, precision):
+    arr = _params_array(params)
+    mb = (ctypes.c_int32 * len(params))(*[int(m) for m in max_blobs])
+    out = ctypes.c_size_t(0)
+    _check(_lib.icm_workspace_bytes(len(params), arr, mb, int(precision), ctypes.byref(out)))
+    return out.value
+
+
+def icm_create(params, max_blobs, precision, workspace=None, workspace_bytes=0, stream=None):
+    """Returns an opaque context handle (ctypes.c_void_p)."""
+    arr = _params_array(params)
+    mb = (ctypes.c_int32 * len(params))(*[int(m) for m in max_blobs])
+    ctx = ctypes.c_void_p()
+    ws = ctypes.c_void_p(workspace) if workspace else None
+    st = ctypes.c_void_p(stream) if stream else None
+    _check(_lib.icm_create(len(params), arr, mb, int(precision), ws, int(workspace_bytes), st, ctypes.byref(ctx)))
+    return ctx
+
+
+def icm_set_blobs(ctx, replica, q, u=None, m_e=None, f_const=None, flags=0):
+    n = int(q.shape[0]) if q is not None else 0
+    pq, kq = _ptr(q, np.float64)
+    pu, ku = _ptr(u, np.float64)
+    pm, km = _ptr(m_e, np.float64)
+    pf, kf = _ptr(f_const, np.float64)
+    _check(_lib.icm_set_blobs(ctx, int(replica), n, pq, pu, pm, pf, int(flags)), ctx)
+
+
+def icm_set_state(ctx, replica, v=None, q=None, u=None, lag_c=None, step=-1, flags=0, field_dtype=np.float64):
+    pv, kv = _ptr(v, field_dtype)
+    pq, kq = _ptr(q, np.float64)
+    pu, ku = _ptr(u, np.float64)
+    pl, kl = _ptr(lag_c, np.float64)
+    _check(_lib.icm_set_state(ctx, int(replica), pv, pq, pu, pl, int(step), int(flags)), ctx)
+
+
+def icm_step(ctx, n_steps, flags=0):
+    _check(_lib.icm_step(ctx, int(n_steps), int(flags)), ctx)
+
+
+def icm_num_blobs(ctx, replica):
+    return int(_lib.icm_num_blobs(ctx, int(replica)))
+
+
+def icm_get_state(ctx, replica, n, field_dtype=np.float64, want_v=True, want_diag=True):
+    """Returns dict(v, q, u, lag_c, diag) of host numpy arrays."""
+    nx, ny, nz = n
+    nb = icm_num_blobs(ctx, replica)
+    v = np.empty((3, nz, ny, nx), dtype=field_dtype) if want_v else None
+    q = np.empty((nb, 3))
+    u = np.empty((nb, 3))
+    lag = np.empty((nb, 3))
+    d = icm_diag()
+    _check(_lib.icm_get_state(ctx, int(replica),
+                              v.ctypes.data_as(ctypes.c_void_p) if v is not None else None,
+                              q.ctypes.data_as(ctypes.c_void_p), u.ctypes.data_as(ctypes.c_void_p),
+                              lag.ctypes.data_as(ctypes.c_void_p),
+                              ctypes.byref(d) if want_diag else None, 0), ctx)
+    diag = None
+    if want_diag:
+        diag = dict(momentum=np.array(d.momentum[:]), ke_fluid=d.ke_fluid, ke_blob=d.ke_blob,
+                    max_div=d.max_div, step=d.step)
+    return dict(v=v, q=q, u=u, lag_c=lag, diag=diag)
+
+
+def icm_set_timing(ctx, enable):
+    _check(_lib.icm_set_timing(ctx, 1 if enable else 0), ctx)
+
+
+def icm_get_timing(ctx, reset=False):
+    """Returns {phase: (total_ms, launches)}."""
+    t = icm_timing()
+    _check(_lib.icm_get_timing(ctx, ctypes.byref(t), 1 if reset else 0), ctx)
+    return {name: (t.ms[i], int(t.launches[i])) for i, name in enumerate(PHASES)}
+
+
+def icm_destroy(ctx):
+    if ctx:
+        _lib.icm_destroy(ctx)
+
+
+def icm_last_error(ctx=None):
+    return _lib.icm_last_error(ctx).decode()
+
+
+class Sim:
+    """Convenience owner of one context (several replicas allowed)."""
+
+    def __init__(self, params, max_blobs, precision=FP64, stream=None, workspace=None):
+        self.params = list(params)
+        self.precision = precision
+        self.dtype = np.float64 if precision == FP64 else np.float32
+        self._ws = workspace
+        ws_ptr, ws_bytes = (None, 0)
+        if workspace is not None:
+            ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+        self.ctx = icm_create(self.params, max_blobs, precision, ws_ptr, ws_bytes, stream)
+
+    def set_blobs(self, replica, q, u=None, m_e=None, f_const=None, flags=0):
+        icm_set_blobs(self.ctx, replica, q, u, m_e, f_const, flags)
+
+    def set_state(self, replica, v=None, q=None, u=None, lag_c=None, step=-1, flags=0):
+        icm_set_state(self.ctx, replica, v, q, u, lag_c, step, flags, self.dtype)
+
+    def step(self, n=1, flags=0):
+        icm_step(self.ctx, n, flags)
+
+    def get_state(self, replica=0, want_v=True, want_diag=True):
+        return icm_get_state(self.ctx, replica, tuple(self.params[replica].n), self.dtype, want_v, want_diag)
+
+    def set_timing(self, enable):
+        icm_set_timing(self.ctx, enable)
+
+    def timing(self, reset=False):
+        return icm_get_timing(self.ctx, reset)
+
+    def close(self):
+        icm_destroy(self.ctx)
+        self.ctx = None
+
+    def __del__(self):
+        try:
+            if self.ctx:
+                self.close()
+        except Exception:
+            pass

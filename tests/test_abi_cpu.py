@@ -1,0 +1,73 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/icm.h declares, and validates parameters."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1212_6427_amd.icm as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "icm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(icm_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert "icm_step" in names and "icm_create" in names
+    lib = ctypes.CDLL(I.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_sizes_match_header_layout():
+    assert ctypes.sizeof(I.icm_replica_params) == 152
+    assert ctypes.sizeof(I.icm_diag) == 56
+
+
+@pytest.mark.parametrize("n,ok", [((32, 32, 32), True), ((48, 36, 24), True), ((6, 12, 18), True),
+                                  ((512, 4, 4), True), ((33, 32, 32), False), ((2, 32, 32), False),
+                                  ((1024, 4, 4), False), ((20, 32, 32), False), ((14, 32, 32), False)])
+def test_grid_size_validation(n, ok):
+    p = I.make_params(n)
+    if ok:
+        assert I.icm_workspace_bytes([p], [3], I.FP64) > 0
+    else:
+        with pytest.raises(I.ICMError) as e:
+            I.icm_workspace_bytes([p], [3], I.FP64)
+        assert e.value.status == I.E_INVALID
+
+
+@pytest.mark.parametrize("field,val", [("kernel", 5), ("h", 0.0), ("rho", -1.0), ("dt", 0.0), ("kT", -1.0),
+                                       ("slip", 3), ("thermal_drift", 2), ("reserved", 1)])
+def test_parameter_validation(field, val):
+    p = I.make_params((16, 16, 16))
+    setattr(p, field, val)
+    with pytest.raises(I.ICMError) as e:
+        I.icm_workspace_bytes([p], [1], I.FP64)
+    assert e.value.status == I.E_INVALID
+
+
+def test_wca_cutoff_must_fit_half_box():
+    p = I.make_params((8, 8, 8), wca_eps=1e-2, wca_sigma=4.0)
+    with pytest.raises(I.ICMError):
+        I.icm_workspace_bytes([p], [2], I.FP64)
+
+
+def test_workspace_scales_with_precision_and_replicas():
+    p = I.make_params((64, 64, 64))
+    b64 = I.icm_workspace_bytes([p], [10], I.FP64)
+    b32 = I.icm_workspace_bytes([p], [10], I.FP32_GRID)
+    assert 0.45 * b64 < b32 < 0.55 * b64
+    q = I.make_params((32, 32, 32))
+    both = I.icm_workspace_bytes([p, q], [10, 1], I.FP32_GRID)
+    assert both > b32
+    with pytest.raises(I.ICMError):
+        I.icm_workspace_bytes([p], [-1], I.FP64)
+    with pytest.raises(I.ICMError):
+        I.icm_workspace_bytes([p], [1], 7)
