@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -148,8 +149,17 @@ void carve_grid(Carver& cv, const icm_replica_params& p, icm::GridDesc<T>& g) {
     g.ny = p.n[1];
     g.nz = p.n[2];
     g.W = g.nx / 2 + 1;
+    g.fast = icm::fast_fft_available<T>(g.nx, g.ny, g.nz) ? 1 : 0;
+    // kx columns per block of the fast y / z passes: 128 bytes of complex
+    // values by default; ICM_FFT_BY / ICM_FFT_BZ override them for tuning.
+    g.By = 128 / (int)sizeof(cplx<T>);
+    g.Bz = 128 / (int)sizeof(cplx<T>);
+    if (const char* e = std::getenv("ICM_FFT_BY")) g.By = std::max(1, std::min(64, std::atoi(e)));
+    if (const char* e = std::getenv("ICM_FFT_BZ")) g.Bz = std::max(1, std::min(64, std::atoi(e)));
     g.ncell = (long long)g.nx * g.ny * g.nz;
-    g.nspec = (long long)g.nz * g.ny * g.W;
+    const int align = 128 / (int)sizeof(cplx<T>);
+    g.Wp = (g.W + align - 1) / align * align;
+    g.nspec = (long long)g.nz * g.ny * g.Wp;
     g.h = p.h;
     g.v = cv.take<T>(3 * g.ncell);
     g.rhs = cv.take<T>(3 * g.ncell);
@@ -176,6 +186,7 @@ void carve_blobs(Carver& cv, int max_nb, icm::BlobBufs& b, double*& diag) {
     b.fconst = cv.take<double>(n3);
     b.lag = cv.take<double>(n3);
     b.qh = cv.take<double>(n3);
+    b.qw = cv.take<double>(n3);
     b.F = cv.take<double>(n3);
     b.Jn = cv.take<double>(n3);
     b.Jhvn = cv.take<double>(n3);
@@ -326,6 +337,7 @@ void harvest_timing(icm_ctx* c) {
     c->ev_used = 0;
 }
 
+// Forward transform, spectral solve, inverse transform.
 template <typename T>
 void enqueue_fft_solve(icm_ctx* c, const icm::GridDesc<T>& g, const T* in, T* out, bool accumulate,
                        icm::SolveCoef sc, hipStream_t s) {

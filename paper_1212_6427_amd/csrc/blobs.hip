@@ -21,41 +21,71 @@ __global__ void k_predict(BlobParams bp, BlobBufs b) {
     b.qh[t] = qh;
 }
 
-// F = f_const - k (q - c) + WCA pair forces (Eq. (WCA), minimum image,
-// unordered pairs), all at q^{n+1/2}. One thread per blob, all pairs.
-__global__ void k_forces(BlobParams bp, BlobBufs b) {
+// Positions folded into the box, q - L floor(q / L), for pair distances.
+__global__ void k_wrap(BlobParams bp, BlobBufs b) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * bp.nb) return;
+    const double L = bp.box[t % 3];
+    b.qw[t] = b.qh[t] - L * floor(b.qh[t] / L);
+}
+
+// F = f_const - k (q - c): the one-body forces at q^{n+1/2}.
+__global__ void k_forces_init(BlobParams bp, BlobBufs b) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * bp.nb) return;
+    double f = b.fconst[t];
+    if (bp.spring_k != 0.0) f -= bp.spring_k * (b.qh[t] - bp.spring_c[t % 3]);
+    b.F[t] = f;
+}
+
+// F += WCA pair forces (Eq. (WCA), minimum image, unordered pairs) at
+// q^{n+1/2}. Block (bx, by) takes blobs i of tile bx against blobs j of
+// tile by: tile by's folded positions sit in LDS, so the minimum image of a
+// difference in (-L, L) is one conditional shift per axis; partial sums are
+// added to F atomically.
+constexpr int kPairTile = 64;
+
+__global__ void __launch_bounds__(kThreads) k_pairs(BlobParams bp, BlobBufs b) {
+    __shared__ double tile[3][kPairTile];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= bp.nb) return;
-    const double qx = b.qh[3 * i], qy = b.qh[3 * i + 1], qz = b.qh[3 * i + 2];
-    double fx = b.fconst[3 * i], fy = b.fconst[3 * i + 1], fz = b.fconst[3 * i + 2];
-    if (bp.spring_k != 0.0) {
-        fx -= bp.spring_k * (qx - bp.spring_c[0]);
-        fy -= bp.spring_k * (qy - bp.spring_c[1]);
-        fz -= bp.spring_k * (qz - bp.spring_c[2]);
+    const int j0 = blockIdx.y * kPairTile;
+    const int jl = j0 + threadIdx.x;
+    if (threadIdx.x < kPairTile && jl < bp.nb) {
+        tile[0][threadIdx.x] = b.qw[3 * jl];
+        tile[1][threadIdx.x] = b.qw[3 * jl + 1];
+        tile[2][threadIdx.x] = b.qw[3 * jl + 2];
     }
-    if (bp.wca_eps != 0.0) {
-        const double s2 = bp.wca_sigma * bp.wca_sigma;
-        const double rc2 = 1.2599210498948732 * s2;  // (2^(1/6) sigma)^2
-        for (int j = 0; j < bp.nb; ++j) {
-            if (j == i) continue;
-            double dx = qx - b.qh[3 * j], dy = qy - b.qh[3 * j + 1], dz = qz - b.qh[3 * j + 2];
-            dx -= bp.box[0] * rint(dx / bp.box[0]);
-            dy -= bp.box[1] * rint(dy / bp.box[1]);
-            dz -= bp.box[2] * rint(dz / bp.box[2]);
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < rc2 && r2 > 0.0) {
-                const double sr2 = s2 / r2;
-                const double sr6 = sr2 * sr2 * sr2;
-                const double f = 24.0 * bp.wca_eps * (2.0 * sr6 * sr6 - sr6) / r2;
-                fx += f * dx;
-                fy += f * dy;
-                fz += f * dz;
-            }
+    __syncthreads();
+    if (i >= bp.nb) return;
+    const double qx = b.qw[3 * i], qy = b.qw[3 * i + 1], qz = b.qw[3 * i + 2];
+    const double s2 = bp.wca_sigma * bp.wca_sigma;
+    const double rc2 = 1.2599210498948732 * s2;  // (2^(1/6) sigma)^2
+    const double Lx = bp.box[0], Ly = bp.box[1], Lz = bp.box[2];
+    const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
+    const int cnt = min(kPairTile, bp.nb - j0);
+    double fx = 0, fy = 0, fz = 0;
+    bool any = false;
+    for (int jj = 0; jj < cnt; ++jj) {
+        double dx = qx - tile[0][jj], dy = qy - tile[1][jj], dz = qz - tile[2][jj];
+        dx = dx > hx ? dx - Lx : (dx < -hx ? dx + Lx : dx);
+        dy = dy > hy ? dy - Ly : (dy < -hy ? dy + Ly : dy);
+        dz = dz > hz ? dz - Lz : (dz < -hz ? dz + Lz : dz);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < rc2 && j0 + jj != i) {
+            const double sr2 = s2 / r2;
+            const double sr6 = sr2 * sr2 * sr2;
+            const double f = 24.0 * bp.wca_eps * (2.0 * sr6 * sr6 - sr6) / r2;
+            fx += f * dx;
+            fy += f * dy;
+            fz += f * dz;
+            any = true;
         }
     }
-    b.F[3 * i] = fx;
-    b.F[3 * i + 1] = fy;
-    b.F[3 * i + 2] = fz;
+    if (any) {
+        atomicAdd(&b.F[3 * i], fx);
+        atomicAdd(&b.F[3 * i + 1], fy);
+        atomicAdd(&b.F[3 * i + 2], fz);
+    }
 }
 
 // Step 4: du = [FULL] (J^{n+1/2} - J^n) v^n + [VISCOUS|FULL] (nu dt/2) c_lag;
@@ -128,9 +158,14 @@ void launch_predict(const BlobParams& bp, const BlobBufs& b, hipStream_t s) {
     if (bp.nb > 0) hipLaunchKernelGGL(k_predict, grid3(bp.nb), dim3(kThreads), 0, s, bp, b);
 }
 void launch_forces(const BlobParams& bp, const BlobBufs& b, hipStream_t s) {
-    if (bp.nb > 0)
-        hipLaunchKernelGGL(k_forces, dim3((unsigned)((bp.nb + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, bp,
-                           b);
+    if (bp.nb <= 0) return;
+    hipLaunchKernelGGL(k_forces_init, grid3(bp.nb), dim3(kThreads), 0, s, bp, b);
+    if (bp.wca_eps != 0.0 && bp.nb > 1) {
+        hipLaunchKernelGGL(k_wrap, grid3(bp.nb), dim3(kThreads), 0, s, bp, b);
+        const unsigned ti = (unsigned)((bp.nb + kThreads - 1) / kThreads);
+        const unsigned tj = (unsigned)((bp.nb + kPairTile - 1) / kPairTile);
+        hipLaunchKernelGGL(k_pairs, dim3(ti, tj), dim3(kThreads), 0, s, bp, b);
+    }
 }
 void launch_inertial_dp(const BlobParams& bp, const BlobBufs& b, hipStream_t s) {
     if (bp.nb > 0) hipLaunchKernelGGL(k_inertial_dp, grid3(bp.nb), dim3(kThreads), 0, s, bp, b);

@@ -165,8 +165,8 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(GridDesc<T> g, const T* __res
         const cplx<T> zk = r[l * N + k];
         const cplx<T> zc = cconj(r[l * N + ((N - k) % N)]);
         const cplx<T> s = cadd(zk, zc), d = csub(zk, zc);
-        dst[(2 * p) * W + k] = {(T)0.5 * s.x, (T)0.5 * s.y};
-        dst[(2 * p + 1) * W + k] = {(T)0.5 * d.y, (T)-0.5 * d.x};
+        dst[(2 * p) * g.Wp + k] = {(T)0.5 * s.x, (T)0.5 * s.y};
+        dst[(2 * p + 1) * g.Wp + k] = {(T)0.5 * d.y, (T)-0.5 * d.x};
     }
 }
 
@@ -190,15 +190,15 @@ __global__ void __launch_bounds__(kThreads) k_xinv(GridDesc<T> g, T* __restrict_
         if (p < npairs) {
             cplx<T> A, B;
             if (k <= H) {
-                A = src[(2 * p) * W + k];
-                B = src[(2 * p + 1) * W + k];
+                A = src[(2 * p) * g.Wp + k];
+                B = src[(2 * p + 1) * g.Wp + k];
                 if (k == 0 || k == H) {
                     A.y = 0;
                     B.y = 0;
                 }
             } else {
-                A = cconj(src[(2 * p) * W + (N - k)]);
-                B = cconj(src[(2 * p + 1) * W + (N - k)]);
+                A = cconj(src[(2 * p) * g.Wp + (N - k)]);
+                B = cconj(src[(2 * p + 1) * g.Wp + (N - k)]);
             }
             z = {A.x - B.y, A.y + B.x};
         }
@@ -236,16 +236,16 @@ __global__ void __launch_bounds__(kThreads) k_ypass(GridDesc<T> g, int B) {
     const int z = blockIdx.y;
     const int c = blockIdx.z;
     load_twiddles(tw, g.twy, N);
-    cplx<T>* base = g.spec + (long long)c * g.nspec + (long long)z * N * W + kx0;
+    cplx<T>* base = g.spec + (long long)c * g.nspec + (long long)z * N * g.Wp + kx0;
     for (int idx = threadIdx.x; idx < N * B; idx += blockDim.x) {
         const int y = idx / B, b = idx - y * B;
-        b0[idx] = (b < bw) ? base[(long long)y * W + b] : cplx<T>{0, 0};
+        b0[idx] = (b < bw) ? base[(long long)y * g.Wp + b] : cplx<T>{0, 0};
     }
     __syncthreads();
     cplx<T>* r = lds_fft<T, DIR>(b0, b1, g.py, B, 1, B, tw);
     for (int idx = threadIdx.x; idx < N * B; idx += blockDim.x) {
         const int y = idx / B, b = idx - y * B;
-        if (b < bw) base[(long long)y * W + b] = r[idx];
+        if (b < bw) base[(long long)y * g.Wp + b] = r[idx];
     }
 }
 
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(kThreads) k_zsolve(GridDesc<T> g, int B, Solve
     for (int idx = threadIdx.x; idx < N * L3; idx += blockDim.x) {
         const int z = idx / L3, rem = idx - z * L3;
         const int c = rem / B, b = rem - c * B;
-        b0[idx] = (b < bw) ? g.spec[(long long)c * g.nspec + ((long long)z * NY + y) * W + kx0 + b]
+        b0[idx] = (b < bw) ? g.spec[(long long)c * g.nspec + ((long long)z * NY + y) * g.Wp + kx0 + b]
                            : cplx<T>{0, 0};
     }
     __syncthreads();
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(kThreads) k_zsolve(GridDesc<T> g, int B, Solve
     for (int idx = threadIdx.x; idx < N * L3; idx += blockDim.x) {
         const int z = idx / L3, rem = idx - z * L3;
         const int c = rem / B, b = rem - c * B;
-        if (b < bw) g.spec[(long long)c * g.nspec + ((long long)z * NY + y) * W + kx0 + b] = r2[idx];
+        if (b < bw) g.spec[(long long)c * g.nspec + ((long long)z * NY + y) * g.Wp + kx0 + b] = r2[idx];
     }
 }
 
@@ -332,7 +332,11 @@ int zpass_width(int N, size_t cs) {
 }  // namespace
 
 template <typename T>
-void launch_fft_x_forward(const GridDesc<T>& g, const T* in, hipStream_t s) {
+void launch_fft_x_forward(const GridDesc<T>& g, const T* in, hipStream_t s, int c) {
+    if (g.fast) {
+        fast_fft_x_forward(g, in, c, s);
+        return;
+    }
     const size_t cs = sizeof(cplx<T>);
     const int N = g.nx;
     const long long pp = (long long)xpass_lines(N, cs);
@@ -343,7 +347,11 @@ void launch_fft_x_forward(const GridDesc<T>& g, const T* in, hipStream_t s) {
 }
 
 template <typename T>
-void launch_fft_y(const GridDesc<T>& g, int dir, hipStream_t s) {
+void launch_fft_y(const GridDesc<T>& g, int dir, hipStream_t s, int c) {
+    if (g.fast) {
+        fast_fft_y(g, dir, c, s);
+        return;
+    }
     const size_t cs = sizeof(cplx<T>);
     const int N = g.ny;
     const int By = ypass_width(N, cs);
@@ -357,6 +365,7 @@ void launch_fft_y(const GridDesc<T>& g, int dir, hipStream_t s) {
 
 template <typename T>
 void launch_fft_z_solve(const GridDesc<T>& g, SolveCoef sc, bool project, hipStream_t s) {
+    if (g.fast && fast_fft_z_solve(g, sc, project, s)) return;
     const size_t cs = sizeof(cplx<T>);
     const int N = g.nz;
     const int Bz = zpass_width(N, cs);
@@ -366,7 +375,11 @@ void launch_fft_z_solve(const GridDesc<T>& g, SolveCoef sc, bool project, hipStr
 }
 
 template <typename T>
-void launch_fft_x_inverse(const GridDesc<T>& g, T* out, bool accumulate, hipStream_t s) {
+void launch_fft_x_inverse(const GridDesc<T>& g, T* out, bool accumulate, hipStream_t s, int c) {
+    if (g.fast) {
+        fast_fft_x_inverse(g, out, accumulate, c, s);
+        return;
+    }
     const size_t cs = sizeof(cplx<T>);
     const int N = g.nx;
     const long long pp = (long long)xpass_lines(N, cs);
@@ -387,10 +400,10 @@ void launch_fft_forward_solve_inverse(const GridDesc<T>& g, const T* in, T* out,
 }
 
 #define ICM_INST(T)                                                                                          \
-    template void launch_fft_x_forward<T>(const GridDesc<T>&, const T*, hipStream_t);                        \
-    template void launch_fft_y<T>(const GridDesc<T>&, int, hipStream_t);                                     \
+    template void launch_fft_x_forward<T>(const GridDesc<T>&, const T*, hipStream_t, int);                   \
+    template void launch_fft_y<T>(const GridDesc<T>&, int, hipStream_t, int);                                \
     template void launch_fft_z_solve<T>(const GridDesc<T>&, SolveCoef, bool, hipStream_t);                   \
-    template void launch_fft_x_inverse<T>(const GridDesc<T>&, T*, bool, hipStream_t);                        \
+    template void launch_fft_x_inverse<T>(const GridDesc<T>&, T*, bool, hipStream_t, int);                   \
     template void launch_fft_forward_solve_inverse<T>(const GridDesc<T>&, const T*, T*, bool, SolveCoef, bool, \
                                                       hipStream_t);
 ICM_INST(float)

@@ -1,0 +1,595 @@
+// Register-resident FFT passes for the grid sizes of the paper's runs
+// (N in {16, 32, 48, 64, 128, 256, 512}); other sizes use the LDS Stockham
+// kernels of fft.hip.
+//
+// Layout of one line of length N on TL = N / E threads: thread t holds the E
+// elements n = t + TL * i (i < E) in registers. A Stockham stage of radix R
+// keeps this layout on input, so the first stage reads global memory in it
+// and the last stage leaves the natural-order result in it; the stages in
+// between exchange through LDS once each. With lines laid side by side along
+// the contiguous kx axis (y and z passes) every global access is a run of B
+// consecutive complex values (128 bytes), and the z pass keeps the three
+// velocity components of a mode in one thread, so the Helmholtz divide and
+// the 3x3 projection of Sec. III.D happen in registers between the forward
+// and inverse transforms.
+#include "icm_internal.h"
+
+namespace icm {
+
+namespace {
+
+constexpr size_t kLdsMax = 64 * 1024;
+
+// ---------------------------------------------------------- register DFTs
+template <typename T, int DIR>
+__device__ __forceinline__ void rdft2(cplx<T>* v) {
+    const cplx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void rdft3(cplx<T>* v) {
+    const T c = (T)0.86602540378443864676;
+    const cplx<T> s = cadd(v[1], v[2]);
+    const cplx<T> d = csub(v[1], v[2]);
+    const cplx<T> t = {v[0].x - (T)0.5 * s.x, v[0].y - (T)0.5 * s.y};
+    const cplx<T> id = cmul_i(d, DIR);
+    v[0] = cadd(v[0], s);
+    v[1] = {t.x + c * id.x, t.y + c * id.y};
+    v[2] = {t.x - c * id.x, t.y - c * id.y};
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void rdft4(cplx<T>* v) {
+    const cplx<T> t0 = cadd(v[0], v[2]);
+    const cplx<T> t1 = csub(v[0], v[2]);
+    const cplx<T> t2 = cadd(v[1], v[3]);
+    const cplx<T> t3 = cmul_i(csub(v[1], v[3]), DIR);
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void rdft8(cplx<T>* v) {
+    cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    rdft4<T, DIR>(e);
+    rdft4<T, DIR>(o);
+    const T r = (T)0.70710678118654752440;
+    o[1] = {r * (o[1].x - DIR * o[1].y), r * (o[1].y + DIR * o[1].x)};
+    o[2] = cmul_i(o[2], DIR);
+    o[3] = {r * (-o[3].x - DIR * o[3].y), r * (-o[3].y + DIR * o[3].x)};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        v[m] = cadd(e[m], o[m]);
+        v[m + 4] = csub(e[m], o[m]);
+    }
+}
+
+// 16-point DFT as 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.
+template <typename T, int DIR>
+__device__ __forceinline__ void rdft16(cplx<T>* v) {
+    cplx<T> A[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        cplx<T> w[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+        rdft4<T, DIR>(w);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) A[n2][k1] = w[k1];
+    }
+    // twiddles exp(DIR 2 pi i n2 k1 / 16)
+    const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173;
+    const T c2 = (T)0.70710678118654752440;
+    const cplx<T> w1 = {c1, DIR * s1}, w2 = {c2, DIR * c2}, w3 = {s1, DIR * c1};
+    const cplx<T> w6 = {-c2, DIR * c2}, w9 = {-c1, -DIR * s1};
+    A[1][1] = cmul(A[1][1], w1);
+    A[1][2] = cmul(A[1][2], w2);
+    A[1][3] = cmul(A[1][3], w3);
+    A[2][1] = cmul(A[2][1], w2);
+    A[2][2] = cmul_i(A[2][2], DIR);
+    A[2][3] = cmul(A[2][3], w6);
+    A[3][1] = cmul(A[3][1], w3);
+    A[3][2] = cmul(A[3][2], w6);
+    A[3][3] = cmul(A[3][3], w9);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cplx<T> w[4] = {A[0][k1], A[1][k1], A[2][k1], A[3][k1]};
+        rdft4<T, DIR>(w);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = w[k2];
+    }
+}
+
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void rdft(cplx<T>* v) {
+    if constexpr (R == 2) rdft2<T, DIR>(v);
+    if constexpr (R == 3) rdft3<T, DIR>(v);
+    if constexpr (R == 4) rdft4<T, DIR>(v);
+    if constexpr (R == 8) rdft8<T, DIR>(v);
+    if constexpr (R == 16) rdft16<T, DIR>(v);
+}
+
+// One Stockham stage on the strided register layout. Butterfly j = t + TL m
+// takes x[j + r N/R] (register m + M r), twiddles it by
+// w^(r (j mod Ns)), w = exp(DIR 2 pi i / (Ns R)), and applies a radix-R DFT.
+template <typename T, int N, int E, int R, int Ns, int DIR>
+__device__ __forceinline__ void reg_stage(cplx<T> (&a)[E], int t, const cplx<T>* tw) {
+    constexpr int TL = N / E, M = E / R;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        cplx<T> v[R];
+        const int k = (t + TL * m) % Ns;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cplx<T> x = a[m + M * r];
+            if constexpr (Ns > 1) {
+                if (r > 0) {
+                    cplx<T> w = tw[r * k * (N / (Ns * R))];
+                    if (DIR > 0) w.y = -w.y;
+                    x = cmul(x, w);
+                }
+            }
+            v[r] = x;
+        }
+        rdft<T, R, DIR>(v);
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[m + M * r] = v[r];
+    }
+}
+
+// Stage outputs go to y[(j / Ns) Ns R + j mod Ns + r Ns]; bring them back
+// to the strided layout through LDS (element n at lds[n * ls + lo]).
+// SK skews the LDS index (n -> n + n / 2^SK) so that lines stored
+// contiguously (x pass, ls = 1) do not put a thread's consecutive outputs,
+// which lanes write in lock step, into the same banks; SK >= 16 disables it.
+template <int SK>
+__device__ __forceinline__ int skew(int n) {
+    if constexpr (SK >= 16) return n;
+    else return n + (n >> SK);
+}
+
+template <typename T, int N, int E, int R, int Ns, int SK>
+__device__ __forceinline__ void reg_exchange(cplx<T> (&a)[E], int t, cplx<T>* lds, int ls, int lo) {
+    constexpr int TL = N / E, M = E / R;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int j = t + TL * m;
+        const int base = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[skew<SK>(base + r * Ns) * ls + lo] = a[m + M * r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E; ++i) a[i] = lds[skew<SK>(t + TL * i) * ls + lo];
+}
+
+template <typename T, int N, int E, int R0, int R1, int R2, int DIR, int SK = 16>
+__device__ __forceinline__ void reg_fft(cplx<T> (&a)[E], int t, cplx<T>* lds, int ls, int lo, const cplx<T>* tw) {
+    reg_stage<T, N, E, R0, 1, DIR>(a, t, tw);
+    if constexpr (R1 > 1) {
+        reg_exchange<T, N, E, R0, 1, SK>(a, t, lds, ls, lo);
+        reg_stage<T, N, E, R1, R0, DIR>(a, t, tw);
+        if constexpr (R2 > 1) {
+            reg_exchange<T, N, E, R1, R0, SK>(a, t, lds, ls, lo);
+            reg_stage<T, N, E, R2, R0 * R1, DIR>(a, t, tw);
+        }
+    }
+}
+
+// Line stride (in complex elements) of the x-pass LDS lines with skew.
+template <int N>
+constexpr int xline() { return N + N / 16 + 1; }
+
+template <typename T>
+__device__ __forceinline__ void load_tw(cplx<T>* dst, const cplx<T>* src, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// Spectrum layout: rows of W = nx/2 + 1 complex values at pitch Wp (a
+// multiple of 128 bytes), rows ordered (c, z, y). The y and z passes work in
+// place on column tiles of B consecutive kx; each access of a wave is a run
+// of B complex values.
+
+// ------------------------------------------------------------------ y pass
+// Block: B consecutive kx columns of one (z, component) plane; thread
+// (b = tid mod B, t = tid / B).
+template <typename T, int N, int E, int R0, int R1, int R2, int DIR>
+__global__ void __launch_bounds__(512) k_y_fast(GridDesc<T> g, int B, int c) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* tws = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* lds = tws + N;
+    const int b = threadIdx.x % B, t = threadIdx.x / B;
+    const int kx0 = blockIdx.x * B;
+    const bool ok = kx0 + b < g.W;
+    const int comp = c < 0 ? (int)blockIdx.z : c;
+    cplx<T>* base = g.spec + (long long)comp * g.nspec + (long long)blockIdx.y * N * g.Wp + kx0 + b;
+    load_tw(tws, g.twy, N);
+    constexpr int TL = N / E;
+    cplx<T> a[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) a[i] = ok ? base[(long long)(t + TL * i) * g.Wp] : cplx<T>{0, 0};
+    __syncthreads();
+    reg_fft<T, N, E, R0, R1, R2, DIR>(a, t, lds, B, b, tws);
+    if (ok) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) base[(long long)(t + TL * i) * g.Wp] = a[i];
+    }
+}
+
+// --------------------------------------------------------- z pass + solve
+// Block: B consecutive kx columns of one ky row; each thread (b = tid mod B,
+// t = tid / B) holds all three components of its column, so the Helmholtz
+// divide and the 3 x 3 projection of every mode happen in registers between
+// the forward and inverse transforms.
+template <typename T, int N, int E, int R0, int R1, int R2>
+__global__ void __launch_bounds__(512) k_z_fast(GridDesc<T> g, int B, SolveCoef sc, int project) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* tws = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* lds = tws + N;
+    const int b = threadIdx.x % B, t = threadIdx.x / B;
+    const int kx0 = blockIdx.x * B;
+    const int kx = kx0 + b;
+    const bool ok = kx < g.W;
+    const int y = blockIdx.y;
+    load_tw(tws, g.twz, N);
+    constexpr int TL = N / E;
+    const long long zs = (long long)g.ny * g.Wp;  // stride between z planes
+    cplx<T>* p0 = g.spec + (long long)y * g.Wp + kx;
+    cplx<T>* p1 = p0 + g.nspec;
+    cplx<T>* p2 = p1 + g.nspec;
+    cplx<T> a0[E], a1[E], a2[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const long long o = (long long)(t + TL * i) * zs;
+        a0[i] = ok ? p0[o] : cplx<T>{0, 0};
+        a1[i] = ok ? p1[o] : cplx<T>{0, 0};
+        a2[i] = ok ? p2[o] : cplx<T>{0, 0};
+    }
+    __syncthreads();
+    reg_fft<T, N, E, R0, R1, R2, -1>(a0, t, lds, B, b, tws);
+    reg_fft<T, N, E, R0, R1, R2, -1>(a1, t, lds, B, b, tws);
+    reg_fft<T, N, E, R0, R1, R2, -1>(a2, t, lds, B, b, tws);
+    if (ok) {
+        const T lxy = g.lx[kx] + g.ly[y];
+        const cplx<T> dx = g.dx_hat[kx], dy = g.dy_hat[y];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int kz = t + TL * i;
+            const T lam = lxy + g.lz[kz];
+            const T f = (T)(sc.scale / (sc.a + sc.b * (double)lam));
+            cplx<T> w0 = {a0[i].x * f, a0[i].y * f};
+            cplx<T> w1 = {a1[i].x * f, a1[i].y * f};
+            cplx<T> w2 = {a2[i].x * f, a2[i].y * f};
+            if (project && lam > (T)0) {
+                const cplx<T> dz = g.dz_hat[kz];
+                const cplx<T> d = cadd(cadd(cmul(dx, w0), cmul(dy, w1)), cmul(dz, w2));
+                const T il = (T)1 / lam;
+                const cplx<T> dd = {d.x * il, d.y * il};
+                w0 = csub(w0, cmul(cconj(dx), dd));
+                w1 = csub(w1, cmul(cconj(dy), dd));
+                w2 = csub(w2, cmul(cconj(dz), dd));
+            }
+            a0[i] = w0;
+            a1[i] = w1;
+            a2[i] = w2;
+        }
+    }
+    reg_fft<T, N, E, R0, R1, R2, 1>(a0, t, lds, B, b, tws);
+    reg_fft<T, N, E, R0, R1, R2, 1>(a1, t, lds, B, b, tws);
+    reg_fft<T, N, E, R0, R1, R2, 1>(a2, t, lds, B, b, tws);
+    if (ok) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const long long o = (long long)(t + TL * i) * zs;
+            p0[o] = a0[i];
+            p1[o] = a1[i];
+            p2[o] = a2[i];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ x pass
+// Block: P row pairs of one component; thread (t = tid mod TL, l = tid / TL).
+// Rows 2p and 2p+1 are packed as z = a + i b; their half spectra are
+// separated by Hermitian symmetry after the transform.
+template <typename T, int N, int E, int R0, int R1, int R2>
+__global__ void __launch_bounds__(512) k_xfwd_fast(GridDesc<T> g, const T* __restrict__ in, int P, int cc) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* tws = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* lds = tws + N;
+    constexpr int TL = N / E;
+    const int t = threadIdx.x % TL, l = threadIdx.x / TL;
+    const int W = g.W;
+    const long long npairs = (long long)g.ny * g.nz / 2;
+    const long long p = (long long)blockIdx.x * P + l;
+    const bool ok = p < npairs;
+    const int c = cc < 0 ? (int)blockIdx.y : cc;
+    load_tw(tws, g.twx, N);
+    // stage the block's row pairs through LDS with contiguous loads
+    const long long row0 = (long long)c * g.ncell + 2 * ((long long)blockIdx.x * P) * N;
+    const long long lim = (long long)c * g.ncell + 2 * npairs * N;
+    constexpr int LS = xline<N>();
+    for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
+        const int ll = idx / N, x = idx - ll * N;
+        const long long o = row0 + 2LL * ll * N + x;
+        lds[ll * LS + skew<4>(x)] = (o < lim) ? cplx<T>{in[o], in[o + N]} : cplx<T>{0, 0};
+    }
+    __syncthreads();
+    cplx<T> a[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) a[i] = lds[l * LS + skew<4>(t + TL * i)];
+    __syncthreads();
+    reg_fft<T, N, E, R0, R1, R2, -1, 4>(a, t, lds, 1, l * LS, tws);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E; ++i) lds[l * LS + skew<4>(t + TL * i)] = a[i];
+    __syncthreads();
+    if (!ok) return;
+    cplx<T>* d0 = g.spec + (long long)c * g.nspec + 2 * p * g.Wp;
+    for (int k = t; k < W; k += TL) {
+        const cplx<T> zk = lds[l * LS + skew<4>(k)];
+        const cplx<T> zc = cconj(lds[l * LS + skew<4>((N - k) % N)]);
+        const cplx<T> s = cadd(zk, zc), d = csub(zk, zc);
+        d0[k] = {(T)0.5 * s.x, (T)0.5 * s.y};
+        d0[g.Wp + k] = {(T)0.5 * d.y, (T)-0.5 * d.x};
+    }
+}
+
+template <typename T, int N, int E, int R0, int R1, int R2>
+__global__ void __launch_bounds__(512) k_xinv_fast(GridDesc<T> g, T* __restrict__ out, int P, int accumulate,
+                                                    int cc) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* tws = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* lds = tws + N;
+    constexpr int TL = N / E;
+    constexpr int H = N / 2;
+    const int t = threadIdx.x % TL, l = threadIdx.x / TL;
+    const int W = g.W;
+    const long long npairs = (long long)g.ny * g.nz / 2;
+    const long long p = (long long)blockIdx.x * P + l;
+    const bool ok = p < npairs;
+    const int c = cc < 0 ? (int)blockIdx.y : cc;
+    load_tw(tws, g.twx, N);
+    const long long rp = g.Wp;
+    const cplx<T>* s0 = g.spec + (long long)c * g.nspec + 2 * p * rp;
+    constexpr int LS = xline<N>();
+    for (int k = t; k < W; k += TL) {
+        cplx<T> A = {0, 0}, Bv = {0, 0};
+        if (ok) {
+            A = s0[k];
+            Bv = s0[rp + k];
+        }
+        if (k == 0 || k == H) {
+            A.y = 0;
+            Bv.y = 0;
+        }
+        lds[l * LS + skew<4>(k)] = {A.x - Bv.y, A.y + Bv.x};
+        if (k > 0 && k < H) lds[l * LS + skew<4>(N - k)] = {A.x + Bv.y, -A.y + Bv.x};
+    }
+    __syncthreads();
+    cplx<T> a[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) a[i] = lds[l * LS + skew<4>(t + TL * i)];
+    reg_fft<T, N, E, R0, R1, R2, 1, 4>(a, t, lds, 1, l * LS, tws);
+    // unstage through LDS so that rows are written with contiguous stores
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E; ++i) lds[l * LS + skew<4>(t + TL * i)] = a[i];
+    __syncthreads();
+    const long long row0 = (long long)c * g.ncell + 2 * ((long long)blockIdx.x * P) * N;
+    const long long lim = (long long)c * g.ncell + 2 * npairs * N;
+    for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
+        const int ll = idx / N, x = idx - ll * N;
+        const long long o = row0 + 2LL * ll * N + x;
+        if (o >= lim) continue;
+        const cplx<T> z = lds[ll * LS + skew<4>(x)];
+        if (accumulate) {
+            out[o] += z.x;
+            out[o + N] += z.y;
+        } else {
+            out[o] = z.x;
+            out[o + N] = z.y;
+        }
+    }
+}
+
+// --------------------------------------------------------------- dispatch
+// Plans: (E, R0, R1, R2) per (precision, N); a radix of 1 ends the list.
+template <typename T, int N>
+struct Plan {
+    static constexpr bool ok = false;
+};
+#define ICM_PLAN(TT, NN, EE, A, B_, C)                 \
+    template <>                                        \
+    struct Plan<TT, NN> {                              \
+        static constexpr bool ok = true;               \
+        static constexpr int E = EE, R0 = A, R1 = B_, R2 = C; \
+    };
+ICM_PLAN(float, 16, 16, 16, 1, 1)
+ICM_PLAN(float, 32, 16, 16, 2, 1)
+ICM_PLAN(float, 48, 12, 4, 4, 3)
+ICM_PLAN(float, 64, 16, 16, 4, 1)
+ICM_PLAN(float, 128, 16, 16, 8, 1)
+ICM_PLAN(float, 256, 16, 16, 16, 1)
+ICM_PLAN(float, 512, 16, 8, 8, 8)
+ICM_PLAN(double, 16, 8, 8, 2, 1)
+ICM_PLAN(double, 32, 8, 8, 4, 1)
+ICM_PLAN(double, 48, 12, 4, 4, 3)
+ICM_PLAN(double, 64, 8, 8, 8, 1)
+ICM_PLAN(double, 128, 8, 8, 8, 2)
+ICM_PLAN(double, 256, 8, 8, 8, 4)
+ICM_PLAN(double, 512, 8, 8, 8, 8)
+#undef ICM_PLAN
+
+// The z pass holds three components per thread; a smaller E keeps its
+// register use (and so its occupancy) comparable to the other passes.
+template <typename T, int N>
+struct PlanZ : Plan<T, N> {};
+#define ICM_PLANZ(TT, NN, EE, A, B_, C)                       \
+    template <>                                               \
+    struct PlanZ<TT, NN> {                                    \
+        static constexpr bool ok = true;                      \
+        static constexpr int E = EE, R0 = A, R1 = B_, R2 = C; \
+    };
+#undef ICM_PLANZ
+
+// Kernels whose LDS exceeds 64 KB opt in to the larger gfx950 allocation.
+template <typename K>
+void allow_lds(K kernel, size_t bytes) {
+    if (bytes > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)bytes);
+}
+
+template <typename T>
+int pairs_per_block(int N, int TL) {
+    int P = 256 / TL;
+    if (P < 1) P = 1;
+    while (P > 1 && ((size_t)N + (size_t)P * (N + N / 16 + 1)) * sizeof(cplx<T>) > kLdsMax) P /= 2;
+    return P;
+}
+
+template <typename T, int N>
+bool y_fast(const GridDesc<T>& g, int dir, int c, hipStream_t s) {
+    using Pl = Plan<T, N>;
+    if constexpr (!Pl::ok) {
+        return false;
+    } else {
+        constexpr int TL = N / Pl::E;
+        int B = g.By;
+        while (B > 1 && B * TL > 512) B /= 2;
+        const dim3 grid((unsigned)((g.W + B - 1) / B), g.nz, c < 0 ? 3 : 1);
+        const size_t lds = (size_t)N * (B + 1) * sizeof(cplx<T>);
+        if (dir < 0) {
+            allow_lds(k_y_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, -1>, lds);
+            hipLaunchKernelGGL((k_y_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, -1>), grid, dim3(B * TL), lds, s, g, B, c);
+        } else {
+            allow_lds(k_y_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, 1>, lds);
+            hipLaunchKernelGGL((k_y_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, 1>), grid, dim3(B * TL), lds, s, g, B, c);
+        }
+        return true;
+    }
+}
+
+template <typename T, int N>
+bool z_fast(const GridDesc<T>& g, SolveCoef sc, bool project, hipStream_t s) {
+    using Pl = PlanZ<T, N>;
+    if constexpr (!Pl::ok) {
+        return false;
+    } else {
+        constexpr int TL = N / Pl::E;
+        int B = g.Bz;
+        while (B > 1 && B * TL > 512) B /= 2;
+        const dim3 grid((unsigned)((g.W + B - 1) / B), g.ny);
+        const size_t lds = (size_t)N * (B + 1) * sizeof(cplx<T>);
+        allow_lds(k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>, lds);
+        hipLaunchKernelGGL((k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>), grid, dim3(B * TL), lds, s, g, B, sc,
+                           project ? 1 : 0);
+        return true;
+    }
+}
+
+template <typename T, int N>
+bool xf_fast(const GridDesc<T>& g, const T* in, int c, hipStream_t s) {
+    using Pl = Plan<T, N>;
+    if constexpr (!Pl::ok) {
+        return false;
+    } else {
+        constexpr int TL = N / Pl::E;
+        const int P = pairs_per_block<T>(N, TL);
+        const long long npairs = (long long)g.ny * g.nz / 2;
+        const dim3 grid((unsigned)((npairs + P - 1) / P), c < 0 ? 3 : 1);
+        const size_t lds = (size_t)(N + P * xline<N>()) * sizeof(cplx<T>);
+        hipLaunchKernelGGL((k_xfwd_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>), grid, dim3(P * TL), lds, s, g, in, P, c);
+        return true;
+    }
+}
+
+template <typename T, int N>
+bool xi_fast(const GridDesc<T>& g, T* out, bool acc, int c, hipStream_t s) {
+    using Pl = Plan<T, N>;
+    if constexpr (!Pl::ok) {
+        return false;
+    } else {
+        constexpr int TL = N / Pl::E;
+        const int P = pairs_per_block<T>(N, TL);
+        const long long npairs = (long long)g.ny * g.nz / 2;
+        const dim3 grid((unsigned)((npairs + P - 1) / P), c < 0 ? 3 : 1);
+        const size_t lds = (size_t)(N + P * xline<N>()) * sizeof(cplx<T>);
+        hipLaunchKernelGGL((k_xinv_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>), grid, dim3(P * TL), lds, s, g, out, P,
+                           acc ? 1 : 0, c);
+        return true;
+    }
+}
+
+#define ICM_SWITCH_N(n, CALL) \
+    switch (n) {              \
+        case 16: return CALL(16); \
+        case 32: return CALL(32); \
+        case 48: return CALL(48); \
+        case 64: return CALL(64); \
+        case 128: return CALL(128); \
+        case 256: return CALL(256); \
+        case 512: return CALL(512); \
+        default: return false;    \
+    }
+
+}  // namespace
+
+template <typename T>
+bool fast_fft_available(int nx, int ny, int nz) {
+    auto has = [](int n) {
+        switch (n) {
+            case 16: return Plan<T, 16>::ok;
+            case 32: return Plan<T, 32>::ok;
+            case 48: return Plan<T, 48>::ok;
+            case 64: return Plan<T, 64>::ok;
+            case 128: return Plan<T, 128>::ok;
+            case 256: return Plan<T, 256>::ok;
+            case 512: return Plan<T, 512>::ok;
+            default: return false;
+        }
+    };
+    return has(nx) && has(ny) && has(nz);
+}
+
+template <typename T>
+bool fast_fft_y(const GridDesc<T>& g, int dir, int c, hipStream_t s) {
+#define C(NN) y_fast<T, NN>(g, dir, c, s)
+    ICM_SWITCH_N(g.ny, C)
+#undef C
+}
+template <typename T>
+bool fast_fft_z_solve(const GridDesc<T>& g, SolveCoef sc, bool project, hipStream_t s) {
+#define C(NN) z_fast<T, NN>(g, sc, project, s)
+    ICM_SWITCH_N(g.nz, C)
+#undef C
+}
+template <typename T>
+bool fast_fft_x_forward(const GridDesc<T>& g, const T* in, int c, hipStream_t s) {
+#define C(NN) xf_fast<T, NN>(g, in, c, s)
+    ICM_SWITCH_N(g.nx, C)
+#undef C
+}
+template <typename T>
+bool fast_fft_x_inverse(const GridDesc<T>& g, T* out, bool acc, int c, hipStream_t s) {
+#define C(NN) xi_fast<T, NN>(g, out, acc, c, s)
+    ICM_SWITCH_N(g.nx, C)
+#undef C
+}
+
+#define ICM_INST(T)                                                                      \
+    template bool fast_fft_available<T>(int, int, int);                                  \
+    template bool fast_fft_y<T>(const GridDesc<T>&, int, int, hipStream_t);              \
+    template bool fast_fft_z_solve<T>(const GridDesc<T>&, SolveCoef, bool, hipStream_t); \
+    template bool fast_fft_x_forward<T>(const GridDesc<T>&, const T*, int, hipStream_t); \
+    template bool fast_fft_x_inverse<T>(const GridDesc<T>&, T*, bool, int, hipStream_t);
+ICM_INST(float)
+ICM_INST(double)
+#undef ICM_INST
+
+}  // namespace icm

@@ -25,69 +25,151 @@ __device__ __forceinline__ NormalPair<T> bm(uint32_t wa, uint32_t wb) {
 // Right-hand side of the unperturbed solve (Eq. (provisional_step-1)):
 //   rhs_a = (rho/dt) v_a + (eta/2) (L v)_a + s (D_w Sigma-hat)_a + f_body,a
 // with Sigma-hat = W + W^T realised as 2 W_aa at cell centres and
-// sqrt(2) W_ab on edges. One thread per cell; the neighbouring cells' normals
-// are regenerated from their Philox counters.
+// sqrt(2) W_ab on edges.
+//
+// The kernel marches along z. A block owns a TX x TY tile of
+// (x, y) columns and a chunk of ZC planes; each thread owns one column. Every
+// cell's two Philox blocks are generated once: block 1 of plane k+1 is drawn
+// one plane ahead (the x-z and y-z edge stresses of plane k+1 enter plane k),
+// W_zz of plane k-1 is carried in a register, and the in-plane neighbours'
+// stresses and velocities are shared through LDS. Only the tile's one-cell
+// halo ring regenerates the few normals it needs.
+constexpr int RTX = 32, RTY = 16, RZC = 16;
+
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_rhs(GridDesc<T> g, RhsCoef c) {
-    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= g.ncell) return;
+__global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef c) {
+    __shared__ T sv[3][RTY + 2][RTX + 2];  // velocity of plane k with halo
+    __shared__ T sxx[RTY][RTX + 1];        // W_xx, column 0 = i0 - 1
+    __shared__ T sxy[RTY + 1][RTX + 1];    // W_xy, row RTY = j0 + TY, column RTX = i0 + TX
+    __shared__ T sxz[RTY][RTX + 1];        // W_xz, column RTX = i0 + TX
+    __shared__ T syy[RTY + 1][RTX];        // W_yy, row 0 = j0 - 1
+    __shared__ T syz[RTY + 1][RTX];        // W_yz, row RTY = j0 + TY
     const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const int i = (int)(cell % nx);
-    const int j = (int)((cell / nx) % ny);
-    const int k = (int)(cell / ((long long)nx * ny));
-    const int ip = i + 1 == nx ? 0 : i + 1, im = i == 0 ? nx - 1 : i - 1;
-    const int jp = j + 1 == ny ? 0 : j + 1, jm = j == 0 ? ny - 1 : j - 1;
-    const int kp = k + 1 == nz ? 0 : k + 1, km = k == 0 ? nz - 1 : k - 1;
-    auto lin = [&](int a, int b, int d) -> long long { return ((long long)d * ny + b) * nx + a; };
-    const long long cip = lin(ip, j, k), cim = lin(im, j, k);
-    const long long cjp = lin(i, jp, k), cjm = lin(i, jm, k);
-    const long long ckp = lin(i, j, kp), ckm = lin(i, j, km);
-    T out[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const T* v = g.v + a * g.ncell;
-        const T v0 = v[cell];
-        const T lap = v[cip] + v[cim] + v[cjp] + v[cjm] + v[ckp] + v[ckm] - (T)6 * v0;
-        out[a] = (T)c.rho_dt * v0 + (T)c.half_eta_h2 * lap + (T)c.body[a];
+    const int tx = threadIdx.x % RTX, ty = threadIdx.x / RTX;
+    const int i0 = blockIdx.x * RTX, j0 = blockIdx.y * RTY;
+    const int k0 = blockIdx.z * RZC;
+    const int k1 = min(k0 + RZC, nz);
+    const int i = i0 + tx, j = j0 + ty;
+    const bool own = (i < nx) && (j < ny);
+    const long long plane = (long long)nx * ny;
+    const long long col = (long long)j * nx + i;
+    const bool noisy = c.noise != 0.0;
+    const NoiseKey& nk = c.key;
+    const T r2 = (T)1.41421356237309504880;
+    // halo duty: threads [0, RTY) left column, [RTY, 2RTY) right column,
+    // [2RTY, 2RTY+RTX) bottom row, [2RTY+RTX, 2RTY+2RTX) top row
+    // valid tile extent; the right / top halo sits just past it (wrapped)
+    const int wx = min(RTX, nx - i0), wy = min(RTY, ny - j0);
+    const int tid = threadIdx.x;
+    int hi = -1, hj = -1, hkind = -1;
+    if (tid < RTY) { hkind = 0; hi = i0 - 1; hj = j0 + tid; }
+    else if (tid < 2 * RTY) { hkind = 1; hi = i0 + wx; hj = j0 + tid - RTY; }
+    else if (tid < 2 * RTY + RTX) { hkind = 2; hi = i0 + tid - 2 * RTY; hj = j0 - 1; }
+    else if (tid < 2 * RTY + 2 * RTX) { hkind = 3; hi = i0 + tid - 2 * RTY - RTX; hj = j0 + wy; }
+    const int hiw = wrap(hi, nx), hjw = wrap(hj, ny);
+    const bool hvalid = hkind >= 0 && (hkind >= 2 ? hi - i0 < wx : hj - j0 < wy);
+
+    // registers carried along z
+    T vm[3] = {0, 0, 0}, v0[3] = {0, 0, 0}, vp[3] = {0, 0, 0};
+    T wzz_m = 0, wxz_c = 0, wyz_c = 0;
+    if (own) {
+        const int km = wrap(k0 - 1, nz);
+        for (int a = 0; a < 3; ++a) {
+            vm[a] = g.v[a * g.ncell + km * plane + col];
+            v0[a] = g.v[a * g.ncell + (long long)k0 * plane + col];
+        }
+        if (noisy) {
+            const u32x4 w = noise_words(nk, (uint32_t)(km * plane + col), 0);
+            NormalPair<T> p = bm<T>(w.z, w.w);
+            wzz_m = p.a;
+            const u32x4 w1 = noise_words(nk, (uint32_t)(k0 * plane + col), 1);
+            NormalPair<T> q = bm<T>(w1.x, w1.y);
+            wxz_c = q.a;
+            wyz_c = q.b;
+        }
     }
-    if (c.noise != 0.0) {
-        const NoiseKey& nk = c.key;
-        // own cell: block 0 -> (xx, yy), (zz, xy); block 1 -> (xz, yz)
-        const u32x4 o0 = noise_words(nk, (uint32_t)cell, 0);
-        const u32x4 o1 = noise_words(nk, (uint32_t)cell, 1);
-        const NormalPair<T> oxy = bm<T>(o0.x, o0.y);   // xx, yy
-        const NormalPair<T> ozx = bm<T>(o0.z, o0.w);   // zz, xy
-        const NormalPair<T> oxz = bm<T>(o1.x, o1.y);   // xz, yz
-        const T wxx = oxy.a, wyy = oxy.b, wzz = ozx.a, wxy = ozx.b, wxz = oxz.a, wyz = oxz.b;
-        // neighbours
-        const u32x4 nim = noise_words(nk, (uint32_t)cim, 0);
-        const T wxx_im = bm<T>(nim.x, nim.y).a;
-        const u32x4 nip0 = noise_words(nk, (uint32_t)cip, 0);
-        const u32x4 nip1 = noise_words(nk, (uint32_t)cip, 1);
-        const T wxy_ip = bm<T>(nip0.z, nip0.w).b;
-        const T wxz_ip = bm<T>(nip1.x, nip1.y).a;
-        const u32x4 njm = noise_words(nk, (uint32_t)cjm, 0);
-        const T wyy_jm = bm<T>(njm.x, njm.y).b;
-        const u32x4 njp0 = noise_words(nk, (uint32_t)cjp, 0);
-        const u32x4 njp1 = noise_words(nk, (uint32_t)cjp, 1);
-        const T wxy_jp = bm<T>(njp0.z, njp0.w).b;
-        const T wyz_jp = bm<T>(njp1.x, njp1.y).b;
-        const u32x4 nkm = noise_words(nk, (uint32_t)ckm, 0);
-        const T wzz_km = bm<T>(nkm.z, nkm.w).a;
-        const u32x4 nkp = noise_words(nk, (uint32_t)ckp, 1);
-        const NormalPair<T> kxz = bm<T>(nkp.x, nkp.y);
-        const T wxz_kp = kxz.a, wyz_kp = kxz.b;
-        const T r2 = (T)1.41421356237309504880;
-        const T dx = (T)2 * (wxx - wxx_im) + r2 * (wxy_jp - wxy) + r2 * (wxz_kp - wxz);
-        const T dy = r2 * (wxy_ip - wxy) + (T)2 * (wyy - wyy_jm) + r2 * (wyz_kp - wyz);
-        const T dz = r2 * (wxz_ip - wxz) + r2 * (wyz_jp - wyz) + (T)2 * (wzz - wzz_km);
-        const T s = (T)c.noise;
-        out[0] += s * dx;
-        out[1] += s * dy;
-        out[2] += s * dz;
-    }
+    for (int k = k0; k < k1; ++k) {
+        const int kp = k + 1 == nz ? 0 : k + 1;
+        T wxx = 0, wyy = 0, wzz = 0, wxy = 0, wxz_n = 0, wyz_n = 0;
+        if (own) {
+            for (int a = 0; a < 3; ++a) vp[a] = g.v[a * g.ncell + (long long)kp * plane + col];
+            if (noisy) {
+                const u32x4 w0 = noise_words(nk, (uint32_t)(k * plane + col), 0);
+                NormalPair<T> p0 = bm<T>(w0.x, w0.y), p1 = bm<T>(w0.z, w0.w);
+                wxx = p0.a;
+                wyy = p0.b;
+                wzz = p1.a;
+                wxy = p1.b;
+                const u32x4 w1 = noise_words(nk, (uint32_t)(kp * plane + col), 1);
+                NormalPair<T> p2 = bm<T>(w1.x, w1.y);
+                wxz_n = p2.a;
+                wyz_n = p2.b;
+            }
+            for (int a = 0; a < 3; ++a) sv[a][ty + 1][tx + 1] = v0[a];
+            sxx[ty][tx + 1] = wxx;
+            sxy[ty][tx] = wxy;
+            sxz[ty][tx] = wxz_c;
+            syy[ty + 1][tx] = wyy;
+            syz[ty][tx] = wyz_c;
+        }
+        if (hvalid) {
+            const long long hc = (long long)k * plane + (long long)hjw * nx + hiw;
+            // LDS slot of the halo cell (column/row index within the tile + 1)
+            const int sy = hkind <= 1 ? hj - j0 + 1 : (hkind == 2 ? 0 : wy + 1);
+            const int sx = hkind == 0 ? 0 : (hkind == 1 ? wx + 1 : hi - i0 + 1);
+            for (int a = 0; a < 3; ++a) sv[a][sy][sx] = g.v[a * g.ncell + hc];
+            if (noisy) {
+                if (hkind == 0) {
+                    const u32x4 w = noise_words(nk, (uint32_t)hc, 0);
+                    sxx[hj - j0][0] = bm<T>(w.x, w.y).a;
+                } else if (hkind == 1) {
+                    const u32x4 w = noise_words(nk, (uint32_t)hc, 0);
+                    sxy[hj - j0][wx] = bm<T>(w.z, w.w).b;
+                    const u32x4 w1 = noise_words(nk, (uint32_t)hc, 1);
+                    sxz[hj - j0][wx] = bm<T>(w1.x, w1.y).a;
+                } else if (hkind == 2) {
+                    const u32x4 w = noise_words(nk, (uint32_t)hc, 0);
+                    syy[0][hi - i0] = bm<T>(w.x, w.y).b;
+                } else {
+                    const u32x4 w = noise_words(nk, (uint32_t)hc, 0);
+                    sxy[wy][hi - i0] = bm<T>(w.z, w.w).b;
+                    const u32x4 w1 = noise_words(nk, (uint32_t)hc, 1);
+                    syz[wy][hi - i0] = bm<T>(w1.x, w1.y).b;
+                }
+            }
+        }
+        __syncthreads();
+        if (own) {
+            T out[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) g.rhs[a * g.ncell + cell] = out[a];
+            for (int a = 0; a < 3; ++a) {
+                const T lap = sv[a][ty + 1][tx] + sv[a][ty + 1][tx + 2] + sv[a][ty][tx + 1] + sv[a][ty + 2][tx + 1] +
+                              vm[a] + vp[a] - (T)6 * v0[a];
+                out[a] = (T)c.rho_dt * v0[a] + (T)c.half_eta_h2 * lap + (T)c.body[a];
+            }
+            if (noisy) {
+                const T s = (T)c.noise;
+                const T dx = (T)2 * (wxx - sxx[ty][tx]) + r2 * (sxy[ty + 1][tx] - wxy) + r2 * (wxz_n - wxz_c);
+                const T dy = r2 * (sxy[ty][tx + 1] - wxy) + (T)2 * (wyy - syy[ty][tx]) + r2 * (wyz_n - wyz_c);
+                const T dz = r2 * (sxz[ty][tx + 1] - wxz_c) + r2 * (syz[ty + 1][tx] - wyz_c) + (T)2 * (wzz - wzz_m);
+                out[0] += s * dx;
+                out[1] += s * dy;
+                out[2] += s * dz;
+            }
+            const long long cell = (long long)k * plane + col;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) g.rhs[a * g.ncell + cell] = out[a];
+        }
+        __syncthreads();
+        wzz_m = wzz;
+        wxz_c = wxz_n;
+        wyz_c = wyz_n;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            vm[a] = v0[a];
+            v0[a] = vp[a];
+        }
+    }
 }
 
 // Equilibrium sample: every face N(0, sd^2) from Philox block 2 of the cell
@@ -123,74 +205,79 @@ __global__ void k_axpy(T* y, const T* x, long long n) {
 // (faces normal to a), else 1/2 (cell centres).
 __device__ __forceinline__ double comp_offset(int beta, int a) { return beta == a ? 0.0 : 0.5; }
 
-// S: field_a += h^-3 phi(dx) phi(dy) phi(dz) val_a. One thread per
-// (blob, component); atomics resolve overlapping kernels.
+// S: field_a += h^-3 phi(dx) phi(dy) phi(dz) val_a. A group of 16 lanes
+// serves one (blob, component); lane r < P^2 owns the x-row of z-tap r / P and
+// y-tap r mod P and adds its P values atomically (kernels of neighbouring
+// blobs may overlap).
 template <typename T, int P>
 __global__ void __launch_bounds__(kThreads) k_spread(GridDesc<T> g, T* field, int nb, const double* __restrict__ q,
                                                     const double* __restrict__ F, const double* __restrict__ coef,
                                                     int deriv) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = t / 3, a = t - 3 * (t / 3);
-    if (b >= nb) return;
+    const int grp = t >> 4, r = t & 15;
+    const int b = grp / 3, a = grp - 3 * (grp / 3);
+    if (b >= nb || r >= P * P) return;
+    const int cz = r / P, cy = r - P * (r / P);
     const double inv_h = 1.0 / g.h;
-    double val = (F ? F[3 * b + a] : 1.0) * (coef ? coef[b] : 1.0) * inv_h * inv_h * inv_h;
-    AxisStencil<P> sx, sy, sz;
+    const double val = (F ? F[3 * b + a] : 1.0) * (coef ? coef[b] : 1.0) * inv_h * inv_h * inv_h;
+    AxisStencil<P> sx;
     axis_stencil<P>(q[3 * b + 0] * inv_h - comp_offset(0, a), g.nx, deriv && a == 0, inv_h, sx);
-    axis_stencil<P>(q[3 * b + 1] * inv_h - comp_offset(1, a), g.ny, deriv && a == 1, inv_h, sy);
-    axis_stencil<P>(q[3 * b + 2] * inv_h - comp_offset(2, a), g.nz, deriv && a == 2, inv_h, sz);
-    T* f = field + a * g.ncell;
-    for (int c = 0; c < P; ++c) {
-        for (int bb = 0; bb < P; ++bb) {
-            const double wzy = sz.w[c] * sy.w[bb] * val;
-            const long long row = ((long long)sz.node[c] * g.ny + sy.node[bb]) * g.nx;
+    int ny_, nz_;
+    double wy, wz;
+    axis_tap<P>(q[3 * b + 1] * inv_h - comp_offset(1, a), g.ny, cy, deriv && a == 1, inv_h, ny_, wy);
+    axis_tap<P>(q[3 * b + 2] * inv_h - comp_offset(2, a), g.nz, cz, deriv && a == 2, inv_h, nz_, wz);
+    T* f = field + a * g.ncell + ((long long)nz_ * g.ny + ny_) * g.nx;
+    const double wzy = wz * wy * val;
 #pragma unroll
-            for (int aa = 0; aa < P; ++aa) atomicAdd(&f[row + sx.node[aa]], (T)(wzy * sx.w[aa]));
-        }
-    }
+    for (int aa = 0; aa < P; ++aa) atomicAdd(&f[sx.node[aa]], (T)(wzy * sx.w[aa]));
 }
 
-// J: out[b][a] = sum phi(dx) phi(dy) phi(dz) f_a (FP64 accumulation); with
-// lap = 1 the field value at each node is replaced by its 7-point Laplacian.
+// J: out[b][a] = sum phi(dx) phi(dy) phi(dz) f_a (FP64 accumulation), one
+// 16-lane group per (blob, component) reduced with shuffles; with lap = 1 the
+// field value at each node is replaced by its 7-point Laplacian.
 template <typename T, int P>
 __global__ void __launch_bounds__(kThreads) k_gather(GridDesc<T> g, const T* __restrict__ field, int nb,
                                                     const double* __restrict__ q, double* __restrict__ out, int lap) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = t / 3, a = t - 3 * (t / 3);
-    if (b >= nb) return;
-    const double inv_h = 1.0 / g.h;
-    AxisStencil<P> sx, sy, sz;
-    axis_stencil<P>(q[3 * b + 0] * inv_h - comp_offset(0, a), g.nx, false, inv_h, sx);
-    axis_stencil<P>(q[3 * b + 1] * inv_h - comp_offset(1, a), g.ny, false, inv_h, sy);
-    axis_stencil<P>(q[3 * b + 2] * inv_h - comp_offset(2, a), g.nz, false, inv_h, sz);
-    const T* f = field + a * g.ncell;
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int grp = t >> 4, r = t & 15;
+    const int b = grp / 3, a = grp - 3 * (grp / 3);
     double acc = 0.0;
-    for (int c = 0; c < P; ++c) {
-        for (int bb = 0; bb < P; ++bb) {
-            const double wzy = sz.w[c] * sy.w[bb];
-            const int k = sz.node[c], j = sy.node[bb];
-            const long long row = ((long long)k * ny + j) * nx;
+    if (b < nb && r < P * P) {
+        const int cz = r / P, cy = r - P * (r / P);
+        const double inv_h = 1.0 / g.h;
+        AxisStencil<P> sx;
+        axis_stencil<P>(q[3 * b + 0] * inv_h - comp_offset(0, a), g.nx, false, inv_h, sx);
+        int j, k;
+        double wy, wz;
+        axis_tap<P>(q[3 * b + 1] * inv_h - comp_offset(1, a), g.ny, cy, false, inv_h, j, wy);
+        axis_tap<P>(q[3 * b + 2] * inv_h - comp_offset(2, a), g.nz, cz, false, inv_h, k, wz);
+        const T* f = field + a * g.ncell;
+        const int nx = g.nx, ny = g.ny, nz = g.nz;
+        const long long row = ((long long)k * ny + j) * nx;
+        double s = 0.0;
 #pragma unroll
-            for (int aa = 0; aa < P; ++aa) {
-                const int i = sx.node[aa];
-                double val;
-                if (!lap) {
-                    val = (double)f[row + i];
-                } else {
-                    const int ip = i + 1 == nx ? 0 : i + 1, im = i == 0 ? nx - 1 : i - 1;
-                    const int jp = j + 1 == ny ? 0 : j + 1, jm = j == 0 ? ny - 1 : j - 1;
-                    const int kp = k + 1 == nz ? 0 : k + 1, km = k == 0 ? nz - 1 : k - 1;
-                    const double c0 = (double)f[row + i];
-                    val = ((double)f[row + ip] + (double)f[row + im] +
-                           (double)f[((long long)k * ny + jp) * nx + i] + (double)f[((long long)k * ny + jm) * nx + i] +
-                           (double)f[((long long)kp * ny + j) * nx + i] + (double)f[((long long)km * ny + j) * nx + i] -
-                           6.0 * c0) * inv_h * inv_h;
-                }
-                acc += wzy * sx.w[aa] * val;
+        for (int aa = 0; aa < P; ++aa) {
+            const int i = sx.node[aa];
+            double val;
+            if (!lap) {
+                val = (double)f[row + i];
+            } else {
+                const int ip = i + 1 == nx ? 0 : i + 1, im = i == 0 ? nx - 1 : i - 1;
+                const int jp = j + 1 == ny ? 0 : j + 1, jm = j == 0 ? ny - 1 : j - 1;
+                const int kp = k + 1 == nz ? 0 : k + 1, km = k == 0 ? nz - 1 : k - 1;
+                const double c0 = (double)f[row + i];
+                val = ((double)f[row + ip] + (double)f[row + im] + (double)f[((long long)k * ny + jp) * nx + i] +
+                       (double)f[((long long)k * ny + jm) * nx + i] + (double)f[((long long)kp * ny + j) * nx + i] +
+                       (double)f[((long long)km * ny + j) * nx + i] - 6.0 * c0) *
+                      inv_h * inv_h;
             }
+            s += sx.w[aa] * val;
         }
+        acc = wz * wy * s;
     }
-    out[3 * b + a] = acc;
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+    if (b < nb && r == 0) out[3 * b + a] = acc;
 }
 
 __device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
@@ -257,7 +344,9 @@ unsigned grid_for(long long n) {
 
 template <typename T>
 void launch_rhs(const GridDesc<T>& g, const RhsCoef& c, hipStream_t s) {
-    hipLaunchKernelGGL(k_rhs<T>, dim3(grid_for(g.ncell)), dim3(kThreads), 0, s, g, c);
+    const dim3 grid((unsigned)((g.nx + RTX - 1) / RTX), (unsigned)((g.ny + RTY - 1) / RTY),
+                    (unsigned)((g.nz + RZC - 1) / RZC));
+    hipLaunchKernelGGL(k_rhs_march<T>, grid, dim3(RTX * RTY), 0, s, g, c);
 }
 
 template <typename T>
@@ -285,7 +374,7 @@ template <typename T>
 void launch_spread(const GridDesc<T>& g, T* field, int kernel, int nb, const double* q, const double* F,
                    const double* coef, bool deriv, hipStream_t s) {
     if (nb <= 0) return;
-    const dim3 grid(grid_for(3LL * nb));
+    const dim3 grid(grid_for(48LL * nb));
     if (kernel == 3)
         hipLaunchKernelGGL((k_spread<T, 3>), grid, dim3(kThreads), 0, s, g, field, nb, q, F, coef, deriv ? 1 : 0);
     else
@@ -296,7 +385,7 @@ template <typename T>
 void launch_gather(const GridDesc<T>& g, const T* field, int kernel, int nb, const double* q, double* out,
                    bool laplacian, hipStream_t s) {
     if (nb <= 0) return;
-    const dim3 grid(grid_for(3LL * nb));
+    const dim3 grid(grid_for(48LL * nb));
     if (kernel == 3)
         hipLaunchKernelGGL((k_gather<T, 3>), grid, dim3(kThreads), 0, s, g, field, nb, q, out, laplacian ? 1 : 0);
     else

@@ -40,10 +40,12 @@ struct u32x4 {
 __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        // one 32 x 32 -> 64-bit multiply (v_mad_u64_u32) per product gives
+        // both halves at once
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         c = u32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -76,13 +78,13 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& z0,
 }
 
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z0, float& z1) {
+    // FP32 transform of the same words with the hardware log2 and the
+    // hardware sine/cosine, which take their argument in revolutions.
     const float u1 = fmaf((float)wa, 2.3283064365386963e-10f, 2.3283064365386963e-10f);
     const float u2 = (float)wb * 2.3283064365386963e-10f;
-    const float r = sqrtf(-2.0f * logf(u1));
-    float s, c;
-    sincospif(2.0f * u2, &s, &c);
-    z0 = r * c;
-    z1 = r * s;
+    const float r = sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));  // -2 ln u1
+    z0 = r * __builtin_amdgcn_cosf(u2);
+    z1 = r * __builtin_amdgcn_sinf(u2);
 }
 
 // ---------------------------------------------------------- Peskin kernels
@@ -151,6 +153,22 @@ __device__ __forceinline__ void axis_stencil(double x, int n, bool deriv, double
         else
             st.w[a] = deriv ? dphi4(d) * inv_h : phi4(d);
     }
+}
+
+// Node and weight of tap a (0 <= a < P) of one axis, without arrays (so a
+// runtime tap index stays in registers).
+template <int P>
+__device__ __forceinline__ void axis_tap(double x, int n, int a, bool deriv, double inv_h, int& node, double& w) {
+    const double m0 = (P == 3) ? floor(x + 0.5) : floor(x);
+    const long long nd = (long long)m0 - 1 + a;
+    const double d = x - (double)nd;
+    long long wn = nd % n;
+    if (wn < 0) wn += n;
+    node = (int)wn;
+    if (P == 3)
+        w = deriv ? dphi3(d) * inv_h : phi3(d);
+    else
+        w = deriv ? dphi4(d) * inv_h : phi4(d);
 }
 
 __host__ __device__ __forceinline__ int wrap(int i, int n) {

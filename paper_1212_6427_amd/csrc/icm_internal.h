@@ -21,12 +21,15 @@ struct FFTPlan {
 
 // Field buffers of one replica. Real face fields hold 3 components of
 // ncell values (x fastest); the spectrum holds 3 components of
-// nz * ny * W complex values with W = nx/2 + 1 (kx fastest).
+// nz * ny rows of W = nx/2 + 1 complex values (kx fastest) at row pitch Wp.
 template <typename T>
 struct GridDesc {
     int nx, ny, nz, W;
+    int Wp;            // spectrum row pitch (>= W, a multiple of 128 bytes)
+    int fast;          // 1: register-resident FFT passes (all three N supported)
+    int By, Bz;        // kx columns per block of the fast y and z passes
     long long ncell;   // nx * ny * nz
-    long long nspec;   // nz * ny * W
+    long long nspec;   // nz * ny * Wp
     double h;
     T* v;              // fluid velocity v^n / v^{n+1}
     T* rhs;            // right-hand side / spread scratch field
@@ -62,17 +65,32 @@ struct RhsCoef {
 };
 
 // ------------------------------------------------------------------- FFT
+// The x and y passes work on one component c (0..2) per launch, or on all
+// three with c = -1.
 template <typename T>
-void launch_fft_x_forward(const GridDesc<T>& g, const T* in, hipStream_t s);
+void launch_fft_x_forward(const GridDesc<T>& g, const T* in, hipStream_t s, int c = -1);
 template <typename T>
-void launch_fft_y(const GridDesc<T>& g, int dir, hipStream_t s);
+void launch_fft_y(const GridDesc<T>& g, int dir, hipStream_t s, int c = -1);
 template <typename T>
 void launch_fft_z_solve(const GridDesc<T>& g, SolveCoef sc, bool project, hipStream_t s);
 template <typename T>
-void launch_fft_x_inverse(const GridDesc<T>& g, T* out, bool accumulate, hipStream_t s);
+void launch_fft_x_inverse(const GridDesc<T>& g, T* out, bool accumulate, hipStream_t s, int c = -1);
 template <typename T>
 void launch_fft_forward_solve_inverse(const GridDesc<T>& g, const T* in, T* out, bool accumulate,
                                       SolveCoef sc, bool project, hipStream_t s);
+
+// Register-resident passes for N in {16, 32, 48, 64, 128, 256, 512};
+// return false (launching nothing) for other sizes.
+template <typename T>
+bool fast_fft_available(int nx, int ny, int nz);
+template <typename T>
+bool fast_fft_y(const GridDesc<T>& g, int dir, int c, hipStream_t s);
+template <typename T>
+bool fast_fft_z_solve(const GridDesc<T>& g, SolveCoef sc, bool project, hipStream_t s);
+template <typename T>
+bool fast_fft_x_forward(const GridDesc<T>& g, const T* in, int c, hipStream_t s);
+template <typename T>
+bool fast_fft_x_inverse(const GridDesc<T>& g, T* out, bool accumulate, int c, hipStream_t s);
 
 // ------------------------------------------------------------ grid kernels
 template <typename T>
@@ -112,7 +130,7 @@ struct BlobParams {
 
 struct BlobBufs {
     double *q, *u, *me, *fconst, *lag;     // state
-    double *qh, *F, *Jn, *Jhvn, *Jhvt, *du, *dp, *dp2, *g, *Jhvnew;  // per step
+    double *qh, *qw, *F, *Jn, *Jhvn, *Jhvt, *du, *dp, *dp2, *g, *Jhvnew;  // per step
     double *c5, *cdrift;                   // per-blob coefficients
     unsigned int* flag;                    // numeric error flag
 };
