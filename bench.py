@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 256 MiB device-to-device tensor copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -144,6 +146,13 @@ def main():
 
     wl = icm_inputs.WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 256 MiB read + 256 MiB written")
+        del src, dst
     stream = torch.cuda.current_stream()
     n = tuple(wl["n"])
     ncell = int(np.prod(n))

@@ -179,8 +179,14 @@ void carve_grid(Carver& cv, const icm_replica_params& p, icm::GridDesc<T>& g) {
     g.lz = cv.take<T>(g.nz);
 }
 
-void carve_blobs(Carver& cv, int max_nb, icm::BlobBufs& b, double*& diag) {
+void carve_blobs(Carver& cv, int max_nb, int nz, icm::BlobBufs& b, double*& diag) {
     const size_t n3 = 3 * (size_t)max_nb;
+    const int nchunks = (nz + icm::kRhsZChunk - 1) / icm::kRhsZChunk;
+    b.stc = cv.take<double>((size_t)max_nb * 3 * icm::kStcPerComp);
+    b.chunk_count = cv.take<int>(nchunks + 1);
+    b.chunk_list = cv.take<int>((size_t)nchunks * max_nb);
+    b.ovf_cap = 4 * std::max(max_nb, 1);
+    b.ovf_list = cv.take<int>(2 * (size_t)b.ovf_cap);
     b.q = cv.take<double>(n3);
     b.u = cv.take<double>(n3);
     b.fconst = cv.take<double>(n3);
@@ -213,7 +219,7 @@ size_t layout(int32_t n_rep, const icm_replica_params* p, const int32_t* max_blo
             carve_grid(cv, p[r], R.gd);
         else
             carve_grid(cv, p[r], R.gf);
-        carve_blobs(cv, max_blobs[r], R.bb, R.diag);
+        carve_blobs(cv, max_blobs[r], p[r].n[2], R.bb, R.diag);
     }
     return (cv.off + 255) & ~size_t(255);
 }
@@ -368,10 +374,22 @@ void enqueue_step(icm_ctx* c, Replica& R, hipStream_t s) {
     rc.noise = R.p.kT > 0 ? std::sqrt(R.p.kT * R.p.eta / (R.p.h * R.p.h * R.p.h * R.p.dt)) / R.p.h : 0.0;
     for (int a = 0; a < 3; ++a) rc.body[a] = R.p.body_force[a];
     rc.key = noise_key(R, R.step);
-    timed(c, ICM_PHASE_RHS, s, [&] { icm::launch_rhs(g, rc, s); });
-    timed(c, ICM_PHASE_SPREAD, s, [&] { icm::launch_spread(g, g.rhs, P, nb, b.qh, b.F, nullptr, false, s); });
-    if (R.p.kT > 0 && R.p.thermal_drift)
-        timed(c, ICM_PHASE_SPREAD, s, [&] { icm::launch_spread(g, g.rhs, P, nb, b.qh, nullptr, b.cdrift, true, s); });
+    // S F and the thermal drift are spread inside the right-hand-side kernel.
+    icm::RhsBlobs rb;
+    rb.nb = nb;
+    rb.kernel = P;
+    rb.cap = R.max_nb;
+    rb.stc = b.stc;
+    rb.F = b.F;
+    rb.cdrift = (R.p.kT > 0 && R.p.thermal_drift) ? b.cdrift : nullptr;
+    rb.chunk_count = b.chunk_count;
+    rb.chunk_list = b.chunk_list;
+    rb.ovf_count = b.chunk_count + (g.nz + icm::kRhsZChunk - 1) / icm::kRhsZChunk;
+    rb.ovf_list = b.ovf_list;
+    rb.ovf_cap = b.ovf_cap;
+    timed(c, ICM_PHASE_SPREAD, s, [&] { icm::launch_rhs_bins(g, b.qh, rb, b.chunk_count, b.chunk_list, b.stc, s); });
+    timed(c, ICM_PHASE_RHS, s, [&] { icm::launch_rhs(g, rc, rb, s); });
+    timed(c, ICM_PHASE_SPREAD, s, [&] { icm::launch_spread_overflow(g, rb, s); });
     enqueue_fft_solve(c, g, g.rhs, g.v, false, icm::SolveCoef{R.p.rho / R.p.dt, 0.5 * R.p.eta, inv_n}, s);
     if (R.any_me) {
         // Step 4: slip correction and excess-momentum change.

@@ -22,6 +22,117 @@ __device__ __forceinline__ NormalPair<T> bm(uint32_t wa, uint32_t wb) {
     return r;
 }
 
+// Per-blob stencils for the spread inside the RHS kernel (see RhsBlobs) and
+// z-chunk binning. One thread per blob.
+template <int P>
+__global__ void __launch_bounds__(kThreads) k_rhs_bins(int nb, int nx, int ny, int nz, double h,
+                                                       const double* __restrict__ qh, int cap,
+                                                       int* __restrict__ chunk_count, int* __restrict__ chunk_list,
+                                                       double* __restrict__ stc) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const double inv_h = 1.0 / h;
+    const int n[3] = {nx, ny, nz};
+    int zlo = 1 << 30, zhi = -(1 << 30);
+    for (int a = 0; a < 3; ++a) {
+        double* o = stc + ((long long)b * 3 + a) * kStcPerComp;
+        for (int ax = 0; ax < 3; ++ax) {
+            const double x = qh[3 * b + ax] * inv_h - (ax == a ? 0.0 : 0.5);
+            const double m0 = (P == 3) ? floor(x + 0.5) : floor(x);
+            const long long base = (long long)m0 - 1;
+            long long wb = base % n[ax];
+            if (wb < 0) wb += n[ax];
+            o[ax] = (double)wb;
+            for (int t = 0; t < 4; ++t) {
+                const double d = x - (double)(base + t);
+                o[3 + 4 * ax + t] = (t < P) ? ((P == 3) ? phi3(d) : phi4(d)) : 0.0;
+                if (ax == a) o[15 + t] = (t < P) ? ((P == 3) ? dphi3(d) : dphi4(d)) * inv_h : 0.0;
+            }
+            if (ax == 2) {
+                zlo = min(zlo, (int)base);
+                zhi = max(zhi, (int)base + P - 1);
+            }
+        }
+    }
+    // chunks met by planes zlo..zhi (unwrapped, fewer than kRhsZChunk)
+    const int nchunks = (nz + kRhsZChunk - 1) / kRhsZChunk;
+    const int c0 = (int)(((zlo % nz) + nz) % nz) / kRhsZChunk;
+    const int c1 = (int)(((zhi % nz) + nz) % nz) / kRhsZChunk;
+    int slot = atomicAdd(&chunk_count[c0], 1);
+    if (slot < cap) chunk_list[(long long)c0 * cap + slot] = b;
+    if (c1 != c0 && nchunks > 1) {
+        slot = atomicAdd(&chunk_count[c1], 1);
+        if (slot < cap) chunk_list[(long long)c1 * cap + slot] = b;
+    }
+}
+
+__global__ void k_clear_ints(int* p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// Does blob b's a-component stencil touch cells [i0, i0 + wx) x [j0, j0 + wy)?
+__device__ __forceinline__ bool stencil_meets_tile(const double* o, int P, int nx, int ny, int i0, int wx, int j0,
+                                                   int wy) {
+    const int bx = (int)o[0], by = (int)o[1];
+    bool inx = false, iny = false;
+    for (int t = 0; t < P; ++t) {
+        const int x = bx + t >= nx ? bx + t - nx : bx + t;
+        const int y = by + t >= ny ? by + t - ny : by + t;
+        inx = inx || (x >= i0 && x < i0 + wx);
+        iny = iny || (y >= j0 && y < j0 + wy);
+    }
+    return inx && iny;
+}
+
+// Value spread to one tap (ia, ib, ic) of component a of blob b:
+// (F_a prod w + c_drift prod w') / h^3, w' = phi'/h along axis a.
+template <typename T>
+__device__ __forceinline__ double tap_value(const RhsBlobs& rb, const double* o, int b, int a, int ia, int ib,
+                                            int ic, double inv_h3) {
+    const double wx = o[3 + ia], wy = o[7 + ib], wz = o[11 + ic];
+    double v = rb.F[3 * b + a] * wx * wy * wz;
+    if (rb.cdrift) {
+        const double dx = a == 0 ? o[15 + ia] : wx;
+        const double dy = a == 1 ? o[15 + ib] : wy;
+        const double dz = a == 2 ? o[15 + ic] : wz;
+        v += rb.cdrift[b] * dx * dy * dz;
+    }
+    return v * inv_h3;
+}
+
+// Spread of the (blob, tile) pairs a tile could not hold, restricted to the
+// tile's cells, with atomics. One 16-lane group per (pair, component).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_spread_overflow(GridDesc<T> g, RhsBlobs rb, int tiles_x,
+                                                             int tiles_y, int rtx, int rty) {
+    const int npairs = min(*rb.ovf_count, rb.ovf_cap);
+    const int P = rb.kernel;
+    const double inv_h = 1.0 / g.h;
+    const double inv_h3 = inv_h * inv_h * inv_h;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < npairs * 48; t += gridDim.x * blockDim.x) {
+        const int grp = t >> 4, r = t & 15;
+        const int pr = grp / 3, a = grp - 3 * (grp / 3);
+        if (r >= P * P) continue;
+        const int b = rb.ovf_list[2 * pr], tile = rb.ovf_list[2 * pr + 1];
+        const int txi = tile % tiles_x, tyi = (tile / tiles_x) % tiles_y, tzi = tile / (tiles_x * tiles_y);
+        const int i0 = txi * rtx, j0 = tyi * rty, k0 = tzi * kRhsZChunk;
+        const double* o = rb.stc + ((long long)b * 3 + a) * kStcPerComp;
+        const int ib = r / P, ic_unused = 0;
+        (void)ic_unused;
+        const int y = ((int)o[1] + ib) % g.ny;
+        if (y < j0 || y >= j0 + rty) continue;
+        for (int ic = 0; ic < P; ++ic) {
+            const int z = ((int)o[2] + ic) % g.nz;
+            if (z < k0 || z >= k0 + kRhsZChunk) continue;
+            const int ia = r % P;
+            const int x = ((int)o[0] + ia) % g.nx;
+            if (x < i0 || x >= i0 + rtx) continue;
+            const double v = tap_value<T>(rb, o, b, a, ia, ib, ic, inv_h3);
+            atomicAdd(&g.rhs[a * g.ncell + ((long long)z * g.ny + y) * g.nx + x], (T)v);
+        }
+    }
+}
+
 // Right-hand side of the unperturbed solve (Eq. (provisional_step-1)):
 //   rhs_a = (rho/dt) v_a + (eta/2) (L v)_a + s (D_w Sigma-hat)_a + f_body,a
 // with Sigma-hat = W + W^T realised as 2 W_aa at cell centres and
@@ -34,10 +145,13 @@ __device__ __forceinline__ NormalPair<T> bm(uint32_t wa, uint32_t wb) {
 // W_zz of plane k-1 is carried in a register, and the in-plane neighbours'
 // stresses and velocities are shared through LDS. Only the tile's one-cell
 // halo ring regenerates the few normals it needs.
-constexpr int RTX = 32, RTY = 16, RZC = 16;
+constexpr int RTX = 32, RTY = 16, RZC = kRhsZChunk;
 
 template <typename T>
-__global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef c) {
+__global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef c, RhsBlobs rb) {
+    __shared__ int s_blobs[kRhsTileCap];   // blobs of this z-chunk meeting the tile
+    __shared__ int s_nblobs;
+    __shared__ T s_acc[3][RTY][RTX];       // spread accumulated for the current plane
     __shared__ T sv[3][RTY + 2][RTX + 2];  // velocity of plane k with halo
     __shared__ T sxx[RTY][RTX + 1];        // W_xx, column 0 = i0 - 1
     __shared__ T sxy[RTY + 1][RTX + 1];    // W_xy, row RTY = j0 + TY, column RTX = i0 + TX
@@ -46,8 +160,16 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef 
     __shared__ T syz[RTY + 1][RTX];        // W_yz, row RTY = j0 + TY
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int tx = threadIdx.x % RTX, ty = threadIdx.x / RTX;
-    const int i0 = blockIdx.x * RTX, j0 = blockIdx.y * RTY;
-    const int k0 = blockIdx.z * RZC;
+    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs,
+    // so give XCD j a contiguous run of tiles (x fastest, then y, then z):
+    // neighbouring tiles then share their halo lines in that XCD's L2.
+    const int ntx = gridDim.x, nty = gridDim.y;
+    const int ntiles = ntx * nty * gridDim.z;
+    int tile = blockIdx.x + ntx * (blockIdx.y + nty * blockIdx.z);
+    if (ntiles % 8 == 0) tile = (tile % 8) * (ntiles / 8) + tile / 8;
+    const int tile_x = tile % ntx, tile_y = (tile / ntx) % nty, tile_z = tile / (ntx * nty);
+    const int i0 = tile_x * RTX, j0 = tile_y * RTY;
+    const int k0 = tile_z * RZC;
     const int k1 = min(k0 + RZC, nz);
     const int i = i0 + tx, j = j0 + ty;
     const bool own = (i < nx) && (j < ny);
@@ -88,9 +210,102 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef 
             wyz_c = q.b;
         }
     }
+    // blobs of this z-chunk whose stencil meets the tile
+    if (tid == 0) s_nblobs = 0;
+    for (int a = 0; a < 3; ++a) s_acc[a][ty][tx] = (T)0;
+    __syncthreads();
+    const int P = rb.kernel;
+    if (rb.nb > 0) {
+        const int chunk = tile_z;
+        const int cnt = min(rb.chunk_count[chunk], rb.cap);
+        const int tile_id = (tile_z * nty + tile_y) * ntx + tile_x;
+        for (int s = tid; s < cnt; s += blockDim.x) {
+            const int b = rb.chunk_list[(long long)chunk * rb.cap + s];
+            bool meets = false;
+            for (int a = 0; a < 3; ++a)
+                meets = meets || stencil_meets_tile(rb.stc + ((long long)b * 3 + a) * kStcPerComp, P, nx, ny, i0,
+                                                    wx, j0, wy);
+            if (meets) {
+                const int slot = atomicAdd(&s_nblobs, 1);
+                if (slot < kRhsTileCap) {
+                    s_blobs[slot] = b;
+                } else {
+                    const int os = atomicAdd(rb.ovf_count, 1);
+                    if (os < rb.ovf_cap) {
+                        rb.ovf_list[2 * os] = b;
+                        rb.ovf_list[2 * os + 1] = tile_id;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int nloc = min(s_nblobs, kRhsTileCap);
+    const double inv_h3 = 1.0 / (g.h * g.h * g.h);
+    // This thread's first spread item (local blob, component, x-y tap) is
+    // plane independent apart from its z weight: keep it in registers.
+    bool it_ok = false;
+    int it_a = 0, it_x = 0, it_y = 0, it_z0 = 0;
+    double it_f = 0, it_d = 0, wz0 = 0, wz1 = 0, wz2 = 0, wz3 = 0, dz0 = 0, dz1 = 0, dz2 = 0, dz3 = 0;
+    if (tid < nloc * 48) {
+        const int lb = tid / 48, rem = tid - 48 * lb;
+        const int a = rem >> 4, r = rem & 15;
+        if (r < P * P) {
+            const int b = s_blobs[lb];
+            const double* o = rb.stc + ((long long)b * 3 + a) * kStcPerComp;
+            const int ia = r % P, ib = r / P;
+            int x = (int)o[0] + ia, y = (int)o[1] + ib;
+            if (x >= nx) x -= nx;
+            if (y >= ny) y -= ny;
+            if (x >= i0 && x < i0 + wx && y >= j0 && y < j0 + wy) {
+                it_ok = true;
+                it_a = a;
+                it_x = x - i0;
+                it_y = y - j0;
+                it_z0 = (int)o[2];
+                const double wxv = o[3 + ia], wyv = o[7 + ib];
+                it_f = rb.F[3 * b + a] * wxv * wyv * inv_h3;
+                wz0 = o[11]; wz1 = o[12]; wz2 = o[13]; wz3 = o[14];
+                if (rb.cdrift) {
+                    const double cx = a == 0 ? o[15 + ia] : wxv, cy = a == 1 ? o[15 + ib] : wyv;
+                    it_d = rb.cdrift[b] * cx * cy * inv_h3;
+                    if (a == 2) { dz0 = o[15]; dz1 = o[16]; dz2 = o[17]; dz3 = o[18]; }
+                    else { dz0 = wz0; dz1 = wz1; dz2 = wz2; dz3 = wz3; }
+                }
+            }
+        }
+    }
+
     for (int k = k0; k < k1; ++k) {
         const int kp = k + 1 == nz ? 0 : k + 1;
         T wxx = 0, wyy = 0, wzz = 0, wxy = 0, wxz_n = 0, wyz_n = 0;
+        if (it_ok) {
+            int ic = k - it_z0;
+            if (ic < 0) ic += nz;
+            if (ic < P) {
+                const double wz = ic == 0 ? wz0 : (ic == 1 ? wz1 : (ic == 2 ? wz2 : wz3));
+                const double dz = ic == 0 ? dz0 : (ic == 1 ? dz1 : (ic == 2 ? dz2 : dz3));
+                atomicAdd(&s_acc[it_a][it_y][it_x], (T)(it_f * wz + it_d * dz));
+            }
+        }
+        // further items (tiles met by more than 10 blobs) read their data here
+        for (int it = tid + blockDim.x; it < nloc * 3 * 16; it += blockDim.x) {
+            const int lb = it / 48, rem = it - 48 * lb;
+            const int a = rem >> 4, r = rem & 15;
+            if (r >= P * P) continue;
+            const int b = s_blobs[lb];
+            const double* o = rb.stc + ((long long)b * 3 + a) * kStcPerComp;
+            int ic = k - (int)o[2];
+            if (ic < 0) ic += nz;
+            if (ic >= P) continue;
+            const int ia = r % P, ib = r / P;
+            int x = (int)o[0] + ia, y = (int)o[1] + ib;
+            if (x >= nx) x -= nx;
+            if (y >= ny) y -= ny;
+            if (x < i0 || x >= i0 + wx || y < j0 || y >= j0 + wy) continue;
+            const double v = tap_value<T>(rb, o, b, a, ia, ib, ic, inv_h3);
+            atomicAdd(&s_acc[a][y - j0][x - i0], (T)v);
+        }
         if (own) {
             for (int a = 0; a < 3; ++a) vp[a] = g.v[a * g.ncell + (long long)kp * plane + col];
             if (noisy) {
@@ -158,7 +373,11 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef 
             }
             const long long cell = (long long)k * plane + col;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) g.rhs[a * g.ncell + cell] = out[a];
+            for (int a = 0; a < 3; ++a) {
+                out[a] += s_acc[a][ty][tx];
+                s_acc[a][ty][tx] = (T)0;
+                g.rhs[a * g.ncell + cell] = out[a];
+            }
         }
         __syncthreads();
         wzz_m = wzz;
@@ -343,10 +562,32 @@ unsigned grid_for(long long n) {
 }  // namespace
 
 template <typename T>
-void launch_rhs(const GridDesc<T>& g, const RhsCoef& c, hipStream_t s) {
+void launch_rhs(const GridDesc<T>& g, const RhsCoef& c, const RhsBlobs& rb, hipStream_t s) {
     const dim3 grid((unsigned)((g.nx + RTX - 1) / RTX), (unsigned)((g.ny + RTY - 1) / RTY),
                     (unsigned)((g.nz + RZC - 1) / RZC));
-    hipLaunchKernelGGL(k_rhs_march<T>, grid, dim3(RTX * RTY), 0, s, g, c);
+    hipLaunchKernelGGL(k_rhs_march<T>, grid, dim3(RTX * RTY), 0, s, g, c, rb);
+}
+
+template <typename T>
+void launch_rhs_bins(const GridDesc<T>& g, const double* qh, RhsBlobs rb, int* chunk_count, int* chunk_list,
+                     double* stc, hipStream_t s) {
+    const int nchunks = (g.nz + kRhsZChunk - 1) / kRhsZChunk;
+    hipLaunchKernelGGL(k_clear_ints, dim3(1), dim3(kThreads), 0, s, chunk_count, nchunks + 1);
+    if (rb.nb <= 0) return;
+    const dim3 grid((unsigned)((rb.nb + kThreads - 1) / kThreads));
+    if (rb.kernel == 3)
+        hipLaunchKernelGGL(k_rhs_bins<3>, grid, dim3(kThreads), 0, s, rb.nb, g.nx, g.ny, g.nz, g.h, qh, rb.cap,
+                           chunk_count, chunk_list, stc);
+    else
+        hipLaunchKernelGGL(k_rhs_bins<4>, grid, dim3(kThreads), 0, s, rb.nb, g.nx, g.ny, g.nz, g.h, qh, rb.cap,
+                           chunk_count, chunk_list, stc);
+}
+
+template <typename T>
+void launch_spread_overflow(const GridDesc<T>& g, const RhsBlobs& rb, hipStream_t s) {
+    if (rb.nb <= 0) return;
+    const int tiles_x = (g.nx + RTX - 1) / RTX, tiles_y = (g.ny + RTY - 1) / RTY;
+    hipLaunchKernelGGL(k_spread_overflow<T>, dim3(64), dim3(kThreads), 0, s, g, rb, tiles_x, tiles_y, RTX, RTY);
 }
 
 template <typename T>
@@ -400,7 +641,10 @@ void launch_field_diag(const GridDesc<T>& g, double rho, double* acc, hipStream_
 }
 
 #define ICM_INST(T)                                                                                        \
-    template void launch_rhs<T>(const GridDesc<T>&, const RhsCoef&, hipStream_t);                         \
+    template void launch_rhs<T>(const GridDesc<T>&, const RhsCoef&, const RhsBlobs&, hipStream_t);        \
+    template void launch_rhs_bins<T>(const GridDesc<T>&, const double*, RhsBlobs, int*, int*, double*,    \
+                                     hipStream_t);                                                        \
+    template void launch_spread_overflow<T>(const GridDesc<T>&, const RhsBlobs&, hipStream_t);           \
     template void launch_equilibrium_noise<T>(const GridDesc<T>&, double, NoiseKey, hipStream_t);         \
     template void launch_zero<T>(T*, long long, hipStream_t);                                              \
     template void launch_axpy<T>(T*, const T*, long long, hipStream_t);                                    \

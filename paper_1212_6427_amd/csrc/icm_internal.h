@@ -64,6 +64,31 @@ struct RhsCoef {
     NoiseKey key;
 };
 
+// Blobs spread inside the right-hand-side kernel. stc holds, per blob and
+// component a, the wrapped base nodes (as doubles) of the P-tap stencil on
+// the a-component grid, the P weights of each axis, and the P derivative
+// weights phi'(d)/h along axis a (kStcPerComp values per component).
+// Blobs are binned by z-chunk of kRhsZChunk planes: chunk_count[c] blobs of
+// chunk c are listed at chunk_list[c * cap]. A tile that meets more than
+// kRhsTileCap blobs appends the excess (blob, tile) pairs to the overflow
+// list, which launch_spread_overflow spreads with atomics.
+constexpr int kRhsZChunk = 16;
+constexpr int kRhsTileCap = 128;
+constexpr int kStcPerComp = 3 + 4 * 4;
+struct RhsBlobs {
+    int nb;
+    int kernel;
+    int cap;                 // list capacity per chunk (>= nb)
+    const double* stc;       // nb * 3 * kStcPerComp
+    const double* F;         // nb * 3 forces (spread with S)
+    const double* cdrift;    // nb drift coefficients kT m~_f / m~ (NULL = no drift)
+    const int* chunk_count;  // n_chunks
+    const int* chunk_list;   // n_chunks * cap
+    int* ovf_count;          // 1
+    int* ovf_list;           // 2 * ovf_cap ints (blob, tile)
+    int ovf_cap;
+};
+
 // ------------------------------------------------------------------- FFT
 // The x and y passes work on one component c (0..2) per launch, or on all
 // three with c = -1.
@@ -94,7 +119,13 @@ bool fast_fft_x_inverse(const GridDesc<T>& g, T* out, bool accumulate, int c, hi
 
 // ------------------------------------------------------------ grid kernels
 template <typename T>
-void launch_rhs(const GridDesc<T>& g, const RhsCoef& c, hipStream_t s);
+void launch_rhs(const GridDesc<T>& g, const RhsCoef& c, const RhsBlobs& rb, hipStream_t s);
+// blob stencils and z-chunk bins for the right-hand-side spread
+template <typename T>
+void launch_rhs_bins(const GridDesc<T>& g, const double* qh, RhsBlobs rb, int* chunk_count, int* chunk_list,
+                     double* stc, hipStream_t s);
+template <typename T>
+void launch_spread_overflow(const GridDesc<T>& g, const RhsBlobs& rb, hipStream_t s);
 template <typename T>
 void launch_equilibrium_noise(const GridDesc<T>& g, double sd, NoiseKey key, hipStream_t s);
 template <typename T>
@@ -133,6 +164,12 @@ struct BlobBufs {
     double *qh, *qw, *F, *Jn, *Jhvn, *Jhvt, *du, *dp, *dp2, *g, *Jhvnew;  // per step
     double *c5, *cdrift;                   // per-blob coefficients
     unsigned int* flag;                    // numeric error flag
+    // spread inside the right-hand-side kernel
+    double* stc;                           // max_nb * 3 * kStcPerComp
+    int* chunk_count;                      // n_chunks + 1 (the last is the overflow count)
+    int* chunk_list;                       // n_chunks * max_nb
+    int* ovf_list;                         // 2 * ovf_cap
+    int ovf_cap;
 };
 
 void launch_predict(const BlobParams& bp, const BlobBufs& b, hipStream_t s);
