@@ -25,6 +25,8 @@ thread_local std::string g_last_error = "no error";
 
 struct Replica {
     icm_replica_params p;
+    icm::CellGrid cells{};     // pair-force cell list (heads == NULL: all pairs)
+    unsigned int cell_stamp = 0;
     int max_nb = 0;
     int nb = 0;
     int64_t step = 0;
@@ -209,6 +211,31 @@ void carve_blobs(Carver& cv, int max_nb, int nz, icm::BlobBufs& b, double*& diag
     diag = cv.take<double>(16);
 }
 
+// Cell list for the WCA pairs: cells at least one cutoff wide, at most 2^21
+// of them, and at least 3 per axis (else the all-pairs kernel is used).
+void carve_cells(Carver& cv, const icm_replica_params& p, int max_nb, icm::CellGrid& cg) {
+    cg.heads = nullptr;
+    cg.next = nullptr;
+    if (!(p.wca_eps > 0) || max_nb < 2) return;
+    const double rc = std::pow(2.0, 1.0 / 6.0) * p.wca_sigma;
+    long long total = 1;
+    for (int a = 0; a < 3; ++a) {
+        const double L = p.n[a] * p.h;
+        cg.n[a] = std::max(1, (int)std::floor(L / rc));
+    }
+    while ((long long)cg.n[0] * cg.n[1] * cg.n[2] > (1LL << 21)) {
+        for (int a = 0; a < 3; ++a) cg.n[a] = std::max(1, cg.n[a] / 2);
+    }
+    if (cg.n[0] < 3 || cg.n[1] < 3 || cg.n[2] < 3) return;
+    for (int a = 0; a < 3; ++a) {
+        cg.inv_size[a] = cg.n[a] / (p.n[a] * p.h);
+        total *= cg.n[a];
+    }
+    cg.heads = cv.take<unsigned long long>((size_t)total);
+    cg.next = cv.take<int>((size_t)max_nb);
+    if (!cv.base) cg.heads = reinterpret_cast<unsigned long long*>(1);  // sizing pass: mark as used
+}
+
 size_t layout(int32_t n_rep, const icm_replica_params* p, const int32_t* max_blobs, int32_t precision, void* base,
               std::vector<Replica>* reps) {
     Carver cv(base);
@@ -220,6 +247,7 @@ size_t layout(int32_t n_rep, const icm_replica_params* p, const int32_t* max_blo
         else
             carve_grid(cv, p[r], R.gf);
         carve_blobs(cv, max_blobs[r], p[r].n[2], R.bb, R.diag);
+        carve_cells(cv, p[r], max_blobs[r], R.cells);
     }
     return (cv.off + 255) & ~size_t(255);
 }
@@ -363,10 +391,14 @@ void enqueue_step(icm_ctx* c, Replica& R, hipStream_t s) {
     const int P = R.p.kernel, nb = R.nb;
     const double inv_n = 1.0 / (double)g.ncell;
     // Step 1: midpoint predictor, forces, and J^{n+1/2} v^n for step 9.
-    timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather(g, g.v, P, nb, b.q, b.Jn, false, s); });
-    timed(c, ICM_PHASE_BLOB, s, [&] { icm::launch_predict(bp, b, s); });
-    timed(c, ICM_PHASE_FORCES, s, [&] { icm::launch_forces(bp, b, s); });
-    timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather(g, g.v, P, nb, b.qh, b.Jhvn, false, s); });
+    timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather_predict(g, P, bp, b, s); });
+    if (++R.cell_stamp == 0) R.cell_stamp = 1;  // stamp 0 marks never-written heads
+    timed(c, ICM_PHASE_FORCES, s, [&] { icm::launch_forces(bp, b, R.cells, R.cell_stamp, s); });
+    // J^{n+1/2} v^n (step 9), and the stencils and z-chunk bins of the spread
+    timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather_bins(g, P, bp, b, R.max_nb, s); });
+    timed(c, ICM_PHASE_SPREAD, s, [&] {
+        icm::launch_bins(P, nb, g.nz, g.h, b.qh, R.max_nb, b.chunk_count, b.chunk_list, s);
+    });
     // Step 2: unperturbed fluid solve.
     icm::RhsCoef rc;
     rc.rho_dt = R.p.rho / R.p.dt;
@@ -387,7 +419,6 @@ void enqueue_step(icm_ctx* c, Replica& R, hipStream_t s) {
     rb.ovf_count = b.chunk_count + (g.nz + icm::kRhsZChunk - 1) / icm::kRhsZChunk;
     rb.ovf_list = b.ovf_list;
     rb.ovf_cap = b.ovf_cap;
-    timed(c, ICM_PHASE_SPREAD, s, [&] { icm::launch_rhs_bins(g, b.qh, rb, b.chunk_count, b.chunk_list, b.stc, s); });
     timed(c, ICM_PHASE_RHS, s, [&] { icm::launch_rhs(g, rc, rb, s); });
     timed(c, ICM_PHASE_SPREAD, s, [&] { icm::launch_spread_overflow(g, rb, s); });
     enqueue_fft_solve(c, g, g.rhs, g.v, false, icm::SolveCoef{R.p.rho / R.p.dt, 0.5 * R.p.eta, inv_n}, s);
@@ -411,8 +442,8 @@ void enqueue_step(icm_ctx* c, Replica& R, hipStream_t s) {
         timed(c, ICM_PHASE_BLOB, s, [&] { icm::launch_inertial_u(bp, b, s); });
     }
     // Step 9.
-    timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather(g, g.v, P, nb, b.qh, b.Jhvnew, false, s); });
-    timed(c, ICM_PHASE_BLOB, s, [&] { icm::launch_final(bp, b, R.p.h, s); });
+    const int n_clear = (g.nz + icm::kRhsZChunk - 1) / icm::kRhsZChunk + 1;
+    timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather_final(g, P, bp, b, n_clear, s); });
     R.step += 1;
 }
 
@@ -505,6 +536,13 @@ icm_status icm_create(int32_t n_rep, const icm_replica_params* p, const int32_t*
         const size_t fb = field_bytes(c, R);
         hipError_t e = hipMemsetAsync(field_ptr(c, R), 0, fb, c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(R.bb.flag, 0, sizeof(unsigned int), c->stream);
+        if (e == hipSuccess && R.cells.heads)
+            e = hipMemsetAsync(R.cells.heads, 0,
+                               sizeof(unsigned long long) * (size_t)R.cells.n[0] * R.cells.n[1] * R.cells.n[2],
+                               c->stream);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(R.bb.chunk_count, 0,
+                               sizeof(int) * ((p[r].n[2] + icm::kRhsZChunk - 1) / icm::kRhsZChunk + 1), c->stream);
         if (e != hipSuccess) {
             g_last_error = std::string("hipMemsetAsync failed: ") + hipGetErrorString(e);
             icm_destroy(c);

@@ -1,7 +1,8 @@
-// Per-blob FP64 kernels of the ICM step (Sec. III.C): midpoint predictor
-// (step 1), forces, slip correction and excess-momentum change (step 4), the
-// inertial right-hand side of step 6, the momentum-conserving blob velocity
-// update (step 8, Eq. (update_u)) and the position update (step 9).
+// Per-blob FP64 kernels of the ICM step (Sec. III.C): forces at the
+// midpoint, slip correction and excess-momentum change (step 4), the inertial
+// right-hand side of step 6 and the momentum-conserving blob velocity update
+// (step 8, Eq. (update_u)). The predictor (step 1) and the position update
+// (step 9) are fused with their gathers in grid.hip.
 #include "icm_internal.h"
 
 namespace icm {
@@ -10,39 +11,91 @@ namespace {
 
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ void raise_flag(unsigned int* flag, unsigned int bit) { atomicOr(flag, bit); }
 
-// Step 1: q^{n+1/2} = q^n + dt/2 J^n v^n.
-__global__ void k_predict(BlobParams bp, BlobBufs b) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * bp.nb) return;
-    const double qh = b.q[t] + 0.5 * bp.dt * b.Jn[t];
-    if (!isfinite(qh)) raise_flag(b.flag, 1u);
-    b.qh[t] = qh;
+// F = f_const - k (q - c): the one-body forces at q^{n+1/2}, the positions
+// folded into the box, q - L floor(q / L), and (with pair forces) the blob's
+// insertion into its cell's list. A cell head holds (stamp << 32 | blob) with
+// the step's stamp, so heads left from earlier steps read as empty and the
+// head array never needs clearing.
+__global__ void k_forces_init(BlobParams bp, BlobBufs b, CellGrid cg, unsigned int stamp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= bp.nb) return;
+    int ci[3];
+    for (int a = 0; a < 3; ++a) {
+        const int t = 3 * i + a;
+        double f = b.fconst[t];
+        if (bp.spring_k != 0.0) f -= bp.spring_k * (b.qh[t] - bp.spring_c[a]);
+        b.F[t] = f;
+        const double L = bp.box[a];
+        const double w = b.qh[t] - L * floor(b.qh[t] / L);
+        b.qw[t] = w;
+        int c = (int)(w * cg.inv_size[a]);
+        ci[a] = c >= cg.n[a] ? cg.n[a] - 1 : (c < 0 ? 0 : c);
+    }
+    if (cg.heads) {
+        const long long cell = ((long long)ci[2] * cg.n[1] + ci[1]) * cg.n[0] + ci[0];
+        const unsigned long long mine = ((unsigned long long)stamp << 32) | (unsigned int)i;
+        const unsigned long long old = atomicExch(&cg.heads[cell], mine);
+        cg.next[i] = ((unsigned int)(old >> 32) == stamp) ? (int)(old & 0xffffffffu) : -1;
+    }
 }
 
-// Positions folded into the box, q - L floor(q / L), for pair distances.
-__global__ void k_wrap(BlobParams bp, BlobBufs b) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * bp.nb) return;
-    const double L = bp.box[t % 3];
-    b.qw[t] = b.qh[t] - L * floor(b.qh[t] / L);
+// F += WCA pair forces (Eq. (WCA), minimum image, unordered pairs counted
+// once) at q^{n+1/2}: each blob walks the lists of the 27 cells around its
+// own (cells are at least one cutoff wide, at least 3 per axis).
+__global__ void __launch_bounds__(kThreads) k_pairs_cells(BlobParams bp, BlobBufs b, CellGrid cg,
+                                                          unsigned int stamp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= bp.nb) return;
+    const double qx = b.qw[3 * i], qy = b.qw[3 * i + 1], qz = b.qw[3 * i + 2];
+    const double s2 = bp.wca_sigma * bp.wca_sigma;
+    const double rc2 = 1.2599210498948732 * s2;  // (2^(1/6) sigma)^2
+    const double Lx = bp.box[0], Ly = bp.box[1], Lz = bp.box[2];
+    const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
+    int c[3];
+    const double q3[3] = {qx, qy, qz};
+    for (int a = 0; a < 3; ++a) {
+        const int cc = (int)(q3[a] * cg.inv_size[a]);
+        c[a] = cc >= cg.n[a] ? cg.n[a] - 1 : (cc < 0 ? 0 : cc);
+    }
+    double fx = 0, fy = 0, fz = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int z = (c[2] + dz + cg.n[2]) % cg.n[2];
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int y = (c[1] + dy + cg.n[1]) % cg.n[1];
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int x = (c[0] + dx + cg.n[0]) % cg.n[0];
+                const unsigned long long h = cg.heads[((long long)z * cg.n[1] + y) * cg.n[0] + x];
+                int j = ((unsigned int)(h >> 32) == stamp) ? (int)(h & 0xffffffffu) : -1;
+                while (j >= 0) {
+                    if (j != i) {
+                        double ex = qx - b.qw[3 * j], ey = qy - b.qw[3 * j + 1], ez = qz - b.qw[3 * j + 2];
+                        ex = ex > hx ? ex - Lx : (ex < -hx ? ex + Lx : ex);
+                        ey = ey > hy ? ey - Ly : (ey < -hy ? ey + Ly : ey);
+                        ez = ez > hz ? ez - Lz : (ez < -hz ? ez + Lz : ez);
+                        const double r2 = ex * ex + ey * ey + ez * ez;
+                        if (r2 < rc2 && r2 > 0.0) {
+                            const double sr2 = s2 / r2;
+                            const double sr6 = sr2 * sr2 * sr2;
+                            const double f = 24.0 * bp.wca_eps * (2.0 * sr6 * sr6 - sr6) / r2;
+                            fx += f * ex;
+                            fy += f * ey;
+                            fz += f * ez;
+                        }
+                    }
+                    j = cg.next[j];
+                }
+            }
+        }
+    }
+    b.F[3 * i] += fx;
+    b.F[3 * i + 1] += fy;
+    b.F[3 * i + 2] += fz;
 }
 
-// F = f_const - k (q - c): the one-body forces at q^{n+1/2}.
-__global__ void k_forces_init(BlobParams bp, BlobBufs b) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * bp.nb) return;
-    double f = b.fconst[t];
-    if (bp.spring_k != 0.0) f -= bp.spring_k * (b.qh[t] - bp.spring_c[t % 3]);
-    b.F[t] = f;
-}
-
-// F += WCA pair forces (Eq. (WCA), minimum image, unordered pairs) at
-// q^{n+1/2}. Block (bx, by) takes blobs i of tile bx against blobs j of
-// tile by: tile by's folded positions sit in LDS, so the minimum image of a
-// difference in (-L, L) is one conditional shift per axis; partial sums are
-// added to F atomically.
+// All-pairs WCA forces, for boxes too small for a 3-cell list: block (bx, by)
+// takes blobs i of tile bx against the folded positions of the kPairTile blobs
+// of tile by held in LDS; partial sums are added to F atomically.
 constexpr int kPairTile = 64;
 
 __global__ void __launch_bounds__(kThreads) k_pairs(BlobParams bp, BlobBufs b) {
@@ -114,20 +167,6 @@ __global__ void k_inertial_u(BlobParams bp, BlobBufs b) {
     if (b.me[t / 3] != 0.0) b.u[t] = b.Jhvt[t] + b.g[t] + b.du[t];
 }
 
-// Step 9: q^{n+1} = q^n + dt/2 J^{n+1/2} (v^{n+1} + v^n); blobs with m_e = 0
-// take u^{n+1} = J^{n+1/2} v^{n+1}. Raises the numeric flag on NaN/Inf or a
-// displacement above h.
-__global__ void k_final(BlobParams bp, BlobBufs b, double h) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * bp.nb) return;
-    const double dq = 0.5 * bp.dt * (b.Jhvnew[t] + b.Jhvn[t]);
-    const double qn = b.q[t] + dq;
-    if (!isfinite(qn)) raise_flag(b.flag, 1u);
-    if (fabs(dq) > h) raise_flag(b.flag, 2u);
-    b.q[t] = qn;
-    if (b.me[t / 3] == 0.0) b.u[t] = b.Jhvnew[t];
-}
-
 __global__ void k_blob_diag(int nb, const double* me, const double* u, double* acc) {
     // single block: sum m_e u (3) and sum m_e u^2 / 2
     __shared__ double red[4][kThreads];
@@ -154,14 +193,17 @@ dim3 grid3(int nb) { return dim3((unsigned)((3 * nb + kThreads - 1) / kThreads))
 
 }  // namespace
 
-void launch_predict(const BlobParams& bp, const BlobBufs& b, hipStream_t s) {
-    if (bp.nb > 0) hipLaunchKernelGGL(k_predict, grid3(bp.nb), dim3(kThreads), 0, s, bp, b);
-}
-void launch_forces(const BlobParams& bp, const BlobBufs& b, hipStream_t s) {
+void launch_forces(const BlobParams& bp, const BlobBufs& b, const CellGrid& cg, unsigned int stamp, hipStream_t s) {
     if (bp.nb <= 0) return;
-    hipLaunchKernelGGL(k_forces_init, grid3(bp.nb), dim3(kThreads), 0, s, bp, b);
-    if (bp.wca_eps != 0.0 && bp.nb > 1) {
-        hipLaunchKernelGGL(k_wrap, grid3(bp.nb), dim3(kThreads), 0, s, bp, b);
+    const bool pairs = bp.wca_eps != 0.0 && bp.nb > 1;
+    const bool cells = pairs && cg.heads != nullptr;
+    CellGrid none = cg;
+    if (!cells) none.heads = nullptr;
+    const dim3 g1((unsigned)((bp.nb + kThreads - 1) / kThreads));
+    hipLaunchKernelGGL(k_forces_init, g1, dim3(kThreads), 0, s, bp, b, none, stamp);
+    if (cells) {
+        hipLaunchKernelGGL(k_pairs_cells, g1, dim3(kThreads), 0, s, bp, b, cg, stamp);
+    } else if (pairs) {
         const unsigned ti = (unsigned)((bp.nb + kThreads - 1) / kThreads);
         const unsigned tj = (unsigned)((bp.nb + kPairTile - 1) / kPairTile);
         hipLaunchKernelGGL(k_pairs, dim3(ti, tj), dim3(kThreads), 0, s, bp, b);
@@ -175,9 +217,6 @@ void launch_inertial_dp2(const BlobParams& bp, const BlobBufs& b, hipStream_t s)
 }
 void launch_inertial_u(const BlobParams& bp, const BlobBufs& b, hipStream_t s) {
     if (bp.nb > 0) hipLaunchKernelGGL(k_inertial_u, grid3(bp.nb), dim3(kThreads), 0, s, bp, b);
-}
-void launch_final(const BlobParams& bp, const BlobBufs& b, double h, hipStream_t s) {
-    if (bp.nb > 0) hipLaunchKernelGGL(k_final, grid3(bp.nb), dim3(kThreads), 0, s, bp, b, h);
 }
 void launch_blob_diag(int nb, const double* me, const double* u, double* acc, hipStream_t s) {
     hipLaunchKernelGGL(k_blob_diag, dim3(1), dim3(kThreads), 0, s, nb, me, u, acc);

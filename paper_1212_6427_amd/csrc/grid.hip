@@ -22,50 +22,6 @@ __device__ __forceinline__ NormalPair<T> bm(uint32_t wa, uint32_t wb) {
     return r;
 }
 
-// Per-blob stencils for the spread inside the RHS kernel (see RhsBlobs) and
-// z-chunk binning. One thread per blob.
-template <int P>
-__global__ void __launch_bounds__(kThreads) k_rhs_bins(int nb, int nx, int ny, int nz, double h,
-                                                       const double* __restrict__ qh, int cap,
-                                                       int* __restrict__ chunk_count, int* __restrict__ chunk_list,
-                                                       double* __restrict__ stc) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb) return;
-    const double inv_h = 1.0 / h;
-    const int n[3] = {nx, ny, nz};
-    int zlo = 1 << 30, zhi = -(1 << 30);
-    for (int a = 0; a < 3; ++a) {
-        double* o = stc + ((long long)b * 3 + a) * kStcPerComp;
-        for (int ax = 0; ax < 3; ++ax) {
-            const double x = qh[3 * b + ax] * inv_h - (ax == a ? 0.0 : 0.5);
-            const double m0 = (P == 3) ? floor(x + 0.5) : floor(x);
-            const long long base = (long long)m0 - 1;
-            long long wb = base % n[ax];
-            if (wb < 0) wb += n[ax];
-            o[ax] = (double)wb;
-            for (int t = 0; t < 4; ++t) {
-                const double d = x - (double)(base + t);
-                o[3 + 4 * ax + t] = (t < P) ? ((P == 3) ? phi3(d) : phi4(d)) : 0.0;
-                if (ax == a) o[15 + t] = (t < P) ? ((P == 3) ? dphi3(d) : dphi4(d)) * inv_h : 0.0;
-            }
-            if (ax == 2) {
-                zlo = min(zlo, (int)base);
-                zhi = max(zhi, (int)base + P - 1);
-            }
-        }
-    }
-    // chunks met by planes zlo..zhi (unwrapped, fewer than kRhsZChunk)
-    const int nchunks = (nz + kRhsZChunk - 1) / kRhsZChunk;
-    const int c0 = (int)(((zlo % nz) + nz) % nz) / kRhsZChunk;
-    const int c1 = (int)(((zhi % nz) + nz) % nz) / kRhsZChunk;
-    int slot = atomicAdd(&chunk_count[c0], 1);
-    if (slot < cap) chunk_list[(long long)c0 * cap + slot] = b;
-    if (c1 != c0 && nchunks > 1) {
-        slot = atomicAdd(&chunk_count[c1], 1);
-        if (slot < cap) chunk_list[(long long)c1 * cap + slot] = b;
-    }
-}
-
 __global__ void k_clear_ints(int* p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
@@ -451,6 +407,142 @@ __global__ void __launch_bounds__(kThreads) k_spread(GridDesc<T> g, T* field, in
     for (int aa = 0; aa < P; ++aa) atomicAdd(&f[sx.node[aa]], (T)(wzy * sx.w[aa]));
 }
 
+// One 16-lane group's share of J for component a at position (qx,qy,qz):
+// lane r < P^2 sums the x-row of z-tap r / P and y-tap r mod P; the group
+// total is returned to every lane of the group.
+template <typename T, int P>
+__device__ __forceinline__ double gather_group(const GridDesc<T>& g, const T* __restrict__ field, const double* q3,
+                                               int a, int r, bool active) {
+    double acc = 0.0;
+    if (active && r < P * P) {
+        const int cz = r / P, cy = r - P * (r / P);
+        const double inv_h = 1.0 / g.h;
+        AxisStencil<P> sx;
+        axis_stencil<P>(q3[0] * inv_h - comp_offset(0, a), g.nx, false, inv_h, sx);
+        int j, k;
+        double wy, wz;
+        axis_tap<P>(q3[1] * inv_h - comp_offset(1, a), g.ny, cy, false, inv_h, j, wy);
+        axis_tap<P>(q3[2] * inv_h - comp_offset(2, a), g.nz, cz, false, inv_h, k, wz);
+        const T* f = field + a * g.ncell + ((long long)k * g.ny + j) * g.nx;
+        double s = 0.0;
+#pragma unroll
+        for (int aa = 0; aa < P; ++aa) s += sx.w[aa] * (double)f[sx.node[aa]];
+        acc = wz * wy * s;
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+    return acc;
+}
+
+// Step 1 fused: Jn = J(q^n) v^n and q^{n+1/2} = q^n + dt/2 Jn.
+template <typename T, int P>
+__global__ void __launch_bounds__(kThreads) k_gather_predict(GridDesc<T> g, BlobParams bp, BlobBufs bb) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int grp = t >> 4, r = t & 15;
+    const int b = grp / 3, a = grp - 3 * (grp / 3);
+    const bool active = b < bp.nb;
+    const double J = gather_group<T, P>(g, g.v, active ? bb.q + 3 * b : bb.q, a, r, active);
+    if (active && r == 0) {
+        bb.Jn[3 * b + a] = J;
+        const double qh = bb.q[3 * b + a] + 0.5 * bp.dt * J;
+        if (!isfinite(qh)) atomicOr(bb.flag, 1u);
+        bb.qh[3 * b + a] = qh;
+    }
+}
+
+// Jhvn = J(q^{n+1/2}) v^n, plus, for the spread inside the RHS kernel, the
+// stencil record of component a (wrapped base nodes, the P weights of each
+// axis, the derivative weights along axis a).
+template <typename T, int P>
+__global__ void __launch_bounds__(kThreads) k_gather_bins(GridDesc<T> g, BlobParams bp, BlobBufs bb, int cap) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int grp = t >> 4, r = t & 15;
+    const int b = grp / 3, a = grp - 3 * (grp / 3);
+    const bool active = b < bp.nb;
+    const double J = gather_group<T, P>(g, g.v, active ? bb.qh + 3 * b : bb.qh, a, r, active);
+    if (!active) return;
+    if (r == 0) bb.Jhvn[3 * b + a] = J;
+    const double inv_h = 1.0 / g.h;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    double* o = bb.stc + ((long long)b * 3 + a) * kStcPerComp;
+    // lanes 1..3 write the record of axis ax = r - 1
+    if (r >= 1 && r <= 3) {
+        const int ax = r - 1;
+        const double x = bb.qh[3 * b + ax] * inv_h - (ax == a ? 0.0 : 0.5);
+        const double m0 = (P == 3) ? floor(x + 0.5) : floor(x);
+        const long long base = (long long)m0 - 1;
+        long long wb = base % n[ax];
+        if (wb < 0) wb += n[ax];
+        o[ax] = (double)wb;
+        for (int tt = 0; tt < 4; ++tt) {
+            const double d = x - (double)(base + tt);
+            o[3 + 4 * ax + tt] = (tt < P) ? ((P == 3) ? phi3(d) : phi4(d)) : 0.0;
+            if (ax == a) o[15 + tt] = (tt < P) ? ((P == 3) ? dphi3(d) : dphi4(d)) * inv_h : 0.0;
+        }
+    }
+}
+
+// z-chunk bins of the spread inside the RHS kernel: one thread per blob; the
+// chunks met by the planes of any component grid along z are counted per
+// workgroup in LDS and reserved in the global lists with one atomic per
+// (workgroup, chunk), which keeps same-address contention low.
+constexpr int kMaxChunks = 512 / kRhsZChunk;
+template <int P>
+__global__ void __launch_bounds__(kThreads) k_bins(int nb, int nz, double h, const double* __restrict__ qh, int cap,
+                                                   int* __restrict__ chunk_count, int* __restrict__ chunk_list) {
+    __shared__ int s_cnt[kMaxChunks];
+    __shared__ int s_base[kMaxChunks];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nchunks = (nz + kRhsZChunk - 1) / kRhsZChunk;
+    for (int i = threadIdx.x; i < nchunks; i += blockDim.x) s_cnt[i] = 0;
+    __syncthreads();
+    int c0 = -1, c1 = -1, s0 = 0, s1 = 0;
+    if (b < nb) {
+        const double z = qh[3 * b + 2] / h;
+        const long long lo0 = (long long)((P == 3) ? floor(z + 0.5) : floor(z)) - 1;
+        const long long lo1 = (long long)((P == 3) ? floor(z) : floor(z - 0.5)) - 1;
+        const long long zlo = lo0 < lo1 ? lo0 : lo1;
+        const long long zhi = (lo0 > lo1 ? lo0 : lo1) + P - 1;
+        c0 = (int)(((zlo % nz) + nz) % nz) / kRhsZChunk;
+        c1 = (int)(((zhi % nz) + nz) % nz) / kRhsZChunk;
+        if (c1 == c0 || nchunks == 1) c1 = -1;
+        s0 = atomicAdd(&s_cnt[c0], 1);
+        if (c1 >= 0) s1 = atomicAdd(&s_cnt[c1], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nchunks; i += blockDim.x)
+        s_base[i] = s_cnt[i] ? atomicAdd(&chunk_count[i], s_cnt[i]) : 0;
+    __syncthreads();
+    if (c0 >= 0 && s_base[c0] + s0 < cap) chunk_list[(long long)c0 * cap + s_base[c0] + s0] = b;
+    if (c1 >= 0 && s_base[c1] + s1 < cap) chunk_list[(long long)c1 * cap + s_base[c1] + s1] = b;
+}
+
+// Step 9 fused: Jhvnew = J(q^{n+1/2}) v^{n+1}; q^{n+1} = q^n + dt/2
+// (Jhvnew + Jhvn); u^{n+1} = Jhvnew for m_e = 0 blobs; numeric flag on
+// NaN/Inf or a displacement above h. The first block clears the z-chunk bins
+// for the next step.
+template <typename T, int P>
+__global__ void __launch_bounds__(kThreads) k_gather_final(GridDesc<T> g, BlobParams bp, BlobBufs bb,
+                                                          int n_clear) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < n_clear; i += blockDim.x) bb.chunk_count[i] = 0;
+    const int grp = t >> 4, r = t & 15;
+    const int b = grp / 3, a = grp - 3 * (grp / 3);
+    const bool active = b < bp.nb;
+    const double J = gather_group<T, P>(g, g.v, active ? bb.qh + 3 * b : bb.qh, a, r, active);
+    if (active && r == 0) {
+        const int i = 3 * b + a;
+        bb.Jhvnew[i] = J;
+        const double dq = 0.5 * bp.dt * (J + bb.Jhvn[i]);
+        const double qn = bb.q[i] + dq;
+        if (!isfinite(qn)) atomicOr(bb.flag, 1u);
+        if (fabs(dq) > g.h) atomicOr(bb.flag, 2u);
+        bb.q[i] = qn;
+        if (bb.me[b] == 0.0) bb.u[i] = J;
+    }
+}
+
 // J: out[b][a] = sum phi(dx) phi(dy) phi(dz) f_a (FP64 accumulation), one
 // 16-lane group per (blob, component) reduced with shuffles; with lap = 1 the
 // field value at each node is replaced by its 7-point Laplacian.
@@ -569,21 +661,6 @@ void launch_rhs(const GridDesc<T>& g, const RhsCoef& c, const RhsBlobs& rb, hipS
 }
 
 template <typename T>
-void launch_rhs_bins(const GridDesc<T>& g, const double* qh, RhsBlobs rb, int* chunk_count, int* chunk_list,
-                     double* stc, hipStream_t s) {
-    const int nchunks = (g.nz + kRhsZChunk - 1) / kRhsZChunk;
-    hipLaunchKernelGGL(k_clear_ints, dim3(1), dim3(kThreads), 0, s, chunk_count, nchunks + 1);
-    if (rb.nb <= 0) return;
-    const dim3 grid((unsigned)((rb.nb + kThreads - 1) / kThreads));
-    if (rb.kernel == 3)
-        hipLaunchKernelGGL(k_rhs_bins<3>, grid, dim3(kThreads), 0, s, rb.nb, g.nx, g.ny, g.nz, g.h, qh, rb.cap,
-                           chunk_count, chunk_list, stc);
-    else
-        hipLaunchKernelGGL(k_rhs_bins<4>, grid, dim3(kThreads), 0, s, rb.nb, g.nx, g.ny, g.nz, g.h, qh, rb.cap,
-                           chunk_count, chunk_list, stc);
-}
-
-template <typename T>
 void launch_spread_overflow(const GridDesc<T>& g, const RhsBlobs& rb, hipStream_t s) {
     if (rb.nb <= 0) return;
     const int tiles_x = (g.nx + RTX - 1) / RTX, tiles_y = (g.ny + RTY - 1) / RTY;
@@ -634,6 +711,48 @@ void launch_gather(const GridDesc<T>& g, const T* field, int kernel, int nb, con
 }
 
 template <typename T>
+void launch_gather_predict(const GridDesc<T>& g, int kernel, const BlobParams& bp, const BlobBufs& bb,
+                           hipStream_t s) {
+    if (bp.nb <= 0) return;
+    const dim3 grid(grid_for(48LL * bp.nb));
+    if (kernel == 3)
+        hipLaunchKernelGGL((k_gather_predict<T, 3>), grid, dim3(kThreads), 0, s, g, bp, bb);
+    else
+        hipLaunchKernelGGL((k_gather_predict<T, 4>), grid, dim3(kThreads), 0, s, g, bp, bb);
+}
+
+template <typename T>
+void launch_gather_bins(const GridDesc<T>& g, int kernel, const BlobParams& bp, const BlobBufs& bb, int cap,
+                        hipStream_t s) {
+    if (bp.nb <= 0) return;
+    const dim3 grid(grid_for(48LL * bp.nb));
+    if (kernel == 3)
+        hipLaunchKernelGGL((k_gather_bins<T, 3>), grid, dim3(kThreads), 0, s, g, bp, bb, cap);
+    else
+        hipLaunchKernelGGL((k_gather_bins<T, 4>), grid, dim3(kThreads), 0, s, g, bp, bb, cap);
+}
+
+void launch_bins(int kernel, int nb, int nz, double h, const double* qh, int cap, int* chunk_count,
+                 int* chunk_list, hipStream_t s) {
+    if (nb <= 0) return;
+    const dim3 grid((unsigned)((nb + kThreads - 1) / kThreads));
+    if (kernel == 3)
+        hipLaunchKernelGGL(k_bins<3>, grid, dim3(kThreads), 0, s, nb, nz, h, qh, cap, chunk_count, chunk_list);
+    else
+        hipLaunchKernelGGL(k_bins<4>, grid, dim3(kThreads), 0, s, nb, nz, h, qh, cap, chunk_count, chunk_list);
+}
+
+template <typename T>
+void launch_gather_final(const GridDesc<T>& g, int kernel, const BlobParams& bp, const BlobBufs& bb, int n_clear,
+                         hipStream_t s) {
+    const dim3 grid(grid_for(48LL * (bp.nb > 0 ? bp.nb : 1)));
+    if (kernel == 3)
+        hipLaunchKernelGGL((k_gather_final<T, 3>), grid, dim3(kThreads), 0, s, g, bp, bb, n_clear);
+    else
+        hipLaunchKernelGGL((k_gather_final<T, 4>), grid, dim3(kThreads), 0, s, g, bp, bb, n_clear);
+}
+
+template <typename T>
 void launch_field_diag(const GridDesc<T>& g, double rho, double* acc, hipStream_t s) {
     long long b = (g.ncell + kThreads - 1) / kThreads;
     if (b > 2048) b = 2048;
@@ -642,8 +761,6 @@ void launch_field_diag(const GridDesc<T>& g, double rho, double* acc, hipStream_
 
 #define ICM_INST(T)                                                                                        \
     template void launch_rhs<T>(const GridDesc<T>&, const RhsCoef&, const RhsBlobs&, hipStream_t);        \
-    template void launch_rhs_bins<T>(const GridDesc<T>&, const double*, RhsBlobs, int*, int*, double*,    \
-                                     hipStream_t);                                                        \
     template void launch_spread_overflow<T>(const GridDesc<T>&, const RhsBlobs&, hipStream_t);           \
     template void launch_equilibrium_noise<T>(const GridDesc<T>&, double, NoiseKey, hipStream_t);         \
     template void launch_zero<T>(T*, long long, hipStream_t);                                              \
@@ -652,7 +769,13 @@ void launch_field_diag(const GridDesc<T>& g, double rho, double* acc, hipStream_
                                    const double*, bool, hipStream_t);                                     \
     template void launch_gather<T>(const GridDesc<T>&, const T*, int, int, const double*, double*, bool, \
                                    hipStream_t);                                                          \
-    template void launch_field_diag<T>(const GridDesc<T>&, double, double*, hipStream_t);
+    template void launch_field_diag<T>(const GridDesc<T>&, double, double*, hipStream_t);                 \
+    template void launch_gather_predict<T>(const GridDesc<T>&, int, const BlobParams&, const BlobBufs&,   \
+                                           hipStream_t);                                                  \
+    template void launch_gather_bins<T>(const GridDesc<T>&, int, const BlobParams&, const BlobBufs&, int, \
+                                        hipStream_t);                                                     \
+    template void launch_gather_final<T>(const GridDesc<T>&, int, const BlobParams&, const BlobBufs&, int, \
+                                         hipStream_t);
 ICM_INST(float)
 ICM_INST(double)
 #undef ICM_INST

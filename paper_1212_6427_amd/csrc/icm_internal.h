@@ -120,10 +120,6 @@ bool fast_fft_x_inverse(const GridDesc<T>& g, T* out, bool accumulate, int c, hi
 // ------------------------------------------------------------ grid kernels
 template <typename T>
 void launch_rhs(const GridDesc<T>& g, const RhsCoef& c, const RhsBlobs& rb, hipStream_t s);
-// blob stencils and z-chunk bins for the right-hand-side spread
-template <typename T>
-void launch_rhs_bins(const GridDesc<T>& g, const double* qh, RhsBlobs rb, int* chunk_count, int* chunk_list,
-                     double* stc, hipStream_t s);
 template <typename T>
 void launch_spread_overflow(const GridDesc<T>& g, const RhsBlobs& rb, hipStream_t s);
 template <typename T>
@@ -172,12 +168,36 @@ struct BlobBufs {
     int ovf_cap;
 };
 
-void launch_predict(const BlobParams& bp, const BlobBufs& b, hipStream_t s);
-void launch_forces(const BlobParams& bp, const BlobBufs& b, hipStream_t s);
+// Cell list of the pair forces: n[a] cells of width >= the cutoff per axis
+// (at least 3), heads[cell] = (stamp << 32 | first blob), next[blob]. With
+// heads == NULL the forces use the all-pairs kernel.
+struct CellGrid {
+    int n[3];
+    double inv_size[3];
+    unsigned long long* heads;
+    int* next;
+};
+void launch_forces(const BlobParams& bp, const BlobBufs& b, const CellGrid& cg, unsigned int stamp, hipStream_t s);
 void launch_inertial_dp(const BlobParams& bp, const BlobBufs& b, hipStream_t s);
 void launch_inertial_dp2(const BlobParams& bp, const BlobBufs& b, hipStream_t s);
 void launch_inertial_u(const BlobParams& bp, const BlobBufs& b, hipStream_t s);
-void launch_final(const BlobParams& bp, const BlobBufs& b, double h, hipStream_t s);
 void launch_blob_diag(int nb, const double* me, const double* u, double* acc, hipStream_t s);
+
+// Fused gathers of the step (one 16-lane group per blob component):
+// J^n v^n with the predictor; J^{n+1/2} v^n with the RHS stencils and z-chunk
+// bins; J^{n+1/2} v^{n+1} with the position update (which also clears the
+// first n_clear bin counters for the next step).
+template <typename T>
+void launch_gather_predict(const GridDesc<T>& g, int kernel, const BlobParams& bp, const BlobBufs& bb,
+                           hipStream_t s);
+template <typename T>
+void launch_gather_bins(const GridDesc<T>& g, int kernel, const BlobParams& bp, const BlobBufs& bb, int cap,
+                        hipStream_t s);
+template <typename T>
+void launch_gather_final(const GridDesc<T>& g, int kernel, const BlobParams& bp, const BlobBufs& bb, int n_clear,
+                         hipStream_t s);
+// z-chunk bins of the RHS spread (positions qh); counters must start at zero.
+void launch_bins(int kernel, int nb, int nz, double h, const double* qh, int cap, int* chunk_count,
+                 int* chunk_list, hipStream_t s);
 
 }  // namespace icm

@@ -159,3 +159,44 @@ def test_equilibrium_and_projection_initialisers(I):
         assert got["diag"]["max_div"] < 1e-12
     finally:
         sim.close()
+
+
+def test_wca_small_box_all_pairs_fp64(I):
+    """A box fewer than three cutoffs wide takes the all-pairs force path."""
+    sigma = 3.0 / 2 ** (1 / 6)
+    p = oracle_params((8, 8, 12), kernel=3, kT=1e-3, dt=0.2, seed=71, wca_eps=5e-2, wca_sigma=sigma)
+    st = initial_state(p, 4, (0.0, 1.0), seed=31, min_sep=2.9)
+    run_parity(I, p, st, 3, I.FP64, TOL64, "all-pairs")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_uneven_replicas_match_single(I, precision):
+    """Several replicas of uneven grids and different physics in one context
+    (one icm_step call) each match the oracle run on their own."""
+    prec = I.FP64 if precision == "fp64" else I.FP32_GRID
+    tol = TOL64 if precision == "fp64" else TOL32
+    steps = 3 if precision == "fp64" else 1
+    dtype = np.float64 if prec == I.FP64 else np.float32
+    cases = [
+        (oracle_params((32, 32, 32), kernel=4, kT=1e-3, dt=0.25, seed=81, replica=0), (0.0,), 1),
+        (oracle_params((48, 48, 48), kernel=4, kT=1e-3, dt=0.25, seed=81, replica=1), (1.0,), 1),
+        (oracle_params((64, 48, 32), kernel=3, kT=2e-3, dt=0.2, seed=82, replica=2), (-0.5, 0.0), 2),
+    ]
+    states = [initial_state(p, nb, me, seed=40 + i, min_sep=3.0) for i, (p, me, nb) in enumerate(cases)]
+    if prec == I.FP32_GRID:
+        for st in states:
+            st.v = st.v.astype(np.float32).astype(np.float64)
+    banner("batched %s: %s" % (precision, [c[0].n for c in cases]))
+    sim = I.Sim([gpu_params(I, p) for p, _, _ in cases], [nb for _, _, nb in cases], prec)
+    try:
+        for r, st in enumerate(states):
+            load_into_gpu(I, sim, r, st, dtype)
+        sim.step(steps)
+        for r, ((p, _, _), st) in enumerate(zip(cases, states)):
+            ref = O.run(p, st, steps)
+            got = sim.get_state(r)
+            errs, bad = compare(got, ref, st.q, tol)
+            print("replica", r, {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+            assert not bad, (r, bad)
+    finally:
+        sim.close()
