@@ -57,6 +57,43 @@ def algorithmic_bytes(phase, n, nb, kernel, w):
     return 0
 
 
+PROFILE = os.path.join(ROOT, "profiles", "many_blobs_256_fp32.md")
+PHASE_KERNEL = {"rhs": "k_rhs_march<float>", "fft_z_solve": "k_z_fast<float, 256, 16, 16, 16, 1>",
+                "fft_x_fwd": "k_xfwd_fast<float, 256, 16, 16, 16, 1>",
+                "fft_x_inv": "k_xinv_fast<float, 256, 16, 16, 16, 1>"}
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1212_6427_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(phase):
+    """HBM bytes per launch of a phase's kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
+    the kernel sources changed after the counters were taken."""
+    kernel = PHASE_KERNEL.get(phase)
+    if kernel is None or not os.path.exists(PROFILE):
+        return None
+    at_hash, traffic = None, {}
+    with open(PROFILE) as fh:
+        for line in fh:
+            if line.startswith("source hash"):
+                at_hash = line.split()[-1]
+            elif line.startswith("traffic "):
+                name, val = line[len("traffic "):].rsplit(" ", 1)
+                traffic[name] = float(val)
+    if at_hash != source_hash():
+        return None
+    return traffic.get(kernel)
+
+
 def setup(I, torch, wl, precision, stream):
     n = tuple(wl["n"])
     import icm_inputs
@@ -173,7 +210,7 @@ def main():
     dom = max(phases.items(), key=lambda kv: kv[1]["total_ms_per_step"])
     dom_name, dom_v = dom
     roofline = dict(bound="hbm", kernel=dom_name, achieved=dom_v["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=dom_v["achieved_GBs"] / HBM_PEAK_GBS, traffic=None,
+                    frac=dom_v["achieved_GBs"] / HBM_PEAK_GBS, traffic=measured_traffic(dom_name),
                     alg_bytes_per_launch=dom_v["alg_bytes_per_launch"], avg_launch_us=dom_v["avg_launch_us"])
     step_alg_bytes = 12 * ncell * 4
     out = {
