@@ -140,6 +140,67 @@ def profile_phases(sim, steps, n, nb, kernel, w):
     return phases
 
 
+def ensemble_sims(I, torch, stream, batched):
+    """The batched ensemble: 96 replicas (32 each of 32^3, 48^3, 64^3), one
+    blob each with m_e / m_f drawn from {0, 1, -1/2}, FP32 grid, fluid started
+    from the discrete equilibrium. batched: one context holding every replica;
+    else one context per replica."""
+    import icm_inputs
+    wl = icm_inputs.WORKLOADS["batched_ensemble"]
+    grids = wl["grids"]
+    nrep = len(grids)
+    ratios = icm_inputs.excess_mass_ratios(nrep, wl["me_over_mf"], seed=wl["seed"])
+    m_f = wl["rho"] * wl["h"] ** 3 / (0.375 ** 3 if wl["kernel"] == 4 else 0.5 ** 3)
+    params = [I.make_params(n, h=wl["h"], rho=wl["rho"], eta=wl["eta"], kT=wl["kT"], dt=wl["dt"],
+                            kernel=wl["kernel"], seed=wl["seed"], replica_id=r) for r, n in enumerate(grids)]
+    blobs = [(icm_inputs.uniform_positions(1, n, wl["h"], seed=wl["seed"] + 1 + r), np.array([ratios[r] * m_f]))
+             for r, n in enumerate(grids)]
+
+    def make(ps):
+        nbytes = I.icm_workspace_bytes(ps, [1] * len(ps), I.FP32_GRID)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        return I.Sim(ps, [1] * len(ps), I.FP32_GRID, stream=stream.cuda_stream, workspace=ws)
+
+    sims = [make(params)] if batched else [make([pp]) for pp in params]
+    for r in range(nrep):
+        sim, loc = (sims[0], r) if batched else (sims[r], 0)
+        q, me = blobs[r]
+        sim.set_blobs(loc, q, m_e=me)
+        sim.set_state(loc, flags=I.STATE_EQUILIBRIUM)
+    cells = sum(int(np.prod(n)) for n in grids)
+    return sims, cells, nrep
+
+
+def ensemble_leg(I, torch, stream, steps, warmup):
+    """cell-steps/s of the batched ensemble as one context (one recorded graph
+    per step) against the same replicas stepped one context at a time."""
+    out = {}
+    for mode in ("batched", "single"):
+        sims, cells, nrep = ensemble_sims(I, torch, stream, mode == "batched")
+        for sim in sims:
+            sim.step(warmup, I.STEP_GRAPH)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for sim in sims:
+            sim.step(steps, I.STEP_GRAPH)
+        b.record(stream)
+        torch.cuda.synchronize()
+        sec = a.elapsed_time(b) / 1000.0
+        wall = time.perf_counter() - t0
+        for sim in sims:
+            sim.close()
+        out[mode] = {"value": cells * steps / sec, "unit": "cell-steps/s", "blob_steps_per_s": nrep * steps / sec,
+                     "ms_per_step": sec * 1000.0 / steps, "steps": steps, "wall_s": wall, "contexts": len(sims)}
+        log("ensemble %s: %.3f ms/step, %.3e cell-steps/s" % (mode, out[mode]["ms_per_step"], out[mode]["value"]))
+    out["replicas"] = nrep
+    out["cells"] = cells
+    out["speedup_batched_vs_single"] = out["batched"]["value"] / out["single"]["value"]
+    return out
+
+
 def cpu_baseline(wl, seed_positions):
     """The FP64 oracle, untuned, on one full step of the same workload."""
     from oracle import icm as O
@@ -168,6 +229,8 @@ def main():
     ap.add_argument("--workload", default="many_blobs_256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=200)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device tensor copy first (counter calibration)")
@@ -246,6 +309,9 @@ def main():
         out["fp64"] = {"value": ncell * k64 / sec64, "ms_per_step": sec64 * 1000.0 / k64, "steps": k64,
                        "blob_steps_per_s": nb * k64 / sec64}
         log("FP64: %.3f ms/step" % out["fp64"]["ms_per_step"])
+    if not args.no_ensemble:
+        log("batched ensemble: 96 replicas of 32^3 / 48^3 / 64^3")
+        out["ensemble"] = ensemble_leg(I, torch, stream, args.ensemble_steps, max(2, args.warmup // 2))
     if not args.no_cpu_baseline:
         log("CPU oracle: one step of the same workload")
         out["cpu_baseline"] = cpu_baseline(wl, q)

@@ -77,6 +77,15 @@ enum {
                                from Philox block 2 of (seed, replica_id)     */
 };
 
+/* flags of icm_step */
+enum {
+    ICM_STEP_GRAPH = 1u     /* replay one recorded HIP graph of the whole step
+                               (all replicas) per step instead of launching
+                               its kernels one by one; the graph is recorded
+                               on first use and again after icm_set_blobs.
+                               Ignored while per-kernel timing is on.        */
+};
+
 /* Physical and numerical parameters of one replica (one periodic box). */
 typedef struct {
     int32_t n[3];            /* Nx, Ny, Nz                                   */
@@ -109,7 +118,7 @@ typedef struct {
 } icm_diag;
 
 /* Bytes of device workspace icm_create needs for these replicas.
- * p: n_rep parameter blocks; max_blobs: n_rep capacities (>= 0).           */
+ * p: n_rep parameter blocks; max_blobs: n_rep capacities in [0, 2^24).     */
 icm_status icm_workspace_bytes(int32_t n_rep, const icm_replica_params* p,
                                const int32_t* max_blobs, int32_t precision,
                                size_t* bytes);
@@ -145,11 +154,13 @@ icm_status icm_set_state(icm_ctx* ctx, int32_t replica, const void* v,
                          const double* q, const double* u,
                          const double* lag_c, int64_t step, uint32_t flags);
 
-/* Advance every replica by n_steps steps (Sec. III.C). Work is enqueued on
- * the context stream; the call then synchronises once to check the numeric
- * flag (NaN/Inf in a blob, or a blob displacement above h in one step, which
- * breaks the advective CFL condition alpha < 1 of Sec. III.D) and returns
- * ICM_E_NUMERIC if it was raised.                                          */
+/* Advance every replica by n_steps steps (Sec. III.C). Replicas of equal
+ * grid shape, kernel and inertial path (all m_e = 0, or not) are advanced by
+ * the same kernel launches. Work is enqueued on the context stream; the call
+ * then synchronises once to check the numeric flag (NaN/Inf in a blob, or a
+ * blob displacement above h in one step, which breaks the advective CFL
+ * condition alpha < 1 of Sec. III.D) and returns ICM_E_NUMERIC if it was
+ * raised. Flags: ICM_STEP_GRAPH (other bits: ICM_E_INVALID).               */
 icm_status icm_step(icm_ctx* ctx, int64_t n_steps, uint32_t flags);
 
 /* Read a replica's state. Any output may be NULL. v: face field in the

@@ -26,7 +26,6 @@ thread_local std::string g_last_error = "no error";
 struct Replica {
     icm_replica_params p;
     icm::CellGrid cells{};     // pair-force cell list (heads == NULL: all pairs)
-    unsigned int cell_stamp = 0;
     int max_nb = 0;
     int nb = 0;
     int64_t step = 0;
@@ -36,6 +35,21 @@ struct Replica {
     icm::GridDesc<double> gd{};
     icm::BlobBufs bb{};
     double* diag = nullptr;  // 16 doubles
+    unsigned long long* d_step = nullptr;  // device step counter
+    int slot = 0;            // index of the replica's descriptor in the device array
+};
+
+// Replicas stepped by the same launches: equal grid shape and kernel, and
+// the same inertial path (all m_e = 0 or not). Their descriptors occupy
+// slots [first, first + count) of the device array.
+struct BatchInfo {
+    int n[3];
+    int kernel;
+    bool any_me;
+    int first, count;
+    int max_nb;
+    bool any_cells, any_all_pairs;
+    std::vector<int> reps;
 };
 
 }  // namespace
@@ -56,6 +70,14 @@ struct icm_ctx {
     bool error_state = false;
     std::vector<Replica> reps;
     std::string err = "no error";
+    // device descriptor array (RepDesc<float> or RepDesc<double> per slot)
+    void* d_desc = nullptr;
+    std::vector<unsigned char> h_desc;
+    std::vector<BatchInfo> batches;
+    // captured step (icm_step with ICM_STEP_GRAPH)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace {
@@ -126,7 +148,8 @@ icm_status validate(int32_t n_rep, const icm_replica_params* p, const int32_t* m
             if (!(q.wca_sigma > 0) || !(rc < 0.5 * lmin))
                 return fail(nullptr, ICM_E_INVALID, "replica %d: need wca_sigma > 0 and cutoff < half the box", r);
         }
-        if (max_blobs[r] < 0) return fail(nullptr, ICM_E_INVALID, "replica %d: max_blobs must be >= 0", r);
+        if (max_blobs[r] < 0 || max_blobs[r] >= (1 << icm::kHeadBlobBits))
+            return fail(nullptr, ICM_E_INVALID, "replica %d: max_blobs must be in [0, 2^%d)", r, icm::kHeadBlobBits);
     }
     return ICM_OK;
 }
@@ -236,9 +259,18 @@ void carve_cells(Carver& cv, const icm_replica_params& p, int max_nb, icm::CellG
     if (!cv.base) cg.heads = reinterpret_cast<unsigned long long*>(1);  // sizing pass: mark as used
 }
 
+size_t desc_bytes(int32_t precision) {
+    return precision == ICM_FP64 ? sizeof(icm::RepDesc<double>) : sizeof(icm::RepDesc<float>);
+}
+
 size_t layout(int32_t n_rep, const icm_replica_params* p, const int32_t* max_blobs, int32_t precision, void* base,
-              std::vector<Replica>* reps) {
+              std::vector<Replica>* reps, void** d_desc = nullptr) {
     Carver cv(base);
+    void* desc = cv.take<unsigned char>(desc_bytes(precision) * (size_t)n_rep);
+    if (d_desc) *d_desc = desc;
+    unsigned long long* steps = cv.take<unsigned long long>((size_t)n_rep);
+    if (reps)
+        for (int r = 0; r < n_rep; ++r) (*reps)[r].d_step = steps + r;
     for (int r = 0; r < n_rep; ++r) {
         Replica tmp;
         Replica& R = reps ? (*reps)[r] : tmp;
@@ -371,87 +403,224 @@ void harvest_timing(icm_ctx* c) {
     c->ev_used = 0;
 }
 
+// --------------------------------------------------------- descriptors
+template <typename T>
+icm::RepDesc<T> build_desc(const Replica& R) {
+    icm::RepDesc<T> d{};
+    d.g = grid_of<T>(const_cast<Replica&>(R));
+    const icm::GridDesc<T>& g = d.g;
+    const icm_replica_params& p = R.p;
+    d.rc.rho_dt = p.rho / p.dt;
+    d.rc.half_eta_h2 = 0.5 * p.eta / (p.h * p.h);
+    d.rc.noise = p.kT > 0 ? std::sqrt(p.kT * p.eta / (p.h * p.h * p.h * p.dt)) / p.h : 0.0;
+    for (int a = 0; a < 3; ++a) d.rc.body[a] = p.body_force[a];
+    d.rc.key = noise_key(R, 0);
+    const icm::BlobBufs& b = R.bb;
+    const int nchunks = (g.nz + icm::kRhsZChunk - 1) / icm::kRhsZChunk;
+    d.rb.nb = R.nb;
+    d.rb.kernel = p.kernel;
+    d.rb.cap = R.max_nb;
+    d.rb.stc = b.stc;
+    d.rb.F = b.F;
+    d.rb.cdrift = (p.kT > 0 && p.thermal_drift) ? b.cdrift : nullptr;
+    d.rb.chunk_count = b.chunk_count;
+    d.rb.chunk_list = b.chunk_list;
+    d.rb.ovf_count = b.chunk_count + nchunks;
+    d.rb.ovf_list = b.ovf_list;
+    d.rb.ovf_cap = b.ovf_cap;
+    d.bp = blob_params(R);
+    d.bb = b;
+    d.cg = R.cells;
+    const double inv_n = 1.0 / (double)g.ncell;
+    d.solve[icm::kSolveH1] = icm::SolveCoef{p.rho / p.dt, 0.5 * p.eta, inv_n};
+    d.solve[icm::kSolveP] = icm::SolveCoef{1.0, 0.0, inv_n};
+    d.solve[icm::kSolveH2] = icm::SolveCoef{p.rho, 0.5 * p.dt * p.eta, inv_n};
+    const bool pairs = p.wca_eps > 0 && R.nb > 1;
+    d.pair_mode = !pairs ? 0 : (R.cells.heads ? 1 : 2);
+    d.step = R.d_step;
+    return d;
+}
+
+void drop_graph(icm_ctx* c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+// Group the replicas into batches and upload their descriptors (after any
+// change of blob counts or masses). Drops a captured step.
+template <typename T>
+icm_status sync_batches_t(icm_ctx* c) {
+    drop_graph(c);
+    c->batches.clear();
+    for (int r = 0; r < (int)c->reps.size(); ++r) {
+        const Replica& R = c->reps[r];
+        BatchInfo* hit = nullptr;
+        for (BatchInfo& B : c->batches)
+            if (B.n[0] == R.p.n[0] && B.n[1] == R.p.n[1] && B.n[2] == R.p.n[2] && B.kernel == R.p.kernel &&
+                B.any_me == R.any_me)
+                hit = &B;
+        if (!hit) {
+            BatchInfo B{};
+            for (int a = 0; a < 3; ++a) B.n[a] = R.p.n[a];
+            B.kernel = R.p.kernel;
+            B.any_me = R.any_me;
+            c->batches.push_back(B);
+            hit = &c->batches.back();
+        }
+        hit->reps.push_back(r);
+    }
+    std::vector<icm::RepDesc<T>> h(c->reps.size());
+    int slot = 0;
+    for (BatchInfo& B : c->batches) {
+        B.first = slot;
+        B.count = (int)B.reps.size();
+        B.max_nb = 0;
+        B.any_cells = B.any_all_pairs = false;
+        for (int r : B.reps) {
+            Replica& R = c->reps[r];
+            R.slot = slot;
+            h[slot] = build_desc<T>(R);
+            B.max_nb = std::max(B.max_nb, R.nb);
+            B.any_cells = B.any_cells || h[slot].pair_mode == 1;
+            B.any_all_pairs = B.any_all_pairs || h[slot].pair_mode == 2;
+            ++slot;
+        }
+    }
+    const size_t bytes = h.size() * sizeof(icm::RepDesc<T>);
+    c->h_desc.resize(bytes);
+    std::memcpy(c->h_desc.data(), h.data(), bytes);
+    HIP_TRY(c, hipMemcpyAsync(c->d_desc, c->h_desc.data(), bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return ICM_OK;
+}
+
+icm_status sync_batches(icm_ctx* c) {
+    return c->precision == ICM_FP64 ? sync_batches_t<double>(c) : sync_batches_t<float>(c);
+}
+
+template <typename T>
+icm::Batch<T> batch_view(icm_ctx* c, int first, int count, const Replica& R0, int max_nb, bool cells, bool all_pairs) {
+    icm::Batch<T> B;
+    B.d = static_cast<const icm::RepDesc<T>*>(c->d_desc) + first;
+    B.nrep = count;
+    B.g = grid_of<T>(const_cast<Replica&>(R0));
+    B.kernel = R0.p.kernel;
+    B.max_nb = max_nb;
+    B.any_cells = cells;
+    B.any_all_pairs = all_pairs;
+    B.one = count == 1 ? reinterpret_cast<const icm::RepDesc<T>*>(c->h_desc.data()) + first : nullptr;
+    return B;
+}
+
+template <typename T>
+icm::Batch<T> batch_of(icm_ctx* c, const BatchInfo& bi) {
+    return batch_view<T>(c, bi.first, bi.count, c->reps[bi.reps[0]], bi.max_nb, bi.any_cells, bi.any_all_pairs);
+}
+
+// The one-replica batch of replica R (set-up work outside the step).
+template <typename T>
+icm::Batch<T> single(icm_ctx* c, const Replica& R) {
+    return batch_view<T>(c, R.slot, 1, R, R.nb, false, false);
+}
+
 // Forward transform, spectral solve, inverse transform.
 template <typename T>
-void enqueue_fft_solve(icm_ctx* c, const icm::GridDesc<T>& g, const T* in, T* out, bool accumulate,
-                       icm::SolveCoef sc, hipStream_t s) {
-    timed(c, ICM_PHASE_FFT_X_FWD, s, [&] { icm::launch_fft_x_forward(g, in, s); });
-    timed(c, ICM_PHASE_FFT_Y_FWD, s, [&] { icm::launch_fft_y(g, -1, s); });
-    timed(c, ICM_PHASE_FFT_Z_SOLVE, s, [&] { icm::launch_fft_z_solve(g, sc, true, s); });
-    timed(c, ICM_PHASE_FFT_Y_INV, s, [&] { icm::launch_fft_y(g, 1, s); });
-    timed(c, ICM_PHASE_FFT_X_INV, s, [&] { icm::launch_fft_x_inverse(g, out, accumulate, s); });
+void enqueue_fft_solve(icm_ctx* c, const icm::Batch<T>& B, int in, int out, bool accumulate, int solve,
+                       hipStream_t s) {
+    timed(c, ICM_PHASE_FFT_X_FWD, s, [&] { icm::launch_fft_x_forward(B, in, s); });
+    timed(c, ICM_PHASE_FFT_Y_FWD, s, [&] { icm::launch_fft_y(B, -1, s); });
+    timed(c, ICM_PHASE_FFT_Z_SOLVE, s, [&] { icm::launch_fft_z_solve(B, solve, true, s); });
+    timed(c, ICM_PHASE_FFT_Y_INV, s, [&] { icm::launch_fft_y(B, 1, s); });
+    timed(c, ICM_PHASE_FFT_X_INV, s, [&] { icm::launch_fft_x_inverse(B, out, accumulate, s); });
 }
 
-// One step of Sec. III.C for one replica, enqueued on stream s.
+// One step of Sec. III.C for every replica of a batch, enqueued on stream s.
+// Nothing here reads host state that changes from step to step.
 template <typename T>
-void enqueue_step(icm_ctx* c, Replica& R, hipStream_t s) {
-    icm::GridDesc<T>& g = grid_of<T>(R);
-    icm::BlobBufs& b = R.bb;
-    const icm::BlobParams bp = blob_params(R);
-    const int P = R.p.kernel, nb = R.nb;
-    const double inv_n = 1.0 / (double)g.ncell;
-    // Step 1: midpoint predictor, forces, and J^{n+1/2} v^n for step 9.
-    timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather_predict(g, P, bp, b, s); });
-    if (++R.cell_stamp == 0) R.cell_stamp = 1;  // stamp 0 marks never-written heads
-    timed(c, ICM_PHASE_FORCES, s, [&] { icm::launch_forces(bp, b, R.cells, R.cell_stamp, s); });
-    // J^{n+1/2} v^n (step 9), and the stencils and z-chunk bins of the spread
-    timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather_bins(g, P, bp, b, R.max_nb, s); });
-    timed(c, ICM_PHASE_SPREAD, s, [&] {
-        icm::launch_bins(P, nb, g.nz, g.h, b.qh, R.max_nb, b.chunk_count, b.chunk_list, s);
-    });
-    // Step 2: unperturbed fluid solve.
-    icm::RhsCoef rc;
-    rc.rho_dt = R.p.rho / R.p.dt;
-    rc.half_eta_h2 = 0.5 * R.p.eta / (R.p.h * R.p.h);
-    rc.noise = R.p.kT > 0 ? std::sqrt(R.p.kT * R.p.eta / (R.p.h * R.p.h * R.p.h * R.p.dt)) / R.p.h : 0.0;
-    for (int a = 0; a < 3; ++a) rc.body[a] = R.p.body_force[a];
-    rc.key = noise_key(R, R.step);
-    // S F and the thermal drift are spread inside the right-hand-side kernel.
-    icm::RhsBlobs rb;
-    rb.nb = nb;
-    rb.kernel = P;
-    rb.cap = R.max_nb;
-    rb.stc = b.stc;
-    rb.F = b.F;
-    rb.cdrift = (R.p.kT > 0 && R.p.thermal_drift) ? b.cdrift : nullptr;
-    rb.chunk_count = b.chunk_count;
-    rb.chunk_list = b.chunk_list;
-    rb.ovf_count = b.chunk_count + (g.nz + icm::kRhsZChunk - 1) / icm::kRhsZChunk;
-    rb.ovf_list = b.ovf_list;
-    rb.ovf_cap = b.ovf_cap;
-    timed(c, ICM_PHASE_RHS, s, [&] { icm::launch_rhs(g, rc, rb, s); });
-    timed(c, ICM_PHASE_SPREAD, s, [&] { icm::launch_spread_overflow(g, rb, s); });
-    enqueue_fft_solve(c, g, g.rhs, g.v, false, icm::SolveCoef{R.p.rho / R.p.dt, 0.5 * R.p.eta, inv_n}, s);
-    if (R.any_me) {
+void enqueue_step(icm_ctx* c, const BatchInfo& bi, hipStream_t s) {
+    const icm::Batch<T> B = batch_of<T>(c, bi);
+    using namespace icm;
+    // Step 1: midpoint predictor; forces at q^{n+1/2}; J^{n+1/2} v^n (for
+    // step 9) with the stencils and z-chunk bins of the spread.
+    timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather_predict(B, s); });
+    timed(c, ICM_PHASE_FORCES, s, [&] { launch_forces(B, s); });
+    timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather_bins(B, s); });
+    timed(c, ICM_PHASE_SPREAD, s, [&] { launch_bins(B, s); });
+    // Step 2: unperturbed fluid solve; S F and the thermal drift are spread
+    // inside the right-hand-side kernel.
+    timed(c, ICM_PHASE_RHS, s, [&] { launch_rhs(B, s); });
+    timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread_overflow(B, s); });
+    enqueue_fft_solve(c, B, kFieldRhs, kFieldV, false, kSolveH1, s);
+    if (bi.any_me) {
         // Step 4: slip correction and excess-momentum change.
-        timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather(g, g.v, P, nb, b.qh, b.Jhvt, false, s); });
-        timed(c, ICM_PHASE_BLOB, s, [&] { icm::launch_inertial_dp(bp, b, s); });
+        timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather(B, kFieldV, kBlobQh, kBlobJhvt, false, s); });
+        timed(c, ICM_PHASE_BLOB, s, [&] { launch_inertial_dp(B, s); });
         // Step 5: dv~ = m~_f/(rho m~) P S dp.
-        timed(c, ICM_PHASE_FIELD_OPS, s, [&] { icm::launch_zero(g.rhs, 3 * g.ncell, s); });
-        timed(c, ICM_PHASE_SPREAD, s, [&] { icm::launch_spread(g, g.rhs, P, nb, b.qh, b.dp, b.c5, false, s); });
-        enqueue_fft_solve(c, g, g.rhs, g.aux, false, icm::SolveCoef{1.0, 0.0, inv_n}, s);
-        timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather(g, g.aux, P, nb, b.qh, b.g, false, s); });
+        timed(c, ICM_PHASE_FIELD_OPS, s, [&] { launch_zero(B, kFieldRhs, s); });
+        timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread(B, kFieldRhs, kBlobQh, kBlobDp, kBlobC5, s); });
+        enqueue_fft_solve(c, B, kFieldRhs, kFieldAux, false, kSolveP, s);
+        timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather(B, kFieldAux, kBlobQh, kBlobG, false, s); });
         // Step 6: (rho - dt/2 eta L) dv + dt G dpi = S (dp - m_e J dv~).
-        timed(c, ICM_PHASE_BLOB, s, [&] { icm::launch_inertial_dp2(bp, b, s); });
-        timed(c, ICM_PHASE_FIELD_OPS, s, [&] { icm::launch_zero(g.rhs, 3 * g.ncell, s); });
-        timed(c, ICM_PHASE_SPREAD, s, [&] { icm::launch_spread(g, g.rhs, P, nb, b.qh, b.dp2, nullptr, false, s); });
-        enqueue_fft_solve(c, g, g.rhs, g.aux, false, icm::SolveCoef{R.p.rho, 0.5 * R.p.dt * R.p.eta, inv_n}, s);
+        timed(c, ICM_PHASE_BLOB, s, [&] { launch_inertial_dp2(B, s); });
+        timed(c, ICM_PHASE_FIELD_OPS, s, [&] { launch_zero(B, kFieldRhs, s); });
+        timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread(B, kFieldRhs, kBlobQh, kBlobDp2, kBlobNone, s); });
+        enqueue_fft_solve(c, B, kFieldRhs, kFieldAux, false, kSolveH2, s);
         // Step 7, lagged J L dv, step 8.
-        timed(c, ICM_PHASE_FIELD_OPS, s, [&] { icm::launch_axpy(g.v, g.aux, 3 * g.ncell, s); });
-        timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather(g, g.aux, P, nb, b.qh, b.lag, true, s); });
-        timed(c, ICM_PHASE_BLOB, s, [&] { icm::launch_inertial_u(bp, b, s); });
+        timed(c, ICM_PHASE_FIELD_OPS, s, [&] { launch_axpy(B, kFieldV, kFieldAux, s); });
+        timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather(B, kFieldAux, kBlobQh, kBlobLag, true, s); });
+        timed(c, ICM_PHASE_BLOB, s, [&] { launch_inertial_u(B, s); });
     }
-    // Step 9.
-    const int n_clear = (g.nz + icm::kRhsZChunk - 1) / icm::kRhsZChunk + 1;
-    timed(c, ICM_PHASE_GATHER, s, [&] { icm::launch_gather_final(g, P, bp, b, n_clear, s); });
-    R.step += 1;
+    // Step 9 (also advances the device step counters).
+    timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather_final(B, s); });
 }
 
 template <typename T>
-void enqueue_project(Replica& R, const T* in, bool accumulate, hipStream_t s) {
-    icm::GridDesc<T>& g = grid_of<T>(R);
-    icm::launch_fft_forward_solve_inverse(g, in, g.v, accumulate, icm::SolveCoef{1.0, 0.0, 1.0 / (double)g.ncell},
-                                          true, s);
+void enqueue_all(icm_ctx* c, hipStream_t s) {
+    for (const BatchInfo& bi : c->batches) enqueue_step<T>(c, bi, s);
+}
+
+// v (+)= P(field in) for one replica.
+template <typename T>
+void enqueue_project(icm_ctx* c, const Replica& R, int in, bool accumulate, hipStream_t s) {
+    const icm::Batch<T> B = single<T>(c, R);
+    icm::launch_fft_x_forward(B, in, s);
+    icm::launch_fft_y(B, -1, s);
+    icm::launch_fft_z_solve(B, icm::kSolveP, true, s);
+    icm::launch_fft_y(B, 1, s);
+    icm::launch_fft_x_inverse(B, icm::kFieldV, accumulate, s);
+}
+
+// v += P S (impulse) / rho with the impulse already in dp (ICM_BLOBS_KICK).
+template <typename T>
+void kick(icm_ctx* c, const Replica& R, hipStream_t s) {
+    const icm::Batch<T> B = single<T>(c, R);
+    icm::launch_zero(B, icm::kFieldRhs, s);
+    icm::launch_spread(B, icm::kFieldRhs, icm::kBlobQ, icm::kBlobDp, icm::kBlobNone, s);
+    enqueue_project<T>(c, R, icm::kFieldRhs, true, s);
+}
+
+// Record one step of every batch into a graph (kernel launches only; the
+// step counters and all per-replica data live in device memory).
+icm_status capture_step(icm_ctx* c) {
+    drop_graph(c);
+    if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    if (c->precision == ICM_FP64)
+        enqueue_all<double>(c, c->cap_stream);
+    else
+        enqueue_all<float>(c, c->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        c->error_state = true;
+        return fail(c, ICM_E_DEVICE, "step capture failed: %s", hipGetErrorString(e));
+    }
+    c->graph = g;
+    HIP_TRY(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+    return ICM_OK;
 }
 
 icm_status check_replica(icm_ctx* c, int32_t replica) {
@@ -518,7 +687,7 @@ icm_status icm_create(int32_t n_rep, const icm_replica_params* p, const int32_t*
         c->ws_bytes = need;
     }
     c->reps.resize(n_rep);
-    layout(n_rep, p, max_blobs, precision, c->ws, &c->reps);
+    layout(n_rep, p, max_blobs, precision, c->ws, &c->reps, &c->d_desc);
     for (int r = 0; r < n_rep; ++r) {
         Replica& R = c->reps[r];
         R.p = p[r];
@@ -543,6 +712,7 @@ icm_status icm_create(int32_t n_rep, const icm_replica_params* p, const int32_t*
         if (e == hipSuccess)
             e = hipMemsetAsync(R.bb.chunk_count, 0,
                                sizeof(int) * ((p[r].n[2] + icm::kRhsZChunk - 1) / icm::kRhsZChunk + 1), c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(R.d_step, 0, sizeof(unsigned long long), c->stream);
         if (e != hipSuccess) {
             g_last_error = std::string("hipMemsetAsync failed: ") + hipGetErrorString(e);
             icm_destroy(c);
@@ -553,6 +723,12 @@ icm_status icm_create(int32_t n_rep, const icm_replica_params* p, const int32_t*
         g_last_error = "stream synchronisation failed after create";
         icm_destroy(c);
         return ICM_E_DEVICE;
+    }
+    st = sync_batches(c);
+    if (st != ICM_OK) {
+        g_last_error = c->err;
+        icm_destroy(c);
+        return st;
     }
     *out = c;
     return ICM_OK;
@@ -607,6 +783,8 @@ icm_status icm_set_blobs(icm_ctx* c, int32_t replica, int32_t n_blobs, const dou
     }
     R.nb = n_blobs;
     R.any_me = any;
+    st = sync_batches(c);
+    if (st != ICM_OK) return st;
     if ((flags & ICM_BLOBS_KICK) && n_blobs) {
         // v += P S (m~_f u0) / rho
         std::vector<double> imp(n3, 0.0);
@@ -620,15 +798,10 @@ icm_status icm_set_blobs(icm_ctx* c, int32_t replica, int32_t n_blobs, const dou
         }
         for (auto& x : imp) x *= R.mt_f / R.p.rho;
         HIP_TRY(c, hipMemcpyAsync(R.bb.dp, imp.data(), n3 * sizeof(double), hipMemcpyHostToDevice, s));
-        if (c->precision == ICM_FP64) {
-            icm::launch_zero(R.gd.rhs, 3 * R.gd.ncell, s);
-            icm::launch_spread(R.gd, R.gd.rhs, R.p.kernel, n_blobs, R.bb.q, R.bb.dp, nullptr, false, s);
-            enqueue_project<double>(R, R.gd.rhs, true, s);
-        } else {
-            icm::launch_zero(R.gf.rhs, 3 * R.gf.ncell, s);
-            icm::launch_spread(R.gf, R.gf.rhs, R.p.kernel, n_blobs, R.bb.q, R.bb.dp, nullptr, false, s);
-            enqueue_project<float>(R, R.gf.rhs, true, s);
-        }
+        if (c->precision == ICM_FP64)
+            kick<double>(c, R, s);
+        else
+            kick<float>(c, R, s);
         HIP_TRY(c, hipGetLastError());
     }
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -647,22 +820,21 @@ icm_status icm_set_state(icm_ctx* c, int32_t replica, const void* v, const doubl
     const size_t fb = field_bytes(c, R);
     if (flags & ICM_STATE_EQUILIBRIUM) {
         const double sd = std::sqrt(R.p.kT / (R.p.rho * R.p.h * R.p.h * R.p.h));
-        const icm::NoiseKey nk = noise_key(R, 0);
         if (c->precision == ICM_FP64) {
-            icm::launch_equilibrium_noise(R.gd, sd, nk, s);
-            enqueue_project<double>(R, R.gd.rhs, false, s);
+            icm::launch_equilibrium_noise(single<double>(c, R), sd, s);
+            enqueue_project<double>(c, R, icm::kFieldRhs, false, s);
         } else {
-            icm::launch_equilibrium_noise(R.gf, sd, nk, s);
-            enqueue_project<float>(R, R.gf.rhs, false, s);
+            icm::launch_equilibrium_noise(single<float>(c, R), sd, s);
+            enqueue_project<float>(c, R, icm::kFieldRhs, false, s);
         }
         HIP_TRY(c, hipGetLastError());
     } else if (v) {
         if (flags & ICM_STATE_PROJECT) {
             HIP_TRY(c, hipMemcpyAsync(rhs_ptr(c, R), v, fb, kind, s));
             if (c->precision == ICM_FP64)
-                enqueue_project<double>(R, R.gd.rhs, false, s);
+                enqueue_project<double>(c, R, icm::kFieldRhs, false, s);
             else
-                enqueue_project<float>(R, R.gf.rhs, false, s);
+                enqueue_project<float>(c, R, icm::kFieldRhs, false, s);
             HIP_TRY(c, hipGetLastError());
         } else {
             HIP_TRY(c, hipMemcpyAsync(field_ptr(c, R), v, fb, kind, s));
@@ -676,7 +848,11 @@ icm_status icm_set_state(icm_ctx* c, int32_t replica, const void* v, const doubl
         else
             HIP_TRY(c, hipMemsetAsync(R.bb.lag, 0, n3 * sizeof(double), s));
     }
-    if (step >= 0) R.step = step;
+    if (step >= 0) {
+        R.step = step;
+        const unsigned long long st64 = (unsigned long long)step;
+        HIP_TRY(c, hipMemcpyAsync(R.d_step, &st64, sizeof(st64), hipMemcpyHostToDevice, s));
+    }
     HIP_TRY(c, hipMemsetAsync(R.bb.flag, 0, sizeof(unsigned int), s));
     HIP_TRY(c, hipStreamSynchronize(s));
     c->error_state = false;
@@ -684,19 +860,26 @@ icm_status icm_set_state(icm_ctx* c, int32_t replica, const void* v, const doubl
 }
 
 icm_status icm_step(icm_ctx* c, int64_t n_steps, uint32_t flags) {
-    (void)flags;
     if (!c) return fail(nullptr, ICM_E_INVALID, "NULL context");
     if (c->error_state) return fail(c, ICM_E_STATE, "context is in an error state; call icm_set_state first");
     if (n_steps < 0) return fail(c, ICM_E_INVALID, "n_steps must be >= 0");
+    if (flags & ~(uint32_t)ICM_STEP_GRAPH) return fail(c, ICM_E_INVALID, "unknown icm_step flags 0x%x", flags);
     hipStream_t s = c->stream;
+    const bool graph = (flags & ICM_STEP_GRAPH) && !c->timing;
+    if (graph && n_steps > 0 && !c->graph_exec) {
+        icm_status st = capture_step(c);
+        if (st != ICM_OK) return st;
+    }
     for (int64_t n = 0; n < n_steps; ++n) {
-        for (Replica& R : c->reps) {
-            if (c->precision == ICM_FP64)
-                enqueue_step<double>(c, R, s);
-            else
-                enqueue_step<float>(c, R, s);
+        if (graph) {
+            HIP_TRY(c, hipGraphLaunch(c->graph_exec, s));
+        } else if (c->precision == ICM_FP64) {
+            enqueue_all<double>(c, s);
+        } else {
+            enqueue_all<float>(c, s);
         }
     }
+    for (Replica& R : c->reps) R.step += n_steps;
     HIP_TRY(c, hipGetLastError());
     unsigned int flag = 0;
     for (Replica& R : c->reps) {
@@ -779,6 +962,8 @@ void icm_destroy(icm_ctx* c) {
     if (!c) return;
     if (c->stream || c->owns_ws) (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->owns_ws && c->ws) (void)hipFree(c->ws);
     delete c;
 }

@@ -14,10 +14,19 @@ constexpr int kThreads = 256;
 
 // F = f_const - k (q - c): the one-body forces at q^{n+1/2}, the positions
 // folded into the box, q - L floor(q / L), and (with pair forces) the blob's
-// insertion into its cell's list. A cell head holds (stamp << 32 | blob) with
+// insertion into its cell's list. A cell head holds (stamp << 24 | blob) with
 // the step's stamp, so heads left from earlier steps read as empty and the
-// head array never needs clearing.
-__global__ void k_forces_init(BlobParams bp, BlobBufs b, CellGrid cg, unsigned int stamp) {
+// head array never needs clearing. Replica blockIdx.y.
+__device__ __forceinline__ unsigned long long cell_stamp(unsigned long long step) {
+    return (step + 1) & ((1ULL << (64 - kHeadBlobBits)) - 1);
+}
+
+template <typename T>
+__global__ void k_forces_init(const RepDesc<T>* __restrict__ rd) {
+    const BlobParams bp = rd[blockIdx.y].bp;
+    const BlobBufs b = rd[blockIdx.y].bb;
+    const CellGrid cg = rd[blockIdx.y].cg;
+    const bool cells = rd[blockIdx.y].pair_mode == 1;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= bp.nb) return;
     int ci[3];
@@ -32,19 +41,26 @@ __global__ void k_forces_init(BlobParams bp, BlobBufs b, CellGrid cg, unsigned i
         int c = (int)(w * cg.inv_size[a]);
         ci[a] = c >= cg.n[a] ? cg.n[a] - 1 : (c < 0 ? 0 : c);
     }
-    if (cg.heads) {
+    if (cells) {
+        const unsigned long long stamp = cell_stamp(*rd[blockIdx.y].step);
         const long long cell = ((long long)ci[2] * cg.n[1] + ci[1]) * cg.n[0] + ci[0];
-        const unsigned long long mine = ((unsigned long long)stamp << 32) | (unsigned int)i;
+        const unsigned long long mine = (stamp << kHeadBlobBits) | (unsigned long long)i;
         const unsigned long long old = atomicExch(&cg.heads[cell], mine);
-        cg.next[i] = ((unsigned int)(old >> 32) == stamp) ? (int)(old & 0xffffffffu) : -1;
+        cg.next[i] = ((old >> kHeadBlobBits) == stamp) ? (int)(old & ((1u << kHeadBlobBits) - 1)) : -1;
     }
 }
 
 // F += WCA pair forces (Eq. (WCA), minimum image, unordered pairs counted
 // once) at q^{n+1/2}: each blob walks the lists of the 27 cells around its
-// own (cells are at least one cutoff wide, at least 3 per axis).
-__global__ void __launch_bounds__(kThreads) k_pairs_cells(BlobParams bp, BlobBufs b, CellGrid cg,
-                                                          unsigned int stamp) {
+// own (cells are at least one cutoff wide, at least 3 per axis). Replica
+// blockIdx.y.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_pairs_cells(const RepDesc<T>* __restrict__ rd) {
+    if (rd[blockIdx.y].pair_mode != 1) return;
+    const BlobParams bp = rd[blockIdx.y].bp;
+    const BlobBufs b = rd[blockIdx.y].bb;
+    const CellGrid cg = rd[blockIdx.y].cg;
+    const unsigned long long stamp = cell_stamp(*rd[blockIdx.y].step);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= bp.nb) return;
     const double qx = b.qw[3 * i], qy = b.qw[3 * i + 1], qz = b.qw[3 * i + 2];
@@ -66,7 +82,7 @@ __global__ void __launch_bounds__(kThreads) k_pairs_cells(BlobParams bp, BlobBuf
             for (int dx = -1; dx <= 1; ++dx) {
                 const int x = (c[0] + dx + cg.n[0]) % cg.n[0];
                 const unsigned long long h = cg.heads[((long long)z * cg.n[1] + y) * cg.n[0] + x];
-                int j = ((unsigned int)(h >> 32) == stamp) ? (int)(h & 0xffffffffu) : -1;
+                int j = ((h >> kHeadBlobBits) == stamp) ? (int)(h & ((1u << kHeadBlobBits) - 1)) : -1;
                 while (j >= 0) {
                     if (j != i) {
                         double ex = qx - b.qw[3 * j], ey = qy - b.qw[3 * j + 1], ez = qz - b.qw[3 * j + 2];
@@ -95,11 +111,16 @@ __global__ void __launch_bounds__(kThreads) k_pairs_cells(BlobParams bp, BlobBuf
 
 // All-pairs WCA forces, for boxes too small for a 3-cell list: block (bx, by)
 // takes blobs i of tile bx against the folded positions of the kPairTile blobs
-// of tile by held in LDS; partial sums are added to F atomically.
+// of tile by held in LDS; partial sums are added to F atomically. Replica
+// blockIdx.z.
 constexpr int kPairTile = 64;
 
-__global__ void __launch_bounds__(kThreads) k_pairs(BlobParams bp, BlobBufs b) {
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_pairs(const RepDesc<T>* __restrict__ rd) {
     __shared__ double tile[3][kPairTile];
+    if (rd[blockIdx.z].pair_mode != 2) return;
+    const BlobParams bp = rd[blockIdx.z].bp;
+    const BlobBufs b = rd[blockIdx.z].bb;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j0 = blockIdx.y * kPairTile;
     const int jl = j0 + threadIdx.x;
@@ -143,7 +164,10 @@ __global__ void __launch_bounds__(kThreads) k_pairs(BlobParams bp, BlobBufs b) {
 
 // Step 4: du = [FULL] (J^{n+1/2} - J^n) v^n + [VISCOUS|FULL] (nu dt/2) c_lag;
 // dp = m_e (u^n - J^{n+1/2} v~ - du).
-__global__ void k_inertial_dp(BlobParams bp, BlobBufs b) {
+template <typename T>
+__global__ void k_inertial_dp(const RepDesc<T>* __restrict__ rd) {
+    const BlobParams bp = rd[blockIdx.y].bp;
+    const BlobBufs b = rd[blockIdx.y].bb;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 3 * bp.nb) return;
     double du = 0.0;
@@ -154,14 +178,20 @@ __global__ void k_inertial_dp(BlobParams bp, BlobBufs b) {
 }
 
 // Step 6 right-hand side: dp - m_e J dv~.
-__global__ void k_inertial_dp2(BlobParams bp, BlobBufs b) {
+template <typename T>
+__global__ void k_inertial_dp2(const RepDesc<T>* __restrict__ rd) {
+    const BlobParams bp = rd[blockIdx.y].bp;
+    const BlobBufs b = rd[blockIdx.y].bb;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 3 * bp.nb) return;
     b.dp2[t] = b.dp[t] - b.me[t / 3] * b.g[t];
 }
 
 // Step 8: u^{n+1} = J (v~ + dv~) + du for blobs with m_e != 0.
-__global__ void k_inertial_u(BlobParams bp, BlobBufs b) {
+template <typename T>
+__global__ void k_inertial_u(const RepDesc<T>* __restrict__ rd) {
+    const BlobParams bp = rd[blockIdx.y].bp;
+    const BlobBufs b = rd[blockIdx.y].bb;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 3 * bp.nb) return;
     if (b.me[t / 3] != 0.0) b.u[t] = b.Jhvt[t] + b.g[t] + b.du[t];
@@ -189,37 +219,45 @@ __global__ void k_blob_diag(int nb, const double* me, const double* u, double* a
         for (int m = 0; m < 4; ++m) acc[m] = red[m][0];
 }
 
-dim3 grid3(int nb) { return dim3((unsigned)((3 * nb + kThreads - 1) / kThreads)); }
+dim3 grid3(const int nb, int nrep) { return dim3((unsigned)((3 * nb + kThreads - 1) / kThreads), nrep); }
 
 }  // namespace
 
-void launch_forces(const BlobParams& bp, const BlobBufs& b, const CellGrid& cg, unsigned int stamp, hipStream_t s) {
-    if (bp.nb <= 0) return;
-    const bool pairs = bp.wca_eps != 0.0 && bp.nb > 1;
-    const bool cells = pairs && cg.heads != nullptr;
-    CellGrid none = cg;
-    if (!cells) none.heads = nullptr;
-    const dim3 g1((unsigned)((bp.nb + kThreads - 1) / kThreads));
-    hipLaunchKernelGGL(k_forces_init, g1, dim3(kThreads), 0, s, bp, b, none, stamp);
-    if (cells) {
-        hipLaunchKernelGGL(k_pairs_cells, g1, dim3(kThreads), 0, s, bp, b, cg, stamp);
-    } else if (pairs) {
-        const unsigned ti = (unsigned)((bp.nb + kThreads - 1) / kThreads);
-        const unsigned tj = (unsigned)((bp.nb + kPairTile - 1) / kPairTile);
-        hipLaunchKernelGGL(k_pairs, dim3(ti, tj), dim3(kThreads), 0, s, bp, b);
+template <typename T>
+void launch_forces(const Batch<T>& B, hipStream_t s) {
+    if (B.max_nb <= 0) return;
+    const dim3 g1((unsigned)((B.max_nb + kThreads - 1) / kThreads), B.nrep);
+    hipLaunchKernelGGL(k_forces_init<T>, g1, dim3(kThreads), 0, s, B.d);
+    if (B.any_cells) hipLaunchKernelGGL(k_pairs_cells<T>, g1, dim3(kThreads), 0, s, B.d);
+    if (B.any_all_pairs) {
+        const unsigned ti = (unsigned)((B.max_nb + kThreads - 1) / kThreads);
+        const unsigned tj = (unsigned)((B.max_nb + kPairTile - 1) / kPairTile);
+        hipLaunchKernelGGL(k_pairs<T>, dim3(ti, tj, B.nrep), dim3(kThreads), 0, s, B.d);
     }
 }
-void launch_inertial_dp(const BlobParams& bp, const BlobBufs& b, hipStream_t s) {
-    if (bp.nb > 0) hipLaunchKernelGGL(k_inertial_dp, grid3(bp.nb), dim3(kThreads), 0, s, bp, b);
+template <typename T>
+void launch_inertial_dp(const Batch<T>& B, hipStream_t s) {
+    if (B.max_nb > 0) hipLaunchKernelGGL(k_inertial_dp<T>, grid3(B.max_nb, B.nrep), dim3(kThreads), 0, s, B.d);
 }
-void launch_inertial_dp2(const BlobParams& bp, const BlobBufs& b, hipStream_t s) {
-    if (bp.nb > 0) hipLaunchKernelGGL(k_inertial_dp2, grid3(bp.nb), dim3(kThreads), 0, s, bp, b);
+template <typename T>
+void launch_inertial_dp2(const Batch<T>& B, hipStream_t s) {
+    if (B.max_nb > 0) hipLaunchKernelGGL(k_inertial_dp2<T>, grid3(B.max_nb, B.nrep), dim3(kThreads), 0, s, B.d);
 }
-void launch_inertial_u(const BlobParams& bp, const BlobBufs& b, hipStream_t s) {
-    if (bp.nb > 0) hipLaunchKernelGGL(k_inertial_u, grid3(bp.nb), dim3(kThreads), 0, s, bp, b);
+template <typename T>
+void launch_inertial_u(const Batch<T>& B, hipStream_t s) {
+    if (B.max_nb > 0) hipLaunchKernelGGL(k_inertial_u<T>, grid3(B.max_nb, B.nrep), dim3(kThreads), 0, s, B.d);
 }
 void launch_blob_diag(int nb, const double* me, const double* u, double* acc, hipStream_t s) {
     hipLaunchKernelGGL(k_blob_diag, dim3(1), dim3(kThreads), 0, s, nb, me, u, acc);
 }
+
+#define ICM_INST(T)                                                          \
+    template void launch_forces<T>(const Batch<T>&, hipStream_t);            \
+    template void launch_inertial_dp<T>(const Batch<T>&, hipStream_t);       \
+    template void launch_inertial_dp2<T>(const Batch<T>&, hipStream_t);      \
+    template void launch_inertial_u<T>(const Batch<T>&, hipStream_t);
+ICM_INST(float)
+ICM_INST(double)
+#undef ICM_INST
 
 }  // namespace icm

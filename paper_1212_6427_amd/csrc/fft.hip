@@ -136,14 +136,16 @@ __device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* src, 
 // ----------------------------------------------------------------- x pass
 // Rows 2p and 2p+1 of a component (same z, y and y+1) form z = a + i b.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_xfwd(GridDesc<T> g, const T* __restrict__ in, int pp) {
+__global__ void __launch_bounds__(kThreads) k_xfwd(const RepDesc<T>* __restrict__ rd, int in_sel, int pp) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* sm = reinterpret_cast<cplx<T>*>(smem_raw);
+    const GridDesc<T>& g = rd[blockIdx.y / 3].g;
+    const T* __restrict__ in = field_of(g, in_sel);
     const int N = g.nx, W = g.W;
     cplx<T>* tw = sm;
     cplx<T>* b0 = sm + N;
     cplx<T>* b1 = b0 + pp * N;
-    const int c = blockIdx.y;
+    const int c = (int)(blockIdx.y % 3);
     const long long npairs = (long long)g.ny * g.nz / 2;
     const long long p0 = (long long)blockIdx.x * pp;
     load_twiddles(tw, g.twx, N);
@@ -171,14 +173,17 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(GridDesc<T> g, const T* __res
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_xinv(GridDesc<T> g, T* __restrict__ out, int pp, int accumulate) {
+__global__ void __launch_bounds__(kThreads) k_xinv(const RepDesc<T>* __restrict__ rd, int out_sel, int pp,
+                                                   int accumulate) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* sm = reinterpret_cast<cplx<T>*>(smem_raw);
+    const GridDesc<T>& g = rd[blockIdx.y / 3].g;
+    T* __restrict__ out = field_of(g, out_sel);
     const int N = g.nx, W = g.W, H = g.nx / 2;
     cplx<T>* tw = sm;
     cplx<T>* b0 = sm + N;
     cplx<T>* b1 = b0 + pp * N;
-    const int c = blockIdx.y;
+    const int c = (int)(blockIdx.y % 3);
     const long long npairs = (long long)g.ny * g.nz / 2;
     const long long p0 = (long long)blockIdx.x * pp;
     load_twiddles(tw, g.twx, N);
@@ -224,9 +229,10 @@ __global__ void __launch_bounds__(kThreads) k_xinv(GridDesc<T> g, T* __restrict_
 
 // ----------------------------------------------------------------- y pass
 template <typename T, int DIR>
-__global__ void __launch_bounds__(kThreads) k_ypass(GridDesc<T> g, int B) {
+__global__ void __launch_bounds__(kThreads) k_ypass(const RepDesc<T>* __restrict__ rd, int B) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* sm = reinterpret_cast<cplx<T>*>(smem_raw);
+    const GridDesc<T>& g = rd[blockIdx.z / 3].g;
     const int N = g.ny, W = g.W;
     cplx<T>* tw = sm;
     cplx<T>* b0 = sm + N;
@@ -234,7 +240,7 @@ __global__ void __launch_bounds__(kThreads) k_ypass(GridDesc<T> g, int B) {
     const int kx0 = blockIdx.x * B;
     const int bw = min(B, W - kx0);
     const int z = blockIdx.y;
-    const int c = blockIdx.z;
+    const int c = (int)(blockIdx.z % 3);
     load_twiddles(tw, g.twy, N);
     cplx<T>* base = g.spec + (long long)c * g.nspec + (long long)z * N * g.Wp + kx0;
     for (int idx = threadIdx.x; idx < N * B; idx += blockDim.x) {
@@ -251,9 +257,12 @@ __global__ void __launch_bounds__(kThreads) k_ypass(GridDesc<T> g, int B) {
 
 // -------------------------------------------------------- z pass + solve
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_zsolve(GridDesc<T> g, int B, SolveCoef sc, int project) {
+__global__ void __launch_bounds__(kThreads) k_zsolve(const RepDesc<T>* __restrict__ rd, int B, int solve,
+                                                     int project) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* sm = reinterpret_cast<cplx<T>*>(smem_raw);
+    const GridDesc<T>& g = rd[blockIdx.z].g;
+    const SolveCoef sc = rd[blockIdx.z].solve[solve];
     const int N = g.nz, W = g.W, NY = g.ny;
     const int L3 = 3 * B;
     cplx<T>* tw = sm;
@@ -332,80 +341,63 @@ int zpass_width(int N, size_t cs) {
 }  // namespace
 
 template <typename T>
-void launch_fft_x_forward(const GridDesc<T>& g, const T* in, hipStream_t s, int c) {
-    if (g.fast) {
-        fast_fft_x_forward(g, in, c, s);
-        return;
-    }
+void launch_fft_x_forward(const Batch<T>& B, int in, hipStream_t s) {
+    const GridDesc<T>& g = B.g;
+    if (g.fast && fast_fft_x_forward(B, in, s)) return;
     const size_t cs = sizeof(cplx<T>);
     const int N = g.nx;
     const long long pp = (long long)xpass_lines(N, cs);
     const long long npairs = (long long)g.ny * g.nz / 2;
-    const dim3 grid((unsigned)((npairs + pp - 1) / pp), 3);
+    const dim3 grid((unsigned)((npairs + pp - 1) / pp), 3 * B.nrep);
     const size_t lds = (size_t)(N + 2 * pp * N) * cs;
-    hipLaunchKernelGGL(k_xfwd<T>, grid, dim3(kThreads), lds, s, g, in, (int)pp);
+    hipLaunchKernelGGL(k_xfwd<T>, grid, dim3(kThreads), lds, s, B.d, in, (int)pp);
 }
 
 template <typename T>
-void launch_fft_y(const GridDesc<T>& g, int dir, hipStream_t s, int c) {
-    if (g.fast) {
-        fast_fft_y(g, dir, c, s);
-        return;
-    }
+void launch_fft_y(const Batch<T>& B, int dir, hipStream_t s) {
+    const GridDesc<T>& g = B.g;
+    if (g.fast && fast_fft_y(B, dir, s)) return;
     const size_t cs = sizeof(cplx<T>);
     const int N = g.ny;
     const int By = ypass_width(N, cs);
-    const dim3 grid((unsigned)((g.W + By - 1) / By), g.nz, 3);
+    const dim3 grid((unsigned)((g.W + By - 1) / By), g.nz, 3 * B.nrep);
     const size_t lds = (size_t)(N + 2 * N * By) * cs;
     if (dir < 0)
-        hipLaunchKernelGGL((k_ypass<T, -1>), grid, dim3(kThreads), lds, s, g, By);
+        hipLaunchKernelGGL((k_ypass<T, -1>), grid, dim3(kThreads), lds, s, B.d, By);
     else
-        hipLaunchKernelGGL((k_ypass<T, 1>), grid, dim3(kThreads), lds, s, g, By);
+        hipLaunchKernelGGL((k_ypass<T, 1>), grid, dim3(kThreads), lds, s, B.d, By);
 }
 
 template <typename T>
-void launch_fft_z_solve(const GridDesc<T>& g, SolveCoef sc, bool project, hipStream_t s) {
-    if (g.fast && fast_fft_z_solve(g, sc, project, s)) return;
+void launch_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s) {
+    const GridDesc<T>& g = B.g;
+    if (g.fast && fast_fft_z_solve(B, solve, project, s)) return;
     const size_t cs = sizeof(cplx<T>);
     const int N = g.nz;
     const int Bz = zpass_width(N, cs);
-    const dim3 grid((unsigned)((g.W + Bz - 1) / Bz), g.ny);
+    const dim3 grid((unsigned)((g.W + Bz - 1) / Bz), g.ny, B.nrep);
     const size_t lds = (size_t)(N + 6 * N * Bz) * cs;
-    hipLaunchKernelGGL(k_zsolve<T>, grid, dim3(kThreads), lds, s, g, Bz, sc, project ? 1 : 0);
+    hipLaunchKernelGGL(k_zsolve<T>, grid, dim3(kThreads), lds, s, B.d, Bz, solve, project ? 1 : 0);
 }
 
 template <typename T>
-void launch_fft_x_inverse(const GridDesc<T>& g, T* out, bool accumulate, hipStream_t s, int c) {
-    if (g.fast) {
-        fast_fft_x_inverse(g, out, accumulate, c, s);
-        return;
-    }
+void launch_fft_x_inverse(const Batch<T>& B, int out, bool accumulate, hipStream_t s) {
+    const GridDesc<T>& g = B.g;
+    if (g.fast && fast_fft_x_inverse(B, out, accumulate, s)) return;
     const size_t cs = sizeof(cplx<T>);
     const int N = g.nx;
     const long long pp = (long long)xpass_lines(N, cs);
     const long long npairs = (long long)g.ny * g.nz / 2;
-    const dim3 grid((unsigned)((npairs + pp - 1) / pp), 3);
+    const dim3 grid((unsigned)((npairs + pp - 1) / pp), 3 * B.nrep);
     const size_t lds = (size_t)(N + 2 * pp * N) * cs;
-    hipLaunchKernelGGL(k_xinv<T>, grid, dim3(kThreads), lds, s, g, out, (int)pp, accumulate ? 1 : 0);
+    hipLaunchKernelGGL(k_xinv<T>, grid, dim3(kThreads), lds, s, B.d, out, (int)pp, accumulate ? 1 : 0);
 }
 
-template <typename T>
-void launch_fft_forward_solve_inverse(const GridDesc<T>& g, const T* in, T* out, bool accumulate,
-                                      SolveCoef sc, bool project, hipStream_t s) {
-    launch_fft_x_forward(g, in, s);
-    launch_fft_y(g, -1, s);
-    launch_fft_z_solve(g, sc, project, s);
-    launch_fft_y(g, 1, s);
-    launch_fft_x_inverse(g, out, accumulate, s);
-}
-
-#define ICM_INST(T)                                                                                          \
-    template void launch_fft_x_forward<T>(const GridDesc<T>&, const T*, hipStream_t, int);                   \
-    template void launch_fft_y<T>(const GridDesc<T>&, int, hipStream_t, int);                                \
-    template void launch_fft_z_solve<T>(const GridDesc<T>&, SolveCoef, bool, hipStream_t);                   \
-    template void launch_fft_x_inverse<T>(const GridDesc<T>&, T*, bool, hipStream_t, int);                   \
-    template void launch_fft_forward_solve_inverse<T>(const GridDesc<T>&, const T*, T*, bool, SolveCoef, bool, \
-                                                      hipStream_t);
+#define ICM_INST(T)                                                                     \
+    template void launch_fft_x_forward<T>(const Batch<T>&, int, hipStream_t);           \
+    template void launch_fft_y<T>(const Batch<T>&, int, hipStream_t);                   \
+    template void launch_fft_z_solve<T>(const Batch<T>&, int, bool, hipStream_t);       \
+    template void launch_fft_x_inverse<T>(const Batch<T>&, int, bool, hipStream_t);
 ICM_INST(float)
 ICM_INST(double)
 #undef ICM_INST

@@ -186,7 +186,8 @@ constexpr int xline() { return N + N / 16 + 1; }
 
 template <typename T>
 __device__ __forceinline__ void load_tw(cplx<T>* dst, const cplx<T>* src, int n) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+    const gptr<const cplx<T>> gs = as_global(src);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = gs[i];
 }
 
 // Spectrum layout: rows of W = nx/2 + 1 complex values at pitch Wp (a
@@ -195,18 +196,19 @@ __device__ __forceinline__ void load_tw(cplx<T>* dst, const cplx<T>* src, int n)
 // of B complex values.
 
 // ------------------------------------------------------------------ y pass
-// Block: B consecutive kx columns of one (z, component) plane; thread
-// (b = tid mod B, t = tid / B).
+// Block: B consecutive kx columns of one (z, component) plane of replica
+// blockIdx.z / 3; thread (b = tid mod B, t = tid / B).
 template <typename T, int N, int E, int R0, int R1, int R2, int DIR>
-__global__ void __launch_bounds__(512) k_y_fast(GridDesc<T> g, int B, int c) {
+__global__ void __launch_bounds__(512) k_y_fast(const RepDesc<T>* __restrict__ rd, int B) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* tws = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* lds = tws + N;
+    const GridDesc<T> g = rd[blockIdx.z / 3].g;
     const int b = threadIdx.x % B, t = threadIdx.x / B;
     const int kx0 = blockIdx.x * B;
     const bool ok = kx0 + b < g.W;
-    const int comp = c < 0 ? (int)blockIdx.z : c;
-    cplx<T>* base = g.spec + (long long)comp * g.nspec + (long long)blockIdx.y * N * g.Wp + kx0 + b;
+    const int comp = (int)(blockIdx.z % 3);
+    const gptr<cplx<T>> base = as_global(g.spec) + (long long)comp * g.nspec + (long long)blockIdx.y * N * g.Wp + kx0 + b;
     load_tw(tws, g.twy, N);
     constexpr int TL = N / E;
     cplx<T> a[E];
@@ -221,15 +223,19 @@ __global__ void __launch_bounds__(512) k_y_fast(GridDesc<T> g, int B, int c) {
 }
 
 // --------------------------------------------------------- z pass + solve
-// Block: B consecutive kx columns of one ky row; each thread (b = tid mod B,
+// Block: B consecutive kx columns of one ky row of replica blockIdx.z; each
+// thread (b = tid mod B,
 // t = tid / B) holds all three components of its column, so the Helmholtz
 // divide and the 3 x 3 projection of every mode happen in registers between
 // the forward and inverse transforms.
 template <typename T, int N, int E, int R0, int R1, int R2>
-__global__ void __launch_bounds__(512) k_z_fast(GridDesc<T> g, int B, SolveCoef sc, int project) {
+__global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ rd, int B, int solve,
+                                                 int project) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* tws = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* lds = tws + N;
+    const GridDesc<T> g = rd[blockIdx.z].g;
+    const SolveCoef sc = rd[blockIdx.z].solve[solve];
     const int b = threadIdx.x % B, t = threadIdx.x / B;
     const int kx0 = blockIdx.x * B;
     const int kx = kx0 + b;
@@ -238,9 +244,9 @@ __global__ void __launch_bounds__(512) k_z_fast(GridDesc<T> g, int B, SolveCoef 
     load_tw(tws, g.twz, N);
     constexpr int TL = N / E;
     const long long zs = (long long)g.ny * g.Wp;  // stride between z planes
-    cplx<T>* p0 = g.spec + (long long)y * g.Wp + kx;
-    cplx<T>* p1 = p0 + g.nspec;
-    cplx<T>* p2 = p1 + g.nspec;
+    const gptr<cplx<T>> p0 = as_global(g.spec) + (long long)y * g.Wp + kx;
+    const gptr<cplx<T>> p1 = p0 + g.nspec;
+    const gptr<cplx<T>> p2 = p1 + g.nspec;
     cplx<T> a0[E], a1[E], a2[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -254,18 +260,20 @@ __global__ void __launch_bounds__(512) k_z_fast(GridDesc<T> g, int B, SolveCoef 
     reg_fft<T, N, E, R0, R1, R2, -1>(a1, t, lds, B, b, tws);
     reg_fft<T, N, E, R0, R1, R2, -1>(a2, t, lds, B, b, tws);
     if (ok) {
-        const T lxy = g.lx[kx] + g.ly[y];
-        const cplx<T> dx = g.dx_hat[kx], dy = g.dy_hat[y];
+        const gptr<const T> glz = as_global(g.lz);
+        const gptr<const cplx<T>> gdz = as_global(g.dz_hat);
+        const T lxy = as_global(g.lx)[kx] + as_global(g.ly)[y];
+        const cplx<T> dx = as_global(g.dx_hat)[kx], dy = as_global(g.dy_hat)[y];
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int kz = t + TL * i;
-            const T lam = lxy + g.lz[kz];
+            const T lam = lxy + glz[kz];
             const T f = (T)(sc.scale / (sc.a + sc.b * (double)lam));
             cplx<T> w0 = {a0[i].x * f, a0[i].y * f};
             cplx<T> w1 = {a1[i].x * f, a1[i].y * f};
             cplx<T> w2 = {a2[i].x * f, a2[i].y * f};
             if (project && lam > (T)0) {
-                const cplx<T> dz = g.dz_hat[kz];
+                const cplx<T> dz = gdz[kz];
                 const cplx<T> d = cadd(cadd(cmul(dx, w0), cmul(dy, w1)), cmul(dz, w2));
                 const T il = (T)1 / lam;
                 const cplx<T> dd = {d.x * il, d.y * il};
@@ -293,21 +301,24 @@ __global__ void __launch_bounds__(512) k_z_fast(GridDesc<T> g, int B, SolveCoef 
 }
 
 // ------------------------------------------------------------------ x pass
-// Block: P row pairs of one component; thread (t = tid mod TL, l = tid / TL).
+// Block: P row pairs of component blockIdx.y mod 3 of replica blockIdx.y / 3;
+// thread (t = tid mod TL, l = tid / TL).
 // Rows 2p and 2p+1 are packed as z = a + i b; their half spectra are
 // separated by Hermitian symmetry after the transform.
 template <typename T, int N, int E, int R0, int R1, int R2>
-__global__ void __launch_bounds__(512) k_xfwd_fast(GridDesc<T> g, const T* __restrict__ in, int P, int cc) {
+__global__ void __launch_bounds__(512) k_xfwd_fast(const RepDesc<T>* __restrict__ rd, int in_sel, int P) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* tws = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* lds = tws + N;
+    const GridDesc<T> g = rd[blockIdx.y / 3].g;
+    const gptr<const T> in = as_global((const T*)field_of(rd[blockIdx.y / 3].g, in_sel));
+    const int c = (int)(blockIdx.y % 3);
     constexpr int TL = N / E;
     const int t = threadIdx.x % TL, l = threadIdx.x / TL;
     const int W = g.W;
     const long long npairs = (long long)g.ny * g.nz / 2;
     const long long p = (long long)blockIdx.x * P + l;
     const bool ok = p < npairs;
-    const int c = cc < 0 ? (int)blockIdx.y : cc;
     load_tw(tws, g.twx, N);
     // stage the block's row pairs through LDS with contiguous loads
     const long long row0 = (long long)c * g.ncell + 2 * ((long long)blockIdx.x * P) * N;
@@ -329,7 +340,7 @@ __global__ void __launch_bounds__(512) k_xfwd_fast(GridDesc<T> g, const T* __res
     for (int i = 0; i < E; ++i) lds[l * LS + skew<4>(t + TL * i)] = a[i];
     __syncthreads();
     if (!ok) return;
-    cplx<T>* d0 = g.spec + (long long)c * g.nspec + 2 * p * g.Wp;
+    const gptr<cplx<T>> d0 = as_global(g.spec) + (long long)c * g.nspec + 2 * p * g.Wp;
     for (int k = t; k < W; k += TL) {
         const cplx<T> zk = lds[l * LS + skew<4>(k)];
         const cplx<T> zc = cconj(lds[l * LS + skew<4>((N - k) % N)]);
@@ -340,11 +351,14 @@ __global__ void __launch_bounds__(512) k_xfwd_fast(GridDesc<T> g, const T* __res
 }
 
 template <typename T, int N, int E, int R0, int R1, int R2>
-__global__ void __launch_bounds__(512) k_xinv_fast(GridDesc<T> g, T* __restrict__ out, int P, int accumulate,
-                                                    int cc) {
+__global__ void __launch_bounds__(512) k_xinv_fast(const RepDesc<T>* __restrict__ rd, int out_sel, int P,
+                                                    int accumulate) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* tws = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* lds = tws + N;
+    const GridDesc<T> g = rd[blockIdx.y / 3].g;
+    const gptr<T> out = as_global(field_of(rd[blockIdx.y / 3].g, out_sel));
+    const int c = (int)(blockIdx.y % 3);
     constexpr int TL = N / E;
     constexpr int H = N / 2;
     const int t = threadIdx.x % TL, l = threadIdx.x / TL;
@@ -352,10 +366,9 @@ __global__ void __launch_bounds__(512) k_xinv_fast(GridDesc<T> g, T* __restrict_
     const long long npairs = (long long)g.ny * g.nz / 2;
     const long long p = (long long)blockIdx.x * P + l;
     const bool ok = p < npairs;
-    const int c = cc < 0 ? (int)blockIdx.y : cc;
     load_tw(tws, g.twx, N);
     const long long rp = g.Wp;
-    const cplx<T>* s0 = g.spec + (long long)c * g.nspec + 2 * p * rp;
+    const gptr<const cplx<T>> s0 = as_global((const cplx<T>*)g.spec) + (long long)c * g.nspec + 2 * p * rp;
     constexpr int LS = xline<N>();
     for (int k = t; k < W; k += TL) {
         cplx<T> A = {0, 0}, Bv = {0, 0};
@@ -454,74 +467,81 @@ int pairs_per_block(int N, int TL) {
 }
 
 template <typename T, int N>
-bool y_fast(const GridDesc<T>& g, int dir, int c, hipStream_t s) {
+bool y_fast(const Batch<T>& Bt, int dir, hipStream_t s) {
     using Pl = Plan<T, N>;
     if constexpr (!Pl::ok) {
         return false;
     } else {
+        const GridDesc<T>& g = Bt.g;
         constexpr int TL = N / Pl::E;
         int B = g.By;
         while (B > 1 && B * TL > 512) B /= 2;
-        const dim3 grid((unsigned)((g.W + B - 1) / B), g.nz, c < 0 ? 3 : 1);
+        const dim3 grid((unsigned)((g.W + B - 1) / B), g.nz, 3 * Bt.nrep);
         const size_t lds = (size_t)N * (B + 1) * sizeof(cplx<T>);
         if (dir < 0) {
             allow_lds(k_y_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, -1>, lds);
-            hipLaunchKernelGGL((k_y_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, -1>), grid, dim3(B * TL), lds, s, g, B, c);
+            hipLaunchKernelGGL((k_y_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, -1>), grid, dim3(B * TL), lds, s, Bt.d,
+                               B);
         } else {
             allow_lds(k_y_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, 1>, lds);
-            hipLaunchKernelGGL((k_y_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, 1>), grid, dim3(B * TL), lds, s, g, B, c);
+            hipLaunchKernelGGL((k_y_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, 1>), grid, dim3(B * TL), lds, s, Bt.d,
+                               B);
         }
         return true;
     }
 }
 
 template <typename T, int N>
-bool z_fast(const GridDesc<T>& g, SolveCoef sc, bool project, hipStream_t s) {
+bool z_fast(const Batch<T>& Bt, int solve, bool project, hipStream_t s) {
     using Pl = PlanZ<T, N>;
     if constexpr (!Pl::ok) {
         return false;
     } else {
+        const GridDesc<T>& g = Bt.g;
         constexpr int TL = N / Pl::E;
         int B = g.Bz;
         while (B > 1 && B * TL > 512) B /= 2;
-        const dim3 grid((unsigned)((g.W + B - 1) / B), g.ny);
+        const dim3 grid((unsigned)((g.W + B - 1) / B), g.ny, Bt.nrep);
         const size_t lds = (size_t)N * (B + 1) * sizeof(cplx<T>);
         allow_lds(k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>, lds);
-        hipLaunchKernelGGL((k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>), grid, dim3(B * TL), lds, s, g, B, sc,
-                           project ? 1 : 0);
+        hipLaunchKernelGGL((k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>), grid, dim3(B * TL), lds, s, Bt.d, B,
+                           solve, project ? 1 : 0);
         return true;
     }
 }
 
 template <typename T, int N>
-bool xf_fast(const GridDesc<T>& g, const T* in, int c, hipStream_t s) {
+bool xf_fast(const Batch<T>& Bt, int in, hipStream_t s) {
     using Pl = Plan<T, N>;
     if constexpr (!Pl::ok) {
         return false;
     } else {
+        const GridDesc<T>& g = Bt.g;
         constexpr int TL = N / Pl::E;
         const int P = pairs_per_block<T>(N, TL);
         const long long npairs = (long long)g.ny * g.nz / 2;
-        const dim3 grid((unsigned)((npairs + P - 1) / P), c < 0 ? 3 : 1);
+        const dim3 grid((unsigned)((npairs + P - 1) / P), 3 * Bt.nrep);
         const size_t lds = (size_t)(N + P * xline<N>()) * sizeof(cplx<T>);
-        hipLaunchKernelGGL((k_xfwd_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>), grid, dim3(P * TL), lds, s, g, in, P, c);
+        hipLaunchKernelGGL((k_xfwd_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>), grid, dim3(P * TL), lds, s, Bt.d, in,
+                           P);
         return true;
     }
 }
 
 template <typename T, int N>
-bool xi_fast(const GridDesc<T>& g, T* out, bool acc, int c, hipStream_t s) {
+bool xi_fast(const Batch<T>& Bt, int out, bool acc, hipStream_t s) {
     using Pl = Plan<T, N>;
     if constexpr (!Pl::ok) {
         return false;
     } else {
+        const GridDesc<T>& g = Bt.g;
         constexpr int TL = N / Pl::E;
         const int P = pairs_per_block<T>(N, TL);
         const long long npairs = (long long)g.ny * g.nz / 2;
-        const dim3 grid((unsigned)((npairs + P - 1) / P), c < 0 ? 3 : 1);
+        const dim3 grid((unsigned)((npairs + P - 1) / P), 3 * Bt.nrep);
         const size_t lds = (size_t)(N + P * xline<N>()) * sizeof(cplx<T>);
-        hipLaunchKernelGGL((k_xinv_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>), grid, dim3(P * TL), lds, s, g, out, P,
-                           acc ? 1 : 0, c);
+        hipLaunchKernelGGL((k_xinv_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>), grid, dim3(P * TL), lds, s, Bt.d, out,
+                           P, acc ? 1 : 0);
         return true;
     }
 }
@@ -558,36 +578,36 @@ bool fast_fft_available(int nx, int ny, int nz) {
 }
 
 template <typename T>
-bool fast_fft_y(const GridDesc<T>& g, int dir, int c, hipStream_t s) {
-#define C(NN) y_fast<T, NN>(g, dir, c, s)
-    ICM_SWITCH_N(g.ny, C)
+bool fast_fft_y(const Batch<T>& B, int dir, hipStream_t s) {
+#define C(NN) y_fast<T, NN>(B, dir, s)
+    ICM_SWITCH_N(B.g.ny, C)
 #undef C
 }
 template <typename T>
-bool fast_fft_z_solve(const GridDesc<T>& g, SolveCoef sc, bool project, hipStream_t s) {
-#define C(NN) z_fast<T, NN>(g, sc, project, s)
-    ICM_SWITCH_N(g.nz, C)
+bool fast_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s) {
+#define C(NN) z_fast<T, NN>(B, solve, project, s)
+    ICM_SWITCH_N(B.g.nz, C)
 #undef C
 }
 template <typename T>
-bool fast_fft_x_forward(const GridDesc<T>& g, const T* in, int c, hipStream_t s) {
-#define C(NN) xf_fast<T, NN>(g, in, c, s)
-    ICM_SWITCH_N(g.nx, C)
+bool fast_fft_x_forward(const Batch<T>& B, int in, hipStream_t s) {
+#define C(NN) xf_fast<T, NN>(B, in, s)
+    ICM_SWITCH_N(B.g.nx, C)
 #undef C
 }
 template <typename T>
-bool fast_fft_x_inverse(const GridDesc<T>& g, T* out, bool acc, int c, hipStream_t s) {
-#define C(NN) xi_fast<T, NN>(g, out, acc, c, s)
-    ICM_SWITCH_N(g.nx, C)
+bool fast_fft_x_inverse(const Batch<T>& B, int out, bool acc, hipStream_t s) {
+#define C(NN) xi_fast<T, NN>(B, out, acc, s)
+    ICM_SWITCH_N(B.g.nx, C)
 #undef C
 }
 
-#define ICM_INST(T)                                                                      \
-    template bool fast_fft_available<T>(int, int, int);                                  \
-    template bool fast_fft_y<T>(const GridDesc<T>&, int, int, hipStream_t);              \
-    template bool fast_fft_z_solve<T>(const GridDesc<T>&, SolveCoef, bool, hipStream_t); \
-    template bool fast_fft_x_forward<T>(const GridDesc<T>&, const T*, int, hipStream_t); \
-    template bool fast_fft_x_inverse<T>(const GridDesc<T>&, T*, bool, int, hipStream_t);
+#define ICM_INST(T)                                                                \
+    template bool fast_fft_available<T>(int, int, int);                            \
+    template bool fast_fft_y<T>(const Batch<T>&, int, hipStream_t);                \
+    template bool fast_fft_z_solve<T>(const Batch<T>&, int, bool, hipStream_t);    \
+    template bool fast_fft_x_forward<T>(const Batch<T>&, int, hipStream_t);        \
+    template bool fast_fft_x_inverse<T>(const Batch<T>&, int, bool, hipStream_t);
 ICM_INST(float)
 ICM_INST(double)
 #undef ICM_INST

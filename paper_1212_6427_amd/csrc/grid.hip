@@ -27,7 +27,7 @@ __global__ void k_clear_ints(int* p, int n) {
 }
 
 // Does blob b's a-component stencil touch cells [i0, i0 + wx) x [j0, j0 + wy)?
-__device__ __forceinline__ bool stencil_meets_tile(const double* o, int P, int nx, int ny, int i0, int wx, int j0,
+__device__ __forceinline__ bool stencil_meets_tile(gptr<const double> o, int P, int nx, int ny, int i0, int wx, int j0,
                                                    int wy) {
     const int bx = (int)o[0], by = (int)o[1];
     bool inx = false, iny = false;
@@ -43,24 +43,28 @@ __device__ __forceinline__ bool stencil_meets_tile(const double* o, int P, int n
 // Value spread to one tap (ia, ib, ic) of component a of blob b:
 // (F_a prod w + c_drift prod w') / h^3, w' = phi'/h along axis a.
 template <typename T>
-__device__ __forceinline__ double tap_value(const RhsBlobs& rb, const double* o, int b, int a, int ia, int ib,
+__device__ __forceinline__ double tap_value(const RhsBlobs& rb, gptr<const double> o, int b, int a, int ia, int ib,
                                             int ic, double inv_h3) {
     const double wx = o[3 + ia], wy = o[7 + ib], wz = o[11 + ic];
-    double v = rb.F[3 * b + a] * wx * wy * wz;
+    double v = as_global(rb.F)[3 * b + a] * wx * wy * wz;
     if (rb.cdrift) {
         const double dx = a == 0 ? o[15 + ia] : wx;
         const double dy = a == 1 ? o[15 + ib] : wy;
         const double dz = a == 2 ? o[15 + ic] : wz;
-        v += rb.cdrift[b] * dx * dy * dz;
+        v += as_global(rb.cdrift)[b] * dx * dy * dz;
     }
     return v * inv_h3;
 }
 
 // Spread of the (blob, tile) pairs a tile could not hold, restricted to the
-// tile's cells, with atomics. One 16-lane group per (pair, component).
+// tile's cells, with atomics. One 16-lane group per (pair, component);
+// replica blockIdx.y.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_spread_overflow(GridDesc<T> g, RhsBlobs rb, int tiles_x,
+__global__ void __launch_bounds__(kThreads) k_spread_overflow(const RepDesc<T>* __restrict__ rd, int tiles_x,
                                                              int tiles_y, int rtx, int rty) {
+    const GridDesc<T> g = rd[blockIdx.y].g;
+    const RhsBlobs rb = rd[blockIdx.y].rb;
+    if (rb.nb <= 0) return;
     const int npairs = min(*rb.ovf_count, rb.ovf_cap);
     const int P = rb.kernel;
     const double inv_h = 1.0 / g.h;
@@ -72,7 +76,7 @@ __global__ void __launch_bounds__(kThreads) k_spread_overflow(GridDesc<T> g, Rhs
         const int b = rb.ovf_list[2 * pr], tile = rb.ovf_list[2 * pr + 1];
         const int txi = tile % tiles_x, tyi = (tile / tiles_x) % tiles_y, tzi = tile / (tiles_x * tiles_y);
         const int i0 = txi * rtx, j0 = tyi * rty, k0 = tzi * kRhsZChunk;
-        const double* o = rb.stc + ((long long)b * 3 + a) * kStcPerComp;
+        gptr<const double> o = as_global(rb.stc) + ((long long)b * 3 + a) * kStcPerComp;
         const int ib = r / P, ic_unused = 0;
         (void)ic_unused;
         const int y = ((int)o[1] + ib) % g.ny;
@@ -103,8 +107,12 @@ __global__ void __launch_bounds__(kThreads) k_spread_overflow(GridDesc<T> g, Rhs
 // halo ring regenerates the few normals it needs.
 constexpr int RTX = 32, RTY = 16, RZC = kRhsZChunk;
 
-template <typename T>
-__global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef c, RhsBlobs rb) {
+// ONE: a batch of one replica whose descriptor comes by value in the kernel
+// arguments (constant memory the compiler may re-read at will); otherwise the
+// replica's descriptor is read from the device array.
+template <typename T, bool ONE>
+__global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __restrict__ rd, const RepDesc<T> one,
+                                                        int ntz) {
     __shared__ int s_blobs[kRhsTileCap];   // blobs of this z-chunk meeting the tile
     __shared__ int s_nblobs;
     __shared__ T s_acc[3][RTY][RTX];       // spread accumulated for the current plane
@@ -114,16 +122,27 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef 
     __shared__ T sxz[RTY][RTX + 1];        // W_xz, column RTX = i0 + TX
     __shared__ T syy[RTY + 1][RTX];        // W_yy, row 0 = j0 - 1
     __shared__ T syz[RTY + 1][RTX];        // W_yz, row RTY = j0 + TY
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int tx = threadIdx.x % RTX, ty = threadIdx.x / RTX;
     // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs,
-    // so give XCD j a contiguous run of tiles (x fastest, then y, then z):
-    // neighbouring tiles then share their halo lines in that XCD's L2.
+    // so give XCD j a contiguous run of tiles (x fastest, then y, then z,
+    // then replica): neighbouring tiles then share their halo lines in that
+    // XCD's L2.
     const int ntx = gridDim.x, nty = gridDim.y;
     const int ntiles = ntx * nty * gridDim.z;
     int tile = blockIdx.x + ntx * (blockIdx.y + nty * blockIdx.z);
     if (ntiles % 8 == 0) tile = (tile % 8) * (ntiles / 8) + tile / 8;
-    const int tile_x = tile % ntx, tile_y = (tile / ntx) % nty, tile_z = tile / (ntx * nty);
+    const int tile_x = tile % ntx, tile_y = (tile / ntx) % nty, tile_zr = tile / (ntx * nty);
+    const int rep = ONE ? 0 : tile_zr / ntz, tile_z = tile_zr - rep * ntz;
+    const RepDesc<T>& R = ONE ? one : rd[rep];
+    const GridDesc<T>& g = R.g;
+    const RhsCoef& c = R.rc;
+    const RhsBlobs& rb = R.rb;
+    const unsigned long long step_n = *as_global(R.step);
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const gptr<const T> gv = as_global((const T*)g.v);
+    const gptr<T> grhs = as_global(g.rhs);
+    const gptr<const double> gstc = as_global(rb.stc);
+    const gptr<const double> gF = as_global(rb.F);
     const int i0 = tile_x * RTX, j0 = tile_y * RTY;
     const int k0 = tile_z * RZC;
     const int k1 = min(k0 + RZC, nz);
@@ -132,7 +151,11 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef 
     const long long plane = (long long)nx * ny;
     const long long col = (long long)j * nx + i;
     const bool noisy = c.noise != 0.0;
-    const NoiseKey& nk = c.key;
+    // The step words are uniform: keep them in scalar registers, so that the
+    // uniform parts of the first Philox rounds run on the scalar unit.
+    NoiseKey nk = c.key;
+    nk.step_lo = __builtin_amdgcn_readfirstlane((uint32_t)step_n);
+    nk.step_hi = __builtin_amdgcn_readfirstlane((uint32_t)(step_n >> 32));
     const T r2 = (T)1.41421356237309504880;
     // halo duty: threads [0, RTY) left column, [RTY, 2RTY) right column,
     // [2RTY, 2RTY+RTX) bottom row, [2RTY+RTX, 2RTY+2RTX) top row
@@ -153,8 +176,8 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef 
     if (own) {
         const int km = wrap(k0 - 1, nz);
         for (int a = 0; a < 3; ++a) {
-            vm[a] = g.v[a * g.ncell + km * plane + col];
-            v0[a] = g.v[a * g.ncell + (long long)k0 * plane + col];
+            vm[a] = gv[a * g.ncell + km * plane + col];
+            v0[a] = gv[a * g.ncell + (long long)k0 * plane + col];
         }
         if (noisy) {
             const u32x4 w = noise_words(nk, (uint32_t)(km * plane + col), 0);
@@ -173,23 +196,25 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef 
     const int P = rb.kernel;
     if (rb.nb > 0) {
         const int chunk = tile_z;
-        const int cnt = min(rb.chunk_count[chunk], rb.cap);
+        const int cnt = min(as_global(rb.chunk_count)[chunk], rb.cap);
         const int tile_id = (tile_z * nty + tile_y) * ntx + tile_x;
+        const gptr<const int> glist = as_global(rb.chunk_list);
         for (int s = tid; s < cnt; s += blockDim.x) {
-            const int b = rb.chunk_list[(long long)chunk * rb.cap + s];
+            const int b = glist[(long long)chunk * rb.cap + s];
             bool meets = false;
             for (int a = 0; a < 3; ++a)
-                meets = meets || stencil_meets_tile(rb.stc + ((long long)b * 3 + a) * kStcPerComp, P, nx, ny, i0,
-                                                    wx, j0, wy);
+                meets = meets || stencil_meets_tile(gstc + ((long long)b * 3 + a) * kStcPerComp, P, nx, ny, i0, wx,
+                                                    j0, wy);
             if (meets) {
                 const int slot = atomicAdd(&s_nblobs, 1);
                 if (slot < kRhsTileCap) {
                     s_blobs[slot] = b;
                 } else {
-                    const int os = atomicAdd(rb.ovf_count, 1);
+                    const int os = __hip_atomic_fetch_add(as_global(rb.ovf_count), 1, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
                     if (os < rb.ovf_cap) {
-                        rb.ovf_list[2 * os] = b;
-                        rb.ovf_list[2 * os + 1] = tile_id;
+                        as_global(rb.ovf_list)[2 * os] = b;
+                        as_global(rb.ovf_list)[2 * os + 1] = tile_id;
                     }
                 }
             }
@@ -208,7 +233,7 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef 
         const int a = rem >> 4, r = rem & 15;
         if (r < P * P) {
             const int b = s_blobs[lb];
-            const double* o = rb.stc + ((long long)b * 3 + a) * kStcPerComp;
+            gptr<const double> o = gstc + ((long long)b * 3 + a) * kStcPerComp;
             const int ia = r % P, ib = r / P;
             int x = (int)o[0] + ia, y = (int)o[1] + ib;
             if (x >= nx) x -= nx;
@@ -220,11 +245,11 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef 
                 it_y = y - j0;
                 it_z0 = (int)o[2];
                 const double wxv = o[3 + ia], wyv = o[7 + ib];
-                it_f = rb.F[3 * b + a] * wxv * wyv * inv_h3;
+                it_f = gF[3 * b + a] * wxv * wyv * inv_h3;
                 wz0 = o[11]; wz1 = o[12]; wz2 = o[13]; wz3 = o[14];
                 if (rb.cdrift) {
                     const double cx = a == 0 ? o[15 + ia] : wxv, cy = a == 1 ? o[15 + ib] : wyv;
-                    it_d = rb.cdrift[b] * cx * cy * inv_h3;
+                    it_d = as_global(rb.cdrift)[b] * cx * cy * inv_h3;
                     if (a == 2) { dz0 = o[15]; dz1 = o[16]; dz2 = o[17]; dz3 = o[18]; }
                     else { dz0 = wz0; dz1 = wz1; dz2 = wz2; dz3 = wz3; }
                 }
@@ -250,7 +275,7 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef 
             const int a = rem >> 4, r = rem & 15;
             if (r >= P * P) continue;
             const int b = s_blobs[lb];
-            const double* o = rb.stc + ((long long)b * 3 + a) * kStcPerComp;
+            gptr<const double> o = gstc + ((long long)b * 3 + a) * kStcPerComp;
             int ic = k - (int)o[2];
             if (ic < 0) ic += nz;
             if (ic >= P) continue;
@@ -263,7 +288,7 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef 
             atomicAdd(&s_acc[a][y - j0][x - i0], (T)v);
         }
         if (own) {
-            for (int a = 0; a < 3; ++a) vp[a] = g.v[a * g.ncell + (long long)kp * plane + col];
+            for (int a = 0; a < 3; ++a) vp[a] = gv[a * g.ncell + (long long)kp * plane + col];
             if (noisy) {
                 const u32x4 w0 = noise_words(nk, (uint32_t)(k * plane + col), 0);
                 NormalPair<T> p0 = bm<T>(w0.x, w0.y), p1 = bm<T>(w0.z, w0.w);
@@ -288,7 +313,7 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef 
             // LDS slot of the halo cell (column/row index within the tile + 1)
             const int sy = hkind <= 1 ? hj - j0 + 1 : (hkind == 2 ? 0 : wy + 1);
             const int sx = hkind == 0 ? 0 : (hkind == 1 ? wx + 1 : hi - i0 + 1);
-            for (int a = 0; a < 3; ++a) sv[a][sy][sx] = g.v[a * g.ncell + hc];
+            for (int a = 0; a < 3; ++a) sv[a][sy][sx] = gv[a * g.ncell + hc];
             if (noisy) {
                 if (hkind == 0) {
                     const u32x4 w = noise_words(nk, (uint32_t)hc, 0);
@@ -332,7 +357,7 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef 
             for (int a = 0; a < 3; ++a) {
                 out[a] += s_acc[a][ty][tx];
                 s_acc[a][ty][tx] = (T)0;
-                g.rhs[a * g.ncell + cell] = out[a];
+                grhs[a * g.ncell + cell] = out[a];
             }
         }
         __syncthreads();
@@ -348,9 +373,14 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(GridDesc<T> g, RhsCoef 
 }
 
 // Equilibrium sample: every face N(0, sd^2) from Philox block 2 of the cell
-// (words (w0,w1) -> (x, y) faces, (w2,w3) -> (z face, unused)).
+// (words (w0,w1) -> (x, y) faces, (w2,w3) -> (z face, unused)), with the
+// noise key of step 0; replica blockIdx.y.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_eq_noise(GridDesc<T> g, double sd, NoiseKey nk) {
+__global__ void __launch_bounds__(kThreads) k_eq_noise(const RepDesc<T>* __restrict__ rd, double sd) {
+    const GridDesc<T> g = rd[blockIdx.y].g;
+    NoiseKey nk = rd[blockIdx.y].rc.key;
+    nk.step_lo = 0;
+    nk.step_hi = 0;
     const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= g.ncell) return;
     const u32x4 w = noise_words(nk, (uint32_t)cell, 2);
@@ -363,14 +393,21 @@ __global__ void __launch_bounds__(kThreads) k_eq_noise(GridDesc<T> g, double sd,
 }
 
 template <typename T>
-__global__ void k_zero(T* p, long long n) {
+__global__ void k_zero(const RepDesc<T>* __restrict__ rd, int sel) {
+    const GridDesc<T> g = rd[blockIdx.y].g;
+    T* p = field_of(rd[blockIdx.y].g, sel);
+    const long long n = 3 * g.ncell;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
         p[i] = (T)0;
 }
 
 template <typename T>
-__global__ void k_axpy(T* y, const T* x, long long n) {
+__global__ void k_axpy(const RepDesc<T>* __restrict__ rd, int ysel, int xsel) {
+    const GridDesc<T> g = rd[blockIdx.y].g;
+    T* y = field_of(rd[blockIdx.y].g, ysel);
+    const T* x = field_of(rd[blockIdx.y].g, xsel);
+    const long long n = 3 * g.ncell;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
         y[i] += x[i];
@@ -383,24 +420,30 @@ __device__ __forceinline__ double comp_offset(int beta, int a) { return beta == 
 // S: field_a += h^-3 phi(dx) phi(dy) phi(dz) val_a. A group of 16 lanes
 // serves one (blob, component); lane r < P^2 owns the x-row of z-tap r / P and
 // y-tap r mod P and adds its P values atomically (kernels of neighbouring
-// blobs may overlap).
+// blobs may overlap). Replica blockIdx.y.
 template <typename T, int P>
-__global__ void __launch_bounds__(kThreads) k_spread(GridDesc<T> g, T* field, int nb, const double* __restrict__ q,
-                                                    const double* __restrict__ F, const double* __restrict__ coef,
-                                                    int deriv) {
+__global__ void __launch_bounds__(kThreads) k_spread(const RepDesc<T>* __restrict__ rd, int fsel, int qsel, int Fsel,
+                                                    int csel) {
+    const GridDesc<T> g = rd[blockIdx.y].g;
+    const BlobBufs bb = rd[blockIdx.y].bb;
+    const int nb = rd[blockIdx.y].bp.nb;
+    T* field = field_of(rd[blockIdx.y].g, fsel);
+    const double* __restrict__ q = blob_of(rd[blockIdx.y].bb, qsel);
+    const double* __restrict__ F = blob_of(rd[blockIdx.y].bb, Fsel);
+    const double* __restrict__ coef = blob_of(rd[blockIdx.y].bb, csel);
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int grp = t >> 4, r = t & 15;
     const int b = grp / 3, a = grp - 3 * (grp / 3);
     if (b >= nb || r >= P * P) return;
     const int cz = r / P, cy = r - P * (r / P);
     const double inv_h = 1.0 / g.h;
-    const double val = (F ? F[3 * b + a] : 1.0) * (coef ? coef[b] : 1.0) * inv_h * inv_h * inv_h;
+    const double val = F[3 * b + a] * (coef ? coef[b] : 1.0) * inv_h * inv_h * inv_h;
     AxisStencil<P> sx;
-    axis_stencil<P>(q[3 * b + 0] * inv_h - comp_offset(0, a), g.nx, deriv && a == 0, inv_h, sx);
+    axis_stencil<P>(q[3 * b + 0] * inv_h - comp_offset(0, a), g.nx, false, inv_h, sx);
     int ny_, nz_;
     double wy, wz;
-    axis_tap<P>(q[3 * b + 1] * inv_h - comp_offset(1, a), g.ny, cy, deriv && a == 1, inv_h, ny_, wy);
-    axis_tap<P>(q[3 * b + 2] * inv_h - comp_offset(2, a), g.nz, cz, deriv && a == 2, inv_h, nz_, wz);
+    axis_tap<P>(q[3 * b + 1] * inv_h - comp_offset(1, a), g.ny, cy, false, inv_h, ny_, wy);
+    axis_tap<P>(q[3 * b + 2] * inv_h - comp_offset(2, a), g.nz, cz, false, inv_h, nz_, wz);
     T* f = field + a * g.ncell + ((long long)nz_ * g.ny + ny_) * g.nx;
     const double wzy = wz * wy * val;
 #pragma unroll
@@ -436,7 +479,10 @@ __device__ __forceinline__ double gather_group(const GridDesc<T>& g, const T* __
 
 // Step 1 fused: Jn = J(q^n) v^n and q^{n+1/2} = q^n + dt/2 Jn.
 template <typename T, int P>
-__global__ void __launch_bounds__(kThreads) k_gather_predict(GridDesc<T> g, BlobParams bp, BlobBufs bb) {
+__global__ void __launch_bounds__(kThreads) k_gather_predict(const RepDesc<T>* __restrict__ rd) {
+    const GridDesc<T> g = rd[blockIdx.y].g;
+    const BlobParams bp = rd[blockIdx.y].bp;
+    const BlobBufs bb = rd[blockIdx.y].bb;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int grp = t >> 4, r = t & 15;
     const int b = grp / 3, a = grp - 3 * (grp / 3);
@@ -454,7 +500,10 @@ __global__ void __launch_bounds__(kThreads) k_gather_predict(GridDesc<T> g, Blob
 // stencil record of component a (wrapped base nodes, the P weights of each
 // axis, the derivative weights along axis a).
 template <typename T, int P>
-__global__ void __launch_bounds__(kThreads) k_gather_bins(GridDesc<T> g, BlobParams bp, BlobBufs bb, int cap) {
+__global__ void __launch_bounds__(kThreads) k_gather_bins(const RepDesc<T>* __restrict__ rd) {
+    const GridDesc<T> g = rd[blockIdx.y].g;
+    const BlobParams bp = rd[blockIdx.y].bp;
+    const BlobBufs bb = rd[blockIdx.y].bb;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int grp = t >> 4, r = t & 15;
     const int b = grp / 3, a = grp - 3 * (grp / 3);
@@ -487,11 +536,16 @@ __global__ void __launch_bounds__(kThreads) k_gather_bins(GridDesc<T> g, BlobPar
 // workgroup in LDS and reserved in the global lists with one atomic per
 // (workgroup, chunk), which keeps same-address contention low.
 constexpr int kMaxChunks = 512 / kRhsZChunk;
-template <int P>
-__global__ void __launch_bounds__(kThreads) k_bins(int nb, int nz, double h, const double* __restrict__ qh, int cap,
-                                                   int* __restrict__ chunk_count, int* __restrict__ chunk_list) {
+template <typename T, int P>
+__global__ void __launch_bounds__(kThreads) k_bins(const RepDesc<T>* __restrict__ rd) {
     __shared__ int s_cnt[kMaxChunks];
     __shared__ int s_base[kMaxChunks];
+    const int nb = rd[blockIdx.y].bp.nb, nz = rd[blockIdx.y].g.nz;
+    const double h = rd[blockIdx.y].g.h;
+    const double* __restrict__ qh = rd[blockIdx.y].bb.qh;
+    const int cap = rd[blockIdx.y].rb.cap;
+    int* __restrict__ chunk_count = rd[blockIdx.y].bb.chunk_count;
+    int* __restrict__ chunk_list = rd[blockIdx.y].bb.chunk_list;
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     const int nchunks = (nz + kRhsZChunk - 1) / kRhsZChunk;
     for (int i = threadIdx.x; i < nchunks; i += blockDim.x) s_cnt[i] = 0;
@@ -519,14 +573,19 @@ __global__ void __launch_bounds__(kThreads) k_bins(int nb, int nz, double h, con
 
 // Step 9 fused: Jhvnew = J(q^{n+1/2}) v^{n+1}; q^{n+1} = q^n + dt/2
 // (Jhvnew + Jhvn); u^{n+1} = Jhvnew for m_e = 0 blobs; numeric flag on
-// NaN/Inf or a displacement above h. The first block clears the z-chunk bins
-// for the next step.
+// NaN/Inf or a displacement above h. The first block of a replica clears its
+// z-chunk bins for the next step and advances its step counter (no other
+// kernel of the step reads the counter after the RHS).
 template <typename T, int P>
-__global__ void __launch_bounds__(kThreads) k_gather_final(GridDesc<T> g, BlobParams bp, BlobBufs bb,
-                                                          int n_clear) {
+__global__ void __launch_bounds__(kThreads) k_gather_final(const RepDesc<T>* __restrict__ rd, int n_clear) {
+    const GridDesc<T> g = rd[blockIdx.y].g;
+    const BlobParams bp = rd[blockIdx.y].bp;
+    const BlobBufs bb = rd[blockIdx.y].bb;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (blockIdx.x == 0)
+    if (blockIdx.x == 0) {
         for (int i = threadIdx.x; i < n_clear; i += blockDim.x) bb.chunk_count[i] = 0;
+        if (threadIdx.x == 0) *rd[blockIdx.y].step += 1;
+    }
     const int grp = t >> 4, r = t & 15;
     const int b = grp / 3, a = grp - 3 * (grp / 3);
     const bool active = b < bp.nb;
@@ -547,8 +606,14 @@ __global__ void __launch_bounds__(kThreads) k_gather_final(GridDesc<T> g, BlobPa
 // 16-lane group per (blob, component) reduced with shuffles; with lap = 1 the
 // field value at each node is replaced by its 7-point Laplacian.
 template <typename T, int P>
-__global__ void __launch_bounds__(kThreads) k_gather(GridDesc<T> g, const T* __restrict__ field, int nb,
-                                                    const double* __restrict__ q, double* __restrict__ out, int lap) {
+__global__ void __launch_bounds__(kThreads) k_gather(const RepDesc<T>* __restrict__ rd, int fsel, int qsel, int osel,
+                                                    int lap) {
+    const GridDesc<T> g = rd[blockIdx.y].g;
+    const BlobBufs bb = rd[blockIdx.y].bb;
+    const int nb = rd[blockIdx.y].bp.nb;
+    const T* __restrict__ field = field_of(rd[blockIdx.y].g, fsel);
+    const double* __restrict__ q = blob_of(rd[blockIdx.y].bb, qsel);
+    double* __restrict__ out = blob_of(rd[blockIdx.y].bb, osel);
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int grp = t >> 4, r = t & 15;
     const int b = grp / 3, a = grp - 3 * (grp / 3);
@@ -654,102 +719,107 @@ unsigned grid_for(long long n) {
 }  // namespace
 
 template <typename T>
-void launch_rhs(const GridDesc<T>& g, const RhsCoef& c, const RhsBlobs& rb, hipStream_t s) {
-    const dim3 grid((unsigned)((g.nx + RTX - 1) / RTX), (unsigned)((g.ny + RTY - 1) / RTY),
-                    (unsigned)((g.nz + RZC - 1) / RZC));
-    hipLaunchKernelGGL(k_rhs_march<T>, grid, dim3(RTX * RTY), 0, s, g, c, rb);
+void launch_rhs(const Batch<T>& B, hipStream_t s) {
+    const GridDesc<T>& g = B.g;
+    const int ntz = (g.nz + RZC - 1) / RZC;
+    const dim3 grid((unsigned)((g.nx + RTX - 1) / RTX), (unsigned)((g.ny + RTY - 1) / RTY), (unsigned)(ntz * B.nrep));
+    if (B.nrep == 1 && B.one)
+        hipLaunchKernelGGL((k_rhs_march<T, true>), grid, dim3(RTX * RTY), 0, s, B.d, *B.one, ntz);
+    else
+        hipLaunchKernelGGL((k_rhs_march<T, false>), grid, dim3(RTX * RTY), 0, s, B.d, RepDesc<T>{}, ntz);
 }
 
 template <typename T>
-void launch_spread_overflow(const GridDesc<T>& g, const RhsBlobs& rb, hipStream_t s) {
-    if (rb.nb <= 0) return;
-    const int tiles_x = (g.nx + RTX - 1) / RTX, tiles_y = (g.ny + RTY - 1) / RTY;
-    hipLaunchKernelGGL(k_spread_overflow<T>, dim3(64), dim3(kThreads), 0, s, g, rb, tiles_x, tiles_y, RTX, RTY);
+void launch_spread_overflow(const Batch<T>& B, hipStream_t s) {
+    if (B.max_nb <= 0) return;
+    const int tiles_x = (B.g.nx + RTX - 1) / RTX, tiles_y = (B.g.ny + RTY - 1) / RTY;
+    hipLaunchKernelGGL(k_spread_overflow<T>, dim3(B.nrep > 8 ? 8 : 64, B.nrep), dim3(kThreads), 0, s, B.d, tiles_x,
+                       tiles_y, RTX, RTY);
 }
 
 template <typename T>
-void launch_equilibrium_noise(const GridDesc<T>& g, double sd, NoiseKey key, hipStream_t s) {
-    hipLaunchKernelGGL(k_eq_noise<T>, dim3(grid_for(g.ncell)), dim3(kThreads), 0, s, g, sd, key);
+void launch_equilibrium_noise(const Batch<T>& B, double sd, hipStream_t s) {
+    hipLaunchKernelGGL(k_eq_noise<T>, dim3(grid_for(B.g.ncell), B.nrep), dim3(kThreads), 0, s, B.d, sd);
 }
 
-template <typename T>
-void launch_zero(T* p, long long n, hipStream_t s) {
+unsigned stream_blocks(long long n, int nrep) {
     long long b = (n + kThreads - 1) / kThreads;
-    if (b > 4096) b = 4096;
-    if (b < 1) b = 1;
-    hipLaunchKernelGGL(k_zero<T>, dim3((unsigned)b), dim3(kThreads), 0, s, p, n);
+    const long long cap = 4096 / (nrep > 0 ? nrep : 1) + 1;
+    if (b > cap) b = cap;
+    return (unsigned)(b < 1 ? 1 : b);
 }
 
 template <typename T>
-void launch_axpy(T* y, const T* x, long long n, hipStream_t s) {
-    long long b = (n + kThreads - 1) / kThreads;
-    if (b > 4096) b = 4096;
-    if (b < 1) b = 1;
-    hipLaunchKernelGGL(k_axpy<T>, dim3((unsigned)b), dim3(kThreads), 0, s, y, x, n);
+void launch_zero(const Batch<T>& B, int field, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero<T>, dim3(stream_blocks(3 * B.g.ncell, B.nrep), B.nrep), dim3(kThreads), 0, s, B.d,
+                       field);
 }
 
 template <typename T>
-void launch_spread(const GridDesc<T>& g, T* field, int kernel, int nb, const double* q, const double* F,
-                   const double* coef, bool deriv, hipStream_t s) {
-    if (nb <= 0) return;
-    const dim3 grid(grid_for(48LL * nb));
-    if (kernel == 3)
-        hipLaunchKernelGGL((k_spread<T, 3>), grid, dim3(kThreads), 0, s, g, field, nb, q, F, coef, deriv ? 1 : 0);
-    else
-        hipLaunchKernelGGL((k_spread<T, 4>), grid, dim3(kThreads), 0, s, g, field, nb, q, F, coef, deriv ? 1 : 0);
+void launch_axpy(const Batch<T>& B, int y, int x, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy<T>, dim3(stream_blocks(3 * B.g.ncell, B.nrep), B.nrep), dim3(kThreads), 0, s, B.d, y,
+                       x);
 }
 
 template <typename T>
-void launch_gather(const GridDesc<T>& g, const T* field, int kernel, int nb, const double* q, double* out,
-                   bool laplacian, hipStream_t s) {
-    if (nb <= 0) return;
-    const dim3 grid(grid_for(48LL * nb));
-    if (kernel == 3)
-        hipLaunchKernelGGL((k_gather<T, 3>), grid, dim3(kThreads), 0, s, g, field, nb, q, out, laplacian ? 1 : 0);
+void launch_spread(const Batch<T>& B, int field, int q, int F, int coef, hipStream_t s) {
+    if (B.max_nb <= 0) return;
+    const dim3 grid(grid_for(48LL * B.max_nb), B.nrep);
+    if (B.kernel == 3)
+        hipLaunchKernelGGL((k_spread<T, 3>), grid, dim3(kThreads), 0, s, B.d, field, q, F, coef);
     else
-        hipLaunchKernelGGL((k_gather<T, 4>), grid, dim3(kThreads), 0, s, g, field, nb, q, out, laplacian ? 1 : 0);
+        hipLaunchKernelGGL((k_spread<T, 4>), grid, dim3(kThreads), 0, s, B.d, field, q, F, coef);
 }
 
 template <typename T>
-void launch_gather_predict(const GridDesc<T>& g, int kernel, const BlobParams& bp, const BlobBufs& bb,
-                           hipStream_t s) {
-    if (bp.nb <= 0) return;
-    const dim3 grid(grid_for(48LL * bp.nb));
-    if (kernel == 3)
-        hipLaunchKernelGGL((k_gather_predict<T, 3>), grid, dim3(kThreads), 0, s, g, bp, bb);
+void launch_gather(const Batch<T>& B, int field, int q, int out, bool laplacian, hipStream_t s) {
+    if (B.max_nb <= 0) return;
+    const dim3 grid(grid_for(48LL * B.max_nb), B.nrep);
+    if (B.kernel == 3)
+        hipLaunchKernelGGL((k_gather<T, 3>), grid, dim3(kThreads), 0, s, B.d, field, q, out, laplacian ? 1 : 0);
     else
-        hipLaunchKernelGGL((k_gather_predict<T, 4>), grid, dim3(kThreads), 0, s, g, bp, bb);
+        hipLaunchKernelGGL((k_gather<T, 4>), grid, dim3(kThreads), 0, s, B.d, field, q, out, laplacian ? 1 : 0);
 }
 
 template <typename T>
-void launch_gather_bins(const GridDesc<T>& g, int kernel, const BlobParams& bp, const BlobBufs& bb, int cap,
-                        hipStream_t s) {
-    if (bp.nb <= 0) return;
-    const dim3 grid(grid_for(48LL * bp.nb));
-    if (kernel == 3)
-        hipLaunchKernelGGL((k_gather_bins<T, 3>), grid, dim3(kThreads), 0, s, g, bp, bb, cap);
+void launch_gather_predict(const Batch<T>& B, hipStream_t s) {
+    if (B.max_nb <= 0) return;
+    const dim3 grid(grid_for(48LL * B.max_nb), B.nrep);
+    if (B.kernel == 3)
+        hipLaunchKernelGGL((k_gather_predict<T, 3>), grid, dim3(kThreads), 0, s, B.d);
     else
-        hipLaunchKernelGGL((k_gather_bins<T, 4>), grid, dim3(kThreads), 0, s, g, bp, bb, cap);
-}
-
-void launch_bins(int kernel, int nb, int nz, double h, const double* qh, int cap, int* chunk_count,
-                 int* chunk_list, hipStream_t s) {
-    if (nb <= 0) return;
-    const dim3 grid((unsigned)((nb + kThreads - 1) / kThreads));
-    if (kernel == 3)
-        hipLaunchKernelGGL(k_bins<3>, grid, dim3(kThreads), 0, s, nb, nz, h, qh, cap, chunk_count, chunk_list);
-    else
-        hipLaunchKernelGGL(k_bins<4>, grid, dim3(kThreads), 0, s, nb, nz, h, qh, cap, chunk_count, chunk_list);
+        hipLaunchKernelGGL((k_gather_predict<T, 4>), grid, dim3(kThreads), 0, s, B.d);
 }
 
 template <typename T>
-void launch_gather_final(const GridDesc<T>& g, int kernel, const BlobParams& bp, const BlobBufs& bb, int n_clear,
-                         hipStream_t s) {
-    const dim3 grid(grid_for(48LL * (bp.nb > 0 ? bp.nb : 1)));
-    if (kernel == 3)
-        hipLaunchKernelGGL((k_gather_final<T, 3>), grid, dim3(kThreads), 0, s, g, bp, bb, n_clear);
+void launch_gather_bins(const Batch<T>& B, hipStream_t s) {
+    if (B.max_nb <= 0) return;
+    const dim3 grid(grid_for(48LL * B.max_nb), B.nrep);
+    if (B.kernel == 3)
+        hipLaunchKernelGGL((k_gather_bins<T, 3>), grid, dim3(kThreads), 0, s, B.d);
     else
-        hipLaunchKernelGGL((k_gather_final<T, 4>), grid, dim3(kThreads), 0, s, g, bp, bb, n_clear);
+        hipLaunchKernelGGL((k_gather_bins<T, 4>), grid, dim3(kThreads), 0, s, B.d);
+}
+
+template <typename T>
+void launch_bins(const Batch<T>& B, hipStream_t s) {
+    if (B.max_nb <= 0) return;
+    const dim3 grid((unsigned)((B.max_nb + kThreads - 1) / kThreads), B.nrep);
+    if (B.kernel == 3)
+        hipLaunchKernelGGL((k_bins<T, 3>), grid, dim3(kThreads), 0, s, B.d);
+    else
+        hipLaunchKernelGGL((k_bins<T, 4>), grid, dim3(kThreads), 0, s, B.d);
+}
+
+template <typename T>
+void launch_gather_final(const Batch<T>& B, hipStream_t s) {
+    // always launched: its first block per replica advances the step counter
+    const int n_clear = (B.g.nz + kRhsZChunk - 1) / kRhsZChunk + 1;
+    const dim3 grid(grid_for(48LL * (B.max_nb > 0 ? B.max_nb : 1)), B.nrep);
+    if (B.kernel == 3)
+        hipLaunchKernelGGL((k_gather_final<T, 3>), grid, dim3(kThreads), 0, s, B.d, n_clear);
+    else
+        hipLaunchKernelGGL((k_gather_final<T, 4>), grid, dim3(kThreads), 0, s, B.d, n_clear);
 }
 
 template <typename T>
@@ -759,23 +829,19 @@ void launch_field_diag(const GridDesc<T>& g, double rho, double* acc, hipStream_
     hipLaunchKernelGGL(k_field_diag<T>, dim3((unsigned)b), dim3(kThreads), 0, s, g, rho, acc);
 }
 
-#define ICM_INST(T)                                                                                        \
-    template void launch_rhs<T>(const GridDesc<T>&, const RhsCoef&, const RhsBlobs&, hipStream_t);        \
-    template void launch_spread_overflow<T>(const GridDesc<T>&, const RhsBlobs&, hipStream_t);           \
-    template void launch_equilibrium_noise<T>(const GridDesc<T>&, double, NoiseKey, hipStream_t);         \
-    template void launch_zero<T>(T*, long long, hipStream_t);                                              \
-    template void launch_axpy<T>(T*, const T*, long long, hipStream_t);                                    \
-    template void launch_spread<T>(const GridDesc<T>&, T*, int, int, const double*, const double*,        \
-                                   const double*, bool, hipStream_t);                                     \
-    template void launch_gather<T>(const GridDesc<T>&, const T*, int, int, const double*, double*, bool, \
-                                   hipStream_t);                                                          \
-    template void launch_field_diag<T>(const GridDesc<T>&, double, double*, hipStream_t);                 \
-    template void launch_gather_predict<T>(const GridDesc<T>&, int, const BlobParams&, const BlobBufs&,   \
-                                           hipStream_t);                                                  \
-    template void launch_gather_bins<T>(const GridDesc<T>&, int, const BlobParams&, const BlobBufs&, int, \
-                                        hipStream_t);                                                     \
-    template void launch_gather_final<T>(const GridDesc<T>&, int, const BlobParams&, const BlobBufs&, int, \
-                                         hipStream_t);
+#define ICM_INST(T)                                                                              \
+    template void launch_rhs<T>(const Batch<T>&, hipStream_t);                                   \
+    template void launch_spread_overflow<T>(const Batch<T>&, hipStream_t);                       \
+    template void launch_equilibrium_noise<T>(const Batch<T>&, double, hipStream_t);             \
+    template void launch_zero<T>(const Batch<T>&, int, hipStream_t);                             \
+    template void launch_axpy<T>(const Batch<T>&, int, int, hipStream_t);                        \
+    template void launch_spread<T>(const Batch<T>&, int, int, int, int, hipStream_t);            \
+    template void launch_gather<T>(const Batch<T>&, int, int, int, bool, hipStream_t);           \
+    template void launch_field_diag<T>(const GridDesc<T>&, double, double*, hipStream_t);        \
+    template void launch_gather_predict<T>(const Batch<T>&, hipStream_t);                        \
+    template void launch_gather_bins<T>(const Batch<T>&, hipStream_t);                           \
+    template void launch_bins<T>(const Batch<T>&, hipStream_t);                                  \
+    template void launch_gather_final<T>(const Batch<T>&, hipStream_t);
 ICM_INST(float)
 ICM_INST(double)
 #undef ICM_INST

@@ -7,6 +7,23 @@
 
 namespace icm {
 
+// Global-memory pointers. Pointers read from a device-resident descriptor are
+// generic to the compiler and would be accessed with flat instructions, which
+// also count against the LDS wait counter; converting them once gives plain
+// global loads and stores.
+// (The host pass only checks kernel bodies, so there they are plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <typename T>
+using gptr = T*;
+#endif
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+    return (gptr<T>)p;
+}
+
 template <typename T>
 struct cplx {
     T x, y;

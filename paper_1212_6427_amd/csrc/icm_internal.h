@@ -89,63 +89,7 @@ struct RhsBlobs {
     int ovf_cap;
 };
 
-// ------------------------------------------------------------------- FFT
-// The x and y passes work on one component c (0..2) per launch, or on all
-// three with c = -1.
-template <typename T>
-void launch_fft_x_forward(const GridDesc<T>& g, const T* in, hipStream_t s, int c = -1);
-template <typename T>
-void launch_fft_y(const GridDesc<T>& g, int dir, hipStream_t s, int c = -1);
-template <typename T>
-void launch_fft_z_solve(const GridDesc<T>& g, SolveCoef sc, bool project, hipStream_t s);
-template <typename T>
-void launch_fft_x_inverse(const GridDesc<T>& g, T* out, bool accumulate, hipStream_t s, int c = -1);
-template <typename T>
-void launch_fft_forward_solve_inverse(const GridDesc<T>& g, const T* in, T* out, bool accumulate,
-                                      SolveCoef sc, bool project, hipStream_t s);
-
-// Register-resident passes for N in {16, 32, 48, 64, 128, 256, 512};
-// return false (launching nothing) for other sizes.
-template <typename T>
-bool fast_fft_available(int nx, int ny, int nz);
-template <typename T>
-bool fast_fft_y(const GridDesc<T>& g, int dir, int c, hipStream_t s);
-template <typename T>
-bool fast_fft_z_solve(const GridDesc<T>& g, SolveCoef sc, bool project, hipStream_t s);
-template <typename T>
-bool fast_fft_x_forward(const GridDesc<T>& g, const T* in, int c, hipStream_t s);
-template <typename T>
-bool fast_fft_x_inverse(const GridDesc<T>& g, T* out, bool accumulate, int c, hipStream_t s);
-
-// ------------------------------------------------------------ grid kernels
-template <typename T>
-void launch_rhs(const GridDesc<T>& g, const RhsCoef& c, const RhsBlobs& rb, hipStream_t s);
-template <typename T>
-void launch_spread_overflow(const GridDesc<T>& g, const RhsBlobs& rb, hipStream_t s);
-template <typename T>
-void launch_equilibrium_noise(const GridDesc<T>& g, double sd, NoiseKey key, hipStream_t s);
-template <typename T>
-void launch_zero(T* p, long long n, hipStream_t s);
-template <typename T>
-void launch_axpy(T* y, const T* x, long long n, hipStream_t s);
-
-// spread: field += h^-3 * prod(phi) * val, val_a = (F ? F[b][a] : 1) * (coef ? coef[b] : 1);
-// deriv: the a-axis weight of component a is phi'(d)/h (thermal drift).
-template <typename T>
-void launch_spread(const GridDesc<T>& g, T* field, int kernel, int nb, const double* q,
-                   const double* F, const double* coef, bool deriv, hipStream_t s);
-// gather: out[b][a] = sum prod(phi) f_a (or of (L f)_a with laplacian = true)
-template <typename T>
-void launch_gather(const GridDesc<T>& g, const T* field, int kernel, int nb, const double* q,
-                   double* out, bool laplacian, hipStream_t s);
-
-// ------------------------------------------------------------ reductions
-// acc[0..2] += rho h^3 sum v; acc[3] += rho h^3 sum v^2 / 2;
-// acc[4] = max |v| (as bits), acc[5] = max |Dv| (as bits)
-template <typename T>
-void launch_field_diag(const GridDesc<T>& g, double rho, double* acc, hipStream_t s);
-
-// ----------------------------------------------------------- blob kernels
+// ----------------------------------------------------------- blob buffers
 struct BlobParams {
     int nb;
     double dt, rho, eta, kT;
@@ -169,35 +113,151 @@ struct BlobBufs {
 };
 
 // Cell list of the pair forces: n[a] cells of width >= the cutoff per axis
-// (at least 3), heads[cell] = (stamp << 32 | first blob), next[blob]. With
-// heads == NULL the forces use the all-pairs kernel.
+// (at least 3), heads[cell] = (stamp << kHeadBlobBits | first blob),
+// next[blob]. The stamp is the step number + 1 modulo 2^40, so heads left by
+// earlier steps read as empty. With heads == NULL the forces use the
+// all-pairs kernel.
+constexpr int kHeadBlobBits = 24;
 struct CellGrid {
     int n[3];
     double inv_size[3];
     unsigned long long* heads;
     int* next;
 };
-void launch_forces(const BlobParams& bp, const BlobBufs& b, const CellGrid& cg, unsigned int stamp, hipStream_t s);
-void launch_inertial_dp(const BlobParams& bp, const BlobBufs& b, hipStream_t s);
-void launch_inertial_dp2(const BlobParams& bp, const BlobBufs& b, hipStream_t s);
-void launch_inertial_u(const BlobParams& bp, const BlobBufs& b, hipStream_t s);
-void launch_blob_diag(int nb, const double* me, const double* u, double* acc, hipStream_t s);
+
+// Selectors of per-replica arrays, resolved on the device.
+enum FieldSel { kFieldV = 0, kFieldRhs = 1, kFieldAux = 2 };
+enum BlobSel { kBlobNone = -1, kBlobQ = 0, kBlobQh, kBlobDp, kBlobDp2, kBlobC5, kBlobJhvt, kBlobG, kBlobLag };
+enum SolveSel { kSolveH1 = 0, kSolveP = 1, kSolveH2 = 2 };
+
+template <typename T>
+__host__ __device__ __forceinline__ T* field_of(const GridDesc<T>& g, int sel) {
+    return sel == kFieldV ? g.v : (sel == kFieldRhs ? g.rhs : g.aux);
+}
+
+__host__ __device__ __forceinline__ double* blob_of(const BlobBufs& b, int sel) {
+    switch (sel) {
+        case kBlobQ: return b.q;
+        case kBlobQh: return b.qh;
+        case kBlobDp: return b.dp;
+        case kBlobDp2: return b.dp2;
+        case kBlobC5: return b.c5;
+        case kBlobJhvt: return b.Jhvt;
+        case kBlobG: return b.g;
+        case kBlobLag: return b.lag;
+        default: return nullptr;
+    }
+}
+
+// Everything a kernel needs to know about one replica. The descriptors of a
+// context live in one device array; the replicas of a batch (same grid shape,
+// kernel and inertial path) are contiguous there, and a batched launch finds
+// its replica from the grid. The only value that changes from step to step is
+// the device step counter, so a captured step replays unchanged.
+template <typename T>
+struct RepDesc {
+    GridDesc<T> g;
+    RhsCoef rc;                 // rc.key.step_* unused: see *step
+    RhsBlobs rb;
+    BlobParams bp;
+    BlobBufs bb;
+    CellGrid cg;
+    SolveCoef solve[3];         // indexed by SolveSel
+    int pair_mode;              // 0 no pair forces, 1 cell list, 2 all pairs
+    unsigned long long* step;   // step counter n (incremented at the end of the step)
+};
+
+// Host view of a batch: the device descriptors and the shape they share.
+template <typename T>
+struct Batch {
+    const RepDesc<T>* d;  // nrep device descriptors
+    int nrep;
+    GridDesc<T> g;        // grid of the first replica (shape, FFT choice)
+    int kernel;           // 3 or 4
+    int max_nb;           // largest blob count of the batch
+    bool any_cells, any_all_pairs;
+    const RepDesc<T>* one;  // host copy of the descriptor when nrep == 1 (else NULL)
+};
+
+// ------------------------------------------------------------------- FFT
+// Forward transform of field `in` (all three components), the spectral
+// solve P-hat / (a + b lambda) with the replica's coefficients `solve`, and
+// the inverse transform into field `out` (added to it with accumulate).
+template <typename T>
+void launch_fft_x_forward(const Batch<T>& B, int in, hipStream_t s);
+template <typename T>
+void launch_fft_y(const Batch<T>& B, int dir, hipStream_t s);
+template <typename T>
+void launch_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s);
+template <typename T>
+void launch_fft_x_inverse(const Batch<T>& B, int out, bool accumulate, hipStream_t s);
+
+// Register-resident passes for N in {16, 32, 48, 64, 128, 256, 512};
+// return false (launching nothing) for other sizes.
+template <typename T>
+bool fast_fft_available(int nx, int ny, int nz);
+template <typename T>
+bool fast_fft_y(const Batch<T>& B, int dir, hipStream_t s);
+template <typename T>
+bool fast_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s);
+template <typename T>
+bool fast_fft_x_forward(const Batch<T>& B, int in, hipStream_t s);
+template <typename T>
+bool fast_fft_x_inverse(const Batch<T>& B, int out, bool accumulate, hipStream_t s);
+
+// ------------------------------------------------------------ grid kernels
+template <typename T>
+void launch_rhs(const Batch<T>& B, hipStream_t s);
+template <typename T>
+void launch_spread_overflow(const Batch<T>& B, hipStream_t s);
+// rhs field of every replica = equilibrium sample N(0, sd^2) per face
+// (noise key of step 0).
+template <typename T>
+void launch_equilibrium_noise(const Batch<T>& B, double sd, hipStream_t s);
+template <typename T>
+void launch_zero(const Batch<T>& B, int field, hipStream_t s);
+// field y += field x
+template <typename T>
+void launch_axpy(const Batch<T>& B, int y, int x, hipStream_t s);
+
+// spread: field += h^-3 * prod(phi) * val at positions q, val_a = F[b][a] *
+// (coef ? coef[b] : 1).
+template <typename T>
+void launch_spread(const Batch<T>& B, int field, int q, int F, int coef, hipStream_t s);
+// gather: out[b][a] = sum prod(phi) f_a (or of (L f)_a with laplacian = true)
+// at positions q.
+template <typename T>
+void launch_gather(const Batch<T>& B, int field, int q, int out, bool laplacian, hipStream_t s);
 
 // Fused gathers of the step (one 16-lane group per blob component):
-// J^n v^n with the predictor; J^{n+1/2} v^n with the RHS stencils and z-chunk
-// bins; J^{n+1/2} v^{n+1} with the position update (which also clears the
-// first n_clear bin counters for the next step).
+// J^n v^n with the predictor; J^{n+1/2} v^n with the RHS stencils; J^{n+1/2}
+// v^{n+1} with the position update (which also clears the z-chunk bin
+// counters and advances the step counter).
 template <typename T>
-void launch_gather_predict(const GridDesc<T>& g, int kernel, const BlobParams& bp, const BlobBufs& bb,
-                           hipStream_t s);
+void launch_gather_predict(const Batch<T>& B, hipStream_t s);
 template <typename T>
-void launch_gather_bins(const GridDesc<T>& g, int kernel, const BlobParams& bp, const BlobBufs& bb, int cap,
-                        hipStream_t s);
+void launch_gather_bins(const Batch<T>& B, hipStream_t s);
 template <typename T>
-void launch_gather_final(const GridDesc<T>& g, int kernel, const BlobParams& bp, const BlobBufs& bb, int n_clear,
-                         hipStream_t s);
+void launch_gather_final(const Batch<T>& B, hipStream_t s);
 // z-chunk bins of the RHS spread (positions qh); counters must start at zero.
-void launch_bins(int kernel, int nb, int nz, double h, const double* qh, int cap, int* chunk_count,
-                 int* chunk_list, hipStream_t s);
+template <typename T>
+void launch_bins(const Batch<T>& B, hipStream_t s);
+
+// ------------------------------------------------------------ reductions
+// acc[0..2] += rho h^3 sum v; acc[3] += rho h^3 sum v^2 / 2;
+// acc[4] = max |v| (as bits), acc[5] = max |Dv| (as bits)
+template <typename T>
+void launch_field_diag(const GridDesc<T>& g, double rho, double* acc, hipStream_t s);
+
+// ----------------------------------------------------------- blob kernels
+template <typename T>
+void launch_forces(const Batch<T>& B, hipStream_t s);
+template <typename T>
+void launch_inertial_dp(const Batch<T>& B, hipStream_t s);
+template <typename T>
+void launch_inertial_dp2(const Batch<T>& B, hipStream_t s);
+template <typename T>
+void launch_inertial_u(const Batch<T>& B, hipStream_t s);
+void launch_blob_diag(int nb, const double* me, const double* u, double* acc, hipStream_t s);
 
 }  // namespace icm

@@ -27,6 +27,7 @@ OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_STATE, E_NUMERIC = 0, -1, -2,
 FP64, FP32_GRID = 0, 1
 SLIP_NONE, SLIP_VISCOUS, SLIP_FULL = 0, 1, 2
 PTRS_DEVICE, BLOBS_KICK, STATE_PROJECT, STATE_EQUILIBRIUM = 1, 2, 4, 8
+STEP_GRAPH = 1
 
 _STATUS_NAMES = {OK: "ICM_OK", E_INVALID: "ICM_E_INVALID", E_UNSUPPORTED: "ICM_E_UNSUPPORTED",
                  E_NOMEM: "ICM_E_NOMEM", E_DEVICE: "ICM_E_DEVICE", E_STATE: "ICM_E_STATE",

@@ -200,3 +200,75 @@ def test_batched_uneven_replicas_match_single(I, precision):
             assert not bad, (r, bad)
     finally:
         sim.close()
+
+
+def _batch_cases():
+    """Six replicas, two grid shapes; one shape mixes m_e = 0 and m_e != 0
+    replicas (two batches), the other takes the generic FFT path."""
+    cases = []
+    mes = [(0.0,), (1.0,), (-0.5,), (0.0, 1.0)]
+    for i, me in enumerate(mes):
+        p = oracle_params((32, 32, 32), kernel=4, kT=1e-3, dt=0.25, seed=90 + i, replica=i)
+        cases.append((p, me, len(me)))
+    cases.append((oracle_params((24, 18, 12), kernel=3, kT=2e-3, dt=0.2, seed=95, replica=4), (0.0,), 3))
+    cases.append((oracle_params((24, 18, 12), kernel=3, kT=2e-3, dt=0.2, seed=95, replica=5), (0.0,), 0))
+    return cases
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_same_shape_batches_match_oracle(I, precision, graph):
+    """Replicas of one shape share launches (replica index from the grid);
+    each must still match its own oracle run, eagerly and replayed from a
+    recorded step graph."""
+    prec = I.FP64 if precision == "fp64" else I.FP32_GRID
+    tol = TOL64 if precision == "fp64" else TOL32
+    steps = 3 if precision == "fp64" else 1
+    dtype = np.float64 if prec == I.FP64 else np.float32
+    cases = _batch_cases()
+    states = [initial_state(p, nb, me, seed=60 + i, min_sep=3.0) for i, (p, me, nb) in enumerate(cases)]
+    if prec == I.FP32_GRID:
+        for st in states:
+            st.v = st.v.astype(np.float32).astype(np.float64)
+    banner("same-shape batches %s graph=%s" % (precision, graph))
+    sim = I.Sim([gpu_params(I, p) for p, _, _ in cases], [max(nb, 1) for _, _, nb in cases], prec)
+    try:
+        for r, st in enumerate(states):
+            load_into_gpu(I, sim, r, st, dtype)
+        sim.step(steps, I.STEP_GRAPH if graph else 0)
+        for r, ((p, _, _), st) in enumerate(zip(cases, states)):
+            ref = O.run(p, st, steps)
+            got = sim.get_state(r)
+            assert got["diag"]["step"] == steps
+            errs, bad = compare(got, ref, st.q, tol)
+            print("replica", r, {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+            assert not bad, (r, bad)
+    finally:
+        sim.close()
+
+
+def test_graph_replay_after_set_blobs(I):
+    """A recorded step is dropped and recorded again when the blobs change;
+    replays continue the Philox stream from the device step counter."""
+    p = oracle_params((32, 48, 32), kernel=4, kT=1e-3, dt=0.2, seed=101)
+    st = initial_state(p, 3, (0.0, 1.0, -0.5), seed=5, min_sep=4.0)
+    banner("graph replay after set_blobs")
+    sim = I.Sim([gpu_params(I, p)], [4], I.FP64)
+    try:
+        load_into_gpu(I, sim, 0, st, np.float64)
+        sim.step(2, I.STEP_GRAPH)
+        ref = O.run(p, st, 2)
+        # replace the blobs (new count and masses) and keep stepping
+        st2 = initial_state(p, 4, (0.0, 0.0, 2.0, 0.0), seed=6, min_sep=4.0)
+        st2.v = ref.v.copy()
+        st2.step = ref.step
+        load_into_gpu(I, sim, 0, st2, np.float64)
+        sim.step(2, I.STEP_GRAPH)
+        ref2 = O.run(p, st2, 2)
+        got = sim.get_state(0)
+        assert got["diag"]["step"] == 4
+        errs, bad = compare(got, ref2, st2.q, TOL64)
+        print({k: "%.2e" % v for k, v in errs.items()}, flush=True)
+        assert not bad, bad
+    finally:
+        sim.close()
