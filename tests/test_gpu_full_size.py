@@ -1,0 +1,117 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times (FP32 grid, FP64 blobs, eager and recorded-graph steps).
+
+256^3 with 4096 blobs: one step compared element by element with the FP64
+oracle (about 10 s of CPU time), plus the equilibrium initialiser.
+512^3 with 10^5 blobs: too large for the oracle within a test, so it is
+checked through properties that hold at any size: FP32 against FP64 on the
+same GPU from the same state, exact momentum balance, discrete divergence."""
+import numpy as np
+import pytest
+
+import icm_inputs
+from oracle import icm as O
+
+from .parity_cases import banner, compare, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 2e-5
+
+
+@pytest.fixture(scope="module")
+def I():
+    import paper_1212_6427_amd.icm as lib
+    return lib
+
+
+def _wl_params(wl):
+    sigma = wl["wca_cutoff"] / 2 ** (1.0 / 6.0)
+    return O.Params(n=tuple(wl["n"]), h=wl["h"], rho=wl["rho"], eta=wl["eta"], kT=wl["kT"], dt=wl["dt"],
+                    kernel=wl["kernel"], seed=wl["seed"], wca_eps=wl["wca_eps"], wca_sigma=sigma)
+
+
+def _gpu_params(I, p, body=(0.0, 0.0, 0.0)):
+    return I.make_params(p.n, h=p.h, rho=p.rho, eta=p.eta, kT=p.kT, dt=p.dt, kernel=p.kernel, seed=p.seed,
+                         wca_eps=p.wca_eps, wca_sigma=p.wca_sigma, body_force=body)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_many_blobs_256_one_step_fp32(I, graph):
+    wl = icm_inputs.WORKLOADS["many_blobs_256"]
+    p = _wl_params(wl)
+    q = icm_inputs.separated_positions(wl["n_blobs"], p.n, p.h, min_sep=wl["min_sep"], seed=wl["seed"])
+    banner("many_blobs_256 full size graph=%s" % graph)
+    v_eq = O.equilibrium_field(p)
+    sim = I.Sim([_gpu_params(I, p)], [wl["n_blobs"]], I.FP32_GRID)
+    try:
+        sim.set_blobs(0, q)
+        # the equilibrium initialiser at full size
+        sim.set_state(0, flags=I.STATE_EQUILIBRIUM)
+        got0 = sim.get_state(0)
+        e0 = max(rel_err(got0["v"][a], v_eq[a]) for a in range(3))
+        print("equilibrium initialiser rel err %.2e" % e0, flush=True)
+        assert e0 <= TOL32
+        # one step from the oracle's sample (rounded to FP32) on both sides
+        st = O.new_state(p, q)
+        st.v = v_eq.astype(np.float32).astype(np.float64)
+        sim.set_state(0, v=st.v.astype(np.float32), step=0)
+        sim.step(1, I.STEP_GRAPH if graph else 0)
+        got = sim.get_state(0)
+    finally:
+        sim.close()
+    ref = O.run(p, st, 1)
+    errs, bad = compare(got, ref, st.q, TOL32)
+    print({k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    assert not bad, bad
+
+
+def test_scale_512_fp32_against_fp64(I):
+    """512^3, 10^5 three-point blobs, WCA, a per-blob drag-scale force with the
+    opposite uniform force density on the fluid (net external force zero),
+    kT = 1e-3, dt = 0.2: two steps in FP32 and in FP64 from the same state."""
+    wl = icm_inputs.WORKLOADS["scale_512"]
+    sigma = wl["wca_cutoff"] / 2 ** (1.0 / 6.0)
+    n = tuple(wl["n"])
+    nb = wl["n_blobs"]
+    h, eta = wl["h"], wl["eta"]
+    # F0 = 3 pi eta nu Re_P per blob (rho = 1); the fluid carries -nb F0 / V
+    F0 = 3.0 * np.pi * eta * (eta / wl["rho"]) * wl["re_p"]
+    body = (-nb * F0 / (np.prod(n) * h ** 3), 0.0, 0.0)
+    p = O.Params(n=n, h=h, rho=wl["rho"], eta=eta, kT=wl["kT"], dt=wl["dt"], kernel=wl["kernel"], seed=wl["seed"],
+                 wca_eps=wl["wca_eps"], wca_sigma=sigma, body_force=body)
+    q = icm_inputs.separated_positions(nb, n, h, min_sep=wl["min_sep"], seed=wl["seed"])
+    F = np.zeros((nb, 3))
+    F[:, 0] = F0
+    banner("scale_512 fp32 vs fp64")
+    gp = _gpu_params(I, p, body)
+    s64 = I.Sim([gp], [nb], I.FP64)
+    s32 = I.Sim([gp], [nb], I.FP32_GRID)
+    try:
+        s64.set_blobs(0, q, f_const=F)
+        s64.set_state(0, flags=I.STATE_EQUILIBRIUM)
+        v0 = s64.get_state(0, want_diag=False)["v"].astype(np.float32)
+        s64.set_state(0, v=v0.astype(np.float64), step=0)
+        s32.set_blobs(0, q, f_const=F)
+        s32.set_state(0, v=v0, step=0)
+        d0 = s64.get_state(0, want_v=False)["diag"]
+        s64.step(2, I.STEP_GRAPH)
+        s32.step(2, I.STEP_GRAPH)
+        a = s64.get_state(0)
+        b = s32.get_state(0)
+    finally:
+        s64.close()
+        s32.close()
+    ev = max(rel_err(b["v"][c], a["v"][c]) for c in range(3))
+    eu = rel_err(b["u"], a["u"])
+    edq = rel_err(b["q"] - q, a["q"] - q)
+    print("fp32 vs fp64: v %.2e  u %.2e  dq %.2e" % (ev, eu, edq), flush=True)
+    assert ev <= 2 * TOL32 and eu <= 2 * TOL32 and edq <= 2 * TOL32
+    # zero net external force: total momentum is conserved (FP64 run exactly,
+    # up to the rounding of the sums; FP32 run to the storage rounding)
+    scale = p.rho * h ** 3 * float(np.sum(np.abs(a["v"])))
+    for name, s in (("fp64", a), ("fp32", b)):
+        drift = np.abs(np.asarray(s["diag"]["momentum"]) - np.asarray(d0["momentum"]))
+        print(name, "momentum drift / scale", drift / scale, flush=True)
+        assert np.all(drift <= (1e-12 if name == "fp64" else 1e-6) * scale)
+        assert s["diag"]["max_div"] <= (1e-12 if name == "fp64" else 1e-5)
