@@ -110,13 +110,13 @@ def setup(I, torch, wl, precision, stream):
     return sim, p, q
 
 
-def time_steps(torch, sim, stream, steps):
+def time_steps(torch, sim, stream, steps, flags=0):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
     a.record(stream)
-    sim.step(steps)
+    sim.step(steps, flags)
     b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -201,6 +201,60 @@ def ensemble_leg(I, torch, stream, steps, warmup):
     return out
 
 
+def scale_leg(I, torch, stream, steps):
+    """512^3 with 10^5 three-point blobs, WCA, kT = 1e-3, dt = 0.2, a per-blob
+    force F0 x (F0 = 3 pi eta nu Re_P, Re_P = 1) and the opposite uniform force
+    density on the fluid: FP32 grid and FP64 runs from the same state; their
+    throughput, the largest relative differences of v and u after `steps`
+    steps, and the drift of the total momentum (zero net external force)."""
+    import icm_inputs
+    wl = icm_inputs.WORKLOADS["scale_512"]
+    n = tuple(wl["n"])
+    nb = wl["n_blobs"]
+    h, eta, rho = wl["h"], wl["eta"], wl["rho"]
+    sigma = wl["wca_cutoff"] / 2 ** (1.0 / 6.0)
+    F0 = 3.0 * np.pi * eta * (eta / rho) * wl["re_p"]
+    body = (-nb * F0 / (float(np.prod(n)) * h ** 3), 0.0, 0.0)
+    p = I.make_params(n, h=h, rho=rho, eta=eta, kT=wl["kT"], dt=wl["dt"], kernel=wl["kernel"], seed=wl["seed"],
+                      wca_eps=wl["wca_eps"], wca_sigma=sigma, body_force=body)
+    q = icm_inputs.separated_positions(nb, n, h, min_sep=wl["min_sep"], seed=wl["seed"])
+    F = np.zeros((nb, 3))
+    F[:, 0] = F0
+    out = {"grid": list(n), "n_blobs": nb, "steps": steps}
+    sims = {}
+    for name, prec in (("fp64", I.FP64), ("fp32", I.FP32_GRID)):
+        nbytes = I.icm_workspace_bytes([p], [nb], prec)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        sims[name] = (I.Sim([p], [nb], prec, stream=stream.cuda_stream, workspace=ws), ws)
+    s64, s32 = sims["fp64"][0], sims["fp32"][0]
+    s64.set_blobs(0, q, f_const=F)
+    s64.set_state(0, flags=I.STATE_EQUILIBRIUM)
+    v0 = s64.get_state(0, want_diag=False)["v"].astype(np.float32)
+    s64.set_state(0, v=v0.astype(np.float64), step=0)
+    s32.set_blobs(0, q, f_const=F)
+    s32.set_state(0, v=v0, step=0)
+    del v0
+    p0 = np.asarray(s64.get_state(0, want_v=False)["diag"]["momentum"])
+    for name, sim in (("fp64", s64), ("fp32", s32)):
+        sec, _ = time_steps(torch, sim, stream, steps, I.STEP_GRAPH)
+        out[name] = {"value": float(np.prod(n)) * steps / sec, "unit": "cell-steps/s",
+                     "blob_steps_per_s": nb * steps / sec, "ms_per_step": sec * 1000.0 / steps}
+        log("scale_512 %s: %.3f ms/step" % (name, out[name]["ms_per_step"]))
+    a = s64.get_state(0)
+    b = s32.get_state(0)
+    scale_v = max(float(np.max(np.abs(a["v"][c]))) for c in range(3))
+    out["max_rel_err_v"] = max(float(np.max(np.abs(b["v"][c].astype(np.float64) - a["v"][c]))) for c in range(3)) / scale_v
+    out["max_rel_err_u"] = float(np.max(np.abs(b["u"] - a["u"])) / np.max(np.abs(a["u"])))
+    mscale = rho * h ** 3 * float(np.sum(np.abs(a["v"])))
+    for name, st in (("fp64", a), ("fp32", b)):
+        out[name]["momentum_drift_rel"] = float(np.max(np.abs(np.asarray(st["diag"]["momentum"]) - p0)) / mscale)
+        out[name]["max_div"] = st["diag"]["max_div"]
+    for name in sims:
+        sims[name][0].close()
+    log("scale_512 fp32 vs fp64 after %d steps: v %.2e, u %.2e" % (steps, out["max_rel_err_v"], out["max_rel_err_u"]))
+    return out
+
+
 def cpu_baseline(wl, seed_positions):
     """The FP64 oracle, untuned, on one full step of the same workload."""
     from oracle import icm as O
@@ -231,6 +285,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=200)
+    ap.add_argument("--no-scale", action="store_true")
+    ap.add_argument("--eager", action="store_true", help="launch the step's kernels one by one instead of replaying "
+                                                         "the recorded step graph")
+    ap.add_argument("--scale-steps", type=int, default=200)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device tensor copy first (counter calibration)")
@@ -260,10 +318,11 @@ def main():
 
     log("setup FP32-grid context %s with %d blobs" % (n, nb))
     sim, p, q = setup(I, torch, wl, I.FP32_GRID, stream)
+    step_flags = 0 if args.eager else I.STEP_GRAPH
     log("warmup %d steps" % args.warmup)
-    sim.step(args.warmup)
-    log("timing %d steps" % args.steps)
-    sec, wall = time_steps(torch, sim, stream, args.steps)
+    sim.step(args.warmup, step_flags)
+    log("timing %d steps (%s)" % (args.steps, "eager launches" if args.eager else "recorded step graph"))
+    sec, wall = time_steps(torch, sim, stream, args.steps, step_flags)
     ms_per_step = sec * 1000.0 / args.steps
     value = ncell * args.steps / sec
     log("FP32 grid: %.3f ms/step, %.3e cell-steps/s" % (ms_per_step, value))
@@ -290,6 +349,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(n), "n_blobs": nb, "kernel": wl["kernel"],
+                   "launch": "eager" if args.eager else "recorded step graph",
                    "precision": "fp32 grid, fp64 blobs", "kT": wl["kT"], "dt": wl["dt"],
                    "forces": "WCA eps=%g cutoff=%gh" % (wl["wca_eps"], wl["wca_cutoff"])},
         "blob_steps_per_s": nb * args.steps / sec,
@@ -302,9 +362,9 @@ def main():
     if not args.no_fp64:
         log("setup FP64 context")
         sim64, _, _ = setup(I, torch, wl, I.FP64, stream)
-        sim64.step(max(2, args.warmup // 4))
+        sim64.step(max(2, args.warmup // 4), step_flags)
         k64 = max(10, args.steps // 4)
-        sec64, _ = time_steps(torch, sim64, stream, k64)
+        sec64, _ = time_steps(torch, sim64, stream, k64, step_flags)
         sim64.close()
         out["fp64"] = {"value": ncell * k64 / sec64, "ms_per_step": sec64 * 1000.0 / k64, "steps": k64,
                        "blob_steps_per_s": nb * k64 / sec64}
@@ -312,6 +372,9 @@ def main():
     if not args.no_ensemble:
         log("batched ensemble: 96 replicas of 32^3 / 48^3 / 64^3")
         out["ensemble"] = ensemble_leg(I, torch, stream, args.ensemble_steps, max(2, args.warmup // 2))
+    if not args.no_scale:
+        log("scale run: 512^3, 10^5 blobs, FP32 grid against FP64")
+        out["scale_512"] = scale_leg(I, torch, stream, args.scale_steps)
     if not args.no_cpu_baseline:
         log("CPU oracle: one step of the same workload")
         out["cpu_baseline"] = cpu_baseline(wl, q)
