@@ -182,7 +182,8 @@ void carve_grid(Carver& cv, const icm_replica_params& p, icm::GridDesc<T>& g) {
     if (const char* e = std::getenv("ICM_FFT_BY")) g.By = std::max(1, std::min(64, std::atoi(e)));
     if (const char* e = std::getenv("ICM_FFT_BZ")) g.Bz = std::max(1, std::min(64, std::atoi(e)));
     g.ncell = (long long)g.nx * g.ny * g.nz;
-    const int align = 128 / (int)sizeof(cplx<T>);
+    int align = 128 / (int)sizeof(cplx<T>);
+    if (const char* e = std::getenv("ICM_SPEC_ALIGN")) align = std::max(1, std::min(64, std::atoi(e)));
     g.Wp = (g.W + align - 1) / align * align;
     g.nspec = (long long)g.nz * g.ny * g.Wp;
     g.h = p.h;

@@ -12,6 +12,9 @@
 // velocity components of a mode in one thread, so the Helmholtz divide and
 // the 3x3 projection of Sec. III.D happen in registers between the forward
 // and inverse transforms.
+#include <algorithm>
+#include <cstdlib>
+
 #include "icm_internal.h"
 
 namespace icm {
@@ -184,6 +187,18 @@ __device__ __forceinline__ void reg_fft(cplx<T> (&a)[E], int t, cplx<T>* lds, in
 template <int N>
 constexpr int xline() { return N + N / 16 + 1; }
 
+// Two consecutive complex values (one dwordx4 access in FP32).
+template <typename T>
+struct alignas(2 * sizeof(cplx<T>)) CPair {
+    cplx<T> v[2];
+};
+
+// 16 bytes of real values (one dwordx4 access).
+template <typename T>
+struct alignas(16) Vec16 {
+    T v[16 / sizeof(T)];
+};
+
 template <typename T>
 __device__ __forceinline__ void load_tw(cplx<T>* dst, const cplx<T>* src, int n) {
     const gptr<const cplx<T>> gs = as_global(src);
@@ -324,10 +339,18 @@ __global__ void __launch_bounds__(512) k_xfwd_fast(const RepDesc<T>* __restrict_
     const long long row0 = (long long)c * g.ncell + 2 * ((long long)blockIdx.x * P) * N;
     const long long lim = (long long)c * g.ncell + 2 * npairs * N;
     constexpr int LS = xline<N>();
-    for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
-        const int ll = idx / N, x = idx - ll * N;
+    // 16-byte loads: V consecutive values of both rows per thread
+    constexpr int V = 16 / (int)sizeof(T);
+    for (int idx = threadIdx.x; idx < P * (N / V); idx += blockDim.x) {
+        const int ll = idx / (N / V), x = (idx - ll * (N / V)) * V;
         const long long o = row0 + 2LL * ll * N + x;
-        lds[ll * LS + skew<4>(x)] = (o < lim) ? cplx<T>{in[o], in[o + N]} : cplx<T>{0, 0};
+        Vec16<T> ra{}, rb{};
+        if (o < lim) {
+            ra = *(gptr<const Vec16<T>>)(in + o);
+            rb = *(gptr<const Vec16<T>>)(in + o + N);
+        }
+#pragma unroll
+        for (int q = 0; q < V; ++q) lds[ll * LS + skew<4>(x + q)] = cplx<T>{ra.v[q], rb.v[q]};
     }
     __syncthreads();
     cplx<T> a[E];
@@ -341,12 +364,26 @@ __global__ void __launch_bounds__(512) k_xfwd_fast(const RepDesc<T>* __restrict_
     __syncthreads();
     if (!ok) return;
     const gptr<cplx<T>> d0 = as_global(g.spec) + (long long)c * g.nspec + 2 * p * g.Wp;
-    for (int k = t; k < W; k += TL) {
-        const cplx<T> zk = lds[l * LS + skew<4>(k)];
-        const cplx<T> zc = cconj(lds[l * LS + skew<4>((N - k) % N)]);
-        const cplx<T> s = cadd(zk, zc), d = csub(zk, zc);
-        d0[k] = {(T)0.5 * s.x, (T)0.5 * s.y};
-        d0[g.Wp + k] = {(T)0.5 * d.y, (T)-0.5 * d.x};
+    // two consecutive modes per thread (16-byte stores for FP32); W is odd,
+    // so the last pair holds the Nyquist mode alone
+    for (int k = 2 * t; k < W; k += 2 * TL) {
+        CPair<T> ea, eb;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int kk = k + q < W ? k + q : k;
+            const cplx<T> zk = lds[l * LS + skew<4>(kk)];
+            const cplx<T> zc = cconj(lds[l * LS + skew<4>((N - kk) % N)]);
+            const cplx<T> s = cadd(zk, zc), d = csub(zk, zc);
+            ea.v[q] = {(T)0.5 * s.x, (T)0.5 * s.y};
+            eb.v[q] = {(T)0.5 * d.y, (T)-0.5 * d.x};
+        }
+        if (k + 1 < W) {
+            *(gptr<CPair<T>>)(d0 + k) = ea;
+            *(gptr<CPair<T>>)(d0 + g.Wp + k) = eb;
+        } else {
+            d0[k] = ea.v[0];
+            d0[g.Wp + k] = eb.v[0];
+        }
     }
 }
 
@@ -370,18 +407,30 @@ __global__ void __launch_bounds__(512) k_xinv_fast(const RepDesc<T>* __restrict_
     const long long rp = g.Wp;
     const gptr<const cplx<T>> s0 = as_global((const cplx<T>*)g.spec) + (long long)c * g.nspec + 2 * p * rp;
     constexpr int LS = xline<N>();
-    for (int k = t; k < W; k += TL) {
-        cplx<T> A = {0, 0}, Bv = {0, 0};
+    // two consecutive modes per thread (16-byte loads for FP32)
+    for (int k = 2 * t; k < W; k += 2 * TL) {
+        CPair<T> ea{}, eb{};
         if (ok) {
-            A = s0[k];
-            Bv = s0[rp + k];
+            if (k + 1 < W) {
+                ea = *(gptr<const CPair<T>>)(s0 + k);
+                eb = *(gptr<const CPair<T>>)(s0 + rp + k);
+            } else {
+                ea.v[0] = s0[k];
+                eb.v[0] = s0[rp + k];
+            }
         }
-        if (k == 0 || k == H) {
-            A.y = 0;
-            Bv.y = 0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int kk = k + q;
+            if (kk >= W) break;
+            cplx<T> A = ea.v[q], Bv = eb.v[q];
+            if (kk == 0 || kk == H) {
+                A.y = 0;
+                Bv.y = 0;
+            }
+            lds[l * LS + skew<4>(kk)] = {A.x - Bv.y, A.y + Bv.x};
+            if (kk > 0 && kk < H) lds[l * LS + skew<4>(N - kk)] = {A.x + Bv.y, -A.y + Bv.x};
         }
-        lds[l * LS + skew<4>(k)] = {A.x - Bv.y, A.y + Bv.x};
-        if (k > 0 && k < H) lds[l * LS + skew<4>(N - k)] = {A.x + Bv.y, -A.y + Bv.x};
     }
     __syncthreads();
     cplx<T> a[E];
@@ -395,18 +444,31 @@ __global__ void __launch_bounds__(512) k_xinv_fast(const RepDesc<T>* __restrict_
     __syncthreads();
     const long long row0 = (long long)c * g.ncell + 2 * ((long long)blockIdx.x * P) * N;
     const long long lim = (long long)c * g.ncell + 2 * npairs * N;
-    for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
-        const int ll = idx / N, x = idx - ll * N;
+    // 16-byte stores: V consecutive values of both rows per thread
+    constexpr int V = 16 / (int)sizeof(T);
+    for (int idx = threadIdx.x; idx < P * (N / V); idx += blockDim.x) {
+        const int ll = idx / (N / V), x = (idx - ll * (N / V)) * V;
         const long long o = row0 + 2LL * ll * N + x;
         if (o >= lim) continue;
-        const cplx<T> z = lds[ll * LS + skew<4>(x)];
-        if (accumulate) {
-            out[o] += z.x;
-            out[o + N] += z.y;
-        } else {
-            out[o] = z.x;
-            out[o + N] = z.y;
+        Vec16<T> ra, rb;
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            const cplx<T> z = lds[ll * LS + skew<4>(x + q)];
+            ra.v[q] = z.x;
+            rb.v[q] = z.y;
         }
+        const gptr<Vec16<T>> oa = (gptr<Vec16<T>>)(out + o);
+        const gptr<Vec16<T>> ob = (gptr<Vec16<T>>)(out + o + N);
+        if (accumulate) {
+            const Vec16<T> pa = *oa, pb = *ob;
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                ra.v[q] += pa.v[q];
+                rb.v[q] += pb.v[q];
+            }
+        }
+        *oa = ra;
+        *ob = rb;
     }
 }
 
@@ -461,6 +523,7 @@ void allow_lds(K kernel, size_t bytes) {
 template <typename T>
 int pairs_per_block(int N, int TL) {
     int P = 256 / TL;
+    if (const char* e = std::getenv("ICM_FFT_XT")) P = std::max(1, std::atoi(e)) / TL;
     if (P < 1) P = 1;
     while (P > 1 && ((size_t)N + (size_t)P * (N + N / 16 + 1)) * sizeof(cplx<T>) > kLdsMax) P /= 2;
     return P;
