@@ -187,6 +187,32 @@ __device__ __forceinline__ void reg_fft(cplx<T> (&a)[E], int t, cplx<T>* lds, in
 template <int N>
 constexpr int xline() { return N + N / 16 + 1; }
 
+// The spectrum as a buffer resource (gfx9-family descriptor word 3); byte
+// offsets are 32-bit, which covers 3 components of a 512^3 FP64 spectrum.
+template <typename T>
+struct SpecBuf {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ explicit SpecBuf(const GridDesc<T>& g)
+        : r(__builtin_amdgcn_make_buffer_rsrc(g.spec, (short)0,
+                                              (int)(uint32_t)(3ull * (unsigned long long)g.nspec * sizeof(cplx<T>)),
+                                              0x00020000)) {}
+    __device__ cplx<T> load(uint32_t vo, uint32_t so) const {
+        if constexpr (sizeof(T) == 4)
+            return __builtin_bit_cast(cplx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+        else
+            return __builtin_bit_cast(cplx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+    }
+    __device__ void store(cplx<T> v, uint32_t vo, uint32_t so) const {
+        if constexpr (sizeof(T) == 4) {
+            typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)vo, (int)so, 0);
+        } else {
+            typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, (int)vo, (int)so, 0);
+        }
+    }
+};
+
 // Two consecutive complex values (one dwordx4 access in FP32).
 template <typename T>
 struct alignas(2 * sizeof(cplx<T>)) CPair {
@@ -258,17 +284,20 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
     const int y = blockIdx.y;
     load_tw(tws, g.twz, N);
     constexpr int TL = N / E;
-    const long long zs = (long long)g.ny * g.Wp;  // stride between z planes
-    const gptr<cplx<T>> p0 = as_global(g.spec) + (long long)y * g.Wp + kx;
-    const gptr<cplx<T>> p1 = p0 + g.nspec;
-    const gptr<cplx<T>> p2 = p1 + g.nspec;
+    // Buffer accesses: one 32-bit per-thread offset (column, first plane); the
+    // plane and component offsets are uniform and go in the scalar offset, so
+    // the 3E loads and stores need no per-access address registers.
+    const SpecBuf<T> sb(g);
+    const uint32_t zb = (uint32_t)(g.ny * g.Wp) * (uint32_t)sizeof(cplx<T>);  // bytes between z planes
+    const uint32_t cb = (uint32_t)g.nspec * (uint32_t)sizeof(cplx<T>);       // bytes between components
+    const uint32_t vo = ((uint32_t)t * (uint32_t)(g.ny * g.Wp) + (uint32_t)(y * g.Wp + kx)) * (uint32_t)sizeof(cplx<T>);
     cplx<T> a0[E], a1[E], a2[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-        const long long o = (long long)(t + TL * i) * zs;
-        a0[i] = ok ? p0[o] : cplx<T>{0, 0};
-        a1[i] = ok ? p1[o] : cplx<T>{0, 0};
-        a2[i] = ok ? p2[o] : cplx<T>{0, 0};
+        const uint32_t so = (uint32_t)(TL * i) * zb;
+        a0[i] = ok ? sb.load(vo, so) : cplx<T>{0, 0};
+        a1[i] = ok ? sb.load(vo, so + cb) : cplx<T>{0, 0};
+        a2[i] = ok ? sb.load(vo, so + 2 * cb) : cplx<T>{0, 0};
     }
     __syncthreads();
     reg_fft<T, N, E, R0, R1, R2, -1>(a0, t, lds, B, b, tws);
@@ -307,10 +336,10 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
     if (ok) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            const long long o = (long long)(t + TL * i) * zs;
-            p0[o] = a0[i];
-            p1[o] = a1[i];
-            p2[o] = a2[i];
+            const uint32_t so = (uint32_t)(TL * i) * zb;
+            sb.store(a0[i], vo, so);
+            sb.store(a1[i], vo, so + cb);
+            sb.store(a2[i], vo, so + 2 * cb);
         }
     }
 }
@@ -510,6 +539,13 @@ struct PlanZ : Plan<T, N> {};
         static constexpr bool ok = true;                      \
         static constexpr int E = EE, R0 = A, R1 = B_, R2 = C; \
     };
+// FP32: eight values per thread halve the registers of the three-component
+// pencil (one more LDS exchange per transform), which doubles the waves the
+// pass keeps in flight; measured faster at 256^3.
+ICM_PLANZ(float, 64, 8, 8, 8, 1)
+ICM_PLANZ(float, 128, 8, 8, 4, 4)
+ICM_PLANZ(float, 256, 8, 8, 8, 4)
+ICM_PLANZ(float, 512, 8, 8, 8, 8)
 #undef ICM_PLANZ
 
 // Kernels whose LDS exceeds 64 KB opt in to the larger gfx950 allocation.
