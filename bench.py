@@ -25,6 +25,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-steps/s and blob-steps/s at 256^3; FP32 vs FP64 and batched vs single"
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 64 lanes x 2.4 GHz (one full-rate 32-bit op per
+# lane per clock), in tera lane-operations per second.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Algorithmic VALU work of the right-hand-side kernel per cell (issue slots,
+# transcendentals at quarter rate): Philox4x32-10 for the six normals
+# (1.5 calls x 10 rounds x (2 multiplies 32x32->64 + 4 xor) = 90), Box-Muller
+# (3 pairs x 23 = 69), stress divergence (21), viscous and inertial terms
+# (24), spread accumulation (3).
+RHS_ALG_OPS_PER_CELL = 90 + 69 + 21 + 24 + 3
 
 
 def log(msg):
@@ -331,9 +340,18 @@ def main():
     sim.close()
     dom = max(phases.items(), key=lambda kv: kv[1]["total_ms_per_step"])
     dom_name, dom_v = dom
-    roofline = dict(bound="hbm", kernel=dom_name, achieved=dom_v["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=dom_v["achieved_GBs"] / HBM_PEAK_GBS, traffic=measured_traffic(dom_name),
-                    alg_bytes_per_launch=dom_v["alg_bytes_per_launch"], avg_launch_us=dom_v["avg_launch_us"])
+    if dom_name == "rhs":
+        # bound by integer and transcendental VALU work (Philox, Box-Muller)
+        ops = RHS_ALG_OPS_PER_CELL * ncell
+        achieved = ops / (dom_v["avg_launch_us"] * 1e-6) / 1e12
+        roofline = dict(bound="alu", kernel="k_rhs_march", achieved=achieved, peak=VALU_PEAK_TOPS, unit="TOP/s",
+                        frac=achieved / VALU_PEAK_TOPS, traffic=measured_traffic(dom_name),
+                        alg_ops_per_launch=ops, avg_launch_us=dom_v["avg_launch_us"],
+                        hbm_achieved_GBs=dom_v["achieved_GBs"], alg_bytes_per_launch=dom_v["alg_bytes_per_launch"])
+    else:
+        roofline = dict(bound="hbm", kernel=dom_name, achieved=dom_v["achieved_GBs"], peak=HBM_PEAK_GBS,
+                        unit="GB/s", frac=dom_v["achieved_GBs"] / HBM_PEAK_GBS, traffic=measured_traffic(dom_name),
+                        alg_bytes_per_launch=dom_v["alg_bytes_per_launch"], avg_launch_us=dom_v["avg_launch_us"])
     step_alg_bytes = 12 * ncell * 4
     out = {
         "metric": METRIC,
