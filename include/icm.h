@@ -74,7 +74,7 @@ enum {
                                discretely divergence-free fields             */
     ICM_STATE_EQUILIBRIUM = 8u /* icm_set_state: replace v by a sample of the
                                discrete equilibrium N(0, kT/(rho h^3)) P drawn
-                               from Philox block 2 of (seed, replica_id)     */
+                               from Philox block 3 of (seed, replica_id)     */
 };
 
 /* flags of icm_step */

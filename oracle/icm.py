@@ -339,8 +339,7 @@ def stochastic_stress_divergence(p, step):
     at (i h, (j+1/2) h, k h), of the yz family at ((i+1/2) h, j h, k h).
     """
     nx, ny, nz = p.n
-    ncell = nx * ny * nz
-    W = philox.stress_normals(ncell, step, p.seed, p.replica)
+    W = philox.stress_normals(p.n, step, p.seed, p.replica)
     shp = (nz, ny, nx)
     sxx = 2.0 * W["xx"].reshape(shp)
     syy = 2.0 * W["yy"].reshape(shp)
@@ -552,7 +551,7 @@ def kick_field(p, q, u0, m_e):
 
 def equilibrium_field(p):
     """A sample of the discrete Gibbs-Boltzmann distribution of the fluid:
-    every face value N(0, kT/(rho dV_f)) from Philox block 2, then projected,
+    every face value N(0, kT/(rho dV_f)) from Philox block 3, then projected,
     so the covariance is (kT/(rho dV_f)) P (Sec. II.F with no blobs)."""
     nx, ny, nz = p.n
     a, b, c = philox.equilibrium_normals(nx * ny * nz, p.seed, p.replica)

@@ -14,9 +14,11 @@ Box-Muller transform (Box & Muller, 1958).
 
 Counter and key layout (a convention of this project, shared with the GPU):
   key     = (seed mod 2^32, seed >> 32)
-  counter = (cell, step mod 2^32, (replica << 4) | block, step >> 32)
-with cell = i + Nx*(j + Ny*k). Blocks 0 and 1 feed the stochastic stress of a
-step, block 2 the optional equilibrium initial velocity.
+  counter = (index, step mod 2^32, (replica << 4) | block, step >> 32)
+For the stochastic stress of a step, the two cells (i, j, 2m) and
+(i, j, 2m+1) share index i + Nx*(j + Ny*m) and blocks 0, 1, 2: twelve words
+for their twelve normals. Block 3, with index i + Nx*(j + Ny*k) per cell,
+draws the optional equilibrium initial velocity.
 
 Parity unpinned: no known-answer vectors are available to this project, so the
 exact words are checked only by the two independent implementations agreeing
@@ -86,7 +88,7 @@ def box_muller(wa, wb):
 
 
 def cell_words(n_cells, step, seed, replica, block):
-    """The four Philox words of `block` for every cell 0..n_cells-1."""
+    """The four Philox words of `block` for every counter index 0..n_cells-1."""
     cells = np.arange(n_cells, dtype=np.uint64)
     step = int(step)
     seed = int(seed)
@@ -96,27 +98,45 @@ def cell_words(n_cells, step, seed, replica, block):
                          seed & MASK32, (seed >> 32) & MASK32)
 
 
-def stress_normals(n_cells, step, seed, replica):
-    """Six unit normals per cell for the symmetric stochastic stress.
+def stress_normals(n, step, seed, replica):
+    """Six unit normals per cell for the symmetric stochastic stress on an
+    Nx x Ny x Nz grid (Nz even).
 
-    Block 0 words (w0,w1) -> (W_xx, W_yy) and (w2,w3) -> (W_zz, W_xy);
-    block 1 words (w0,w1) -> (W_xz, W_yz); the last two words of block 1 are
-    unused. Returns a dict of flat float64 arrays indexed by cell.
+    Cells (i, j, 2m) (lower) and (i, j, 2m+1) (upper) share the counter index
+    i + Nx*(j + Ny*m). With A, B, C the words of blocks 0, 1, 2:
+      lower: (A0,A1) -> (W_xx, W_yy), (A2,A3) -> (W_zz, W_xy), (B0,B1) -> (W_xz, W_yz)
+      upper: (B2,B3) -> (W_xx, W_yy), (C0,C1) -> (W_zz, W_xy), (C2,C3) -> (W_xz, W_yz)
+    Returns a dict of flat float64 arrays indexed by cell i + Nx*(j + Ny*k).
     """
-    a0, a1, a2, a3 = cell_words(n_cells, step, seed, replica, 0)
-    b0, b1, _, _ = cell_words(n_cells, step, seed, replica, 1)
-    wxx, wyy = box_muller(a0, a1)
-    wzz, wxy = box_muller(a2, a3)
-    wxz, wyz = box_muller(b0, b1)
-    return dict(xx=wxx, yy=wyy, zz=wzz, xy=wxy, xz=wxz, yz=wyz)
+    nx, ny, nz = (int(x) for x in n)
+    if nz % 2:
+        raise ValueError("the paired stress stream needs an even Nz (got %d)" % nz)
+    npairs = nx * ny * (nz // 2)
+    A = cell_words(npairs, step, seed, replica, 0)
+    B = cell_words(npairs, step, seed, replica, 1)
+    C = cell_words(npairs, step, seed, replica, 2)
+    lower, upper = {}, {}
+    lower["xx"], lower["yy"] = box_muller(A[0], A[1])
+    lower["zz"], lower["xy"] = box_muller(A[2], A[3])
+    lower["xz"], lower["yz"] = box_muller(B[0], B[1])
+    upper["xx"], upper["yy"] = box_muller(B[2], B[3])
+    upper["zz"], upper["xy"] = box_muller(C[0], C[1])
+    upper["xz"], upper["yz"] = box_muller(C[2], C[3])
+    out = {}
+    for key in ("xx", "yy", "zz", "xy", "xz", "yz"):
+        w = np.empty((nz // 2, 2, ny * nx))
+        w[:, 0, :] = lower[key].reshape(nz // 2, ny * nx)
+        w[:, 1, :] = upper[key].reshape(nz // 2, ny * nx)
+        out[key] = w.reshape(-1)
+    return out
 
 
 def equilibrium_normals(n_cells, seed, replica):
-    """Three unit normals per cell (one per face family) from block 2.
+    """Three unit normals per cell (one per face family) from block 3.
 
     Words (w0,w1) -> (x-face, y-face), (w2,w3) -> (z-face, unused).
     """
-    a0, a1, a2, a3 = cell_words(n_cells, 0, seed, replica, 2)
+    a0, a1, a2, a3 = cell_words(n_cells, 0, seed, replica, 3)
     nx_, ny_ = box_muller(a0, a1)
     nz_, _ = box_muller(a2, a3)
     return nx_, ny_, nz_

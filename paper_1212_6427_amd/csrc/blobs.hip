@@ -75,33 +75,41 @@ __global__ void __launch_bounds__(kThreads) k_pairs_cells(const RepDesc<T>* __re
         c[a] = cc >= cg.n[a] ? cg.n[a] - 1 : (cc < 0 ? 0 : cc);
     }
     double fx = 0, fy = 0, fz = 0;
-    for (int dz = -1; dz <= 1; ++dz) {
-        const int z = (c[2] + dz + cg.n[2]) % cg.n[2];
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int y = (c[1] + dy + cg.n[1]) % cg.n[1];
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int x = (c[0] + dx + cg.n[0]) % cg.n[0];
-                const unsigned long long h = cg.heads[((long long)z * cg.n[1] + y) * cg.n[0] + x];
-                int j = ((h >> kHeadBlobBits) == stamp) ? (int)(h & ((1u << kHeadBlobBits) - 1)) : -1;
-                while (j >= 0) {
-                    if (j != i) {
-                        double ex = qx - b.qw[3 * j], ey = qy - b.qw[3 * j + 1], ez = qz - b.qw[3 * j + 2];
-                        ex = ex > hx ? ex - Lx : (ex < -hx ? ex + Lx : ex);
-                        ey = ey > hy ? ey - Ly : (ey < -hy ? ey + Ly : ey);
-                        ez = ez > hz ? ez - Lz : (ez < -hz ? ez + Lz : ez);
-                        const double r2 = ex * ex + ey * ey + ez * ez;
-                        if (r2 < rc2 && r2 > 0.0) {
-                            const double sr2 = s2 / r2;
-                            const double sr6 = sr2 * sr2 * sr2;
-                            const double f = 24.0 * bp.wca_eps * (2.0 * sr6 * sr6 - sr6) / r2;
-                            fx += f * ex;
-                            fy += f * ey;
-                            fz += f * ez;
-                        }
-                    }
-                    j = cg.next[j];
+    // the 27 head loads are independent: issue them all before walking
+    const gptr<const unsigned long long> heads = as_global((const unsigned long long*)cg.heads);
+    // neighbour cell coordinates per axis, wrapped (c in [0, n), n >= 3)
+    int nc[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        nc[a][0] = c[a] == 0 ? cg.n[a] - 1 : c[a] - 1;
+        nc[a][1] = c[a];
+        nc[a][2] = c[a] + 1 == cg.n[a] ? 0 : c[a] + 1;
+    }
+    unsigned long long hv[27];
+#pragma unroll
+    for (int n = 0; n < 27; ++n)
+        hv[n] = heads[((long long)nc[2][n / 9] * cg.n[1] + nc[1][(n / 3) % 3]) * cg.n[0] + nc[0][n % 3]];
+#pragma unroll
+    for (int n = 0; n < 27; ++n) {
+        const unsigned long long h = hv[n];
+        int j = ((h >> kHeadBlobBits) == stamp) ? (int)(h & ((1u << kHeadBlobBits) - 1)) : -1;
+        while (j >= 0) {
+            if (j != i) {
+                double ex = qx - b.qw[3 * j], ey = qy - b.qw[3 * j + 1], ez = qz - b.qw[3 * j + 2];
+                ex = ex > hx ? ex - Lx : (ex < -hx ? ex + Lx : ex);
+                ey = ey > hy ? ey - Ly : (ey < -hy ? ey + Ly : ey);
+                ez = ez > hz ? ez - Lz : (ez < -hz ? ez + Lz : ez);
+                const double r2 = ex * ex + ey * ey + ez * ez;
+                if (r2 < rc2 && r2 > 0.0) {
+                    const double sr2 = s2 / r2;
+                    const double sr6 = sr2 * sr2 * sr2;
+                    const double f = 24.0 * bp.wca_eps * (2.0 * sr6 * sr6 - sr6) / r2;
+                    fx += f * ex;
+                    fy += f * ey;
+                    fz += f * ez;
                 }
             }
+            j = cg.next[j];
         }
     }
     b.F[3 * i] += fx;

@@ -157,36 +157,61 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
     nk.step_lo = __builtin_amdgcn_readfirstlane((uint32_t)step_n);
     nk.step_hi = __builtin_amdgcn_readfirstlane((uint32_t)(step_n >> 32));
     const T r2 = (T)1.41421356237309504880;
-    // halo duty: threads [0, RTY) left column, [RTY, 2RTY) right column,
-    // [2RTY, 2RTY+RTX) bottom row, [2RTY+RTX, 2RTY+2RTX) top row
-    // valid tile extent; the right / top halo sits just past it (wrapped)
+    // halo duty (valid tile extent; the right / top halo sits just past it,
+    // wrapped): wave 0 takes the ring cells that need one Philox block per
+    // plane (left column, bottom row), wave 1 those that need up to two
+    // (right column, top row), so each of the two waves runs one halo branch
+    // and their SIMDs carry similar extra work.
+    static_assert(RTX + RTY <= 64, "one wave per half of the halo ring");
     const int wx = min(RTX, nx - i0), wy = min(RTY, ny - j0);
     const int tid = threadIdx.x;
     int hi = -1, hj = -1, hkind = -1;
     if (tid < RTY) { hkind = 0; hi = i0 - 1; hj = j0 + tid; }
-    else if (tid < 2 * RTY) { hkind = 1; hi = i0 + wx; hj = j0 + tid - RTY; }
-    else if (tid < 2 * RTY + RTX) { hkind = 2; hi = i0 + tid - 2 * RTY; hj = j0 - 1; }
-    else if (tid < 2 * RTY + 2 * RTX) { hkind = 3; hi = i0 + tid - 2 * RTY - RTX; hj = j0 + wy; }
+    else if (tid < RTY + RTX) { hkind = 2; hi = i0 + tid - RTY; hj = j0 - 1; }
+    else if (tid >= 64 && tid < 64 + RTY) { hkind = 1; hi = i0 + wx; hj = j0 + tid - 64; }
+    else if (tid >= 64 + RTY && tid < 64 + RTY + RTX) { hkind = 3; hi = i0 + tid - 64 - RTY; hj = j0 + wy; }
     const int hiw = wrap(hi, nx), hjw = wrap(hj, ny);
     const bool hvalid = hkind >= 0 && (hkind >= 2 ? hi - i0 < wx : hj - j0 < wy);
 
-    // registers carried along z
+    // registers carried along z. Cells (i, j, 2m) and (i, j, 2m+1) share the
+    // Philox counter of pair m = i + Nx (j + Ny m); blocks A = 0, B = 1, C = 2:
+    //   lower: A(0,1) -> xx, yy; A(2,3) -> zz, xy; B(0,1) -> xz, yz
+    //   upper: B(2,3) -> xx, yy; C(0,1) -> zz, xy; C(2,3) -> xz, yz
+    // An even plane draws A and C of its pair, an odd plane B of the next
+    // pair (whose xz, yz enter the odd plane and whose xx, yy wait for the
+    // pair's upper plane): three calls per two cells.
     T vm[3] = {0, 0, 0}, v0[3] = {0, 0, 0}, vp[3] = {0, 0, 0};
     T wzz_m = 0, wxz_c = 0, wyz_c = 0;
+    T up_xx = 0, up_yy = 0, up_zz = 0, up_xy = 0;  // upper-cell normals of the current pair
+    const uint32_t pairs_plane = (uint32_t)plane;  // pair counters per pair of planes
+    // v is read one plane ahead of its use (vp for plane k + 1 was loaded
+    // during plane k - 1; the halo ring's values likewise), so the loads'
+    // latency overlaps a whole plane of work.
+    T hcur[3] = {0, 0, 0};
+    if (hvalid) {
+        const long long hc = (long long)k0 * plane + (long long)hjw * nx + hiw;
+        for (int a = 0; a < 3; ++a) hcur[a] = gv[a * g.ncell + hc];
+    }
     if (own) {
         const int km = wrap(k0 - 1, nz);
+        const int k0p = k0 + 1 == nz ? 0 : k0 + 1;
         for (int a = 0; a < 3; ++a) {
             vm[a] = gv[a * g.ncell + km * plane + col];
             v0[a] = gv[a * g.ncell + (long long)k0 * plane + col];
+            vp[a] = gv[a * g.ncell + (long long)k0p * plane + col];
         }
         if (noisy) {
-            const u32x4 w = noise_words(nk, (uint32_t)(km * plane + col), 0);
-            NormalPair<T> p = bm<T>(w.z, w.w);
-            wzz_m = p.a;
-            const u32x4 w1 = noise_words(nk, (uint32_t)(k0 * plane + col), 1);
-            NormalPair<T> q = bm<T>(w1.x, w1.y);
+            // W_zz of the odd plane k0 - 1 (C of the previous pair); xz, yz of
+            // plane k0 and xx, yy of plane k0 + 1 (B of the first pair)
+            const uint32_t mprev = (uint32_t)(km / 2), m0 = (uint32_t)(k0 / 2);
+            const u32x4 wc = noise_words(nk, mprev * pairs_plane + (uint32_t)col, 2);
+            wzz_m = bm<T>(wc.x, wc.y).a;
+            const u32x4 wb = noise_words(nk, m0 * pairs_plane + (uint32_t)col, 1);
+            const NormalPair<T> q = bm<T>(wb.x, wb.y), r = bm<T>(wb.z, wb.w);
             wxz_c = q.a;
             wyz_c = q.b;
+            up_xx = r.a;
+            up_yy = r.b;
         }
     }
     // blobs of this z-chunk whose stencil meets the tile
@@ -287,19 +312,45 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
             const double v = tap_value<T>(rb, o, b, a, ia, ib, ic, inv_h3);
             atomicAdd(&s_acc[a][y - j0][x - i0], (T)v);
         }
+        const bool more = k + 1 < k1;
+        T vq[3] = {0, 0, 0}, hq[3] = {0, 0, 0};
+        if (own && more) {
+            const int kq = kp + 1 == nz ? 0 : kp + 1;
+            for (int a = 0; a < 3; ++a) vq[a] = gv[a * g.ncell + (long long)kq * plane + col];
+        }
+        if (hvalid && more) {
+            const long long hn = (long long)kp * plane + (long long)hjw * nx + hiw;
+            for (int a = 0; a < 3; ++a) hq[a] = gv[a * g.ncell + hn];
+        }
         if (own) {
-            for (int a = 0; a < 3; ++a) vp[a] = gv[a * g.ncell + (long long)kp * plane + col];
             if (noisy) {
-                const u32x4 w0 = noise_words(nk, (uint32_t)(k * plane + col), 0);
-                NormalPair<T> p0 = bm<T>(w0.x, w0.y), p1 = bm<T>(w0.z, w0.w);
-                wxx = p0.a;
-                wyy = p0.b;
-                wzz = p1.a;
-                wxy = p1.b;
-                const u32x4 w1 = noise_words(nk, (uint32_t)(kp * plane + col), 1);
-                NormalPair<T> p2 = bm<T>(w1.x, w1.y);
-                wxz_n = p2.a;
-                wyz_n = p2.b;
+                if ((k & 1) == 0) {
+                    const uint32_t ctr = (uint32_t)(k / 2) * pairs_plane + (uint32_t)col;
+                    const u32x4 wa = noise_words(nk, ctr, 0);
+                    const NormalPair<T> p0 = bm<T>(wa.x, wa.y), p1 = bm<T>(wa.z, wa.w);
+                    wxx = p0.a;
+                    wyy = p0.b;
+                    wzz = p1.a;
+                    wxy = p1.b;
+                    const u32x4 wc = noise_words(nk, ctr, 2);
+                    const NormalPair<T> p2 = bm<T>(wc.x, wc.y), p3 = bm<T>(wc.z, wc.w);
+                    up_zz = p2.a;
+                    up_xy = p2.b;
+                    wxz_n = p3.a;
+                    wyz_n = p3.b;
+                } else {
+                    wxx = up_xx;
+                    wyy = up_yy;
+                    wzz = up_zz;
+                    wxy = up_xy;
+                    const uint32_t ctr = (uint32_t)(kp / 2) * pairs_plane + (uint32_t)col;
+                    const u32x4 wb = noise_words(nk, ctr, 1);
+                    const NormalPair<T> p0 = bm<T>(wb.x, wb.y), p1 = bm<T>(wb.z, wb.w);
+                    wxz_n = p0.a;
+                    wyz_n = p0.b;
+                    up_xx = p1.a;
+                    up_yy = p1.b;
+                }
             }
             for (int a = 0; a < 3; ++a) sv[a][ty + 1][tx + 1] = v0[a];
             sxx[ty][tx + 1] = wxx;
@@ -309,28 +360,46 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
             syz[ty][tx] = wyz_c;
         }
         if (hvalid) {
-            const long long hc = (long long)k * plane + (long long)hjw * nx + hiw;
             // LDS slot of the halo cell (column/row index within the tile + 1)
             const int sy = hkind <= 1 ? hj - j0 + 1 : (hkind == 2 ? 0 : wy + 1);
             const int sx = hkind == 0 ? 0 : (hkind == 1 ? wx + 1 : hi - i0 + 1);
-            for (int a = 0; a < 3; ++a) sv[a][sy][sx] = gv[a * g.ncell + hc];
+            for (int a = 0; a < 3; ++a) sv[a][sy][sx] = hcur[a];
             if (noisy) {
-                if (hkind == 0) {
-                    const u32x4 w = noise_words(nk, (uint32_t)hc, 0);
-                    sxx[hj - j0][0] = bm<T>(w.x, w.y).a;
-                } else if (hkind == 1) {
-                    const u32x4 w = noise_words(nk, (uint32_t)hc, 0);
-                    sxy[hj - j0][wx] = bm<T>(w.z, w.w).b;
-                    const u32x4 w1 = noise_words(nk, (uint32_t)hc, 1);
-                    sxz[hj - j0][wx] = bm<T>(w1.x, w1.y).a;
-                } else if (hkind == 2) {
-                    const u32x4 w = noise_words(nk, (uint32_t)hc, 0);
-                    syy[0][hi - i0] = bm<T>(w.x, w.y).b;
+                // the halo cell's pair counter; which words hold its normals
+                // depends on the parity of k (see the pair layout above)
+                const uint32_t hctr = (uint32_t)(k / 2) * pairs_plane + (uint32_t)((long long)hjw * nx + hiw);
+                const bool odd = (k & 1) != 0;
+                if (hkind == 0 || hkind == 2) {
+                    // xx (left) or yy (bottom): A(0,1) on even planes, B(2,3) on odd
+                    const u32x4 w = noise_words(nk, hctr, odd ? 1 : 0);
+                    const NormalPair<T> pr = odd ? bm<T>(w.z, w.w) : bm<T>(w.x, w.y);
+                    if (hkind == 0)
+                        sxx[hj - j0][0] = pr.a;
+                    else
+                        syy[0][hi - i0] = pr.b;
                 } else {
-                    const u32x4 w = noise_words(nk, (uint32_t)hc, 0);
-                    sxy[wy][hi - i0] = bm<T>(w.z, w.w).b;
-                    const u32x4 w1 = noise_words(nk, (uint32_t)hc, 1);
-                    syz[wy][hi - i0] = bm<T>(w1.x, w1.y).b;
+                    // right: xy and xz; top: xy and yz. Even planes: xy from
+                    // A(2,3), xz / yz from B(0,1); odd planes: all from C.
+                    T exy, ez;
+                    if (odd) {
+                        const u32x4 w = noise_words(nk, hctr, 2);
+                        exy = bm<T>(w.x, w.y).b;
+                        const NormalPair<T> q = bm<T>(w.z, w.w);
+                        ez = hkind == 1 ? q.a : q.b;
+                    } else {
+                        const u32x4 w = noise_words(nk, hctr, 0);
+                        exy = bm<T>(w.z, w.w).b;
+                        const u32x4 w1 = noise_words(nk, hctr, 1);
+                        const NormalPair<T> q = bm<T>(w1.x, w1.y);
+                        ez = hkind == 1 ? q.a : q.b;
+                    }
+                    if (hkind == 1) {
+                        sxy[hj - j0][wx] = exy;
+                        sxz[hj - j0][wx] = ez;
+                    } else {
+                        sxy[wy][hi - i0] = exy;
+                        syz[wy][hi - i0] = ez;
+                    }
                 }
             }
         }
@@ -368,11 +437,13 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
         for (int a = 0; a < 3; ++a) {
             vm[a] = v0[a];
             v0[a] = vp[a];
+            vp[a] = vq[a];
+            hcur[a] = hq[a];
         }
     }
 }
 
-// Equilibrium sample: every face N(0, sd^2) from Philox block 2 of the cell
+// Equilibrium sample: every face N(0, sd^2) from Philox block 3 of the cell
 // (words (w0,w1) -> (x, y) faces, (w2,w3) -> (z face, unused)), with the
 // noise key of step 0; replica blockIdx.y.
 template <typename T>
@@ -383,7 +454,7 @@ __global__ void __launch_bounds__(kThreads) k_eq_noise(const RepDesc<T>* __restr
     nk.step_hi = 0;
     const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= g.ncell) return;
-    const u32x4 w = noise_words(nk, (uint32_t)cell, 2);
+    const u32x4 w = noise_words(nk, (uint32_t)cell, 3);
     double a, b, cz, unused;
     box_muller(w.x, w.y, a, b);
     box_muller(w.z, w.w, cz, unused);

@@ -70,16 +70,18 @@ __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
-// Counter layout: (cell, step mod 2^32, (replica << 4) | block, step >> 32),
-// key (seed mod 2^32, seed >> 32).
+// Counter layout: (index, step mod 2^32, (replica << 4) | block, step >> 32),
+// key (seed mod 2^32, seed >> 32). The stochastic stress uses the index of a
+// z pair of cells and blocks 0-2; the equilibrium sample the cell index and
+// block 3.
 struct NoiseKey {
     uint32_t k0, k1;      // seed words
     uint32_t step_lo, step_hi;
     uint32_t rep_tag;     // replica << 4
 };
 
-__device__ __forceinline__ u32x4 noise_words(const NoiseKey& nk, uint32_t cell, uint32_t block) {
-    return philox4x32_10(u32x4{cell, nk.step_lo, nk.rep_tag | block, nk.step_hi}, nk.k0, nk.k1);
+__device__ __forceinline__ u32x4 noise_words(const NoiseKey& nk, uint32_t index, uint32_t block) {
+    return philox4x32_10(u32x4{index, nk.step_lo, nk.rep_tag | block, nk.step_hi}, nk.k0, nk.k1);
 }
 
 // Box-Muller: first word -> radius via u1 = (w+1) 2^-32 in (0,1], second word
@@ -95,11 +97,12 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& z0,
 }
 
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z0, float& z1) {
-    // FP32 transform of the same words with the hardware log2 and the
-    // hardware sine/cosine, which take their argument in revolutions.
+    // FP32 transform of the same words with the hardware log2, square root
+    // (-2 ln u1 lies in [0, 44.4], no denormals) and sine/cosine, which take
+    // their argument in revolutions.
     const float u1 = fmaf((float)wa, 2.3283064365386963e-10f, 2.3283064365386963e-10f);
     const float u2 = (float)wb * 2.3283064365386963e-10f;
-    const float r = sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));  // -2 ln u1
+    const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));  // (-2 ln u1)^(1/2)
     z0 = r * __builtin_amdgcn_cosf(u2);
     z1 = r * __builtin_amdgcn_sinf(u2);
 }

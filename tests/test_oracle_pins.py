@@ -475,8 +475,9 @@ def test_philox_vectorised_matches_bigint_statement():
 
 
 def test_philox_normals_statistics():
-    n = 200000
-    W = philox.stress_normals(n, step=7, seed=123456789, replica=3)
+    shape = (40, 50, 100)
+    n = 40 * 50 * 100
+    W = philox.stress_normals(shape, step=7, seed=123456789, replica=3)
     allw = np.stack(list(W.values()))
     assert abs(allw.mean()) < 5 / np.sqrt(allw.size)
     assert abs(allw.var() - 1.0) < 5 * np.sqrt(2.0 / allw.size)
@@ -485,8 +486,13 @@ def test_philox_normals_statistics():
     C = np.corrcoef(allw)
     assert np.max(np.abs(C - np.eye(6))) < 5 / np.sqrt(n)
     # a different step gives an independent stream
-    W2 = philox.stress_normals(n, step=8, seed=123456789, replica=3)
+    W2 = philox.stress_normals(shape, step=8, seed=123456789, replica=3)
     assert abs(np.corrcoef(W["xx"], W2["xx"])[0, 1]) < 5 / np.sqrt(n)
+    # the two cells of a z pair (sharing a counter) are independent
+    lo = W["xx"].reshape(50, 2, -1)
+    assert abs(np.corrcoef(lo[:, 0].ravel(), lo[:, 1].ravel())[0, 1]) < 5 / np.sqrt(n / 2)
+    up = W["xz"].reshape(50, 2, -1)
+    assert abs(np.corrcoef(up[:, 0].ravel(), W["xx"].reshape(50, 2, -1)[:, 1].ravel())[0, 1]) < 5 / np.sqrt(n / 2)
     # uniform words: each bit is balanced
     words = philox.cell_words(n, 0, 5, 0, 0)[0]
     bits = ((words[:, None] >> np.arange(32, dtype=np.uint32)) & 1).mean(0)
