@@ -312,14 +312,22 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
         for (int i = 0; i < E; ++i) {
             const int kz = t + TL * i;
             const T lam = lxy + glz[kz];
-            const T f = (T)(sc.scale / (sc.a + sc.b * (double)lam));
+            T f;
+            if constexpr (sizeof(T) == 4)  // hardware reciprocal (1 ulp) in FP32
+                f = (T)sc.scale * __builtin_amdgcn_rcpf((T)sc.a + (T)sc.b * lam);
+            else
+                f = sc.scale / (sc.a + sc.b * lam);
             cplx<T> w0 = {a0[i].x * f, a0[i].y * f};
             cplx<T> w1 = {a1[i].x * f, a1[i].y * f};
             cplx<T> w2 = {a2[i].x * f, a2[i].y * f};
             if (project && lam > (T)0) {
                 const cplx<T> dz = gdz[kz];
                 const cplx<T> d = cadd(cadd(cmul(dx, w0), cmul(dy, w1)), cmul(dz, w2));
-                const T il = (T)1 / lam;
+                T il;
+                if constexpr (sizeof(T) == 4)
+                    il = __builtin_amdgcn_rcpf(lam);
+                else
+                    il = (T)1 / lam;
                 const cplx<T> dd = {d.x * il, d.y * il};
                 w0 = csub(w0, cmul(cconj(dx), dd));
                 w1 = csub(w1, cmul(cconj(dy), dd));
