@@ -149,7 +149,7 @@ def profile_phases(sim, steps, n, nb, kernel, w):
     return phases
 
 
-def ensemble_sims(I, torch, stream, batched):
+def ensemble_sims(I, torch, stream, batched, tune=True):
     """The batched ensemble: 96 replicas (32 each of 32^3, 48^3, 64^3), one
     blob each with m_e / m_f drawn from {0, 1, -1/2}, FP32 grid, fluid started
     from the discrete equilibrium. batched: one context holding every replica;
@@ -176,16 +176,19 @@ def ensemble_sims(I, torch, stream, batched):
         q, me = blobs[r]
         sim.set_blobs(loc, q, m_e=me)
         sim.set_state(loc, flags=I.STATE_EQUILIBRIUM)
+    if tune:
+        for sim in sims:
+            sim.autotune()
     cells = sum(int(np.prod(n)) for n in grids)
     return sims, cells, nrep
 
 
-def ensemble_leg(I, torch, stream, steps, warmup):
+def ensemble_leg(I, torch, stream, steps, warmup, tune=True):
     """cell-steps/s of the batched ensemble as one context (one recorded graph
     per step) against the same replicas stepped one context at a time."""
     out = {}
     for mode in ("batched", "single"):
-        sims, cells, nrep = ensemble_sims(I, torch, stream, mode == "batched")
+        sims, cells, nrep = ensemble_sims(I, torch, stream, mode == "batched", tune)
         for sim in sims:
             sim.step(warmup, I.STEP_GRAPH)
         torch.cuda.synchronize()
@@ -210,7 +213,7 @@ def ensemble_leg(I, torch, stream, steps, warmup):
     return out
 
 
-def scale_leg(I, torch, stream, steps):
+def scale_leg(I, torch, stream, steps, tune=True):
     """512^3 with 10^5 three-point blobs, WCA, kT = 1e-3, dt = 0.2, a per-blob
     force F0 x (F0 = 3 pi eta nu Re_P, Re_P = 1) and the opposite uniform force
     density on the fluid: FP32 grid and FP64 runs from the same state; their
@@ -243,6 +246,9 @@ def scale_leg(I, torch, stream, steps):
     s32.set_blobs(0, q, f_const=F)
     s32.set_state(0, v=v0, step=0)
     del v0
+    if tune:
+        s64.autotune()
+        s32.autotune()
     p0 = np.asarray(s64.get_state(0, want_v=False)["diag"]["momentum"])
     for name, sim in (("fp64", s64), ("fp32", s32)):
         sec, _ = time_steps(torch, sim, stream, steps, I.STEP_GRAPH)
@@ -295,6 +301,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=200)
     ap.add_argument("--no-scale", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default FFT launch shapes")
     ap.add_argument("--eager", action="store_true", help="launch the step's kernels one by one instead of replaying "
                                                          "the recorded step graph")
     ap.add_argument("--scale-steps", type=int, default=200)
@@ -327,6 +334,10 @@ def main():
 
     log("setup FP32-grid context %s with %d blobs" % (n, nb))
     sim, p, q = setup(I, torch, wl, I.FP32_GRID, stream)
+    tune = None
+    if not args.no_autotune:
+        tune = sim.autotune()
+        log("autotuned FFT launch shapes: %s" % tune)
     step_flags = 0 if args.eager else I.STEP_GRAPH
     log("warmup %d steps" % args.warmup)
     sim.step(args.warmup, step_flags)
@@ -368,6 +379,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(n), "n_blobs": nb, "kernel": wl["kernel"],
                    "launch": "eager" if args.eager else "recorded step graph",
+                   "fft_shapes": ({k: v for k, v in tune[0].items() if k not in ("n",)} if tune else "defaults"),
                    "precision": "fp32 grid, fp64 blobs", "kT": wl["kT"], "dt": wl["dt"],
                    "forces": "WCA eps=%g cutoff=%gh" % (wl["wca_eps"], wl["wca_cutoff"])},
         "blob_steps_per_s": nb * args.steps / sec,
@@ -380,6 +392,8 @@ def main():
     if not args.no_fp64:
         log("setup FP64 context")
         sim64, _, _ = setup(I, torch, wl, I.FP64, stream)
+        if not args.no_autotune:
+            sim64.autotune()
         sim64.step(max(2, args.warmup // 4), step_flags)
         k64 = max(10, args.steps // 4)
         sec64, _ = time_steps(torch, sim64, stream, k64, step_flags)
@@ -389,10 +403,11 @@ def main():
         log("FP64: %.3f ms/step" % out["fp64"]["ms_per_step"])
     if not args.no_ensemble:
         log("batched ensemble: 96 replicas of 32^3 / 48^3 / 64^3")
-        out["ensemble"] = ensemble_leg(I, torch, stream, args.ensemble_steps, max(2, args.warmup // 2))
+        out["ensemble"] = ensemble_leg(I, torch, stream, args.ensemble_steps, max(2, args.warmup // 2),
+                                       not args.no_autotune)
     if not args.no_scale:
         log("scale run: 512^3, 10^5 blobs, FP32 grid against FP64")
-        out["scale_512"] = scale_leg(I, torch, stream, args.scale_steps)
+        out["scale_512"] = scale_leg(I, torch, stream, args.scale_steps, not args.no_autotune)
     if not args.no_cpu_baseline:
         log("CPU oracle: one step of the same workload")
         out["cpu_baseline"] = cpu_baseline(wl, q)

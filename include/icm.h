@@ -163,6 +163,30 @@ icm_status icm_set_state(icm_ctx* ctx, int32_t replica, const void* v,
  * raised. Flags: ICM_STEP_GRAPH (other bits: ICM_E_INVALID).               */
 icm_status icm_step(icm_ctx* ctx, int64_t n_steps, uint32_t flags);
 
+/* Launch shapes of the FFT passes for one grid shape, as chosen by
+ * icm_autotune. Times are the five passes of one spectral solve (x forward,
+ * y forward, z with the solve, y inverse, x inverse) for all replicas of
+ * that shape, in microseconds.                                             */
+typedef struct {
+    int32_t n[3];          /* grid shape                                      */
+    int32_t y_columns;     /* kx columns per workgroup of the y passes         */
+    int32_t z_columns;     /* kx columns per workgroup of the z pass           */
+    int32_t z_small_plan;  /* 1: fewer values per thread in the z pass (FP32)  */
+    int32_t x_threads;     /* threads per workgroup of the x passes            */
+    int32_t tuned;         /* 0: this shape takes the generic passes (nothing
+                              to tune)                                        */
+    double us_default;     /* with the default shapes                         */
+    double us_tuned;       /* with the chosen shapes                          */
+} icm_tune_result;
+
+/* Measure the launch-shape variants of the FFT passes on the context's own
+ * scratch buffers (right-hand side, spectrum and inertial-correction fields;
+ * the state v, q, u is not touched) and keep the fastest for each grid
+ * shape. Enqueued on the context stream; synchronises. results: room for
+ * `capacity` entries (may be NULL when capacity is 0); *n_results receives
+ * the number of distinct grid shapes. A recorded step graph is dropped.     */
+icm_status icm_autotune(icm_ctx* ctx, icm_tune_result* results, int32_t capacity, int32_t* n_results);
+
 /* Read a replica's state. Any output may be NULL. v: face field in the
  * context precision; q, u, lag_c: n_blobs x 3; diag: FP64 diagnostics.     */
 icm_status icm_get_state(icm_ctx* ctx, int32_t replica, void* v, double* q,

@@ -6,6 +6,7 @@
 // nine steps of the Summary of Algorithm (Sec. III.C) as a fixed sequence of
 // kernels; no host synchronisation happens inside a step.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -175,15 +176,15 @@ void carve_grid(Carver& cv, const icm_replica_params& p, icm::GridDesc<T>& g) {
     g.nz = p.n[2];
     g.W = g.nx / 2 + 1;
     g.fast = icm::fast_fft_available<T>(g.nx, g.ny, g.nz) ? 1 : 0;
-    // kx columns per block of the fast y / z passes: 128 bytes of complex
-    // values by default; ICM_FFT_BY / ICM_FFT_BZ override them for tuning.
+    // Launch shapes of the fast FFT passes (icm_autotune may change them):
+    // 128 bytes of kx columns per y / z block, 256 threads per x block, the
+    // smaller per-thread z plan.
     g.By = 128 / (int)sizeof(cplx<T>);
     g.Bz = 128 / (int)sizeof(cplx<T>);
-    if (const char* e = std::getenv("ICM_FFT_BY")) g.By = std::max(1, std::min(64, std::atoi(e)));
-    if (const char* e = std::getenv("ICM_FFT_BZ")) g.Bz = std::max(1, std::min(64, std::atoi(e)));
+    g.xt = 256;
+    g.zsmall = 1;
     g.ncell = (long long)g.nx * g.ny * g.nz;
-    int align = 128 / (int)sizeof(cplx<T>);
-    if (const char* e = std::getenv("ICM_SPEC_ALIGN")) align = std::max(1, std::min(64, std::atoi(e)));
+    const int align = 128 / (int)sizeof(cplx<T>);
     g.Wp = (g.W + align - 1) / align * align;
     g.nspec = (long long)g.nz * g.ny * g.Wp;
     g.h = p.h;
@@ -624,6 +625,120 @@ icm_status capture_step(icm_ctx* c) {
     return ICM_OK;
 }
 
+// ----------------------------------------------------------- autotuner
+// Average time of one solve's FFT passes, or of one kind of pass, for the
+// batch B with its current launch shapes. which: 0 all five, 1 x pair, 2 y
+// pair, 3 z. The spectrum is refilled from the right-hand side before each
+// measurement so that repeated unnormalised transforms stay finite.
+template <typename T>
+float time_fft(icm_ctx* c, const icm::Batch<T>& B, int which, hipEvent_t ea, hipEvent_t eb) {
+    using namespace icm;
+    hipStream_t s = c->stream;
+    auto once = [&] {
+        if (which == 0 || which == 1) launch_fft_x_forward(B, kFieldRhs, s);
+        if (which == 0 || which == 2) launch_fft_y(B, -1, s);
+        if (which == 0 || which == 3) launch_fft_z_solve(B, kSolveP, true, s);
+        if (which == 0 || which == 2) launch_fft_y(B, 1, s);
+        if (which == 0 || which == 1) launch_fft_x_inverse(B, kFieldAux, false, s);
+    };
+    constexpr int kReps = 5;
+    launch_fft_x_forward(B, kFieldRhs, s);
+    once();  // warm-up
+    launch_fft_x_forward(B, kFieldRhs, s);
+    (void)hipEventRecord(ea, s);
+    for (int r = 0; r < kReps; ++r) once();
+    (void)hipEventRecord(eb, s);
+    if (hipEventSynchronize(eb) != hipSuccess) return -1.f;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ea, eb) != hipSuccess) return -1.f;
+    return ms * 1000.f / kReps;
+}
+
+template <typename T>
+icm_status autotune_t(icm_ctx* c, icm_tune_result* res, int32_t cap, int32_t* nres) {
+    hipEvent_t ea = nullptr, eb = nullptr;
+    HIP_TRY(c, hipEventCreate(&ea));
+    if (hipEventCreate(&eb) != hipSuccess) {
+        (void)hipEventDestroy(ea);
+        return fail(c, ICM_E_DEVICE, "hipEventCreate failed");
+    }
+    std::vector<std::array<int, 3>> done;
+    int count = 0;
+    icm_status st = ICM_OK;
+    for (const BatchInfo& bi : c->batches) {
+        const std::array<int, 3> shape = {bi.n[0], bi.n[1], bi.n[2]};
+        if (std::find(done.begin(), done.end(), shape) != done.end()) continue;
+        done.push_back(shape);
+        // all replicas of this shape, whichever batch holds them
+        icm::Batch<T> B = batch_of<T>(c, bi);
+        icm_tune_result r{};
+        for (int a = 0; a < 3; ++a) r.n[a] = shape[a];
+        const float t0 = time_fft<T>(c, B, 0, ea, eb);
+        if (t0 < 0) {
+            st = fail(c, ICM_E_DEVICE, "autotune timing failed");
+            break;
+        }
+        r.us_default = t0;
+        icm::GridDesc<T>& g = B.g;
+        if (g.fast) {
+            r.tuned = 1;
+            // z pass: plan size x columns; then y columns; then x threads
+            const int zplans[2] = {1, 0};
+            const int cols[3] = {8, 16, 32};
+            const int xts[3] = {128, 256, 512};
+            float best = 1e30f;
+            int bz = g.Bz, zs = g.zsmall;
+            for (int zp : zplans)
+                for (int cz : cols) {
+                    g.zsmall = zp;
+                    g.Bz = cz;
+                    const float t = time_fft<T>(c, B, 3, ea, eb);
+                    if (t >= 0 && t < best) { best = t; bz = cz; zs = zp; }
+                }
+            g.Bz = bz;
+            g.zsmall = zs;
+            best = 1e30f;
+            int by = g.By;
+            for (int cy : cols) {
+                g.By = cy;
+                const float t = time_fft<T>(c, B, 2, ea, eb);
+                if (t >= 0 && t < best) { best = t; by = cy; }
+            }
+            g.By = by;
+            best = 1e30f;
+            int xt = g.xt;
+            for (int x : xts) {
+                g.xt = x;
+                const float t = time_fft<T>(c, B, 1, ea, eb);
+                if (t >= 0 && t < best) { best = t; xt = x; }
+            }
+            g.xt = xt;
+            r.us_tuned = time_fft<T>(c, B, 0, ea, eb);
+            for (Replica& R : c->reps)
+                if (R.p.n[0] == shape[0] && R.p.n[1] == shape[1] && R.p.n[2] == shape[2]) {
+                    icm::GridDesc<T>& gr = grid_of<T>(R);
+                    gr.By = g.By;
+                    gr.Bz = g.Bz;
+                    gr.xt = g.xt;
+                    gr.zsmall = g.zsmall;
+                }
+        } else {
+            r.us_tuned = r.us_default;
+        }
+        r.y_columns = g.By;
+        r.z_columns = g.Bz;
+        r.z_small_plan = g.zsmall;
+        r.x_threads = g.xt;
+        if (res && count < cap) res[count] = r;
+        ++count;
+    }
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    if (st != ICM_OK) return st;
+    if (nres) *nres = count;
+    return sync_batches(c);
+}
+
 icm_status check_replica(icm_ctx* c, int32_t replica) {
     if (!c) return fail(nullptr, ICM_E_INVALID, "NULL context");
     if (replica < 0 || replica >= (int32_t)c->reps.size())
@@ -930,6 +1045,15 @@ icm_status icm_get_state(icm_ctx* c, int32_t replica, void* v, double* q, double
     }
     HIP_TRY(c, hipStreamSynchronize(s));
     return ICM_OK;
+}
+
+icm_status icm_autotune(icm_ctx* c, icm_tune_result* results, int32_t capacity, int32_t* n_results) {
+    if (!c) return fail(nullptr, ICM_E_INVALID, "NULL context");
+    if (c->error_state) return fail(c, ICM_E_STATE, "context is in an error state; call icm_set_state first");
+    if (capacity < 0 || (capacity > 0 && !results)) return fail(c, ICM_E_INVALID, "results must hold capacity entries");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return c->precision == ICM_FP64 ? autotune_t<double>(c, results, capacity, n_results)
+                                    : autotune_t<float>(c, results, capacity, n_results);
 }
 
 icm_status icm_set_timing(icm_ctx* c, int32_t enable) {

@@ -565,9 +565,8 @@ void allow_lds(K kernel, size_t bytes) {
 }
 
 template <typename T>
-int pairs_per_block(int N, int TL) {
-    int P = 256 / TL;
-    if (const char* e = std::getenv("ICM_FFT_XT")) P = std::max(1, std::atoi(e)) / TL;
+int pairs_per_block(int N, int TL, int xt) {
+    int P = (xt > 0 ? xt : 256) / TL;
     if (P < 1) P = 1;
     while (P > 1 && ((size_t)N + (size_t)P * (N + N / 16 + 1)) * sizeof(cplx<T>) > kLdsMax) P /= 2;
     return P;
@@ -598,9 +597,8 @@ bool y_fast(const Batch<T>& Bt, int dir, hipStream_t s) {
     }
 }
 
-template <typename T, int N>
-bool z_fast(const Batch<T>& Bt, int solve, bool project, hipStream_t s) {
-    using Pl = PlanZ<T, N>;
+template <typename T, int N, typename Pl>
+bool z_fast_plan(const Batch<T>& Bt, int solve, bool project, hipStream_t s) {
     if constexpr (!Pl::ok) {
         return false;
     } else {
@@ -618,6 +616,12 @@ bool z_fast(const Batch<T>& Bt, int solve, bool project, hipStream_t s) {
 }
 
 template <typename T, int N>
+bool z_fast(const Batch<T>& Bt, int solve, bool project, hipStream_t s) {
+    if (Bt.g.zsmall) return z_fast_plan<T, N, PlanZ<T, N>>(Bt, solve, project, s);
+    return z_fast_plan<T, N, Plan<T, N>>(Bt, solve, project, s);
+}
+
+template <typename T, int N>
 bool xf_fast(const Batch<T>& Bt, int in, hipStream_t s) {
     using Pl = Plan<T, N>;
     if constexpr (!Pl::ok) {
@@ -625,7 +629,7 @@ bool xf_fast(const Batch<T>& Bt, int in, hipStream_t s) {
     } else {
         const GridDesc<T>& g = Bt.g;
         constexpr int TL = N / Pl::E;
-        const int P = pairs_per_block<T>(N, TL);
+        const int P = pairs_per_block<T>(N, TL, g.xt);
         const long long npairs = (long long)g.ny * g.nz / 2;
         const dim3 grid((unsigned)((npairs + P - 1) / P), 3 * Bt.nrep);
         const size_t lds = (size_t)(N + P * xline<N>()) * sizeof(cplx<T>);
@@ -643,7 +647,7 @@ bool xi_fast(const Batch<T>& Bt, int out, bool acc, hipStream_t s) {
     } else {
         const GridDesc<T>& g = Bt.g;
         constexpr int TL = N / Pl::E;
-        const int P = pairs_per_block<T>(N, TL);
+        const int P = pairs_per_block<T>(N, TL, g.xt);
         const long long npairs = (long long)g.ny * g.nz / 2;
         const dim3 grid((unsigned)((npairs + P - 1) / P), 3 * Bt.nrep);
         const size_t lds = (size_t)(N + P * xline<N>()) * sizeof(cplx<T>);

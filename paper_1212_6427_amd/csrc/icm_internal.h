@@ -28,6 +28,8 @@ struct GridDesc {
     int Wp;            // spectrum row pitch (>= W, a multiple of 128 bytes)
     int fast;          // 1: register-resident FFT passes (all three N supported)
     int By, Bz;        // kx columns per block of the fast y and z passes
+    int xt;            // threads per block of the fast x passes
+    int zsmall;        // 1: the z pass holds the smaller per-thread plan (FP32)
     long long ncell;   // nx * ny * nz
     long long nspec;   // nz * ny * Wp
     double h;

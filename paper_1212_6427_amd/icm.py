@@ -70,6 +70,19 @@ class icm_timing(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 16), ("launches", ctypes.c_int64 * 16)]
 
 
+class icm_tune_result(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32 * 3),
+        ("y_columns", ctypes.c_int32),
+        ("z_columns", ctypes.c_int32),
+        ("z_small_plan", ctypes.c_int32),
+        ("x_threads", ctypes.c_int32),
+        ("tuned", ctypes.c_int32),
+        ("us_default", ctypes.c_double),
+        ("us_tuned", ctypes.c_double),
+    ]
+
+
 PHASES = ["gather", "blob", "forces", "rhs", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_solve", "fft_y_inv",
           "fft_x_inv", "field_ops"]
 
@@ -85,6 +98,8 @@ _lib.icm_set_blobs.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _p, _p, _
 _lib.icm_set_blobs.restype = ctypes.c_int
 _lib.icm_set_state.argtypes = [_p, ctypes.c_int32, _p, _p, _p, _p, ctypes.c_int64, ctypes.c_uint32]
 _lib.icm_set_state.restype = ctypes.c_int
+_lib.icm_autotune.argtypes = [_p, ctypes.POINTER(icm_tune_result), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+_lib.icm_autotune.restype = ctypes.c_int
 _lib.icm_step.argtypes = [_p, ctypes.c_int64, ctypes.c_uint32]
 _lib.icm_step.restype = ctypes.c_int
 _lib.icm_get_state.argtypes = [_p, ctypes.c_int32, _p, _p, _p, _p, ctypes.POINTER(icm_diag), ctypes.c_uint32]
@@ -185,6 +200,18 @@ def icm_set_state(ctx, replica, v=None, q=None, u=None, lag_c=None, step=-1, fla
     _check(_lib.icm_set_state(ctx, int(replica), pv, pq, pu, pl, int(step), int(flags)), ctx)
 
 
+def icm_autotune(ctx, capacity=64):
+    """Returns one dict per grid shape with the chosen FFT launch shapes."""
+    res = (icm_tune_result * capacity)()
+    n = ctypes.c_int32(0)
+    _check(_lib.icm_autotune(ctx, res, capacity, ctypes.byref(n)), ctx)
+    out = []
+    for r in res[:min(n.value, capacity)]:
+        out.append(dict(n=tuple(r.n), y_columns=r.y_columns, z_columns=r.z_columns, z_small_plan=r.z_small_plan,
+                        x_threads=r.x_threads, tuned=bool(r.tuned), us_default=r.us_default, us_tuned=r.us_tuned))
+    return out
+
+
 def icm_step(ctx, n_steps, flags=0):
     _check(_lib.icm_step(ctx, int(n_steps), int(flags)), ctx)
 
@@ -255,6 +282,9 @@ class Sim:
 
     def step(self, n=1, flags=0):
         icm_step(self.ctx, n, flags)
+
+    def autotune(self):
+        return icm_autotune(self.ctx)
 
     def get_state(self, replica=0, want_v=True, want_diag=True):
         return icm_get_state(self.ctx, replica, tuple(self.params[replica].n), self.dtype, want_v, want_diag)

@@ -28,6 +28,7 @@ def test_every_declared_symbol_is_exported():
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(I.icm_replica_params) == 152
     assert ctypes.sizeof(I.icm_diag) == 56
+    assert ctypes.sizeof(I.icm_tune_result) == 48
 
 
 @pytest.mark.parametrize("n,ok", [((32, 32, 32), True), ((48, 36, 24), True), ((6, 12, 18), True),

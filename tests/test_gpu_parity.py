@@ -272,3 +272,48 @@ def test_graph_replay_after_set_blobs(I):
         assert not bad, bad
     finally:
         sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotuned_launch_shapes_keep_parity(I, precision):
+    """icm_autotune picks FFT launch shapes per grid shape on the context's
+    scratch buffers; the state is untouched and steps still match the oracle."""
+    prec = I.FP64 if precision == "fp64" else I.FP32_GRID
+    tol = TOL64 if precision == "fp64" else TOL32
+    dtype = np.float64 if prec == I.FP64 else np.float32
+    cases = [
+        (oracle_params((64, 64, 64), kernel=4, kT=1e-3, dt=0.25, seed=71, replica=0), (0.0, 1.0), 2),
+        (oracle_params((32, 32, 32), kernel=3, kT=1e-3, dt=0.25, seed=72, replica=1), (0.0,), 1),
+        (oracle_params((48, 32, 36), kernel=4, kT=2e-3, dt=0.2, seed=73, replica=2), (-0.5,), 1),
+    ]
+    states = [initial_state(p, nb, me, seed=80 + i, min_sep=3.0) for i, (p, me, nb) in enumerate(cases)]
+    if prec == I.FP32_GRID:
+        for st in states:
+            st.v = st.v.astype(np.float32).astype(np.float64)
+    banner("autotune %s" % precision)
+    sim = I.Sim([gpu_params(I, p) for p, _, _ in cases], [nb for _, _, nb in cases], prec)
+    try:
+        for r, st in enumerate(states):
+            load_into_gpu(I, sim, r, st, dtype)
+        before = [sim.get_state(r, want_diag=False) for r in range(len(cases))]
+        res = sim.autotune()
+        print(res, flush=True)
+        assert sorted(tuple(r["n"]) for r in res) == sorted(p.n for p, _, _ in cases)
+        for r in res:
+            assert r["tuned"] == (r["n"] != (48, 32, 36))
+            assert r["y_columns"] in (8, 16, 32) and r["z_columns"] in (8, 16, 32)
+            assert r["x_threads"] in (128, 256, 512) and r["z_small_plan"] in (0, 1)
+            assert r["us_default"] > 0 and r["us_tuned"] > 0
+        # the state is not touched by the measurements
+        for r in range(len(cases)):
+            after = sim.get_state(r, want_diag=False)
+            for k in ("v", "q", "u"):
+                assert np.array_equal(after[k], before[r][k]), (r, k)
+        sim.step(2, I.STEP_GRAPH)
+        for r, ((p, _, _), st) in enumerate(zip(cases, states)):
+            ref = O.run(p, st, 2)
+            errs, bad = compare(sim.get_state(r), ref, st.q, 2 * tol)
+            print("replica", r, {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+            assert not bad, (r, bad)
+    finally:
+        sim.close()
