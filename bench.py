@@ -67,7 +67,7 @@ def algorithmic_bytes(phase, n, nb, kernel, w):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "many_blobs_256_fp32.md")
-PHASE_KERNEL = {"rhs": "k_rhs_march<float>", "fft_z_solve": "k_z_fast<float, 256, 16, 16, 16, 1>",
+PHASE_KERNEL = {"rhs": "k_rhs_march<float, true>", "fft_z_solve": "k_z_fast<float, 256, 8, 8, 8, 4>",
                 "fft_x_fwd": "k_xfwd_fast<float, 256, 16, 16, 16, 1>",
                 "fft_x_inv": "k_xinv_fast<float, 256, 16, 16, 16, 1>"}
 
