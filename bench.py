@@ -270,6 +270,135 @@ def scale_leg(I, torch, stream, steps, tune=True):
     return out
 
 
+def vacf(series, lags):
+    """Velocity autocorrelation <u(t) . u(t + lag)> / 3 of a (steps, 3)
+    series, averaged over the time origins."""
+    u = np.asarray(series)
+    return np.array([np.mean(np.sum(u[: len(u) - L] * u[L:], axis=1)) / 3.0 for L in lags])
+
+
+def single_blob_leg(I, torch, stream, steps, tune=True):
+    """The fluctuating single-blob workload: 128^3, FP32 grid, 4-point kernel,
+    kT = 1e-3, dt = 0.25, one blob with m_e / m_f in {0, 1, -1/2} (one replica
+    each, in one context), fluid from the discrete equilibrium. After 200
+    relaxation steps, `steps` steps with the blob velocity recorded every step:
+    equipartition <u_a^2> m~ / kT (Sec. II.F; a dt-dependent bias is expected
+    for m_e != 0) and the normalised velocity autocorrelation."""
+    import icm_inputs
+    wl = icm_inputs.WORKLOADS["single_blob_128"]
+    n = tuple(wl["n"])
+    ratios = wl["me_over_mf"]
+    m_f = wl["rho"] * wl["h"] ** 3 / 0.375 ** 3
+    params = [I.make_params(n, h=wl["h"], rho=wl["rho"], eta=wl["eta"], kT=wl["kT"], dt=wl["dt"],
+                            kernel=wl["kernel"], seed=wl["seed"], replica_id=r) for r in range(len(ratios))]
+    nbytes = I.icm_workspace_bytes(params, [1] * len(params), I.FP32_GRID)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    sim = I.Sim(params, [1] * len(params), I.FP32_GRID, stream=stream.cuda_stream, workspace=ws)
+    q = icm_inputs.uniform_positions(1, n, wl["h"], seed=wl["seed"] + 1)
+    for r, ratio in enumerate(ratios):
+        sim.set_blobs(r, q, m_e=np.array([ratio * m_f]))
+        sim.set_state(r, flags=I.STATE_EQUILIBRIUM)
+    if tune:
+        sim.autotune()
+    sim.step(200, I.STEP_GRAPH)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    series = {r: np.empty((steps, 3)) for r in range(len(ratios))}
+    for t in range(steps):
+        sim.step(1, I.STEP_GRAPH)
+        for r in range(len(ratios)):
+            series[r][t] = sim.get_state(r, want_v=False, want_diag=False)["u"][0]
+    wall = time.perf_counter() - t0
+    sim.close()
+    lags = [0, 1, 2, 5, 10, 20, 50, 100]
+    out = {"grid": list(n), "steps": steps, "wall_s_with_recording": wall, "lags_steps": lags, "classes": {}}
+    kT = wl["kT"]
+    for r, ratio in enumerate(ratios):
+        mt = ratio * m_f + 1.5 * m_f
+        c = vacf(series[r], lags)
+        out["classes"]["m_e/m_f=%g" % ratio] = {"equipartition_u2_mt_over_kT": float(c[0] * mt / kT),
+                                                 "vacf_normalised": [float(x / c[0]) for x in c]}
+    log("single_blob_128: equipartition %s" % {k: round(v["equipartition_u2_mt_over_kT"], 3)
+                                                for k, v in out["classes"].items()})
+    return out
+
+
+def ensemble_vacf_leg(I, torch, stream, steps, per_shape=4, tune=True):
+    """Velocity autocorrelation of the batched ensemble (FP32 grid, one
+    context) against the same replicas on the single-replica FP64 path (same
+    Philox keys and equilibrium initial fields, so nearly the same
+    trajectories): per_shape replicas of each grid shape on both paths."""
+    import icm_inputs
+    wl = icm_inputs.WORKLOADS["batched_ensemble"]
+    grids = wl["grids"]
+    nrep = len(grids)
+    ratios = icm_inputs.excess_mass_ratios(nrep, wl["me_over_mf"], seed=wl["seed"])
+    m_f = wl["rho"] * wl["h"] ** 3 / 0.375 ** 3
+    params = [I.make_params(n, h=wl["h"], rho=wl["rho"], eta=wl["eta"], kT=wl["kT"], dt=wl["dt"],
+                            kernel=wl["kernel"], seed=wl["seed"], replica_id=r) for r, n in enumerate(grids)]
+    qs = [icm_inputs.uniform_positions(1, n, wl["h"], seed=wl["seed"] + 1 + r) for r, n in enumerate(grids)]
+    picked = []
+    for shape in sorted(set(grids)):
+        picked += [r for r, n in enumerate(grids) if n == shape][:per_shape]
+
+    def make(ps, prec):
+        nbytes = I.icm_workspace_bytes(ps, [1] * len(ps), prec)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        return I.Sim(ps, [1] * len(ps), prec, stream=stream.cuda_stream, workspace=ws)
+
+    batched = make(params, I.FP32_GRID)
+    for r in range(nrep):
+        batched.set_blobs(r, qs[r], m_e=np.array([ratios[r] * m_f]))
+        batched.set_state(r, flags=I.STATE_EQUILIBRIUM)
+    singles = {}
+    for r in picked:
+        sm = make([params[r]], I.FP64)
+        sm.set_blobs(0, qs[r], m_e=np.array([ratios[r] * m_f]))
+        sm.set_state(0, flags=I.STATE_EQUILIBRIUM)
+        singles[r] = sm
+    if tune:
+        batched.autotune()
+        for sm in singles.values():
+            sm.autotune()
+    ub = {r: np.empty((steps, 3)) for r in range(nrep)}
+    us = {r: np.empty((steps, 3)) for r in picked}
+    for t in range(steps):
+        batched.step(1, I.STEP_GRAPH)
+        for r in range(nrep):
+            ub[r][t] = batched.get_state(r, want_v=False, want_diag=False)["u"][0]
+        for r, sm in singles.items():
+            sm.step(1, I.STEP_GRAPH)
+            us[r][t] = sm.get_state(0, want_v=False, want_diag=False)["u"][0]
+    batched.close()
+    for sm in singles.values():
+        sm.close()
+    lags = [0, 1, 2, 5, 10, 20, 50]
+    kT = wl["kT"]
+    out = {"steps": steps, "replicas_batched": nrep, "replicas_fp64_single": len(picked), "lags_steps": lags,
+           "classes": {}}
+    worst = 0.0
+    for shape in sorted(set(grids)):
+        for ratio in wl["me_over_mf"]:
+            members = [r for r in range(nrep) if grids[r] == shape and ratios[r] == ratio]
+            if not members:
+                continue
+            mt = ratio * m_f + 1.5 * m_f
+            cb = np.mean([vacf(ub[r], lags) for r in members], axis=0)
+            entry = {"replicas": len(members), "vacf_fp32_batched": [float(x * mt / kT) for x in cb]}
+            both = [r for r in members if r in us]
+            if both:
+                c32 = np.mean([vacf(ub[r], lags) for r in both], axis=0)
+                c64 = np.mean([vacf(us[r], lags) for r in both], axis=0)
+                entry["vacf_fp64_single_same_replicas"] = [float(x * mt / kT) for x in c64]
+                d = float(np.max(np.abs(c32 - c64)) / abs(c64[0]))
+                entry["max_diff_rel_c0"] = d
+                worst = max(worst, d)
+            out["classes"]["%d^3, m_e/m_f=%g" % (shape[0], ratio)] = entry
+    out["max_diff_rel_c0"] = worst
+    log("ensemble VACF: FP32 batched vs FP64 single, largest difference %.2e of C(0)" % worst)
+    return out
+
+
 def cpu_baseline(wl, seed_positions):
     """The FP64 oracle, untuned, on one full step of the same workload."""
     from oracle import icm as O
@@ -301,6 +430,10 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=200)
     ap.add_argument("--no-scale", action="store_true")
+    ap.add_argument("--no-statistics", action="store_true",
+                    help="skip the single-blob and ensemble velocity-autocorrelation legs")
+    ap.add_argument("--single-blob-steps", type=int, default=10000)
+    ap.add_argument("--vacf-steps", type=int, default=1000)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default FFT launch shapes")
     ap.add_argument("--eager", action="store_true", help="launch the step's kernels one by one instead of replaying "
                                                          "the recorded step graph")
@@ -408,6 +541,11 @@ def main():
     if not args.no_scale:
         log("scale run: 512^3, 10^5 blobs, FP32 grid against FP64")
         out["scale_512"] = scale_leg(I, torch, stream, args.scale_steps, not args.no_autotune)
+    if not args.no_statistics:
+        log("single blob at 128^3: %d recorded steps per excess mass" % args.single_blob_steps)
+        out["single_blob_128"] = single_blob_leg(I, torch, stream, args.single_blob_steps, not args.no_autotune)
+        log("ensemble velocity autocorrelation: %d steps" % args.vacf_steps)
+        out["ensemble_vacf"] = ensemble_vacf_leg(I, torch, stream, args.vacf_steps, tune=not args.no_autotune)
     if not args.no_cpu_baseline:
         log("CPU oracle: one step of the same workload")
         out["cpu_baseline"] = cpu_baseline(wl, q)
