@@ -12,44 +12,6 @@ namespace {
 constexpr int kThreads = 256;
 
 
-// F = f_const - k (q - c): the one-body forces at q^{n+1/2}, the positions
-// folded into the box, q - L floor(q / L), and (with pair forces) the blob's
-// insertion into its cell's list. A cell head holds (stamp << 24 | blob) with
-// the step's stamp, so heads left from earlier steps read as empty and the
-// head array never needs clearing. Replica blockIdx.y.
-__device__ __forceinline__ unsigned long long cell_stamp(unsigned long long step) {
-    return (step + 1) & ((1ULL << (64 - kHeadBlobBits)) - 1);
-}
-
-template <typename T>
-__global__ void k_forces_init(const RepDesc<T>* __restrict__ rd) {
-    const BlobParams bp = rd[blockIdx.y].bp;
-    const BlobBufs b = rd[blockIdx.y].bb;
-    const CellGrid cg = rd[blockIdx.y].cg;
-    const bool cells = rd[blockIdx.y].pair_mode == 1;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= bp.nb) return;
-    int ci[3];
-    for (int a = 0; a < 3; ++a) {
-        const int t = 3 * i + a;
-        double f = b.fconst[t];
-        if (bp.spring_k != 0.0) f -= bp.spring_k * (b.qh[t] - bp.spring_c[a]);
-        b.F[t] = f;
-        const double L = bp.box[a];
-        const double w = b.qh[t] - L * floor(b.qh[t] / L);
-        b.qw[t] = w;
-        int c = (int)(w * cg.inv_size[a]);
-        ci[a] = c >= cg.n[a] ? cg.n[a] - 1 : (c < 0 ? 0 : c);
-    }
-    if (cells) {
-        const unsigned long long stamp = cell_stamp(*rd[blockIdx.y].step);
-        const long long cell = ((long long)ci[2] * cg.n[1] + ci[1]) * cg.n[0] + ci[0];
-        const unsigned long long mine = (stamp << kHeadBlobBits) | (unsigned long long)i;
-        const unsigned long long old = atomicExch(&cg.heads[cell], mine);
-        cg.next[i] = ((old >> kHeadBlobBits) == stamp) ? (int)(old & ((1u << kHeadBlobBits) - 1)) : -1;
-    }
-}
-
 // F += WCA pair forces (Eq. (WCA), minimum image, unordered pairs counted
 // once) at q^{n+1/2}: each blob walks the lists of the 27 cells around its
 // own (cells are at least one cutoff wide, at least 3 per axis). Replica
@@ -61,60 +23,79 @@ __global__ void __launch_bounds__(kThreads) k_pairs_cells(const RepDesc<T>* __re
     const BlobBufs b = rd[blockIdx.y].bb;
     const CellGrid cg = rd[blockIdx.y].cg;
     const unsigned long long stamp = cell_stamp(*rd[blockIdx.y].step);
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= bp.nb) return;
-    const double qx = b.qw[3 * i], qy = b.qw[3 * i + 1], qz = b.qw[3 * i + 2];
-    const double s2 = bp.wca_sigma * bp.wca_sigma;
-    const double rc2 = 1.2599210498948732 * s2;  // (2^(1/6) sigma)^2
-    const double Lx = bp.box[0], Ly = bp.box[1], Lz = bp.box[2];
-    const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
-    int c[3];
-    const double q3[3] = {qx, qy, qz};
-    for (int a = 0; a < 3; ++a) {
-        const int cc = (int)(q3[a] * cg.inv_size[a]);
-        c[a] = cc >= cg.n[a] ? cg.n[a] - 1 : (cc < 0 ? 0 : cc);
-    }
+    // four lanes per blob, each walking every fourth of the 27 cells
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = t >> 2, sub = t & 3;
+    const bool active = i < bp.nb;
     double fx = 0, fy = 0, fz = 0;
-    // the 27 head loads are independent: issue them all before walking
-    const gptr<const unsigned long long> heads = as_global((const unsigned long long*)cg.heads);
-    // neighbour cell coordinates per axis, wrapped (c in [0, n), n >= 3)
-    int nc[3][3];
+    if (active) {
+        const double qx = b.qw[3 * i], qy = b.qw[3 * i + 1], qz = b.qw[3 * i + 2];
+        const double s2 = bp.wca_sigma * bp.wca_sigma;
+        const double rc2 = 1.2599210498948732 * s2;  // (2^(1/6) sigma)^2
+        const double Lx = bp.box[0], Ly = bp.box[1], Lz = bp.box[2];
+        const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
+        const double q3[3] = {qx, qy, qz};
+        // neighbour cell coordinates per axis, wrapped (n >= 3)
+        int lo[3], mid[3], hi[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        nc[a][0] = c[a] == 0 ? cg.n[a] - 1 : c[a] - 1;
-        nc[a][1] = c[a];
-        nc[a][2] = c[a] + 1 == cg.n[a] ? 0 : c[a] + 1;
-    }
-    unsigned long long hv[27];
+        for (int a = 0; a < 3; ++a) {
+            const int cc = (int)(q3[a] * cg.inv_size[a]);
+            mid[a] = cc >= cg.n[a] ? cg.n[a] - 1 : (cc < 0 ? 0 : cc);
+            lo[a] = mid[a] == 0 ? cg.n[a] - 1 : mid[a] - 1;
+            hi[a] = mid[a] + 1 == cg.n[a] ? 0 : mid[a] + 1;
+        }
+        auto pick = [](const int* l, const int* m, const int* h, int a, int d) {
+            return d == 0 ? l[a] : (d == 1 ? m[a] : h[a]);
+        };
+        // this lane's (up to 7) head loads are independent: issue them first
+        const gptr<const unsigned long long> heads = as_global((const unsigned long long*)cg.heads);
+        unsigned long long hv[7];
 #pragma unroll
-    for (int n = 0; n < 27; ++n)
-        hv[n] = heads[((long long)nc[2][n / 9] * cg.n[1] + nc[1][(n / 3) % 3]) * cg.n[0] + nc[0][n % 3]];
-#pragma unroll
-    for (int n = 0; n < 27; ++n) {
-        const unsigned long long h = hv[n];
-        int j = ((h >> kHeadBlobBits) == stamp) ? (int)(h & ((1u << kHeadBlobBits) - 1)) : -1;
-        while (j >= 0) {
-            if (j != i) {
-                double ex = qx - b.qw[3 * j], ey = qy - b.qw[3 * j + 1], ez = qz - b.qw[3 * j + 2];
-                ex = ex > hx ? ex - Lx : (ex < -hx ? ex + Lx : ex);
-                ey = ey > hy ? ey - Ly : (ey < -hy ? ey + Ly : ey);
-                ez = ez > hz ? ez - Lz : (ez < -hz ? ez + Lz : ez);
-                const double r2 = ex * ex + ey * ey + ez * ez;
-                if (r2 < rc2 && r2 > 0.0) {
-                    const double sr2 = s2 / r2;
-                    const double sr6 = sr2 * sr2 * sr2;
-                    const double f = 24.0 * bp.wca_eps * (2.0 * sr6 * sr6 - sr6) / r2;
-                    fx += f * ex;
-                    fy += f * ey;
-                    fz += f * ez;
-                }
+        for (int m = 0; m < 7; ++m) {
+            const int n = sub + 4 * m;
+            hv[m] = 0;
+            if (n < 27) {
+                const int z = pick(lo, mid, hi, 2, n / 9), y = pick(lo, mid, hi, 1, (n / 3) % 3);
+                const int x = pick(lo, mid, hi, 0, n % 3);
+                hv[m] = heads[((long long)z * cg.n[1] + y) * cg.n[0] + x];
             }
-            j = cg.next[j];
+        }
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+            if (sub + 4 * m >= 27) break;
+            const unsigned long long h = hv[m];
+            int j = ((h >> kHeadBlobBits) == stamp) ? (int)(h & ((1u << kHeadBlobBits) - 1)) : -1;
+            while (j >= 0) {
+                if (j != i) {
+                    double ex = qx - b.qw[3 * j], ey = qy - b.qw[3 * j + 1], ez = qz - b.qw[3 * j + 2];
+                    ex = ex > hx ? ex - Lx : (ex < -hx ? ex + Lx : ex);
+                    ey = ey > hy ? ey - Ly : (ey < -hy ? ey + Ly : ey);
+                    ez = ez > hz ? ez - Lz : (ez < -hz ? ez + Lz : ez);
+                    const double r2 = ex * ex + ey * ey + ez * ez;
+                    if (r2 < rc2 && r2 > 0.0) {
+                        const double sr2 = s2 / r2;
+                        const double sr6 = sr2 * sr2 * sr2;
+                        const double f = 24.0 * bp.wca_eps * (2.0 * sr6 * sr6 - sr6) / r2;
+                        fx += f * ex;
+                        fy += f * ey;
+                        fz += f * ez;
+                    }
+                }
+                j = cg.next[j];
+            }
         }
     }
-    b.F[3 * i] += fx;
-    b.F[3 * i + 1] += fy;
-    b.F[3 * i + 2] += fz;
+#pragma unroll
+    for (int off = 1; off < 4; off <<= 1) {
+        fx += __shfl_xor(fx, off, 4);
+        fy += __shfl_xor(fy, off, 4);
+        fz += __shfl_xor(fz, off, 4);
+    }
+    if (active && sub == 0) {
+        b.F[3 * i] += fx;
+        b.F[3 * i + 1] += fy;
+        b.F[3 * i + 2] += fz;
+    }
 }
 
 // All-pairs WCA forces, for boxes too small for a 3-cell list: block (bx, by)
@@ -234,9 +215,11 @@ dim3 grid3(const int nb, int nrep) { return dim3((unsigned)((3 * nb + kThreads -
 template <typename T>
 void launch_forces(const Batch<T>& B, hipStream_t s) {
     if (B.max_nb <= 0) return;
-    const dim3 g1((unsigned)((B.max_nb + kThreads - 1) / kThreads), B.nrep);
-    hipLaunchKernelGGL(k_forces_init<T>, g1, dim3(kThreads), 0, s, B.d);
-    if (B.any_cells) hipLaunchKernelGGL(k_pairs_cells<T>, g1, dim3(kThreads), 0, s, B.d);
+    // the one-body forces and the cell lists are set by the gathers before
+    if (B.any_cells) {
+        const dim3 g4((unsigned)((4LL * B.max_nb + kThreads - 1) / kThreads), B.nrep);
+        hipLaunchKernelGGL(k_pairs_cells<T>, g4, dim3(kThreads), 0, s, B.d);
+    }
     if (B.any_all_pairs) {
         const unsigned ti = (unsigned)((B.max_nb + kThreads - 1) / kThreads);
         const unsigned tj = (unsigned)((B.max_nb + kPairTile - 1) / kPairTile);

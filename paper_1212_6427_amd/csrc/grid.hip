@@ -548,7 +548,8 @@ __device__ __forceinline__ double gather_group(const GridDesc<T>& g, const T* __
     return acc;
 }
 
-// Step 1 fused: Jn = J(q^n) v^n and q^{n+1/2} = q^n + dt/2 Jn.
+// Step 1 fused: Jn = J(q^n) v^n, q^{n+1/2} = q^n + dt/2 Jn, the one-body
+// forces at q^{n+1/2} and the folded positions.
 template <typename T, int P>
 __global__ void __launch_bounds__(kThreads) k_gather_predict(const RepDesc<T>* __restrict__ rd) {
     const GridDesc<T> g = rd[blockIdx.y].g;
@@ -560,10 +561,17 @@ __global__ void __launch_bounds__(kThreads) k_gather_predict(const RepDesc<T>* _
     const bool active = b < bp.nb;
     const double J = gather_group<T, P>(g, g.v, active ? bb.q + 3 * b : bb.q, a, r, active);
     if (active && r == 0) {
-        bb.Jn[3 * b + a] = J;
-        const double qh = bb.q[3 * b + a] + 0.5 * bp.dt * J;
+        const int i = 3 * b + a;
+        bb.Jn[i] = J;
+        const double qh = bb.q[i] + 0.5 * bp.dt * J;
         if (!isfinite(qh)) atomicOr(bb.flag, 1u);
-        bb.qh[3 * b + a] = qh;
+        bb.qh[i] = qh;
+        // one-body forces at q^{n+1/2} (constant and tether spring) and the
+        // position folded into the box, for the pair forces
+        double f = bb.fconst[i];
+        if (bp.spring_k != 0.0) f -= bp.spring_k * (qh - bp.spring_c[a]);
+        bb.F[i] = f;
+        bb.qw[i] = qh - bp.box[a] * floor(qh / bp.box[a]);
     }
 }
 
@@ -582,6 +590,23 @@ __global__ void __launch_bounds__(kThreads) k_gather_bins(const RepDesc<T>* __re
     const double J = gather_group<T, P>(g, g.v, active ? bb.qh + 3 * b : bb.qh, a, r, active);
     if (!active) return;
     if (r == 0) bb.Jhvn[3 * b + a] = J;
+    // the blob's insertion into its cell's list for the pair forces: a head
+    // holds (stamp << kHeadBlobBits | blob) with the step's stamp, so heads
+    // left by earlier steps read as empty and are never cleared
+    if (r == 4 && a == 0 && rd[blockIdx.y].pair_mode == 1) {
+        const CellGrid cg = rd[blockIdx.y].cg;
+        int ci[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const int cc = (int)(bb.qw[3 * b + ax] * cg.inv_size[ax]);
+            ci[ax] = cc >= cg.n[ax] ? cg.n[ax] - 1 : (cc < 0 ? 0 : cc);
+        }
+        const unsigned long long stamp = cell_stamp(*rd[blockIdx.y].step);
+        const long long cell = ((long long)ci[2] * cg.n[1] + ci[1]) * cg.n[0] + ci[0];
+        const unsigned long long mine = (stamp << kHeadBlobBits) | (unsigned long long)b;
+        const unsigned long long old = atomicExch(&cg.heads[cell], mine);
+        cg.next[b] = ((old >> kHeadBlobBits) == stamp) ? (int)(old & ((1u << kHeadBlobBits) - 1)) : -1;
+    }
     const double inv_h = 1.0 / g.h;
     const int n[3] = {g.nx, g.ny, g.nz};
     double* o = bb.stc + ((long long)b * 3 + a) * kStcPerComp;

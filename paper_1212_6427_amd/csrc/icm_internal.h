@@ -120,6 +120,9 @@ struct BlobBufs {
 // earlier steps read as empty. With heads == NULL the forces use the
 // all-pairs kernel.
 constexpr int kHeadBlobBits = 24;
+__host__ __device__ __forceinline__ unsigned long long cell_stamp(unsigned long long step) {
+    return (step + 1) & ((1ULL << (64 - kHeadBlobBits)) - 1);
+}
 struct CellGrid {
     int n[3];
     double inv_size[3];
