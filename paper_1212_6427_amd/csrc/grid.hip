@@ -568,10 +568,14 @@ __global__ void __launch_bounds__(kThreads) k_gather_predict(const RepDesc<T>* _
         bb.qh[i] = qh;
         // one-body forces at q^{n+1/2} (constant and tether spring) and the
         // position folded into the box, for the pair forces
+        // (component a's box length and spring centre by select: a runtime
+        // index into the parameter copy would put it in scratch memory)
+        const double L = a == 0 ? bp.box[0] : (a == 1 ? bp.box[1] : bp.box[2]);
+        const double cs = a == 0 ? bp.spring_c[0] : (a == 1 ? bp.spring_c[1] : bp.spring_c[2]);
         double f = bb.fconst[i];
-        if (bp.spring_k != 0.0) f -= bp.spring_k * (qh - bp.spring_c[a]);
+        if (bp.spring_k != 0.0) f -= bp.spring_k * (qh - cs);
         bb.F[i] = f;
-        bb.qw[i] = qh - bp.box[a] * floor(qh / bp.box[a]);
+        bb.qw[i] = qh - L * floor(qh / L);
     }
 }
 
