@@ -30,10 +30,10 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # Algorithmic VALU work of the right-hand-side kernel per cell (issue slots,
 # transcendentals at quarter rate): Philox4x32-10 for the six normals
-# (1.5 calls x 10 rounds x (2 multiplies 32x32->64 + 4 xor) = 90), Box-Muller
-# (3 pairs x 23 = 69), stress divergence (21), viscous and inertial terms
-# (24), spread accumulation (3).
-RHS_ALG_OPS_PER_CELL = 90 + 69 + 21 + 24 + 3
+# (1.5 calls x 10 rounds x (2 multiplies 32x32->64 + 2 three-input xor) = 60),
+# Box-Muller (3 pairs x 23 = 69), stress divergence (21), viscous and
+# inertial terms (24), spread accumulation (3).
+RHS_ALG_OPS_PER_CELL = 60 + 69 + 21 + 24 + 3
 
 
 def log(msg):

@@ -63,7 +63,10 @@ __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
         const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
         const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
-        c = u32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        // each three-input xor is one gfx950 bitop3 (truth table 0x96)
+        const uint32_t x0 = (uint32_t)__builtin_amdgcn_bitop3_b32(hi1, c.y, k0, 0x96);
+        const uint32_t x2 = (uint32_t)__builtin_amdgcn_bitop3_b32(hi0, c.w, k1, 0x96);
+        c = u32x4{x0, lo1, x2, lo0};
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
