@@ -63,6 +63,8 @@ def algorithmic_bytes(phase, n, nb, kernel, w):
         return nb * 3 * 8 * 4
     if phase == "field_ops":
         return 2 * 3 * ncell * w
+    if phase == "advection":
+        return 15 * ncell * w                      # read v, rhs and lag; write rhs and lag
     return 0
 
 
@@ -103,12 +105,12 @@ def measured_traffic(phase):
     return traffic.get(kernel)
 
 
-def setup(I, torch, wl, precision, stream):
+def setup(I, torch, wl, precision, stream, advection=False):
     n = tuple(wl["n"])
     import icm_inputs
     sigma = wl["wca_cutoff"] / 2 ** (1.0 / 6.0)
     p = I.make_params(n, h=wl["h"], rho=wl["rho"], eta=wl["eta"], kT=wl["kT"], dt=wl["dt"], kernel=wl["kernel"],
-                      seed=wl["seed"], wca_eps=wl["wca_eps"], wca_sigma=sigma)
+                      seed=wl["seed"], wca_eps=wl["wca_eps"], wca_sigma=sigma, advection=advection)
     nb = wl["n_blobs"]
     nbytes = I.icm_workspace_bytes([p], [nb], precision)
     ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
@@ -267,6 +269,27 @@ def scale_leg(I, torch, stream, steps, tune=True):
     for name in sims:
         sims[name][0].close()
     log("scale_512 fp32 vs fp64 after %d steps: v %.2e, u %.2e" % (steps, out["max_rel_err_v"], out["max_rel_err_u"]))
+    return out
+
+
+def advection_leg(I, torch, stream, wl, steps, warmup, tune=True):
+    """The benchmark workload with the advective term on (Adams-Bashforth
+    lag): step time and the advection kernel against the HBM roofline."""
+    n = tuple(wl["n"])
+    ncell = int(np.prod(n))
+    sim, _, _ = setup(I, torch, wl, I.FP32_GRID, stream, advection=True)
+    if tune:
+        sim.autotune()
+    sim.step(warmup, I.STEP_GRAPH)
+    sec, _ = time_steps(torch, sim, stream, steps, I.STEP_GRAPH)
+    ph = profile_phases(sim, 10, n, wl["n_blobs"], wl["kernel"], 4)
+    diag = sim.get_state(0, want_v=False)["diag"]
+    sim.close()
+    adv = ph.get("advection", {})
+    out = {"value": ncell * steps / sec, "unit": "cell-steps/s", "ms_per_step": sec * 1000.0 / steps,
+           "steps": steps, "advect_kernel": adv, "max_div_after": diag["max_div"]}
+    if adv.get("achieved_GBs"):
+        out["advect_kernel"] = dict(adv, bound="hbm", peak=HBM_PEAK_GBS, frac=adv["achieved_GBs"] / HBM_PEAK_GBS)
     return out
 
 
@@ -438,6 +461,8 @@ def main():
     ap.add_argument("--eager", action="store_true", help="launch the step's kernels one by one instead of replaying "
                                                          "the recorded step graph")
     ap.add_argument("--scale-steps", type=int, default=200)
+    ap.add_argument("--no-advection", action="store_true", help="skip the leg with the advective term on")
+    ap.add_argument("--advection-steps", type=int, default=100)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device tensor copy first (counter calibration)")
@@ -534,6 +559,12 @@ def main():
         out["fp64"] = {"value": ncell * k64 / sec64, "ms_per_step": sec64 * 1000.0 / k64, "steps": k64,
                        "blob_steps_per_s": nb * k64 / sec64}
         log("FP64: %.3f ms/step" % out["fp64"]["ms_per_step"])
+    if not args.no_advection:
+        log("advection on: %d steps" % args.advection_steps)
+        out["advection"] = advection_leg(I, torch, stream, wl, args.advection_steps, max(2, args.warmup // 4),
+                                         not args.no_autotune)
+        log("advection: %.3f ms/step, advection kernel %s us" % (
+            out["advection"]["ms_per_step"], out["advection"]["advect_kernel"].get("avg_launch_us")))
     if not args.no_ensemble:
         log("batched ensemble: 96 replicas of 32^3 / 48^3 / 64^3")
         out["ensemble"] = ensemble_leg(I, torch, stream, args.ensemble_steps, max(2, args.warmup // 2),

@@ -100,7 +100,16 @@ typedef struct {
                                 kT > 0; 0: omit it                           */
     uint64_t seed;           /* Philox key of the stochastic stress          */
     uint32_t replica_id;     /* Philox counter word distinguishing replicas  */
-    uint32_t reserved;       /* must be 0                                    */
+    uint32_t advection;      /* 1: add the advective term -D.(rho v v^T) to
+                                step 2, lagged by Adams-Bashforth weights
+                                3/2, -1/2 (Eq. (Adams_Bashforth)); fluxes in
+                                the centred conservative form of the
+                                staggered grid, which conserves momentum and,
+                                for divergence-free v, energy (Sec. I.B).
+                                A step with no previous term (the first, and
+                                the first after icm_set_state or a kick)
+                                uses the current term alone. Costs one more
+                                face field of workspace. 0: off (default)  */
     double body_force[3];    /* uniform force density on the fluid           */
     double wca_eps;          /* WCA pair potential of Sec. IV.A (0 = off)    */
     double wca_sigma;        /* WCA diameter; cutoff 2^(1/6) sigma < N h / 2 */
@@ -149,7 +158,7 @@ icm_status icm_set_blobs(icm_ctx* ctx, int32_t replica, int32_t n_blobs,
  * n_blobs x 3 blob arrays for the installed blobs (NULL = keep); step: the
  * step counter n that feeds the Philox counter (negative = keep).
  * Flags: ICM_PTRS_DEVICE, ICM_STATE_PROJECT, ICM_STATE_EQUILIBRIUM.
- * Clears the error state.                                                  */
+ * Clears the error state, and the advective history when v changes.        */
 icm_status icm_set_state(icm_ctx* ctx, int32_t replica, const void* v,
                          const double* q, const double* u,
                          const double* lag_c, int64_t step, uint32_t flags);
@@ -210,7 +219,8 @@ enum {
     ICM_PHASE_FFT_Y_INV = 8, /* inverse transform along y                    */
     ICM_PHASE_FFT_X_INV = 9, /* complex-to-real transform along x            */
     ICM_PHASE_FIELD_OPS = 10, /* field clears and additions                  */
-    ICM_NUM_PHASES = 11
+    ICM_PHASE_ADVECTION = 11, /* advective term of step 2 (advection on)     */
+    ICM_NUM_PHASES = 12
 };
 typedef struct {
     double ms[16];         /* accumulated GPU time per phase (milliseconds) */

@@ -23,6 +23,9 @@ fluid") step by step:
   derivative.
 * App. C, Eqs. (dv_tilde_sol), (dv_eq_modified), (u_np1_modified): the
   momentum-conserving inertial velocity correction.
+* Sec. III.B.2, Eq. (Adams_Bashforth), and Sec. I.B: the optional advective
+  term D.(rho v v^T), time-lagged with the Adams-Bashforth weights 3/2 and
+  -1/2.
 
 Array conventions (shared with the GPU only as a documented convention, not
 as code): a face field is an array of shape (3, Nz, Ny, Nx), C order, so x is
@@ -164,6 +167,7 @@ class Params:
     wca_sigma: float = 0.0
     spring_k: float = 0.0           # 0 disables the tether spring
     spring_center: tuple = (0.0, 0.0, 0.0)
+    advection: bool = False         # include -D.(rho v v^T) in step 2
 
     @property
     def cell_volume(self):
@@ -201,11 +205,13 @@ class State:
     f_const: np.ndarray               # (Nb, 3)
     lag_c: np.ndarray                 # (Nb, 3) lagged J L dv
     step: int = 0
+    adv_prev: np.ndarray = None       # (3, Nz, Ny, Nx) D.(rho v v^T) of the
+                                      # previous step; None: no history yet
 
     def copy(self):
         return State(self.v.copy(), self.q.copy(), self.u.copy(),
                      self.m_e.copy(), self.f_const.copy(), self.lag_c.copy(),
-                     self.step)
+                     self.step, None if self.adv_prev is None else self.adv_prev.copy())
 
 
 def zero_field(p):
@@ -327,6 +333,40 @@ def curl(p, v):
     return np.stack([d(v[2], 1) - d(v[1], 2),
                      d(v[0], 2) - d(v[2], 0),
                      d(v[1], 0) - d(v[0], 1)])
+
+
+def advection(p, v):
+    """Advective momentum flux divergence D.(rho v v^T) at the faces.
+
+    The paper takes the skew-adjoint staggered discretisation of its
+    fluctuating-hydrodynamics reference without printing it (Sec. I.B). The
+    reading used here is the centred conservative (divergence) form of the
+    MAC grid: each momentum component a is a flux balance over the control
+    volume around its face, with fluxes
+      b = a: rho (v_a averaged along a)^2 at the cell centres, and
+      b != a: rho (v_b averaged along a) (v_a averaged along b) on the edges
+              shared by the a- and b-faces,
+    so that component a gains (F_ab[i + 1/2 e_b] - F_ab[i - 1/2 e_b]) / h.
+    It conserves momentum for any v and, for discretely divergence-free v
+    (where it equals the skew-symmetric form), kinetic energy.
+    """
+    A = np.zeros_like(v)
+    for a in range(3):
+        for b in range(3):
+            if a == b:
+                # centre (i + 1/2) along a; the face i sees centres i +- 1/2
+                c = 0.5 * (v[a] + shift(v[a], a, 1))
+                F = p.rho * c * c
+                A[a] += (F - shift(F, a, -1)) / p.h
+            else:
+                # edge at (index - 1/2 e_b) relative to the face of a: v_b
+                # averaged over the two b-faces at i and i - e_a, v_a over
+                # the two a-faces at i and i - e_b
+                vb = 0.5 * (v[b] + shift(v[b], a, -1))
+                va = 0.5 * (v[a] + shift(v[a], b, -1))
+                F = p.rho * vb * va
+                A[a] += (shift(F, b, 1) - F) / p.h
+    return A
 
 
 def stochastic_stress_divergence(p, step):
@@ -476,9 +516,17 @@ def step(p, st):
     q_h = q_n + 0.5 * dt * Jn_vn
     F = forces(p, q_h, st.f_const) if nb else np.zeros((0, 3))
 
-    # Step 2: unperturbed fluid solve, Eq. (provisional_step-1) without the
-    # advective term: (rho/dt - eta/2 L) v~ + G pi~ = rhs.
+    # Step 2: unperturbed fluid solve, Eq. (provisional_step-1):
+    # (rho/dt - eta/2 L) v~ + G pi~ = rhs. The advective term is optional
+    # (off by default); with it, rhs carries -(3/2 A^n - 1/2 A^{n-1}),
+    # Eq. (Adams_Bashforth), and the first step with no history uses A^n
+    # alone (forward Euler).
     rhs = (rho / dt) * v_n + 0.5 * eta * laplacian(p, v_n)
+    adv_new = None
+    if p.advection:
+        adv_new = advection(p, v_n)
+        prev = adv_new if st.adv_prev is None else st.adv_prev
+        rhs -= 1.5 * adv_new - 0.5 * prev
     if p.kT > 0.0:
         rhs += stochastic_stress_divergence(p, st.step)
     rhs += np.asarray(p.body_force, dtype=np.float64).reshape(3, 1, 1, 1)
@@ -527,7 +575,7 @@ def step(p, st):
     else:
         q_new = q_n
     return State(v_new, q_new, u_new, st.m_e.copy(), st.f_const.copy(),
-                 lag_new, st.step + 1)
+                 lag_new, st.step + 1, adv_new)
 
 
 def run(p, st, n_steps):

@@ -40,13 +40,14 @@ struct Replica {
     int slot = 0;            // index of the replica's descriptor in the device array
 };
 
-// Replicas stepped by the same launches: equal grid shape and kernel, and
-// the same inertial path (all m_e = 0 or not). Their descriptors occupy
-// slots [first, first + count) of the device array.
+// Replicas stepped by the same launches: equal grid shape and kernel, the
+// same inertial path (all m_e = 0 or not) and advection setting. Their
+// descriptors occupy slots [first, first + count) of the device array.
 struct BatchInfo {
     int n[3];
     int kernel;
     bool any_me;
+    bool adv;
     int first, count;
     int max_nb;
     bool any_cells, any_all_pairs;
@@ -141,7 +142,7 @@ icm_status validate(int32_t n_rep, const icm_replica_params* p, const int32_t* m
             return fail(nullptr, ICM_E_INVALID, "replica %d: slip must be ICM_SLIP_NONE/VISCOUS/FULL", r);
         if (q.thermal_drift != 0 && q.thermal_drift != 1)
             return fail(nullptr, ICM_E_INVALID, "replica %d: thermal_drift must be 0 or 1", r);
-        if (q.reserved != 0) return fail(nullptr, ICM_E_INVALID, "replica %d: reserved must be 0", r);
+        if (q.advection > 1) return fail(nullptr, ICM_E_INVALID, "replica %d: advection must be 0 or 1", r);
         if (!(q.wca_eps >= 0)) return fail(nullptr, ICM_E_INVALID, "replica %d: wca_eps must be >= 0", r);
         if (q.wca_eps > 0) {
             const double rc = std::pow(2.0, 1.0 / 6.0) * q.wca_sigma;
@@ -192,6 +193,8 @@ void carve_grid(Carver& cv, const icm_replica_params& p, icm::GridDesc<T>& g) {
     g.rhs = cv.take<T>(3 * g.ncell);
     g.aux = cv.take<T>(3 * g.ncell);
     g.spec = cv.take<cplx<T>>(3 * g.nspec);
+    g.adv = p.advection ? cv.take<T>(3 * g.ncell) : nullptr;
+    g.adv_hist = p.advection ? cv.take<unsigned int>(1) : nullptr;
     factor_plan(g.nx, g.px);
     factor_plan(g.ny, g.py);
     factor_plan(g.nz, g.pz);
@@ -415,6 +418,7 @@ icm::RepDesc<T> build_desc(const Replica& R) {
     d.rc.rho_dt = p.rho / p.dt;
     d.rc.half_eta_h2 = 0.5 * p.eta / (p.h * p.h);
     d.rc.noise = p.kT > 0 ? std::sqrt(p.kT * p.eta / (p.h * p.h * p.h * p.dt)) / p.h : 0.0;
+    d.rc.adv = p.advection ? p.rho / p.h : 0.0;
     for (int a = 0; a < 3; ++a) d.rc.body[a] = p.body_force[a];
     d.rc.key = noise_key(R, 0);
     const icm::BlobBufs& b = R.bb;
@@ -461,13 +465,14 @@ icm_status sync_batches_t(icm_ctx* c) {
         BatchInfo* hit = nullptr;
         for (BatchInfo& B : c->batches)
             if (B.n[0] == R.p.n[0] && B.n[1] == R.p.n[1] && B.n[2] == R.p.n[2] && B.kernel == R.p.kernel &&
-                B.any_me == R.any_me)
+                B.any_me == R.any_me && B.adv == (R.p.advection != 0))
                 hit = &B;
         if (!hit) {
             BatchInfo B{};
             for (int a = 0; a < 3; ++a) B.n[a] = R.p.n[a];
             B.kernel = R.p.kernel;
             B.any_me = R.any_me;
+            B.adv = R.p.advection != 0;
             c->batches.push_back(B);
             hit = &c->batches.back();
         }
@@ -555,6 +560,7 @@ void enqueue_step(icm_ctx* c, const BatchInfo& bi, hipStream_t s) {
     // inside the right-hand-side kernel.
     timed(c, ICM_PHASE_RHS, s, [&] { launch_rhs(B, s); });
     timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread_overflow(B, s); });
+    if (bi.adv) timed(c, ICM_PHASE_ADVECTION, s, [&] { launch_advect(B, s); });
     enqueue_fft_solve(c, B, kFieldRhs, kFieldV, false, kSolveH1, s);
     if (bi.any_me) {
         // Step 4: slip correction and excess-momentum change.
@@ -758,6 +764,9 @@ void* field_ptr(icm_ctx* c, Replica& R) {
 void* rhs_ptr(icm_ctx* c, Replica& R) {
     return c->precision == ICM_FP64 ? (void*)R.gd.rhs : (void*)R.gf.rhs;
 }
+unsigned int* adv_hist_of(const icm_ctx* c, const Replica& R) {
+    return c->precision == ICM_FP64 ? R.gd.adv_hist : R.gf.adv_hist;
+}
 
 }  // namespace
 
@@ -830,6 +839,8 @@ icm_status icm_create(int32_t n_rep, const icm_replica_params* p, const int32_t*
             e = hipMemsetAsync(R.bb.chunk_count, 0,
                                sizeof(int) * ((p[r].n[2] + icm::kRhsZChunk - 1) / icm::kRhsZChunk + 1), c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(R.d_step, 0, sizeof(unsigned long long), c->stream);
+        if (e == hipSuccess && adv_hist_of(c, R))
+            e = hipMemsetAsync(adv_hist_of(c, R), 0, sizeof(unsigned int), c->stream);
         if (e != hipSuccess) {
             g_last_error = std::string("hipMemsetAsync failed: ") + hipGetErrorString(e);
             icm_destroy(c);
@@ -920,6 +931,7 @@ icm_status icm_set_blobs(icm_ctx* c, int32_t replica, int32_t n_blobs, const dou
         else
             kick<float>(c, R, s);
         HIP_TRY(c, hipGetLastError());
+        if (adv_hist_of(c, R)) HIP_TRY(c, hipMemsetAsync(adv_hist_of(c, R), 0, sizeof(unsigned int), s));
     }
     HIP_TRY(c, hipStreamSynchronize(s));
     return ICM_OK;
@@ -957,6 +969,9 @@ icm_status icm_set_state(icm_ctx* c, int32_t replica, const void* v, const doubl
             HIP_TRY(c, hipMemcpyAsync(field_ptr(c, R), v, fb, kind, s));
         }
     }
+    // a new field starts the advective history again (first step: Euler)
+    if (((flags & ICM_STATE_EQUILIBRIUM) || v) && adv_hist_of(c, R))
+        HIP_TRY(c, hipMemsetAsync(adv_hist_of(c, R), 0, sizeof(unsigned int), s));
     if (q && n3) HIP_TRY(c, hipMemcpyAsync(R.bb.q, q, n3 * sizeof(double), kind, s));
     if (u && n3) HIP_TRY(c, hipMemcpyAsync(R.bb.u, u, n3 * sizeof(double), kind, s));
     if (lag_c && n3) {

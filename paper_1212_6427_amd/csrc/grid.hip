@@ -484,6 +484,74 @@ __global__ void k_axpy(const RepDesc<T>* __restrict__ rd, int ysel, int xsel) {
         y[i] += x[i];
 }
 
+// Advective term of step 2 (Eq. (provisional_step-1) with the Adams-Bashforth
+// lag of Eq. (Adams_Bashforth)): A = D.(rho v v^T) at the three faces of cell
+// (i, j, k) in the centred conservative form of the staggered grid. Fluxes:
+// rho (v_a averaged along a)^2 at cell centres, and rho (v_b averaged along
+// a)(v_a averaged along b) on the edges shared by a- and b-faces; component
+// a takes the difference of its fluxes across its control volume. Then
+// rhs -= 3/2 A^n - 1/2 A^{n-1} (A^{n-1} := A^n while *adv_hist is 0) and
+// adv = A^n, each element read and rewritten by the thread that owns it.
+// Threads (64 x 4) over (x, y); blockIdx.z = k + nz * replica. The 27
+// neighbour loads per cell hit the caches for all but the cell's own
+// values.
+template <typename T>
+__global__ void __launch_bounds__(256) k_advect(const RepDesc<T>* __restrict__ rd, int nz) {
+    const int rep = (int)blockIdx.z / nz;
+    const int k = (int)blockIdx.z - rep * nz;
+    const GridDesc<T> g = rd[rep].g;
+    const int i = (int)blockIdx.x * 64 + (int)threadIdx.x;
+    const int j = (int)blockIdx.y * 4 + (int)threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const T c = (T)rd[rep].rc.adv;
+    const int nx = g.nx, ny = g.ny;
+    const long long sz = (long long)nx * ny;
+    const long long o = (long long)k * sz + (long long)j * nx + i;
+    // periodic neighbour offsets
+    const long long xm = i == 0 ? nx - 1 : -1, xp = i == nx - 1 ? -(nx - 1) : 1;
+    const long long ym = j == 0 ? (long long)(ny - 1) * nx : -(long long)nx;
+    const long long yp = j == ny - 1 ? -(long long)(ny - 1) * nx : (long long)nx;
+    const long long zm = k == 0 ? (long long)(nz - 1) * sz : -sz;
+    const long long zp = k == nz - 1 ? -(long long)(nz - 1) * sz : sz;
+    const gptr<const T> vx = as_global((const T*)g.v);
+    const gptr<const T> vy = vx + g.ncell;
+    const gptr<const T> vz = vy + g.ncell;
+    const T X0 = vx[o], Xxm = vx[o + xm], Xxp = vx[o + xp], Xym = vx[o + ym], Xyp = vx[o + yp];
+    const T Xzm = vx[o + zm], Xzp = vx[o + zp], Xxpym = vx[o + xp + ym], Xxpzm = vx[o + xp + zm];
+    const T Y0 = vy[o], Yxm = vy[o + xm], Yxp = vy[o + xp], Yym = vy[o + ym], Yyp = vy[o + yp];
+    const T Yzm = vy[o + zm], Yzp = vy[o + zp], Yxmyp = vy[o + xm + yp], Yypzm = vy[o + yp + zm];
+    const T Z0 = vz[o], Zxm = vz[o + xm], Zxp = vz[o + xp], Zym = vz[o + ym], Zyp = vz[o + yp];
+    const T Zzm = vz[o + zm], Zzp = vz[o + zp], Zxmzp = vz[o + xm + zp], Zymzp = vz[o + ym + zp];
+    const T q = (T)0.25;
+    // edge fluxes at this cell's own edges (shared by two components each)
+    const T Fxy = q * (Y0 + Yxm) * (X0 + Xym);
+    const T Fxz = q * (Z0 + Zxm) * (X0 + Xzm);
+    const T Fyz = q * (Z0 + Zym) * (Y0 + Yzm);
+    // x: centres i +- 1/2, edges at j + 1 and k + 1
+    const T cxp = X0 + Xxp, cxm = Xxm + X0;
+    const T Sx = q * (cxp * cxp - cxm * cxm) + q * (Yyp + Yxmyp) * (Xyp + X0) - Fxy +
+                 q * (Zzp + Zxmzp) * (Xzp + X0) - Fxz;
+    // y: centres j +- 1/2, edges at i + 1 and k + 1
+    const T cyp = Y0 + Yyp, cym = Yym + Y0;
+    const T Sy = q * (cyp * cyp - cym * cym) + q * (Xxp + Xxpym) * (Yxp + Y0) - Fxy +
+                 q * (Zzp + Zymzp) * (Yzp + Y0) - Fyz;
+    // z: centres k +- 1/2, edges at i + 1 and j + 1
+    const T czp = Z0 + Zzp, czm = Zzm + Z0;
+    const T Sz = q * (czp * czp - czm * czm) + q * (Xxp + Xxpzm) * (Zxp + Z0) - Fxz +
+                 q * (Yyp + Yypzm) * (Zyp + Z0) - Fyz;
+    const bool hist = *g.adv_hist != 0u;
+    const gptr<T> rhs = as_global(g.rhs);
+    const gptr<T> adv = as_global(g.adv);
+    const T A[3] = {c * Sx, c * Sy, c * Sz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const long long e = o + (long long)a * g.ncell;
+        const T prev = hist ? adv[e] : A[a];
+        rhs[e] -= (T)1.5 * A[a] - (T)0.5 * prev;
+        adv[e] = A[a];
+    }
+}
+
 // Component grid origin along axis beta for component a: 0 if beta == a
 // (faces normal to a), else 1/2 (cell centres).
 __device__ __forceinline__ double comp_offset(int beta, int a) { return beta == a ? 0.0 : 0.5; }
@@ -684,7 +752,10 @@ __global__ void __launch_bounds__(kThreads) k_gather_final(const RepDesc<T>* __r
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (blockIdx.x == 0) {
         for (int i = threadIdx.x; i < n_clear; i += blockDim.x) bb.chunk_count[i] = 0;
-        if (threadIdx.x == 0) *rd[blockIdx.y].step += 1;
+        if (threadIdx.x == 0) {
+            *rd[blockIdx.y].step += 1;
+            if (g.adv_hist) *g.adv_hist = 1u;  // this step's advective term is the next one's lag
+        }
     }
     const int grp = t >> 4, r = t & 15;
     const int b = grp / 3, a = grp - 3 * (grp / 3);
@@ -862,6 +933,17 @@ void launch_axpy(const Batch<T>& B, int y, int x, hipStream_t s) {
 }
 
 template <typename T>
+void launch_advect(const Batch<T>& B, hipStream_t s) {
+    // gridDim.z = planes x replicas stays within 65535: split large batches
+    const int per = std::max(1, 65535 / B.g.nz);
+    for (int r0 = 0; r0 < B.nrep; r0 += per) {
+        const int nr = std::min(per, B.nrep - r0);
+        const dim3 grid((unsigned)((B.g.nx + 63) / 64), (unsigned)((B.g.ny + 3) / 4), (unsigned)(B.g.nz * nr));
+        hipLaunchKernelGGL(k_advect<T>, grid, dim3(64, 4), 0, s, B.d + r0, B.g.nz);
+    }
+}
+
+template <typename T>
 void launch_spread(const Batch<T>& B, int field, int q, int F, int coef, hipStream_t s) {
     if (B.max_nb <= 0) return;
     const dim3 grid(grid_for(48LL * B.max_nb), B.nrep);
@@ -941,7 +1023,8 @@ void launch_field_diag(const GridDesc<T>& g, double rho, double* acc, hipStream_
     template void launch_gather_predict<T>(const Batch<T>&, hipStream_t);                        \
     template void launch_gather_bins<T>(const Batch<T>&, hipStream_t);                           \
     template void launch_bins<T>(const Batch<T>&, hipStream_t);                                  \
-    template void launch_gather_final<T>(const Batch<T>&, hipStream_t);
+    template void launch_gather_final<T>(const Batch<T>&, hipStream_t); \
+    template void launch_advect<T>(const Batch<T>&, hipStream_t);
 ICM_INST(float)
 ICM_INST(double)
 #undef ICM_INST

@@ -49,6 +49,10 @@ struct GridDesc {
     const T* lx;
     const T* ly;
     const T* lz;
+    // advection (NULL when off): the advective term of the previous step,
+    // and a flag that is 1 once it holds one
+    T* adv;
+    unsigned int* adv_hist;
 };
 
 // Spectral multiplier applied between the forward and inverse transforms:
@@ -62,6 +66,7 @@ struct RhsCoef {
     double rho_dt;      // rho / dt
     double half_eta_h2; // (eta / 2) / h^2
     double noise;       // (kT eta / (h^3 dt))^(1/2) / h, 0 = deterministic
+    double adv;         // rho / h: scale of the advective flux differences
     double body[3];
     NoiseKey key;
 };
@@ -224,6 +229,10 @@ void launch_zero(const Batch<T>& B, int field, hipStream_t s);
 // field y += field x
 template <typename T>
 void launch_axpy(const Batch<T>& B, int y, int x, hipStream_t s);
+// rhs -= 3/2 A^n - 1/2 A^{n-1} with A = D.(rho v v^T) of v; A^n kept in adv
+// (replicas of a batch with advection on).
+template <typename T>
+void launch_advect(const Batch<T>& B, hipStream_t s);
 
 // spread: field += h^-3 * prod(phi) * val at positions q, val_a = F[b][a] *
 // (coef ? coef[b] : 1).

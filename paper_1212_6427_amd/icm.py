@@ -47,7 +47,7 @@ class icm_replica_params(ctypes.Structure):
         ("thermal_drift", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("replica_id", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("advection", ctypes.c_uint32),
         ("body_force", ctypes.c_double * 3),
         ("wca_eps", ctypes.c_double),
         ("wca_sigma", ctypes.c_double),
@@ -84,7 +84,7 @@ class icm_tune_result(ctypes.Structure):
 
 
 PHASES = ["gather", "blob", "forces", "rhs", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_solve", "fft_y_inv",
-          "fft_x_inv", "field_ops"]
+          "fft_x_inv", "field_ops", "advection"]
 
 _p = ctypes.c_void_p
 _lib.icm_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(icm_replica_params),
@@ -129,7 +129,7 @@ def _check(status, ctx=None):
 
 def make_params(n, h=1.0, rho=1.0, eta=1.0, kT=0.0, dt=0.1, kernel=3, slip=SLIP_VISCOUS, thermal_drift=True,
                 seed=0, replica_id=0, body_force=(0.0, 0.0, 0.0), wca_eps=0.0, wca_sigma=0.0, spring_k=0.0,
-                spring_center=(0.0, 0.0, 0.0)):
+                spring_center=(0.0, 0.0, 0.0), advection=False):
     p = icm_replica_params()
     p.n[:] = [int(x) for x in n]
     p.kernel = int(kernel)
@@ -138,7 +138,7 @@ def make_params(n, h=1.0, rho=1.0, eta=1.0, kT=0.0, dt=0.1, kernel=3, slip=SLIP_
     p.thermal_drift = 1 if thermal_drift else 0
     p.seed = int(seed)
     p.replica_id = int(replica_id)
-    p.reserved = 0
+    p.advection = 1 if advection else 0
     p.body_force[:] = [float(x) for x in body_force]
     p.wca_eps, p.wca_sigma = float(wca_eps), float(wca_sigma)
     p.spring_k = float(spring_k)

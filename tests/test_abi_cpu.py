@@ -45,7 +45,7 @@ def test_grid_size_validation(n, ok):
 
 
 @pytest.mark.parametrize("field,val", [("kernel", 5), ("h", 0.0), ("rho", -1.0), ("dt", 0.0), ("kT", -1.0),
-                                       ("slip", 3), ("thermal_drift", 2), ("reserved", 1)])
+                                       ("slip", 3), ("thermal_drift", 2), ("advection", 2)])
 def test_parameter_validation(field, val):
     p = I.make_params((16, 16, 16))
     setattr(p, field, val)
@@ -72,3 +72,12 @@ def test_workspace_scales_with_precision_and_replicas():
         I.icm_workspace_bytes([p], [-1], I.FP64)
     with pytest.raises(I.ICMError):
         I.icm_workspace_bytes([p], [1], 7)
+
+
+@pytest.mark.parametrize("prec,w", [("FP64", 8), ("FP32_GRID", 4)])
+def test_advection_adds_one_face_field_of_workspace(prec, w):
+    n = (32, 24, 16)
+    off = I.icm_workspace_bytes([I.make_params(n)], [4], getattr(I, prec))
+    on = I.icm_workspace_bytes([I.make_params(n, advection=True)], [4], getattr(I, prec))
+    field = 3 * 32 * 24 * 16 * w
+    assert field <= on - off <= field + 512

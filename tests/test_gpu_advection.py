@@ -1,0 +1,140 @@
+"""GPU parity of the optional advective term (Eq. (provisional_step-1) with
+the Adams-Bashforth lag of Eq. (Adams_Bashforth); flux form of Sec. I.B)
+against the FP64 oracle, through the C ABI.
+
+Every case also checks that the term is really applied: the GPU result must
+differ from the oracle run without advection by far more than the parity
+tolerance.
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import icm as O
+from tests.parity_cases import (banner, compare, gpu_params, initial_state, load_into_gpu, oracle_params, rel_err)
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+TOL32 = 2e-5
+
+
+@pytest.fixture(scope="module")
+def I():
+    import paper_1212_6427_amd.icm as lib
+    return lib
+
+
+def _with_flow(p, st, amp, seed):
+    """Add a projected random flow whose largest face value is amp."""
+    w = O.project(p, np.random.default_rng(seed).standard_normal(st.v.shape))
+    st.v = st.v + amp * w / np.max(np.abs(w))
+    return st
+
+
+def _run(I, p, st, steps, prec, graph=False):
+    dtype = np.float64 if prec == I.FP64 else np.float32
+    sim = I.Sim([gpu_params(I, p)], [max(st.q.shape[0], 1)], prec)
+    try:
+        load_into_gpu(I, sim, 0, st, dtype)
+        sim.step(steps, I.STEP_GRAPH if graph else 0)
+        return sim.get_state(0)
+    finally:
+        sim.close()
+
+
+def _check(got, p, st, steps, tol):
+    ref = O.run(p, st, steps)
+    errs, bad = compare(got, ref, st.q, tol)
+    print("errors:", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    assert not bad, bad
+    # the advective term is not a no-op at this flow amplitude
+    off = O.run(replace(p, advection=False), st, steps)
+    assert rel_err(got["v"], off.v) > 100 * tol
+    return ref
+
+
+@pytest.mark.parametrize("kernel", [3, 4])
+@pytest.mark.parametrize("n", [(16, 16, 16), (24, 18, 12), (32, 48, 32)])
+def test_advection_deterministic_fp64(I, kernel, n):
+    """kT = 0, a projected random flow of amplitude 0.3, blobs with mixed
+    excess masses; four steps (Euler start, then three AB2 steps)."""
+    p = oracle_params(n, kernel=kernel, kT=0.0, dt=0.2, seed=11, advection=True)
+    st = initial_state(p, 3, (0.0, 1.0, -0.5), seed=21, velocity_field_scale=0.3)
+    banner("advection fp64 n=%s kernel=%d" % (n, kernel))
+    _check(_run(I, p, st, 4, I.FP64), p, st, 4, TOL64)
+
+
+def test_advection_fluctuating_fp64(I):
+    """kT > 0 (equilibrium start plus the stochastic stress), 4-point
+    kernel, WCA pairs, three steps."""
+    p = oracle_params((32, 32, 32), kernel=4, kT=5e-3, dt=0.25, seed=12, advection=True,
+                      wca_eps=1e-2, wca_sigma=2.0 / 2 ** (1 / 6))
+    st = _with_flow(p, initial_state(p, 6, (0.0, 0.0, 1.0), seed=22, min_sep=2.5), 0.3, 5)
+    banner("advection fluctuating fp64")
+    _check(_run(I, p, st, 3, I.FP64), p, st, 3, TOL64)
+
+
+@pytest.mark.parametrize("kernel", [3, 4])
+def test_advection_fp32_grid(I, kernel):
+    """FP32 grid: two steps (the second uses the lagged term)."""
+    p = oracle_params((32, 24, 16), kernel=kernel, kT=1e-3, dt=0.2, seed=13, advection=True)
+    st = _with_flow(p, initial_state(p, 4, (0.0, 1.0), seed=23), 0.3, 6)
+    st.v = st.v.astype(np.float32).astype(np.float64)
+    banner("advection fp32 kernel=%d" % kernel)
+    _check(_run(I, p, st, 2, I.FP32_GRID), p, st, 2, TOL32)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_advection_history_restarts_after_set_state(I, graph):
+    """Installing a field starts the history again: after two steps, a new
+    v (and step counter) from the oracle, then two more steps, matches the
+    oracle started from that state with no lagged term."""
+    p = oracle_params((24, 24, 24), kernel=4, kT=1e-3, dt=0.2, seed=14, advection=True)
+    st = _with_flow(p, initial_state(p, 2, (0.0, 0.5), seed=24), 0.3, 7)
+    banner("advection history restart graph=%s" % graph)
+    sim = I.Sim([gpu_params(I, p)], [2], I.FP64)
+    try:
+        load_into_gpu(I, sim, 0, st, np.float64)
+        sim.step(2, I.STEP_GRAPH if graph else 0)
+        mid = O.run(p, st, 2)
+        mid.v = O.project(p, mid.v + 0.05 * np.random.default_rng(6).standard_normal(mid.v.shape))
+        mid.adv_prev = None
+        load_into_gpu(I, sim, 0, mid, np.float64)
+        sim.step(2, I.STEP_GRAPH if graph else 0)
+        got = sim.get_state(0)
+    finally:
+        sim.close()
+    _check(got, p, mid, 2, TOL64)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_advection_mixed_batch_graph(I, precision):
+    """Replicas of one shape with and without advection (so two batches) in
+    one context, replayed from the recorded step graph: each matches its own
+    oracle run."""
+    prec = I.FP64 if precision == "fp64" else I.FP32_GRID
+    tol = TOL64 if precision == "fp64" else TOL32
+    steps = 3 if precision == "fp64" else 1
+    dtype = np.float64 if prec == I.FP64 else np.float32
+    ps = [oracle_params((32, 32, 32), kernel=4, kT=1e-3, dt=0.25, seed=30 + r, replica=r, advection=(r % 2 == 0))
+          for r in range(4)]
+    states = [_with_flow(p, initial_state(p, 2, (0.0, r * 0.5), seed=40 + r), 0.3, 8 + r) for r, p in enumerate(ps)]
+    if prec == I.FP32_GRID:
+        for st in states:
+            st.v = st.v.astype(np.float32).astype(np.float64)
+    banner("advection mixed batch %s" % precision)
+    sim = I.Sim([gpu_params(I, p) for p in ps], [2] * 4, prec)
+    try:
+        for r, st in enumerate(states):
+            load_into_gpu(I, sim, r, st, dtype)
+        sim.step(steps, I.STEP_GRAPH)
+        for r, (p, st) in enumerate(zip(ps, states)):
+            ref = O.run(p, st, steps)
+            got = sim.get_state(r)
+            errs, bad = compare(got, ref, st.q, tol)
+            print("replica", r, {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+            assert not bad, (r, bad)
+    finally:
+        sim.close()

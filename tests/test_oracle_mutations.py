@@ -105,3 +105,40 @@ def test_thermal_drift_sign(monkeypatch):
     orig = icm.dphi3
     monkeypatch.setattr(icm, "dphi3", lambda r: -orig(r))
     assert _fails(pins.test_kernel_derivative_matches_finite_difference, 3)
+
+
+def test_advection_edge_average_on_the_wrong_side(monkeypatch):
+    def bad(p, v):
+        A = np.zeros_like(v)
+        for a in range(3):
+            for b in range(3):
+                if a == b:
+                    c = 0.5 * (v[a] + icm.shift(v[a], a, 1))
+                    F = p.rho * c * c
+                    A[a] += (F - icm.shift(F, a, -1)) / p.h
+                else:
+                    vb = 0.5 * (v[b] + icm.shift(v[b], a, 1))   # should average towards -e_a
+                    va = 0.5 * (v[a] + icm.shift(v[a], b, -1))
+                    F = p.rho * vb * va
+                    A[a] += (icm.shift(F, b, 1) - F) / p.h
+        return A
+    monkeypatch.setattr(icm, "advection", bad)
+    assert _fails(pins.test_advection_conserves_momentum_and_energy)
+    assert _fails(pins.test_advection_converges_to_v_grad_v_for_the_abc_flow)
+
+
+def test_advection_missing_density(monkeypatch):
+    orig = icm.advection
+    monkeypatch.setattr(icm, "advection", lambda p, v: orig(p, v) / p.rho)
+    assert _fails(pins.test_advection_of_a_shear_mode_by_a_uniform_flow, 0, 1)
+
+
+def test_advection_without_the_lagged_term(monkeypatch):
+    orig = icm.step
+
+    def euler(p, st):
+        st = st.copy()
+        st.adv_prev = None
+        return orig(p, st)
+    monkeypatch.setattr(icm, "step", euler)
+    assert _fails(pins.test_advection_adams_bashforth_is_second_order)

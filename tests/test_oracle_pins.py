@@ -508,3 +508,124 @@ def test_kick_initial_condition_gives_target_velocity():
     v0 = icm.kick_field(p, q, u0, np.zeros(1))
     assert np.max(np.abs(icm.interp(p, v0, q) - u0)) < 0.03 * 0.1
     assert icm.max_divergence(p, v0) < 1e-12
+
+
+# ---------------------------------------------------------------- advection
+def _face_coords(p, a):
+    """(x, y, z) of the a-faces, each of shape (Nz, Ny, Nx)."""
+    nx, ny, nz = p.n
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    off = [0.5, 0.5, 0.5]
+    off[a] = 0.0
+    return (i + off[0]) * p.h, (j + off[1]) * p.h, (k + off[2]) * p.h
+
+
+def _smooth_divergence_free(p, amp, seed):
+    """A few random low Fourier modes per component, projected, scaled so
+    that max |v| = amp."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = p.n
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    v = np.zeros((3, nz, ny, nx))
+    for a in range(3):
+        for _ in range(4):
+            m = rng.integers(-2, 3, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            v[a] += rng.standard_normal() * np.cos(2 * np.pi * (m[0] * i / nx + m[1] * j / ny + m[2] * k / nz) + ph)
+    v = icm.project(p, v)
+    return amp * v / np.max(np.abs(v))
+
+
+def test_advection_conserves_momentum_and_energy():
+    """Sec. I.B: the advective term is discretised so that it conserves
+    momentum and energy and leaves the equilibrium distribution unchanged.
+    The flux form telescopes (sum over faces of D.(rho v v^T) is zero for any
+    v); for a discretely divergence-free v it is skew, sum v.A(v) = 0."""
+    p = P(n=(12, 10, 8), h=0.7, rho=1.3)
+    rng = np.random.default_rng(31)
+    v = rng.standard_normal((3, 8, 10, 12))
+    A = icm.advection(p, v)
+    assert np.max(np.abs(A.sum(axis=(1, 2, 3)))) < 1e-14 * np.abs(A).sum()
+    w = icm.project(p, v)
+    Aw = icm.advection(p, w)
+    assert abs(np.sum(w * Aw)) < 1e-14 * np.sum(np.abs(w * Aw))
+    # not vacuous: a field with divergence does exchange energy
+    assert abs(np.sum(v * A)) > 1e-3 * np.sum(np.abs(v * A))
+
+
+@pytest.mark.parametrize("a,b", [(0, 1), (0, 2), (1, 0), (1, 2), (2, 0), (2, 1)])
+def test_advection_of_a_shear_mode_by_a_uniform_flow(a, b):
+    """A uniform flow U along b carrying the divergence-free mode
+    v_a = B sin(theta (i_b + 1/2)), theta = 2 pi m / N_b: the centred
+    fluxes give exactly A_a = rho U B sin(theta) cos(theta (i_b + 1/2)) / h
+    (rho U dv_a/db with the centred two-cell difference) and zero in the
+    other components."""
+    p = P(n=(12, 10, 8), h=0.8, rho=1.3)
+    U, B, m = 0.37, 0.21, 2
+    nb = p.n[b]
+    th = 2 * np.pi * m / nb
+    shape = [1, 1, 1]
+    shape[2 - b] = nb
+    x = (np.arange(nb) + 0.5).reshape(shape)
+    v = np.zeros((3, 8, 10, 12))
+    v[b] += U
+    v[a] += B * np.sin(th * x)
+    A = icm.advection(p, v)
+    expect = p.rho * U * B * np.sin(th) * np.cos(th * x) / p.h
+    assert np.max(np.abs(A[a] - expect)) < 1e-14
+    for c in range(3):
+        if c != a:
+            assert np.max(np.abs(A[c])) < 1e-14
+
+
+def test_advection_converges_to_v_grad_v_for_the_abc_flow():
+    """The ABC (Beltrami) flow v = (A sin z + C cos y, B sin x + A cos z,
+    C sin y + B cos x) has each component independent of its own coordinate,
+    so on the faces it is exactly discretely divergence-free, and its
+    advective term is rho (v.grad) v in closed form. The discrete operator
+    must approach it at second order in h."""
+    Aa, B, C = 1.0, 0.7, 0.4
+
+    def err(N):
+        p = P(n=(N, N, N), h=2 * np.pi / N, rho=1.3)
+        v = np.zeros((3, N, N, N))
+        exact = np.zeros_like(v)
+        for a in range(3):
+            x, y, z = _face_coords(p, a)
+            ux = Aa * np.sin(z) + C * np.cos(y)
+            uy = B * np.sin(x) + Aa * np.cos(z)
+            uz = C * np.sin(y) + B * np.cos(x)
+            v[a] = (ux, uy, uz)[a]
+            exact[a] = p.rho * (uy * -C * np.sin(y) + uz * Aa * np.cos(z),
+                                ux * B * np.cos(x) + uz * -Aa * np.sin(z),
+                                ux * -B * np.sin(x) + uy * C * np.cos(y))[a]
+        assert icm.max_divergence(p, v) < 1e-13
+        return np.max(np.abs(icm.advection(p, v) - exact))
+
+    e16, e32 = err(16), err(32)
+    assert e32 < 0.02
+    assert np.log2(e16 / e32) > 1.8
+
+
+def test_advection_adams_bashforth_is_second_order():
+    """Eq. (Adams_Bashforth): with the advective term lagged by the weights
+    3/2 and -1/2 (first step forward Euler) a deterministic flow with a
+    neutrally buoyant blob converges at second order in dt, and the term
+    changes the flow by far more than the time-step error."""
+    def run(dt, adv, T=8.0):
+        p = P(n=(16, 16, 16), eta=0.1, dt=dt, kernel=3, advection=adv)
+        st = icm.new_state(p, [[5.3, 7.1, 9.2]])
+        st.v = _smooth_divergence_free(p, 0.3, 5)
+        for _ in range(int(round(T / dt))):
+            st = icm.step(p, st)
+        return st
+
+    r = {dt: run(dt, True) for dt in (1.0, 0.5, 0.25)}
+    E1 = np.max(np.abs(r[1.0].v - r[0.5].v))
+    E2 = np.max(np.abs(r[0.5].v - r[0.25].v))
+    assert np.log2(E1 / E2) > 1.8
+    Q1 = np.max(np.abs(r[1.0].q - r[0.5].q))
+    Q2 = np.max(np.abs(r[0.5].q - r[0.25].q))
+    assert np.log2(Q1 / Q2) > 1.7
+    off = run(0.25, False)
+    assert np.max(np.abs(off.v - r[0.25].v)) > 50 * E2
