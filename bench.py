@@ -293,6 +293,90 @@ def advection_leg(I, torch, stream, wl, steps, warmup, tune=True):
     return out
 
 
+def spring_trajectories(I, stream_handle, wl, combos, dt, k):
+    """FP64 GPU trajectories of the spring test, the blob released from rest
+    at x0, for each (m_e/m_f, slip) combination: the position after every
+    step, shape (len(combos), T/dt, 3). The combinations run as replicas of
+    one context; if the numeric flag stops it (a blob moving more than h in
+    one step: the step is too large for that blob), each runs in a context
+    of its own and a stopped run is all NaN."""
+    n = tuple(wl["n"])
+    m_f = wl["rho"] * wl["h"] ** 3 / 0.5 ** 3      # 3-point kernel: dV = 8 h^3
+    steps = int(round(wl["T"] / dt))
+
+    def run(sub):
+        params = [I.make_params(n, h=wl["h"], rho=wl["rho"], eta=wl["eta"], kT=0.0, dt=dt, kernel=wl["kernel"],
+                                slip=slip, spring_k=k, replica_id=i) for i, (_, slip) in enumerate(sub)]
+        sim = I.Sim(params, [1] * len(sub), I.FP64, stream=stream_handle)
+        try:
+            for i, (ratio, _) in enumerate(sub):
+                sim.set_blobs(i, np.array([wl["x0"]]), m_e=np.array([ratio * m_f]))
+            out = np.empty((len(sub), steps, 3))
+            for t in range(steps):
+                sim.step(1, I.STEP_GRAPH)
+                for i in range(len(sub)):
+                    out[i, t] = sim.get_state(i, want_v=False, want_diag=False)["q"][0]
+            return out
+        finally:
+            sim.close()
+
+    try:
+        return run(combos)
+    except I.ICMError as e:
+        if e.status != I.E_NUMERIC:
+            raise
+    out = np.full((len(combos), steps, 3), np.nan)
+    for i, c in enumerate(combos):
+        try:
+            out[i] = run([c])[0]
+        except I.ICMError as e:
+            if e.status != I.E_NUMERIC:
+                raise
+    return out
+
+
+def convergence_errors(I, stream_handle, wl, combos, dts, k):
+    """E(dt) of Eq. (E_dt_definition) for each combination: mean distance
+    between the run at dt and the run at dt/2 at the same times."""
+    runs = {dt: spring_trajectories(I, stream_handle, wl, combos, dt, k) for dt in list(dts) + [dts[-1] / 2]}
+    E = np.empty((len(combos), len(dts)))
+    for j, dt in enumerate(dts):
+        a, b = runs[dt], runs[dt / 2][:, 1::2]
+        E[:, j] = np.mean(np.linalg.norm(a - b, axis=2), axis=1)
+    return E
+
+
+def convergence_leg(I, stream):
+    """Deterministic temporal convergence of Sec. III.D on the GPU (FP64):
+    E(dt) and the observed orders log2(E(dt)/E(dt/2)) for several excess
+    masses (slip correction of Eq. (delta_u_nph_visc), k = 0.01), and for
+    m_e = 10 m_f the three slip options at larger spring constants."""
+    import icm_inputs
+    wl = icm_inputs.WORKLOADS["convergence_16"]
+    t0 = time.perf_counter()
+    ratios = wl["me_over_mf"]
+    dts = wl["dts"]
+    E = convergence_errors(I, stream.cuda_stream, wl, [(r, I.SLIP_VISCOUS) for r in ratios], dts, wl["spring_k"])
+    def num(x):
+        return None if not np.isfinite(x) else float(x)
+
+    out = {"dts": list(dts), "spring_k": wl["spring_k"], "slip": "viscous", "by_me_over_mf": {},
+           "note": "null: the run at dt or dt/2 stopped on the numeric flag (unstable at that dt)"}
+    for i, r in enumerate(ratios):
+        out["by_me_over_mf"]["%g" % r] = {"E": [num(x) for x in E[i]],
+                                          "order": [num(np.log2(E[i, j] / E[i, j + 1])) for j in range(len(dts) - 1)]}
+    st = wl["slip_test"]
+    names = {I.SLIP_NONE: "none", I.SLIP_VISCOUS: "viscous", I.SLIP_FULL: "full"}
+    slips = [I.SLIP_NONE, I.SLIP_VISCOUS, I.SLIP_FULL]
+    out["slip_options"] = {}
+    for k, dts_k in zip(st["spring_k"], st["dts"]):
+        Ek = convergence_errors(I, stream.cuda_stream, wl, [(st["me_over_mf"], s) for s in slips], dts_k, k)
+        out["slip_options"]["k=%g" % k] = {"dts": list(dts_k), "me_over_mf": st["me_over_mf"],
+                                           "E": {names[s]: [num(x) for x in Ek[i]] for i, s in enumerate(slips)}}
+    out["wall_s"] = time.perf_counter() - t0
+    return out
+
+
 def vacf(series, lags):
     """Velocity autocorrelation <u(t) . u(t + lag)> / 3 of a (steps, 3)
     series, averaged over the time origins."""
@@ -462,6 +546,7 @@ def main():
                                                          "the recorded step graph")
     ap.add_argument("--scale-steps", type=int, default=200)
     ap.add_argument("--no-advection", action="store_true", help="skip the leg with the advective term on")
+    ap.add_argument("--no-convergence", action="store_true", help="skip the temporal-convergence study")
     ap.add_argument("--advection-steps", type=int, default=100)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -577,6 +662,13 @@ def main():
         out["single_blob_128"] = single_blob_leg(I, torch, stream, args.single_blob_steps, not args.no_autotune)
         log("ensemble velocity autocorrelation: %d steps" % args.vacf_steps)
         out["ensemble_vacf"] = ensemble_vacf_leg(I, torch, stream, args.vacf_steps, tune=not args.no_autotune)
+    if not args.no_convergence:
+        log("temporal convergence study (spring test, FP64)")
+        out["convergence"] = convergence_leg(I, stream)
+        log("convergence: orders %s (%.1f s)" % (
+            {r: ["%.2f" % o if o is not None else "-" for o in v["order"]]
+             for r, v in out["convergence"]["by_me_over_mf"].items()},
+            out["convergence"]["wall_s"]))
     if not args.no_cpu_baseline:
         log("CPU oracle: one step of the same workload")
         out["cpu_baseline"] = cpu_baseline(wl, q)

@@ -32,6 +32,15 @@ WORKLOADS = {
         n=(512, 512, 512), h=1.0, rho=1.0, eta=1.0, kT=1e-3, dt=0.2, kernel=3,
         n_blobs=100000, me_over_mf=(0.0,), min_sep=2.0, wca_eps=1e-2,
         wca_cutoff=2.0, re_p=1.0, steps=200, seed=15),
+    # deterministic temporal-convergence test: a blob released from rest in a
+    # harmonic potential centred at the origin (Sec. III.D); dt halved down
+    # the list, error E(dt) between runs at dt and dt/2 up to time T
+    "convergence_16": dict(
+        n=(16, 16, 16), h=1.0, rho=1.0, eta=1.0, kT=0.0, kernel=3, x0=(10.0, 0.3, 0.2),
+        T=80.0, spring_k=0.01, me_over_mf=(0.0, 1.0, 10.0, -0.5),
+        dts=(4.0, 2.0, 1.0, 0.5, 0.25, 0.125, 0.0625, 0.03125),
+        slip_test=dict(me_over_mf=10.0, spring_k=(1.0, 500.0),
+                       dts=((0.4, 0.2, 0.1, 0.05, 0.025), (0.04, 0.02, 0.01, 0.005)))),
 }
 
 

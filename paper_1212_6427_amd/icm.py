@@ -7,6 +7,12 @@ built (python -m paper_1212_6427_amd.build); there is no fallback.
 Host arrays are numpy arrays; device arrays may be passed as torch tensors
 together with PTRS_DEVICE. PyTorch is used only for device memory (the
 optional workspace) and streams.
+
+In a process that also uses PyTorch-ROCm, import torch before this module:
+torch carries its own copy of the HIP runtime, and libicm.so must bind to
+that copy (loaded first, it satisfies libicm's dependency); loaded the other
+way round the process ends up with two HIP runtimes, and the second one to
+start finds no device.
 """
 import ctypes
 import os
