@@ -377,6 +377,77 @@ def convergence_leg(I, stream):
     return out
 
 
+def cell_histogram_bias(frac):
+    """Density near the cell corners (grid nodes) over density near the cell
+    centre, minus one: positions within a cell, frac in [0, 1)^3; each region
+    is the cube of half the cell's side around its point (1/8 of the cell)."""
+    d_corner = np.minimum(frac, 1.0 - frac)
+    corner = np.all(d_corner < 0.25, axis=-1)
+    centre = np.all(np.abs(frac - 0.5) < 0.25, axis=-1)
+    return float(corner.sum() / max(centre.sum(), 1) - 1.0), int(corner.sum()), int(centre.sum())
+
+
+def node_harmonic(frac):
+    """Amplitude eps of the density 1 + eps sum_a cos(2 pi f_a) over the cell
+    (f: position within the cell): (2/3) times the sample mean of
+    sum_a cos(2 pi f_a). Positive: blobs linger near the grid nodes."""
+    return float(np.mean(np.sum(np.cos(2 * np.pi * frac), axis=-1)) * 2.0 / 3.0)
+
+
+def drift_bias_run(I, stream_handle, wl, kernel, steps, every, replicas):
+    """Ideal gas of neutrally buoyant blobs (no forces) at equilibrium, with
+    and without the thermal drift (even / odd replicas), batched in one
+    context: per replica, the positions within a cell sampled every `every`
+    steps after a relaxation of `steps` // 10 steps."""
+    import icm_inputs
+    n = tuple(wl["n"])
+    nb = wl["n_blobs"]
+    params = [I.make_params(n, h=wl["h"], rho=wl["rho"], eta=wl["eta"], kT=wl["kT"], dt=wl["dt"], kernel=kernel,
+                            thermal_drift=(r % 2 == 0), seed=wl["seed"], replica_id=r) for r in range(replicas)]
+    sim = I.Sim(params, [nb] * replicas, I.FP32_GRID, stream=stream_handle)
+    try:
+        for r in range(replicas):
+            sim.set_blobs(r, icm_inputs.uniform_positions(nb, n, wl["h"], seed=wl["seed"] + 1 + r))
+            sim.set_state(r, flags=I.STATE_EQUILIBRIUM)
+        sim.step(steps // 10, I.STEP_GRAPH)
+        samples = [[] for _ in range(replicas)]
+        for _ in range(steps // every):
+            sim.step(every, I.STEP_GRAPH)
+            for r in range(replicas):
+                q = sim.get_state(r, want_v=False, want_diag=False)["q"] / wl["h"]
+                samples[r].append(q - np.floor(q))
+        return [np.concatenate(x) for x in samples]
+    finally:
+        sim.close()
+
+
+def drift_bias_summary(per_replica):
+    """Pooled corner/centre ratio and the node harmonic with its standard
+    error from the spread over (independent) replicas."""
+    eps = np.array([node_harmonic(f) for f in per_replica])
+    ratio, c, z = cell_histogram_bias(np.concatenate(per_replica))
+    return {"corner_over_centre_minus_1": ratio, "corner_centre_counts": [c, z],
+            "node_harmonic": float(eps.mean()), "node_harmonic_se": float(eps.std(ddof=1) / np.sqrt(len(eps)))}
+
+
+def drift_bias_leg(I, stream_handle, steps=None):
+    """The thermal-drift check of App. B.2: positions of freely diffusing
+    blobs projected on one grid cell must be uniform; without the drift they
+    pile up near the grid nodes."""
+    import icm_inputs
+    wl = icm_inputs.WORKLOADS["drift_bias_16"]
+    steps = steps or wl["steps"]
+    t0 = time.perf_counter()
+    out = {"grid": list(wl["n"]), "n_blobs": wl["n_blobs"], "replicas_per_case": wl["replicas"] // 2,
+           "steps": steps, "sample_every": wl["every"], "kT": wl["kT"], "dt": wl["dt"], "kernels": {}}
+    for kernel in wl["kernels"]:
+        per = drift_bias_run(I, stream_handle, wl, kernel, steps, wl["every"], wl["replicas"])
+        out["kernels"]["%d-point" % kernel] = {"with_drift": drift_bias_summary(per[0::2]),
+                                               "without_drift": drift_bias_summary(per[1::2])}
+    out["wall_s"] = time.perf_counter() - t0
+    return out
+
+
 def vacf(series, lags):
     """Velocity autocorrelation <u(t) . u(t + lag)> / 3 of a (steps, 3)
     series, averaged over the time origins."""
@@ -538,7 +609,7 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=200)
     ap.add_argument("--no-scale", action="store_true")
     ap.add_argument("--no-statistics", action="store_true",
-                    help="skip the single-blob and ensemble velocity-autocorrelation legs")
+                    help="skip the single-blob, thermal-drift and ensemble velocity-autocorrelation legs")
     ap.add_argument("--single-blob-steps", type=int, default=10000)
     ap.add_argument("--vacf-steps", type=int, default=1000)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default FFT launch shapes")
@@ -660,6 +731,11 @@ def main():
     if not args.no_statistics:
         log("single blob at 128^3: %d recorded steps per excess mass" % args.single_blob_steps)
         out["single_blob_128"] = single_blob_leg(I, torch, stream, args.single_blob_steps, not args.no_autotune)
+        log("thermal-drift bias: ideal gas in 16^3 boxes, drift on and off")
+        out["drift_bias_16"] = drift_bias_leg(I, stream.cuda_stream)
+        log("drift bias (node harmonic, with / without drift): %s" % {
+            k: ("%.4f" % v["with_drift"]["node_harmonic"], "%.4f" % v["without_drift"]["node_harmonic"])
+            for k, v in out["drift_bias_16"]["kernels"].items()})
         log("ensemble velocity autocorrelation: %d steps" % args.vacf_steps)
         out["ensemble_vacf"] = ensemble_vacf_leg(I, torch, stream, args.vacf_steps, tune=not args.no_autotune)
     if not args.no_convergence:

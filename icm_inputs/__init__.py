@@ -32,6 +32,11 @@ WORKLOADS = {
         n=(512, 512, 512), h=1.0, rho=1.0, eta=1.0, kT=1e-3, dt=0.2, kernel=3,
         n_blobs=100000, me_over_mf=(0.0,), min_sep=2.0, wca_eps=1e-2,
         wca_cutoff=2.0, re_p=1.0, steps=200, seed=15),
+    # ideal gas of neutrally buoyant blobs at equilibrium, thermal drift on
+    # and off (App. B.2): 100 blobs per 16^3 box, viscous CFL 0.05
+    "drift_bias_16": dict(
+        n=(16, 16, 16), h=1.0, rho=1.0, eta=1.0, kT=1.0, dt=0.05, kernels=(3, 4),
+        n_blobs=100, replicas=64, steps=30000, every=20, seed=16),
     # deterministic temporal-convergence test: a blob released from rest in a
     # harmonic potential centred at the origin (Sec. III.D); dt halved down
     # the list, error E(dt) between runs at dt and dt/2 up to time T
