@@ -448,6 +448,91 @@ def drift_bias_leg(I, stream_handle, steps=None):
     return out
 
 
+def pair_histogram(q, L, rmax, nbins):
+    """Pair counts of one configuration on nbins bins of [0, rmax)
+    (minimum-image distances in a periodic cube of side L)."""
+    from scipy.spatial import cKDTree
+    x = np.mod(q, L)
+    x[x >= L] = 0.0
+    d = cKDTree(x, boxsize=L).sparse_distance_matrix(cKDTree(x, boxsize=L), rmax, output_type="ndarray")
+    r = d["v"][d["i"] < d["j"]]
+    return np.histogram(r, bins=nbins, range=(0.0, rmax))[0].astype(np.float64)
+
+
+def gr_from_counts(counts, samples, n, L, rmax):
+    """g(r): pair counts over the ideal-gas count of each spherical shell."""
+    nbins = counts.shape[-1]
+    edges = np.linspace(0.0, rmax, nbins + 1)
+    shell = 4.0 / 3.0 * np.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
+    return counts / (samples * 0.5 * n * (n - 1) * shell / L ** 3)
+
+
+def rdf_run(I, stream_handle, wl, ratio, replicas, steps, every):
+    """GPU dynamics of the WCA suspension of Table RDF: `replicas`
+    independent boxes batched in one context (FP32 grid), equilibrium fluid,
+    blobs from seeded positions at least min_sep apart; after `relax` steps,
+    g(r) of each replica from configurations every `every` steps."""
+    import icm_inputs
+    n = tuple(wl["n"])
+    nb = wl["n_blobs"]
+    L = n[0] * wl["h"]
+    m_f = wl["rho"] * wl["h"] ** 3 / 0.5 ** 3 if wl["kernel"] == 3 else wl["rho"] * wl["h"] ** 3 / 0.375 ** 3
+    params = [I.make_params(n, h=wl["h"], rho=wl["rho"], eta=wl["eta"], kT=wl["kT"], dt=wl["dt"], kernel=wl["kernel"],
+                            wca_eps=wl["wca_eps"], wca_sigma=wl["wca_sigma"], seed=wl["seed"], replica_id=r)
+              for r in range(replicas)]
+    sim = I.Sim(params, [nb] * replicas, I.FP32_GRID, stream=stream_handle)
+    try:
+        for r in range(replicas):
+            q = icm_inputs.separated_positions(nb, n, wl["h"], min_sep=wl["min_sep"], seed=wl["seed"] + 1 + r)
+            sim.set_blobs(r, q, m_e=np.full(nb, ratio * m_f))
+            sim.set_state(r, flags=I.STATE_EQUILIBRIUM)
+        sim.step(wl["relax"], I.STEP_GRAPH)
+        counts = np.zeros((replicas, wl["nbins"]))
+        samples = steps // every
+        for _ in range(samples):
+            sim.step(every, I.STEP_GRAPH)
+            for r in range(replicas):
+                q = sim.get_state(r, want_v=False, want_diag=False)["q"]
+                counts[r] += pair_histogram(q, L, wl["rmax"], wl["nbins"])
+        return gr_from_counts(counts, samples, nb, L, wl["rmax"])
+    finally:
+        sim.close()
+
+
+def rdf_leg(I, stream_handle, steps=None):
+    """Equilibrium pair structure of the WCA suspension (Sec. IV.A, Table
+    RDF) from the GPU dynamics, for each excess mass, with the replica
+    spread as the statistical error."""
+    import icm_inputs
+    wl = icm_inputs.WORKLOADS["rdf_32"]
+    steps = steps or wl["steps"]
+    t0 = time.perf_counter()
+    r = (np.arange(wl["nbins"]) + 0.5) * wl["rmax"] / wl["nbins"]
+    out = {"grid": list(wl["n"]), "n_blobs": wl["n_blobs"], "dt": wl["dt"], "kT": wl["kT"], "wca_eps": wl["wca_eps"],
+           "wca_sigma": wl["wca_sigma"], "replicas": wl["replicas"], "steps": steps, "sample_every": wl["every"],
+           "r": [float(x) for x in r], "g": {}}
+    for ratio in wl["me_over_mf"]:
+        g = rdf_run(I, stream_handle, wl, ratio, wl["replicas"], steps, wl["every"])
+        out["g"]["m_e/m_f=%g" % ratio] = {"mean": [float(x) for x in g.mean(0)],
+                                          "se": [float(x) for x in g.std(0, ddof=1) / np.sqrt(g.shape[0])]}
+    out["wall_s"] = time.perf_counter() - t0
+    return out
+
+
+def rdf_vs_reference(res):
+    """Largest |g - g_MC| over 1.8 < r < 4.5 and the mean difference over
+    the contact peak (2.1 < r < 2.7) against the stored Monte Carlo g(r)."""
+    ref = json.load(open(os.path.join(ROOT, "tests", "golden", "rdf_wca_mc.json")))
+    r = np.asarray(ref["r"])
+    g_mc = np.asarray(ref["g"])
+    band, peak = (r > 1.8) & (r < 4.5), (r > 2.1) & (r < 2.7)
+    out = {}
+    for name, v in res["g"].items():
+        d = np.asarray(v["mean"]) - g_mc
+        out[name] = {"max_abs_diff": float(np.max(np.abs(d[band]))), "mean_diff_contact_peak": float(np.mean(d[peak]))}
+    return out
+
+
 def vacf(series, lags):
     """Velocity autocorrelation <u(t) . u(t + lag)> / 3 of a (steps, 3)
     series, averaged over the time origins."""
@@ -736,6 +821,10 @@ def main():
         log("drift bias (node harmonic, with / without drift): %s" % {
             k: ("%.4f" % v["with_drift"]["node_harmonic"], "%.4f" % v["without_drift"]["node_harmonic"])
             for k, v in out["drift_bias_16"]["kernels"].items()})
+        log("WCA suspension g(r) at 32^3 (Table RDF), against the Monte Carlo reference")
+        out["rdf_32"] = rdf_leg(I, stream.cuda_stream)
+        out["rdf_32"]["vs_monte_carlo"] = rdf_vs_reference(out["rdf_32"])
+        log("rdf: %s" % out["rdf_32"]["vs_monte_carlo"])
         log("ensemble velocity autocorrelation: %d steps" % args.vacf_steps)
         out["ensemble_vacf"] = ensemble_vacf_leg(I, torch, stream, args.vacf_steps, tune=not args.no_autotune)
     if not args.no_convergence:

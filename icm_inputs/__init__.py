@@ -32,6 +32,12 @@ WORKLOADS = {
         n=(512, 512, 512), h=1.0, rho=1.0, eta=1.0, kT=1e-3, dt=0.2, kernel=3,
         n_blobs=100000, me_over_mf=(0.0,), min_sep=2.0, wca_eps=1e-2,
         wca_cutoff=2.0, re_p=1.0, steps=200, seed=15),
+    # WCA suspension at equilibrium, Sec. IV.A Table RDF (left): 1000 blobs in
+    # 32^3, dt = 1, kT = eps = 1e-3, sigma = 2; excess masses 0 and m_f
+    "rdf_32": dict(
+        n=(32, 32, 32), h=1.0, rho=1.0, eta=1.0, kT=1e-3, dt=1.0, kernel=3, n_blobs=1000,
+        wca_eps=1e-3, wca_sigma=2.0, me_over_mf=(0.0, 1.0), replicas=8, steps=40000, every=100,
+        relax=2000, rmax=5.0, nbins=50, min_sep=2.0, seed=17),
     # ideal gas of neutrally buoyant blobs at equilibrium, thermal drift on
     # and off (App. B.2): 100 blobs per 16^3 box, viscous CFL 0.05
     "drift_bias_16": dict(

@@ -629,3 +629,46 @@ def test_advection_adams_bashforth_is_second_order():
     assert np.log2(Q1 / Q2) > 1.7
     off = run(0.25, False)
     assert np.max(np.abs(off.v - r[0.25].v)) > 50 * E2
+
+
+# ------------------------------------------ Monte Carlo reference (Sec. IV.A)
+def _shell_average(f, edges):
+    """Average of f(r) over each spherical shell (weight r^2)."""
+    out = []
+    for a, b in zip(edges[:-1], edges[1:]):
+        r = np.linspace(a, b, 201)
+        w = r * r
+        out.append(np.sum(f(r) * w) / np.sum(w))
+    return np.array(out)
+
+
+def test_monte_carlo_ideal_gas_is_uniform():
+    """Without interactions every trial move is accepted and the sampled
+    pair structure is flat, g(r) = 1."""
+    from oracle import gibbs
+    x0 = np.random.default_rng(3).random((200, 3)) * 20.0
+    r, g, acc, _ = gibbs.wca_gr(x0, 20.0, 0.0, 1.0, 1.0, 1.0, 100, 4000, 5, 1, 5.0, 25)
+    assert acc == 1.0
+    assert np.max(np.abs(g[r > 1.0] - 1.0)) < 0.04
+
+
+def test_monte_carlo_low_density_limit_is_the_boltzmann_factor():
+    """As the density goes to zero, g(r) -> exp(-V(r)/kT) with V the WCA
+    potential of Eq. (WCA): compared shell by shell (eps = kT = sigma = 1,
+    100 particles in a box of side 30)."""
+    from oracle import gibbs
+    eps, sigma, kT = 1.0, 1.0, 1.0
+    rc = 2 ** (1 / 6) * sigma
+
+    def boltz(r):
+        r = np.maximum(r, 0.1 * sigma)   # exp(-V/kT) underflows to 0 long before
+        V = np.where(r < rc, 4 * eps * ((sigma / r) ** 12 - (sigma / r) ** 6) + eps, 0.0)
+        return np.exp(-V / kT)
+
+    x0 = icm_inputs.separated_positions(100, (30, 30, 30), 1.0, min_sep=1.2, seed=4)
+    r, g, acc, _ = gibbs.wca_gr(x0, 30.0, eps, sigma, kT, 2.0, 1000, 40000, 2, 5, 1.6, 16)
+    edges = np.linspace(0.0, 1.6, 17)
+    ref = _shell_average(boltz, edges)
+    sel = (r > 0.85) & (r < 1.55)
+    assert np.max(np.abs(g[sel] - ref[sel])) < 0.06
+    assert np.all(g[r < 0.8] == 0.0)
