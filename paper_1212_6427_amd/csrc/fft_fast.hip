@@ -291,14 +291,19 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
     const uint32_t zb = (uint32_t)(g.ny * g.Wp) * (uint32_t)sizeof(cplx<T>);  // bytes between z planes
     const uint32_t cb = (uint32_t)g.nspec * (uint32_t)sizeof(cplx<T>);       // bytes between components
     const uint32_t vo = ((uint32_t)t * (uint32_t)(g.ny * g.Wp) + (uint32_t)(y * g.Wp + kx)) * (uint32_t)sizeof(cplx<T>);
+    // Loads are issued component by component, so that the transform of
+    // component 0 can start while those of components 1 and 2 are still in
+    // flight (the load counter retires in order). They are unconditional:
+    // a column past W reads row padding, the next row or (past the buffer's
+    // end) zero, transforms it on its own and is never stored, so no select
+    // has to wait for the loads.
     cplx<T> a0[E], a1[E], a2[E];
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const uint32_t so = (uint32_t)(TL * i) * zb;
-        a0[i] = ok ? sb.load(vo, so) : cplx<T>{0, 0};
-        a1[i] = ok ? sb.load(vo, so + cb) : cplx<T>{0, 0};
-        a2[i] = ok ? sb.load(vo, so + 2 * cb) : cplx<T>{0, 0};
-    }
+    for (int i = 0; i < E; ++i) a0[i] = sb.load(vo, (uint32_t)(TL * i) * zb);
+#pragma unroll
+    for (int i = 0; i < E; ++i) a1[i] = sb.load(vo, (uint32_t)(TL * i) * zb + cb);
+#pragma unroll
+    for (int i = 0; i < E; ++i) a2[i] = sb.load(vo, (uint32_t)(TL * i) * zb + 2 * cb);
     __syncthreads();
     reg_fft<T, N, E, R0, R1, R2, -1>(a0, t, lds, B, b, tws);
     reg_fft<T, N, E, R0, R1, R2, -1>(a1, t, lds, B, b, tws);
@@ -338,17 +343,21 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
             a2[i] = w2;
         }
     }
+    // each component is stored as soon as its inverse transform is done
     reg_fft<T, N, E, R0, R1, R2, 1>(a0, t, lds, B, b, tws);
+    if (ok) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) sb.store(a0[i], vo, (uint32_t)(TL * i) * zb);
+    }
     reg_fft<T, N, E, R0, R1, R2, 1>(a1, t, lds, B, b, tws);
+    if (ok) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) sb.store(a1[i], vo, (uint32_t)(TL * i) * zb + cb);
+    }
     reg_fft<T, N, E, R0, R1, R2, 1>(a2, t, lds, B, b, tws);
     if (ok) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const uint32_t so = (uint32_t)(TL * i) * zb;
-            sb.store(a0[i], vo, so);
-            sb.store(a1[i], vo, so + cb);
-            sb.store(a2[i], vo, so + 2 * cb);
-        }
+        for (int i = 0; i < E; ++i) sb.store(a2[i], vo, (uint32_t)(TL * i) * zb + 2 * cb);
     }
 }
 
