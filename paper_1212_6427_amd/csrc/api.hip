@@ -76,8 +76,11 @@ struct icm_ctx {
     void* d_desc = nullptr;
     std::vector<unsigned char> h_desc;
     std::vector<BatchInfo> batches;
-    // captured step (icm_step with ICM_STEP_GRAPH)
+    // captured step (icm_step with ICM_STEP_GRAPH); batches after the first
+    // are recorded on branch streams, so they are parallel branches of the
+    // graph
     hipStream_t cap_stream = nullptr;
+    std::vector<hipStream_t> branch;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
 };
@@ -611,21 +614,55 @@ void kick(icm_ctx* c, const Replica& R, hipStream_t s) {
 }
 
 // Record one step of every batch into a graph (kernel launches only; the
-// step counters and all per-replica data live in device memory).
+// step counters and all per-replica data live in device memory). Batches
+// touch disjoint memory, so each is its own branch of the graph: the first
+// on the capture stream, the others on branch streams forked from it by an
+// event and joined back at the end.
 icm_status capture_step(icm_ctx* c) {
     drop_graph(c);
     if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    if (c->precision == ICM_FP64)
-        enqueue_all<double>(c, c->cap_stream);
-    else
-        enqueue_all<float>(c, c->cap_stream);
+    const size_t nb = c->batches.size();
+    while (c->branch.size() + 1 < nb) {
+        hipStream_t st = nullptr;
+        HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        c->branch.push_back(st);
+    }
+    std::vector<hipEvent_t> ev(nb, nullptr);  // ev[0]: fork; ev[b]: end of branch b
+    for (hipEvent_t& e : ev) {
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            for (hipEvent_t x : ev)
+                if (x) (void)hipEventDestroy(x);
+            return fail(c, ICM_E_DEVICE, "event creation failed");
+        }
+    }
+    const hipError_t eb = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (eb != hipSuccess) {
+        for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+        c->error_state = true;
+        return fail(c, ICM_E_DEVICE, "step capture failed: %s", hipGetErrorString(eb));
+    }
+    hipError_t err = hipSuccess;
+    if (nb > 1) err = hipEventRecord(ev[0], c->cap_stream);
+    for (size_t b = 1; b < nb && err == hipSuccess; ++b) err = hipStreamWaitEvent(c->branch[b - 1], ev[0], 0);
+    for (size_t b = 0; b < nb && err == hipSuccess; ++b) {
+        const hipStream_t s = b == 0 ? c->cap_stream : c->branch[b - 1];
+        if (c->precision == ICM_FP64)
+            enqueue_step<double>(c, c->batches[b], s);
+        else
+            enqueue_step<float>(c, c->batches[b], s);
+        err = hipGetLastError();
+    }
+    for (size_t b = 1; b < nb && err == hipSuccess; ++b) {
+        err = hipEventRecord(ev[b], c->branch[b - 1]);
+        if (err == hipSuccess) err = hipStreamWaitEvent(c->cap_stream, ev[b], 0);
+    }
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
-    if (e != hipSuccess || !g) {
+    for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+    if (err != hipSuccess || e != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
         c->error_state = true;
-        return fail(c, ICM_E_DEVICE, "step capture failed: %s", hipGetErrorString(e));
+        return fail(c, ICM_E_DEVICE, "step capture failed: %s", hipGetErrorString(err != hipSuccess ? err : e));
     }
     c->graph = g;
     HIP_TRY(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
@@ -1105,6 +1142,7 @@ void icm_destroy(icm_ctx* c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (hipStream_t st : c->branch) (void)hipStreamDestroy(st);
     if (c->owns_ws && c->ws) (void)hipFree(c->ws);
     delete c;
 }
