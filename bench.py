@@ -533,6 +533,63 @@ def rdf_vs_reference(res):
     return out
 
 
+def jps_columns(I, stream_handle, n, kernel, q_list, kicked=0):
+    """(3 dV / 2) J_i P S_k e_b on the GPU for each configuration in q_list
+    (an (n_blobs, 3) array per entry) and b = x, y, z: one replica per
+    (configuration, b) in one FP64 context. Blob `kicked` gets the impulse
+    m~_f e_b (ICM_BLOBS_KICK: v = P S (m~_f e_b) / rho); one inviscid,
+    deterministic step of dt = 1e-12 then leaves v unchanged and reports
+    u_i = J_i v for every blob. Returns an array (len(q_list), n_blobs, 3, 3)
+    with [c, i, :, b] the velocity of blob i for the kick along b."""
+    nq = len(q_list)
+    nb = q_list[0].shape[0]
+    params = [I.make_params(n, eta=0.0, kT=0.0, dt=1e-12, kernel=kernel, replica_id=r) for r in range(3 * nq)]
+    sim = I.Sim(params, [nb] * (3 * nq), I.FP64, stream=stream_handle)
+    try:
+        for c, q in enumerate(q_list):
+            for b in range(3):
+                u0 = np.zeros((nb, 3))
+                u0[kicked, b] = 1.0
+                sim.set_blobs(3 * c + b, q, u=u0, flags=I.BLOBS_KICK)
+        sim.step(1, I.STEP_GRAPH)
+        out = np.empty((nq, nb, 3, 3))
+        for c in range(nq):
+            for b in range(3):
+                out[c, :, :, b] = sim.get_state(3 * c + b, want_v=False, want_diag=False)["u"]
+        return out
+    finally:
+        sim.close()
+
+
+def jps_leg(I, stream_handle):
+    """Translational invariance of J P S (Sec. III.A.2) on the GPU: for
+    random positions in a 32^3 box, the deviation of (3 dV / 2) J P S from
+    the identity (diagonal and off-diagonal), and the pair term
+    (3 dV / 2) J_i P S_j against the separation, for both kernels."""
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(18)
+    n = (32, 32, 32)
+    out = {"grid": list(n), "kernels": {}}
+    qs = [rng.uniform(0.0, 32.0, (1, 3)) for _ in range(64)]
+    seps = [2.0, 3.0, 4.0, 5.0, 6.0, 8.0, 10.0, 12.0]
+    base = np.array([10.3, 11.7, 12.2])
+    for kernel in (3, 4):
+        M = jps_columns(I, stream_handle, n, kernel, qs)[:, 0] - np.eye(3)[None]
+        diag = np.abs(np.diagonal(M, axis1=1, axis2=2))
+        off = np.abs(M - np.einsum("cii->ci", M)[:, :, None] * np.eye(3)[None])
+        pairs = {}
+        for name, d in (("x", np.array([1.0, 0.0, 0.0])), ("diagonal", np.ones(3) / np.sqrt(3.0))):
+            cfg = [np.stack([base, base + l * d]) for l in seps]
+            P = jps_columns(I, stream_handle, n, kernel, cfg, kicked=1)[:, 0]
+            pairs[name] = [float(np.max(np.abs(x))) for x in P]
+        out["kernels"]["%d-point" % kernel] = {
+            "positions": len(qs), "diag_dev_mean": float(np.mean(np.diagonal(M, axis1=1, axis2=2))),
+            "diag_dev_max": float(diag.max()), "offdiag_max": float(off.max()),
+            "pair_separations": seps, "pair_max_entry": pairs}
+    out["wall_s"] = time.perf_counter() - t0
+    return out
+
+
 def vacf(series, lags):
     """Velocity autocorrelation <u(t) . u(t + lag)> / 3 of a (steps, 3)
     series, averaged over the time origins."""
@@ -827,6 +884,10 @@ def main():
         log("rdf: %s" % out["rdf_32"]["vs_monte_carlo"])
         log("ensemble velocity autocorrelation: %d steps" % args.vacf_steps)
         out["ensemble_vacf"] = ensemble_vacf_leg(I, torch, stream, args.vacf_steps, tune=not args.no_autotune)
+    log("J P S translational invariance (32^3, both kernels)")
+    out["jps_32"] = jps_leg(I, stream.cuda_stream)
+    log("jps: %s" % {k: (round(v["diag_dev_max"], 4), round(v["offdiag_max"], 5))
+                     for k, v in out["jps_32"]["kernels"].items()})
     if not args.no_convergence:
         log("temporal convergence study (spring test, FP64)")
         out["convergence"] = convergence_leg(I, stream)
