@@ -77,8 +77,7 @@ __global__ void __launch_bounds__(kThreads) k_spread_overflow(const RepDesc<T>* 
         const int txi = tile % tiles_x, tyi = (tile / tiles_x) % tiles_y, tzi = tile / (tiles_x * tiles_y);
         const int i0 = txi * rtx, j0 = tyi * rty, k0 = tzi * kRhsZChunk;
         gptr<const double> o = as_global(rb.stc) + ((long long)b * 3 + a) * kStcPerComp;
-        const int ib = r / P, ic_unused = 0;
-        (void)ic_unused;
+        const int ib = r / P;
         const int y = ((int)o[1] + ib) % g.ny;
         if (y < j0 || y >= j0 + rty) continue;
         for (int ic = 0; ic < P; ++ic) {
