@@ -202,6 +202,20 @@ icm_status icm_get_state(icm_ctx* ctx, int32_t replica, void* v, double* q,
                          double* u, double* lag_c, icm_diag* diag,
                          uint32_t flags);
 
+/* Advective history of a replica with advection on: the advective term
+ * D.(rho v v^T) of its last step (the lagged term of Eq. (Adams_Bashforth)),
+ * in the context precision and laid out like v.
+ * icm_get_advection_lag copies it to lag (NULL: skip) and sets *valid (NULL:
+ * skip) to 1 if the next step will use it, 0 if the next step starts the
+ * history with forward Euler. icm_set_advection_lag installs lag as that
+ * term, so that the next step takes the Adams-Bashforth weights, or clears
+ * the history when lag is NULL. With icm_get_state / icm_set_state (called
+ * first: installing a field clears the history) this restores a run
+ * exactly. ICM_E_INVALID if the replica has advection off.
+ * Flags: ICM_PTRS_DEVICE.                                                  */
+icm_status icm_get_advection_lag(icm_ctx* ctx, int32_t replica, void* lag, int32_t* valid, uint32_t flags);
+icm_status icm_set_advection_lag(icm_ctx* ctx, int32_t replica, const void* lag, uint32_t flags);
+
 /* Per-kernel timing of icm_step. With timing enabled, icm_step records a
  * pair of HIP events on the context stream around every kernel launch and
  * accumulates the elapsed time per phase (a fixed kernel family), so that a

@@ -1100,6 +1100,43 @@ icm_status icm_get_state(icm_ctx* c, int32_t replica, void* v, double* q, double
     return ICM_OK;
 }
 
+icm_status icm_get_advection_lag(icm_ctx* c, int32_t replica, void* lag, int32_t* valid, uint32_t flags) {
+    icm_status st = check_replica(c, replica);
+    if (st != ICM_OK) return st;
+    Replica& R = c->reps[replica];
+    unsigned int* hist = adv_hist_of(c, R);
+    if (!hist) return fail(c, ICM_E_INVALID, "replica %d has advection off", replica);
+    const bool dev = (flags & ICM_PTRS_DEVICE) != 0;
+    hipStream_t s = c->stream;
+    void* adv = c->precision == ICM_FP64 ? (void*)R.gd.adv : (void*)R.gf.adv;
+    if (lag) HIP_TRY(c, hipMemcpyAsync(lag, adv, field_bytes(c, R), dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    unsigned int h = 0;
+    if (valid) HIP_TRY(c, hipMemcpyAsync(&h, hist, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (valid) *valid = h != 0u ? 1 : 0;
+    return ICM_OK;
+}
+
+icm_status icm_set_advection_lag(icm_ctx* c, int32_t replica, const void* lag, uint32_t flags) {
+    icm_status st = check_replica(c, replica);
+    if (st != ICM_OK) return st;
+    Replica& R = c->reps[replica];
+    unsigned int* hist = adv_hist_of(c, R);
+    if (!hist) return fail(c, ICM_E_INVALID, "replica %d has advection off", replica);
+    const bool dev = (flags & ICM_PTRS_DEVICE) != 0;
+    hipStream_t s = c->stream;
+    void* adv = c->precision == ICM_FP64 ? (void*)R.gd.adv : (void*)R.gf.adv;
+    const unsigned int one = 1u;
+    if (lag) {
+        HIP_TRY(c, hipMemcpyAsync(adv, lag, field_bytes(c, R), dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        HIP_TRY(c, hipMemcpyAsync(hist, &one, sizeof(one), hipMemcpyHostToDevice, s));
+    } else {
+        HIP_TRY(c, hipMemsetAsync(hist, 0, sizeof(unsigned int), s));
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return ICM_OK;
+}
+
 icm_status icm_autotune(icm_ctx* c, icm_tune_result* results, int32_t capacity, int32_t* n_results) {
     if (!c) return fail(nullptr, ICM_E_INVALID, "NULL context");
     if (c->error_state) return fail(c, ICM_E_STATE, "context is in an error state; call icm_set_state first");

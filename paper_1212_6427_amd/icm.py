@@ -110,6 +110,10 @@ _lib.icm_step.argtypes = [_p, ctypes.c_int64, ctypes.c_uint32]
 _lib.icm_step.restype = ctypes.c_int
 _lib.icm_get_state.argtypes = [_p, ctypes.c_int32, _p, _p, _p, _p, ctypes.POINTER(icm_diag), ctypes.c_uint32]
 _lib.icm_get_state.restype = ctypes.c_int
+_lib.icm_get_advection_lag.argtypes = [_p, ctypes.c_int32, _p, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32]
+_lib.icm_get_advection_lag.restype = ctypes.c_int
+_lib.icm_set_advection_lag.argtypes = [_p, ctypes.c_int32, _p, ctypes.c_uint32]
+_lib.icm_set_advection_lag.restype = ctypes.c_int
 _lib.icm_num_blobs.argtypes = [_p, ctypes.c_int32]
 _lib.icm_num_blobs.restype = ctypes.c_int32
 _lib.icm_set_timing.argtypes = [_p, ctypes.c_int32]
@@ -247,6 +251,26 @@ def icm_get_state(ctx, replica, n, field_dtype=np.float64, want_v=True, want_dia
     return dict(v=v, q=q, u=u, lag_c=lag, diag=diag)
 
 
+def icm_get_advection_lag(ctx, replica, n, field_dtype=np.float64):
+    """Returns (lag, valid): the lagged advective term (host array shaped
+    like v) and whether the next step uses it."""
+    nx, ny, nz = n
+    lag = np.empty((3, nz, ny, nx), dtype=field_dtype)
+    valid = ctypes.c_int32(0)
+    _check(_lib.icm_get_advection_lag(ctx, int(replica), lag.ctypes.data_as(ctypes.c_void_p), ctypes.byref(valid), 0),
+           ctx)
+    return lag, bool(valid.value)
+
+
+def icm_set_advection_lag(ctx, replica, lag, field_dtype=np.float64):
+    """Install the lagged advective term (None: clear the history)."""
+    if lag is None:
+        _check(_lib.icm_set_advection_lag(ctx, int(replica), None, 0), ctx)
+        return
+    a = np.ascontiguousarray(lag, dtype=field_dtype)
+    _check(_lib.icm_set_advection_lag(ctx, int(replica), a.ctypes.data_as(ctypes.c_void_p), 0), ctx)
+
+
 def icm_set_timing(ctx, enable):
     _check(_lib.icm_set_timing(ctx, 1 if enable else 0), ctx)
 
@@ -294,6 +318,12 @@ class Sim:
 
     def get_state(self, replica=0, want_v=True, want_diag=True):
         return icm_get_state(self.ctx, replica, tuple(self.params[replica].n), self.dtype, want_v, want_diag)
+
+    def get_advection_lag(self, replica=0):
+        return icm_get_advection_lag(self.ctx, replica, tuple(self.params[replica].n), self.dtype)
+
+    def set_advection_lag(self, replica, lag):
+        icm_set_advection_lag(self.ctx, replica, lag, self.dtype)
 
     def set_timing(self, enable):
         icm_set_timing(self.ctx, enable)

@@ -138,3 +138,59 @@ def test_advection_mixed_batch_graph(I, precision):
             assert not bad, (r, bad)
     finally:
         sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_checkpoint_restores_the_advective_history(I, precision):
+    """A run checkpointed after three steps (state plus the lagged advective
+    term) and restored into a new context continues exactly like the
+    original; restored without the lagged term it restarts with Euler and
+    differs."""
+    prec = I.FP64 if precision == "fp64" else I.FP32_GRID
+    dtype = np.float64 if prec == I.FP64 else np.float32
+    p = oracle_params((32, 24, 16), kernel=4, kT=1e-3, dt=0.2, seed=15, advection=True)
+    st = _with_flow(p, initial_state(p, 3, (0.0, 1.0, 0.0), seed=25), 0.3, 9)
+    banner("advection checkpoint %s" % precision)
+    a = I.Sim([gpu_params(I, p)], [3], prec)
+    try:
+        load_into_gpu(I, a, 0, st, dtype)
+        a.step(3, I.STEP_GRAPH)
+        ck = a.get_state(0)
+        lag, valid = a.get_advection_lag(0)
+        assert valid
+        a.step(2, I.STEP_GRAPH)
+        ref = a.get_state(0)
+    finally:
+        a.close()
+
+    def restored(with_lag):
+        b = I.Sim([gpu_params(I, p)], [3], prec)
+        try:
+            b.set_blobs(0, ck["q"], ck["u"], st.m_e, st.f_const)
+            b.set_state(0, v=ck["v"], lag_c=ck["lag_c"], step=ck["diag"]["step"])
+            assert not b.get_advection_lag(0)[1]
+            if with_lag:
+                b.set_advection_lag(0, lag)
+                assert b.get_advection_lag(0)[1]
+            b.step(2, I.STEP_GRAPH)
+            return b.get_state(0)
+        finally:
+            b.close()
+
+    tol = 1e-12 if prec == I.FP64 else 1e-6
+    got = restored(True)
+    assert rel_err(got["v"], ref["v"]) < tol
+    assert rel_err(got["q"] - ck["q"], ref["q"] - ck["q"]) < tol
+    euler = restored(False)
+    assert rel_err(euler["v"], ref["v"]) > 100 * tol
+
+
+def test_advection_lag_needs_advection(I):
+    p = oracle_params((16, 16, 16), kernel=3)
+    sim = I.Sim([gpu_params(I, p)], [1], I.FP64)
+    try:
+        with pytest.raises(I.ICMError) as e:
+            sim.get_advection_lag(0)
+        assert e.value.status == I.E_INVALID
+    finally:
+        sim.close()
