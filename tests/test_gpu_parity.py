@@ -317,3 +317,37 @@ def test_autotuned_launch_shapes_keep_parity(I, precision):
             assert not bad, (r, bad)
     finally:
         sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_checkpoint_restart_continues_exactly(I, precision):
+    """State read by icm_get_state after two steps (v, q, u, lagged slip term,
+    step counter) and installed in a new context continues like the
+    uninterrupted run: same Philox stream, same inertial correction."""
+    prec = I.FP64 if precision == "fp64" else I.FP32_GRID
+    dtype = np.float64 if prec == I.FP64 else np.float32
+    p = oracle_params((32, 32, 32), kernel=4, kT=1e-3, dt=0.25, seed=111, wca_eps=1e-2, wca_sigma=2.0 / 2 ** (1 / 6))
+    st = initial_state(p, 4, (0.0, 1.0, -0.5, 2.0), seed=12, min_sep=4.0)
+    banner("checkpoint restart %s" % precision)
+    a = I.Sim([gpu_params(I, p)], [4], prec)
+    try:
+        load_into_gpu(I, a, 0, st, dtype)
+        a.step(2, I.STEP_GRAPH)
+        ck = a.get_state(0)
+        a.step(3, I.STEP_GRAPH)
+        ref = a.get_state(0)
+    finally:
+        a.close()
+    b = I.Sim([gpu_params(I, p)], [4], prec)
+    try:
+        b.set_blobs(0, ck["q"], ck["u"], st.m_e, st.f_const)
+        b.set_state(0, v=ck["v"], lag_c=ck["lag_c"], step=ck["diag"]["step"])
+        b.step(3, I.STEP_GRAPH)
+        got = b.get_state(0)
+    finally:
+        b.close()
+    tol = 1e-12 if prec == I.FP64 else 1e-6
+    assert got["diag"]["step"] == ref["diag"]["step"] == 5
+    for k in ("v", "u", "lag_c"):
+        assert rel_err(got[k], ref[k]) < tol, k
+    assert rel_err(got["q"] - ck["q"], ref["q"] - ck["q"]) < tol
