@@ -272,16 +272,17 @@ def scale_leg(I, torch, stream, steps, tune=True):
     return out
 
 
-def advection_leg(I, torch, stream, wl, steps, warmup, tune=True):
+def advection_leg(I, torch, stream, wl, steps, warmup, tune=True, flags=None):
     """The benchmark workload with the advective term on (Adams-Bashforth
     lag): step time and the advection kernel against the HBM roofline."""
     n = tuple(wl["n"])
     ncell = int(np.prod(n))
+    flags = I.STEP_GRAPH if flags is None else flags
     sim, _, _ = setup(I, torch, wl, I.FP32_GRID, stream, advection=True)
     if tune:
         sim.autotune()
-    sim.step(warmup, I.STEP_GRAPH)
-    sec, _ = time_steps(torch, sim, stream, steps, I.STEP_GRAPH)
+    sim.step(warmup, flags)
+    sec, _ = time_steps(torch, sim, stream, steps, flags)
     ph = profile_phases(sim, 10, n, wl["n_blobs"], wl["kernel"], 4)
     diag = sim.get_state(0, want_v=False)["diag"]
     sim.close()
@@ -760,6 +761,7 @@ def main():
     ap.add_argument("--scale-steps", type=int, default=200)
     ap.add_argument("--no-advection", action="store_true", help="skip the leg with the advective term on")
     ap.add_argument("--no-convergence", action="store_true", help="skip the temporal-convergence study")
+    ap.add_argument("--no-jps", action="store_true", help="skip the J P S invariance diagnostics")
     ap.add_argument("--advection-steps", type=int, default=100)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -860,7 +862,7 @@ def main():
     if not args.no_advection:
         log("advection on: %d steps" % args.advection_steps)
         out["advection"] = advection_leg(I, torch, stream, wl, args.advection_steps, max(2, args.warmup // 4),
-                                         not args.no_autotune)
+                                         not args.no_autotune, step_flags)
         log("advection: %.3f ms/step, advection kernel %s us" % (
             out["advection"]["ms_per_step"], out["advection"]["advect_kernel"].get("avg_launch_us")))
     if not args.no_ensemble:
@@ -884,10 +886,11 @@ def main():
         log("rdf: %s" % out["rdf_32"]["vs_monte_carlo"])
         log("ensemble velocity autocorrelation: %d steps" % args.vacf_steps)
         out["ensemble_vacf"] = ensemble_vacf_leg(I, torch, stream, args.vacf_steps, tune=not args.no_autotune)
-    log("J P S translational invariance (32^3, both kernels)")
-    out["jps_32"] = jps_leg(I, stream.cuda_stream)
-    log("jps: %s" % {k: (round(v["diag_dev_max"], 4), round(v["offdiag_max"], 5))
-                     for k, v in out["jps_32"]["kernels"].items()})
+    if not args.no_jps:
+        log("J P S translational invariance (32^3, both kernels)")
+        out["jps_32"] = jps_leg(I, stream.cuda_stream)
+        log("jps: %s" % {k: (round(v["diag_dev_max"], 4), round(v["offdiag_max"], 5))
+                         for k, v in out["jps_32"]["kernels"].items()})
     if not args.no_convergence:
         log("temporal convergence study (spring test, FP64)")
         out["convergence"] = convergence_leg(I, stream)
