@@ -101,10 +101,10 @@ def test_wca_suspension_reproduces_the_gibbs_boltzmann_structure(I):
     from the GPU dynamics must match the Monte Carlo sample of
     exp(-U/kT) (tests/golden/rdf_wca_mc.json, written by the oracle's
     sampler), for neutrally buoyant and for heavy (m_e = m_f) blobs, within
-    the resolution of the paper's comparison (a figure): |g - g_MC| < 0.05
-    for 1.8 < r < 4.5. The GPU runs show a systematic deficit of 1-2.5% at
-    the contact peak (about 5 standard errors at dt = 1, shrinking to ~1% at
-    dt = 0.25), which the assertion tolerates and the output reports."""
+    the statistical error of the replicas (plus that of the reference) and
+    |g - g_MC| < 0.03 for 1.8 < r < 4.5. The blobs start at least sigma apart
+    and need ~20000 steps (dt = 1) to build the contact peak: shorter
+    relaxations leave it ~2% low."""
     import json
     import os
 
@@ -123,4 +123,5 @@ def test_wca_suspension_reproduces_the_gibbs_boltzmann_structure(I):
         print("m_e/m_f=%g: max |g - g_MC| = %.4f, max z = %.2f" % (ratio, np.max(np.abs(gm - g_mc)[sel]), z.max()),
               flush=True)
         print(np.c_[r[sel], gm[sel], g_mc[sel], se[sel]].round(4), flush=True)
-        assert np.max(np.abs(gm - g_mc)[sel]) < 0.05
+        assert np.max(np.abs(gm - g_mc)[sel]) < 0.03
+        assert z.max() < 5.0
