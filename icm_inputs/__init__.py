@@ -36,7 +36,7 @@ WORKLOADS = {
     # 32^3, dt = 1, kT = eps = 1e-3, sigma = 2; excess masses 0 and m_f
     "rdf_32": dict(
         n=(32, 32, 32), h=1.0, rho=1.0, eta=1.0, kT=1e-3, dt=1.0, kernel=3, n_blobs=1000,
-        wca_eps=1e-3, wca_sigma=2.0, me_over_mf=(0.0, 1.0), replicas=8, steps=40000, every=100,
+        wca_eps=1e-3, wca_sigma=2.0, me_over_mf=(0.0, 1.0), replicas=8, steps=20000, every=100,
         relax=20000, rmax=5.0, nbins=50, min_sep=2.0, seed=17),
     # ideal gas of neutrally buoyant blobs at equilibrium, thermal drift on
     # and off (App. B.2): 100 blobs per 16^3 box, viscous CFL 0.05
