@@ -125,3 +125,37 @@ def test_wca_suspension_reproduces_the_gibbs_boltzmann_structure(I):
         print(np.c_[r[sel], gm[sel], g_mc[sel], se[sel]].round(4), flush=True)
         assert np.max(np.abs(gm - g_mc)[sel]) < 0.03
         assert z.max() < 5.0
+
+
+def test_light_blob_equipartition_bias_vanishes_with_the_time_step(I):
+    """Sec. IV.A: for m_e != 0 the blob velocity variance carries a time-step
+    bias that needs a small viscous CFL number to go away. For a light blob
+    (m_e = -m_f/2, 64^3, 16 replicas) <u_a^2> m~ / kT is ~1.11 at
+    beta = 0.25 and must fall towards 1 as dt is halved, reaching it within
+    3% at beta = 1/16."""
+    n, kT = (64, 64, 64), 1e-3
+    m_f = 1.0 / 0.375 ** 3
+    mt = -0.5 * m_f + 1.5 * m_f
+    R = 16
+    ratios = {}
+    for dt in (0.25, 0.125, 0.0625):
+        banner("light-blob equipartition dt=%g" % dt)
+        params = [I.make_params(n, kT=kT, dt=dt, kernel=4, seed=77, replica_id=r) for r in range(R)]
+        sim = I.Sim(params, [1] * R, I.FP32_GRID)
+        try:
+            for r in range(R):
+                sim.set_blobs(r, icm_inputs.uniform_positions(1, n, 1.0, seed=500 + r), m_e=np.array([-0.5 * m_f]))
+                sim.set_state(r, flags=I.STATE_EQUILIBRIUM)
+            sim.step(int(50 / dt), I.STEP_GRAPH)
+            acc = []
+            for _ in range(int(500 / dt) // 5):
+                sim.step(5, I.STEP_GRAPH)
+                acc.append([sim.get_state(r, want_v=False, want_diag=False)["u"][0] ** 2 for r in range(R)])
+        finally:
+            sim.close()
+        per = np.asarray(acc).mean(axis=(0, 2)) * mt / kT
+        ratios[dt] = (per.mean(), per.std(ddof=1) / np.sqrt(R))
+        print("dt=%g: <u^2> m~/kT = %.4f +- %.4f" % (dt, *ratios[dt]), flush=True)
+    assert ratios[0.25][0] > ratios[0.125][0] > ratios[0.0625][0] - 3 * ratios[0.0625][1]
+    assert ratios[0.25][0] - 1.0 > 0.05
+    assert abs(ratios[0.0625][0] - 1.0) < 0.03
