@@ -807,6 +807,10 @@ def main():
     ms_per_step = sec * 1000.0 / args.steps
     value = ncell * args.steps / sec
     log("FP32 grid: %.3f ms/step, %.3e cell-steps/s" % (ms_per_step, value))
+    # the same K steps timed four more times: run-to-run spread of the figure above
+    repeats = [ms_per_step] + [time_steps(torch, sim, stream, args.steps, step_flags)[0] * 1000.0 / args.steps
+                               for _ in range(4)]
+    log("FP32 grid, five timings: %s ms/step" % ", ".join("%.4f" % x for x in repeats))
     phases = profile_phases(sim, args.profile_steps, n, nb, wl["kernel"], 4)
     diag = sim.get_state(0, want_v=False)["diag"]
     sim.close()
@@ -844,6 +848,8 @@ def main():
                    "precision": "fp32 grid, fp64 blobs", "kT": wl["kT"], "dt": wl["dt"],
                    "forces": "WCA eps=%g cutoff=%gh" % (wl["wca_eps"], wl["wca_cutoff"])},
         "blob_steps_per_s": nb * args.steps / sec,
+        "ms_per_step_repeats": repeats,
+        "ms_per_step_median_of_5": float(np.median(repeats)),
         "step_hbm_fraction": step_alg_bytes / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "roofline": roofline,
         "phases": phases,
