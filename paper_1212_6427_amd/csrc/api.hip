@@ -218,7 +218,9 @@ void carve_blobs(Carver& cv, int max_nb, int nz, icm::BlobBufs& b, double*& diag
     b.stc = cv.take<double>((size_t)max_nb * 3 * icm::kStcPerComp);
     b.chunk_count = cv.take<int>(nchunks + 1);
     b.chunk_list = cv.take<int>((size_t)nchunks * max_nb);
-    b.ovf_cap = 4 * std::max(max_nb, 1);
+    // a P <= 4 stencil spans at most two tiles per axis (tiles are at least
+    // 16 cells wide), so a blob can overflow at most 8 tiles
+    b.ovf_cap = 8 * std::max(max_nb, 1);
     b.ovf_list = cv.take<int>(2 * (size_t)b.ovf_cap);
     b.q = cv.take<double>(n3);
     b.u = cv.take<double>(n3);

@@ -351,3 +351,22 @@ def test_checkpoint_restart_continues_exactly(I, precision):
     for k in ("v", "u", "lag_c"):
         assert rel_err(got[k], ref[k]) < tol, k
     assert rel_err(got["q"] - ck["q"], ref["q"] - ck["q"]) < tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dense_cluster_overflows_the_tile_lists(I, precision):
+    """400 overlapping blobs inside a cube of side 2.3 cells around the
+    corner shared by eight right-hand-side tiles (x tiles of 32 cells, y
+    tiles of 16, z chunks of 16): every blob's stencil meets all eight tiles,
+    each tile's list (128 blobs) overflows, and the overflow list holds 8
+    entries per blob. Must match the oracle."""
+    prec = I.FP64 if precision == "fp64" else I.FP32_GRID
+    tol = TOL64 if precision == "fp64" else TOL32
+    steps = 2 if precision == "fp64" else 1
+    p = oracle_params((64, 32, 32), kernel=4, kT=1e-3, dt=0.2, seed=120)
+    rng = np.random.default_rng(121)
+    q = np.array([30.6, 14.6, 14.6]) + rng.uniform(0.0, 2.3, (400, 3))
+    st = O.new_state(p, q, m_e=np.zeros(400), f_const=icm_inputs.random_forces(400, seed=122, scale=0.01))
+    st.v = O.equilibrium_field(p)
+    st.u = O.interp(p, st.v, st.q)
+    run_parity(I, p, st, steps, prec, tol, "dense cluster %s" % precision)
