@@ -687,7 +687,7 @@ float time_fft(icm_ctx* c, const icm::Batch<T>& B, int which, hipEvent_t ea, hip
         if (which == 0 || which == 2) launch_fft_y(B, 1, s);
         if (which == 0 || which == 1) launch_fft_x_inverse(B, kFieldAux, false, s);
     };
-    constexpr int kReps = 5;
+    constexpr int kReps = 10;
     launch_fft_x_forward(B, kFieldRhs, s);
     once();  // warm-up
     launch_fft_x_forward(B, kFieldRhs, s);
@@ -728,35 +728,42 @@ icm_status autotune_t(icm_ctx* c, icm_tune_result* res, int32_t cap, int32_t* nr
         icm::GridDesc<T>& g = B.g;
         if (g.fast) {
             r.tuned = 1;
-            // z pass: plan size x columns; then y columns; then x threads
+            // z pass: plan size x columns; then y columns; then x threads.
+            // Every candidate is timed over the whole five-pass round trip
+            // (a pass timed alone keeps its working set in the last-level
+            // cache, which the step does not), and replaces the current
+            // choice only if it is at least 1% faster.
             const int zplans[2] = {1, 0};
             const int cols[3] = {8, 16, 32};
             const int xts[3] = {128, 256, 512};
-            float best = 1e30f;
+            auto better = [](float t, float best) { return t >= 0 && t < 0.99f * best; };
+            float best = t0;
             int bz = g.Bz, zs = g.zsmall;
             for (int zp : zplans)
                 for (int cz : cols) {
+                    if (zp == zs && cz == bz) continue;
                     g.zsmall = zp;
                     g.Bz = cz;
-                    const float t = time_fft<T>(c, B, 3, ea, eb);
-                    if (t >= 0 && t < best) { best = t; bz = cz; zs = zp; }
+                    const float t = time_fft<T>(c, B, 0, ea, eb);
+                    if (better(t, best)) { best = t; bz = cz; zs = zp; }
+                    g.zsmall = zs;
+                    g.Bz = bz;
                 }
-            g.Bz = bz;
-            g.zsmall = zs;
-            best = 1e30f;
             int by = g.By;
             for (int cy : cols) {
+                if (cy == by) continue;
                 g.By = cy;
-                const float t = time_fft<T>(c, B, 2, ea, eb);
-                if (t >= 0 && t < best) { best = t; by = cy; }
+                const float t = time_fft<T>(c, B, 0, ea, eb);
+                if (better(t, best)) { best = t; by = cy; }
+                g.By = by;
             }
-            g.By = by;
-            best = 1e30f;
             int xt = g.xt;
             for (int x : xts) {
+                if (x == xt) continue;
                 g.xt = x;
-                const float t = time_fft<T>(c, B, 1, ea, eb);
-                if (t >= 0 && t < best) { best = t; xt = x; }
+                const float t = time_fft<T>(c, B, 0, ea, eb);
+                if (better(t, best)) { best = t; xt = x; }
+                g.xt = xt;
             }
             g.xt = xt;
             r.us_tuned = time_fft<T>(c, B, 0, ea, eb);
