@@ -592,6 +592,65 @@ def jps_leg(I, stream_handle):
     return out
 
 
+def mobility_columns(I, stream_handle, n, kernel, qs, F=1e-8, dt=1e6):
+    """Periodic steady Stokes mobility of one blob per configuration on the
+    GPU (FP64): the blob at q pushed by F e_b, the fluid by -F e_b / V (zero
+    net force, so no mean flow), one deterministic step from rest. With
+    rho / dt ~ 0 the Crank-Nicolson solve returns twice the Stokes velocity,
+    and the reported blob velocity J v gives 2 mu F e_b. Returns mu as an
+    array (len(qs), 3, 3), [c, :, b] for the force along b."""
+    nq = len(qs)
+    vol = float(np.prod(n))
+    params = []
+    for c in range(nq):
+        for b in range(3):
+            body = [0.0, 0.0, 0.0]
+            body[b] = -F / vol
+            params.append(I.make_params(n, eta=1.0, rho=1.0, kT=0.0, dt=dt, kernel=kernel, body_force=body,
+                                        replica_id=3 * c + b))
+    sim = I.Sim(params, [1] * (3 * nq), I.FP64, stream=stream_handle)
+    try:
+        for c, q in enumerate(qs):
+            for b in range(3):
+                f = np.zeros((1, 3))
+                f[0, b] = F
+                sim.set_blobs(3 * c + b, np.asarray(q).reshape(1, 3), f_const=f)
+        sim.step(1, I.STEP_GRAPH)
+        mu = np.empty((nq, 3, 3))
+        for c in range(nq):
+            for b in range(3):
+                mu[c, :, b] = sim.get_state(3 * c + b, want_v=False, want_diag=False)["u"][0] / (2.0 * F)
+        return mu
+    finally:
+        sim.close()
+
+
+def hydrodynamic_radius(mu, L, eta=1.0):
+    """R_H from a periodic mobility with Hasimoto's finite-size correction,
+    mu = (1 - 2.837297 R/L + (4 pi / 3)(R/L)^3) / (6 pi eta R)."""
+    from scipy.optimize import brentq
+    f = lambda R: (1 - 2.837297 * R / L + 4.18879 * (R / L) ** 3) / (6 * np.pi * eta * R) - mu
+    return brentq(f, 0.05, 0.45 * L)
+
+
+def hydrodynamic_radius_leg(I, stream_handle):
+    """R_H against the box size and the position within a cell
+    (Sec. III.A.2): 16 random positions per box, both kernels."""
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(19)
+    out = {"positions_per_box": 16, "kernels": {}}
+    for kernel in (3, 4):
+        rows = {}
+        for N in (16, 32, 64, 128):
+            qs = [rng.uniform(0.0, N, 3) for _ in range(16)]
+            mu = mobility_columns(I, stream_handle, (N, N, N), kernel, qs)
+            r = np.array([hydrodynamic_radius(np.trace(m) / 3.0, float(N)) for m in mu])
+            rows[str(N)] = {"R_H_mean": float(r.mean()), "R_H_min": float(r.min()), "R_H_max": float(r.max())}
+        out["kernels"]["%d-point" % kernel] = rows
+    out["wall_s"] = time.perf_counter() - t0
+    return out
+
+
 def vacf(series, lags):
     """Velocity autocorrelation <u(t) . u(t + lag)> / 3 of a (steps, 3)
     series, averaged over the time origins."""
@@ -900,6 +959,11 @@ def main():
         out["jps_32"] = jps_leg(I, stream.cuda_stream)
         log("jps: %s" % {k: (round(v["diag_dev_max"], 4), round(v["offdiag_max"], 5))
                          for k, v in out["jps_32"]["kernels"].items()})
+    if not args.no_jps:
+        log("hydrodynamic radius against box size and position (both kernels)")
+        out["hydrodynamic_radius"] = hydrodynamic_radius_leg(I, stream.cuda_stream)
+        log("R_H: %s" % {k: {n: round(v["R_H_mean"], 4) for n, v in rows.items()}
+                         for k, rows in out["hydrodynamic_radius"]["kernels"].items()})
     if not args.no_convergence:
         log("temporal convergence study (spring test, FP64)")
         out["convergence"] = convergence_leg(I, stream)

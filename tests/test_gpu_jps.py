@@ -67,3 +67,36 @@ def test_jps_translational_invariance_bounds(I):
         assert vals[GOLD["jps_pair_bound"]["separation"] + 1.0] < GOLD["jps_pair_bound"]["value"]
     vx = dict(zip(seps, res["pair_max_entry"]["x"]))
     assert vx[8.0] / vx[4.0] == pytest.approx(0.125, rel=0.05)
+
+
+@pytest.mark.parametrize("kernel", [3, 4])
+def test_steady_mobility_matches_oracle(I, kernel):
+    """The periodic Stokes mobility from one GPU step with rho/dt ~ 0 (zero
+    net force) equals the oracle's direct spectral Stokes solve."""
+    import bench
+    rng = np.random.default_rng(50 + kernel)
+    qs = [rng.uniform(0.0, 16.0, 3) for _ in range(3)]
+    banner("steady mobility kernel=%d" % kernel)
+    mu = bench.mobility_columns(I, None, (16, 16, 16), kernel, qs)
+    p = O.Params(n=(16, 16, 16), kernel=kernel)
+    for c, q in enumerate(qs):
+        ref = O.mobility_matrix(p, q[None])
+        err = np.max(np.abs(mu[c] - ref)) / np.max(np.abs(ref))
+        print("q=%s err %.2e" % (q, err), flush=True)
+        assert err < 1e-4
+
+
+def test_hydrodynamic_radius_three_point_kernel(I):
+    """R_H ~ 0.91 dx for the three-point kernel (Sec. III.A.2), from the GPU
+    mobility with Hasimoto's correction, nearly independent of the box size
+    and varying by a few percent with position."""
+    import bench
+    banner("hydrodynamic radius")
+    rng = np.random.default_rng(60)
+    for N in (32, 64):
+        qs = [rng.uniform(0.0, N, 3) for _ in range(8)]
+        mu = bench.mobility_columns(I, None, (N, N, N), 3, qs)
+        r = np.array([bench.hydrodynamic_radius(np.trace(m) / 3.0, float(N)) for m in mu])
+        print("N=%d: R_H %.4f (%.4f .. %.4f)" % (N, r.mean(), r.min(), r.max()), flush=True)
+        assert r.mean() == pytest.approx(GOLD["hydrodynamic_radius_3pt"]["value"], rel=0.02)
+        assert (r.max() - r.min()) / r.mean() < 0.05
