@@ -684,12 +684,9 @@ __global__ void __launch_bounds__(kThreads) k_gather_bins(const RepDesc<T>* __re
     // lanes 1..3 write the record of axis ax = r - 1
     if (r >= 1 && r <= 3) {
         const int ax = r - 1;
-        const double x = bb.qh[3 * b + ax] * inv_h - (ax == a ? 0.0 : 0.5);
-        const double m0 = (P == 3) ? floor(x + 0.5) : floor(x);
-        const long long base = (long long)m0 - 1;
-        long long wb = base % n[ax];
-        if (wb < 0) wb += n[ax];
-        o[ax] = (double)wb;
+        const double x = fold_coord(bb.qh[3 * b + ax] * inv_h - (ax == a ? 0.0 : 0.5), n[ax]);
+        const int base = (int)((P == 3) ? floor(x + 0.5) : floor(x)) - 1;
+        o[ax] = (double)wrap_node(base, n[ax]);
         for (int tt = 0; tt < 4; ++tt) {
             const double d = x - (double)(base + tt);
             o[3 + 4 * ax + tt] = (tt < P) ? ((P == 3) ? phi3(d) : phi4(d)) : 0.0;

@@ -160,17 +160,28 @@ struct AxisStencil {
     double w[P];
 };
 
+// Folds a coordinate into [0, n] (up to rounding at the ends), so that the
+// stencil nodes are small integers in [-2, n + 2] that one conditional wrap
+// brings into [0, n); positions are kept unwrapped and may lie many boxes
+// away. The subtraction is exact (Sterbenz) except within rounding of 0.
+__device__ __forceinline__ double fold_coord(double x, int n) {
+    const double nd = (double)n;
+    return x - nd * floor(x / nd);
+}
+
+__device__ __forceinline__ int wrap_node(int node, int n) {
+    return node < 0 ? node + n : (node >= n ? node - n : node);
+}
+
 template <int P>
 __device__ __forceinline__ void axis_stencil(double x, int n, bool deriv, double inv_h, AxisStencil<P>& st) {
-    const double m0 = (P == 3) ? floor(x + 0.5) : floor(x);
-    const long long mi = (long long)m0;
+    x = fold_coord(x, n);
+    const int mi = (int)((P == 3) ? floor(x + 0.5) : floor(x));
 #pragma unroll
     for (int a = 0; a < P; ++a) {
-        const long long node = mi - 1 + a;
+        const int node = mi - 1 + a;
         const double d = x - (double)node;
-        long long wn = node % n;
-        if (wn < 0) wn += n;
-        st.node[a] = (int)wn;
+        st.node[a] = wrap_node(node, n);
         if (P == 3)
             st.w[a] = deriv ? dphi3(d) * inv_h : phi3(d);
         else
@@ -182,12 +193,10 @@ __device__ __forceinline__ void axis_stencil(double x, int n, bool deriv, double
 // runtime tap index stays in registers).
 template <int P>
 __device__ __forceinline__ void axis_tap(double x, int n, int a, bool deriv, double inv_h, int& node, double& w) {
-    const double m0 = (P == 3) ? floor(x + 0.5) : floor(x);
-    const long long nd = (long long)m0 - 1 + a;
+    x = fold_coord(x, n);
+    const int nd = (int)((P == 3) ? floor(x + 0.5) : floor(x)) - 1 + a;
     const double d = x - (double)nd;
-    long long wn = nd % n;
-    if (wn < 0) wn += n;
-    node = (int)wn;
+    node = wrap_node(nd, n);
     if (P == 3)
         w = deriv ? dphi3(d) * inv_h : phi3(d);
     else

@@ -370,3 +370,17 @@ def test_dense_cluster_overflows_the_tile_lists(I, precision):
     st.v = O.equilibrium_field(p)
     st.u = O.interp(p, st.v, st.q)
     run_parity(I, p, st, steps, prec, tol, "dense cluster %s" % precision)
+
+
+@pytest.mark.parametrize("kernel", [3, 4])
+def test_unwrapped_positions_far_from_the_box(I, kernel):
+    """Positions are kept unwrapped: blobs many box lengths away (in both
+    directions) must spread, interpolate and interact exactly like their
+    images in the box."""
+    p = oracle_params((24, 18, 12), kernel=kernel, kT=1e-3, dt=0.2, seed=130, wca_eps=1e-2,
+                      wca_sigma=2.0 / 2 ** (1 / 6))
+    st = initial_state(p, 5, (0.0, 1.0, 0.0, -0.5, 0.0), seed=131, min_sep=3.0)
+    L = np.array([24.0, 18.0, 12.0])
+    shifts = np.array([[3, -5, 11], [-7, 2, -13], [0, 0, 0], [40, -40, 25], [-1, 1, -1]], dtype=np.float64)
+    st.q = st.q + shifts * L
+    run_parity(I, p, st, 3, I.FP64, TOL64, "unwrapped kernel=%d" % kernel)
