@@ -672,25 +672,23 @@ icm_status capture_step(icm_ctx* c) {
 }
 
 // ----------------------------------------------------------- autotuner
-// Average time of one solve's FFT passes, or of one kind of pass, for the
-// batch B with its current launch shapes. which: 0 all five, 1 x pair, 2 y
-// pair, 3 z. The spectrum is refilled from the right-hand side before each
-// measurement so that repeated unnormalised transforms stay finite.
+// Average time of one solve's five FFT passes (x, y, z with the projection,
+// y inverse, x inverse) for the batch B with its current launch shapes, on
+// the context's scratch fields. The x forward pass reads the right-hand-side
+// field each time, so repeated unnormalised transforms stay finite.
 template <typename T>
-float time_fft(icm_ctx* c, const icm::Batch<T>& B, int which, hipEvent_t ea, hipEvent_t eb) {
+float time_fft(icm_ctx* c, const icm::Batch<T>& B, hipEvent_t ea, hipEvent_t eb) {
     using namespace icm;
     hipStream_t s = c->stream;
     auto once = [&] {
-        if (which == 0 || which == 1) launch_fft_x_forward(B, kFieldRhs, s);
-        if (which == 0 || which == 2) launch_fft_y(B, -1, s);
-        if (which == 0 || which == 3) launch_fft_z_solve(B, kSolveP, true, s);
-        if (which == 0 || which == 2) launch_fft_y(B, 1, s);
-        if (which == 0 || which == 1) launch_fft_x_inverse(B, kFieldAux, false, s);
+        launch_fft_x_forward(B, kFieldRhs, s);
+        launch_fft_y(B, -1, s);
+        launch_fft_z_solve(B, kSolveP, true, s);
+        launch_fft_y(B, 1, s);
+        launch_fft_x_inverse(B, kFieldAux, false, s);
     };
     constexpr int kReps = 10;
-    launch_fft_x_forward(B, kFieldRhs, s);
     once();  // warm-up
-    launch_fft_x_forward(B, kFieldRhs, s);
     (void)hipEventRecord(ea, s);
     for (int r = 0; r < kReps; ++r) once();
     (void)hipEventRecord(eb, s);
@@ -719,7 +717,7 @@ icm_status autotune_t(icm_ctx* c, icm_tune_result* res, int32_t cap, int32_t* nr
         icm::Batch<T> B = batch_of<T>(c, bi);
         icm_tune_result r{};
         for (int a = 0; a < 3; ++a) r.n[a] = shape[a];
-        const float t0 = time_fft<T>(c, B, 0, ea, eb);
+        const float t0 = time_fft<T>(c, B, ea, eb);
         if (t0 < 0) {
             st = fail(c, ICM_E_DEVICE, "autotune timing failed");
             break;
@@ -744,7 +742,7 @@ icm_status autotune_t(icm_ctx* c, icm_tune_result* res, int32_t cap, int32_t* nr
                     if (zp == zs && cz == bz) continue;
                     g.zsmall = zp;
                     g.Bz = cz;
-                    const float t = time_fft<T>(c, B, 0, ea, eb);
+                    const float t = time_fft<T>(c, B, ea, eb);
                     if (better(t, best)) { best = t; bz = cz; zs = zp; }
                     g.zsmall = zs;
                     g.Bz = bz;
@@ -753,7 +751,7 @@ icm_status autotune_t(icm_ctx* c, icm_tune_result* res, int32_t cap, int32_t* nr
             for (int cy : cols) {
                 if (cy == by) continue;
                 g.By = cy;
-                const float t = time_fft<T>(c, B, 0, ea, eb);
+                const float t = time_fft<T>(c, B, ea, eb);
                 if (better(t, best)) { best = t; by = cy; }
                 g.By = by;
             }
@@ -761,12 +759,12 @@ icm_status autotune_t(icm_ctx* c, icm_tune_result* res, int32_t cap, int32_t* nr
             for (int x : xts) {
                 if (x == xt) continue;
                 g.xt = x;
-                const float t = time_fft<T>(c, B, 0, ea, eb);
+                const float t = time_fft<T>(c, B, ea, eb);
                 if (better(t, best)) { best = t; xt = x; }
                 g.xt = xt;
             }
             g.xt = xt;
-            r.us_tuned = time_fft<T>(c, B, 0, ea, eb);
+            r.us_tuned = time_fft<T>(c, B, ea, eb);
             for (Replica& R : c->reps)
                 if (R.p.n[0] == shape[0] && R.p.n[1] == shape[1] && R.p.n[2] == shape[2]) {
                     icm::GridDesc<T>& gr = grid_of<T>(R);
