@@ -196,6 +196,16 @@ typedef struct {
  * the number of distinct grid shapes. A recorded step graph is dropped.     */
 icm_status icm_autotune(icm_ctx* ctx, icm_tune_result* results, int32_t capacity, int32_t* n_results);
 
+/* Install FFT launch shapes without measuring (for instance results saved
+ * from an earlier icm_autotune): for each of the `count` entries, the
+ * replicas whose grid shape equals n take y_columns and z_columns (1, 2, 4,
+ * ..., 64), z_small_plan (0 or 1) and x_threads (64, 128, 256 or 512); the
+ * time and `tuned` fields are ignored. Shapes only change how the passes are
+ * launched, not their results beyond rounding. ICM_E_INVALID (context
+ * unchanged) for a value outside those sets or a shape no replica has.
+ * A recorded step graph is dropped.                                        */
+icm_status icm_set_fft_shapes(icm_ctx* ctx, const icm_tune_result* shapes, int32_t count);
+
 /* Read a replica's state. Any output may be NULL. v: face field in the
  * context precision; q, u, lag_c: n_blobs x 3; diag: FP64 diagnostics.     */
 icm_status icm_get_state(icm_ctx* ctx, int32_t replica, void* v, double* q,

@@ -1107,6 +1107,40 @@ icm_status icm_get_state(icm_ctx* c, int32_t replica, void* v, double* q, double
     return ICM_OK;
 }
 
+icm_status icm_set_fft_shapes(icm_ctx* c, const icm_tune_result* shapes, int32_t count) {
+    if (!c) return fail(nullptr, ICM_E_INVALID, "NULL context");
+    if (count < 0 || (count > 0 && !shapes)) return fail(c, ICM_E_INVALID, "shapes must hold count entries");
+    auto pow2 = [](int v) { return v >= 1 && v <= 64 && (v & (v - 1)) == 0; };
+    for (int e = 0; e < count; ++e) {
+        const icm_tune_result& r = shapes[e];
+        if (!pow2(r.y_columns) || !pow2(r.z_columns) || (r.z_small_plan != 0 && r.z_small_plan != 1) ||
+            !(r.x_threads == 64 || r.x_threads == 128 || r.x_threads == 256 || r.x_threads == 512))
+            return fail(c, ICM_E_INVALID, "entry %d: launch shape out of range", e);
+        bool any = false;
+        for (const Replica& R : c->reps)
+            any = any || (R.p.n[0] == r.n[0] && R.p.n[1] == r.n[1] && R.p.n[2] == r.n[2]);
+        if (!any) return fail(c, ICM_E_INVALID, "entry %d: no replica has grid %d x %d x %d", e, r.n[0], r.n[1], r.n[2]);
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int e = 0; e < count; ++e) {
+        const icm_tune_result& r = shapes[e];
+        for (Replica& R : c->reps) {
+            if (R.p.n[0] != r.n[0] || R.p.n[1] != r.n[1] || R.p.n[2] != r.n[2]) continue;
+            auto apply = [&](auto& g) {
+                g.By = r.y_columns;
+                g.Bz = r.z_columns;
+                g.zsmall = r.z_small_plan;
+                g.xt = r.x_threads;
+            };
+            if (c->precision == ICM_FP64)
+                apply(R.gd);
+            else
+                apply(R.gf);
+        }
+    }
+    return sync_batches(c);
+}
+
 icm_status icm_get_advection_lag(icm_ctx* c, int32_t replica, void* lag, int32_t* valid, uint32_t flags) {
     icm_status st = check_replica(c, replica);
     if (st != ICM_OK) return st;

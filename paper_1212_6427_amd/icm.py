@@ -106,6 +106,8 @@ _lib.icm_set_state.argtypes = [_p, ctypes.c_int32, _p, _p, _p, _p, ctypes.c_int6
 _lib.icm_set_state.restype = ctypes.c_int
 _lib.icm_autotune.argtypes = [_p, ctypes.POINTER(icm_tune_result), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
 _lib.icm_autotune.restype = ctypes.c_int
+_lib.icm_set_fft_shapes.argtypes = [_p, ctypes.POINTER(icm_tune_result), ctypes.c_int32]
+_lib.icm_set_fft_shapes.restype = ctypes.c_int
 _lib.icm_step.argtypes = [_p, ctypes.c_int64, ctypes.c_uint32]
 _lib.icm_step.restype = ctypes.c_int
 _lib.icm_get_state.argtypes = [_p, ctypes.c_int32, _p, _p, _p, _p, ctypes.POINTER(icm_diag), ctypes.c_uint32]
@@ -271,6 +273,19 @@ def icm_set_advection_lag(ctx, replica, lag, field_dtype=np.float64):
     _check(_lib.icm_set_advection_lag(ctx, int(replica), a.ctypes.data_as(ctypes.c_void_p), 0), ctx)
 
 
+def icm_set_fft_shapes(ctx, shapes):
+    """Install FFT launch shapes: a list of dicts with n, y_columns,
+    z_columns, z_small_plan and x_threads (as icm_autotune returns them)."""
+    arr = (icm_tune_result * max(len(shapes), 1))()
+    for i, sh in enumerate(shapes):
+        arr[i].n[:] = [int(x) for x in sh["n"]]
+        arr[i].y_columns = int(sh["y_columns"])
+        arr[i].z_columns = int(sh["z_columns"])
+        arr[i].z_small_plan = int(sh["z_small_plan"])
+        arr[i].x_threads = int(sh["x_threads"])
+    _check(_lib.icm_set_fft_shapes(ctx, arr, len(shapes)), ctx)
+
+
 def icm_set_timing(ctx, enable):
     _check(_lib.icm_set_timing(ctx, 1 if enable else 0), ctx)
 
@@ -315,6 +330,9 @@ class Sim:
 
     def autotune(self):
         return icm_autotune(self.ctx)
+
+    def set_fft_shapes(self, shapes):
+        icm_set_fft_shapes(self.ctx, shapes)
 
     def get_state(self, replica=0, want_v=True, want_diag=True):
         return icm_get_state(self.ctx, replica, tuple(self.params[replica].n), self.dtype, want_v, want_diag)

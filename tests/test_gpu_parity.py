@@ -384,3 +384,52 @@ def test_unwrapped_positions_far_from_the_box(I, kernel):
     shifts = np.array([[3, -5, 11], [-7, 2, -13], [0, 0, 0], [40, -40, 25], [-1, 1, -1]], dtype=np.float64)
     st.q = st.q + shifts * L
     run_parity(I, p, st, 3, I.FP64, TOL64, "unwrapped kernel=%d" % kernel)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_every_fft_launch_shape_keeps_parity(I, precision):
+    """icm_set_fft_shapes installs launch shapes without measuring; every
+    plan and block choice must leave the step's results unchanged (to the
+    parity bar), for two grid shapes in one context."""
+    prec = I.FP64 if precision == "fp64" else I.FP32_GRID
+    tol = TOL64 if precision == "fp64" else TOL32
+    dtype = np.float64 if prec == I.FP64 else np.float32
+    cases = [
+        (oracle_params((64, 64, 64), kernel=4, kT=1e-3, dt=0.25, seed=140, replica=0), (0.0, 1.0), 2),
+        (oracle_params((48, 32, 36), kernel=3, kT=2e-3, dt=0.2, seed=141, replica=1), (0.0,), 2),
+    ]
+    states = [initial_state(p, nb, me, seed=150 + i, min_sep=3.0) for i, (p, me, nb) in enumerate(cases)]
+    if prec == I.FP32_GRID:
+        for st in states:
+            st.v = st.v.astype(np.float32).astype(np.float64)
+    refs = [O.step(p, st) for (p, _, _), st in zip(cases, states)]
+    combos = [(1, 4, 4, 64), (0, 16, 64, 512), (1, 64, 16, 128), (0, 1, 2, 256), (1, 32, 32, 512), (0, 8, 1, 64)]
+    for zs, by, bz, xt in combos:
+        banner("fft shapes %s zsmall=%d By=%d Bz=%d xt=%d" % (precision, zs, by, bz, xt))
+        sim = I.Sim([gpu_params(I, p) for p, _, _ in cases], [nb for _, _, nb in cases], prec)
+        try:
+            for r, st in enumerate(states):
+                load_into_gpu(I, sim, r, st, dtype)
+            sim.set_fft_shapes([dict(n=p.n, y_columns=by, z_columns=bz, z_small_plan=zs, x_threads=xt)
+                                for p, _, _ in cases])
+            sim.step(1, I.STEP_GRAPH)
+            for r, (ref, st) in enumerate(zip(refs, states)):
+                errs, bad = compare(sim.get_state(r), ref, st.q, tol)
+                assert not bad, (zs, by, bz, xt, r, bad)
+        finally:
+            sim.close()
+
+
+def test_set_fft_shapes_rejects_bad_values(I):
+    p = oracle_params((16, 16, 16), kernel=3)
+    sim = I.Sim([gpu_params(I, p)], [1], I.FP64)
+    try:
+        for bad in (dict(n=(16, 16, 16), y_columns=3, z_columns=8, z_small_plan=1, x_threads=256),
+                    dict(n=(16, 16, 16), y_columns=8, z_columns=8, z_small_plan=2, x_threads=256),
+                    dict(n=(16, 16, 16), y_columns=8, z_columns=8, z_small_plan=1, x_threads=1024),
+                    dict(n=(32, 16, 16), y_columns=8, z_columns=8, z_small_plan=1, x_threads=256)):
+            with pytest.raises(I.ICMError) as e:
+                sim.set_fft_shapes([bad])
+            assert e.value.status == I.E_INVALID
+    finally:
+        sim.close()
