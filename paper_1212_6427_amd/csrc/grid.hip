@@ -179,25 +179,27 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
     // An even plane draws A and C of its pair, an odd plane B of the next
     // pair (whose xz, yz enter the odd plane and whose xx, yy wait for the
     // pair's upper plane): three calls per two cells.
-    T vm[3] = {0, 0, 0}, v0[3] = {0, 0, 0}, vp[3] = {0, 0, 0};
+    // vr[s] and hr[s] are a ring of prefetch registers: see the march below
+    T vr[4][3] = {}, hr[2][3] = {};
     T wzz_m = 0, wxz_c = 0, wyz_c = 0;
     T up_xx = 0, up_yy = 0, up_zz = 0, up_xy = 0;  // upper-cell normals of the current pair
     const uint32_t pairs_plane = (uint32_t)plane;  // pair counters per pair of planes
     // v is read one plane ahead of its use (vp for plane k + 1 was loaded
     // during plane k - 1; the halo ring's values likewise), so the loads'
     // latency overlaps a whole plane of work.
-    T hcur[3] = {0, 0, 0};
     if (hvalid) {
         const long long hc = (long long)k0 * plane + (long long)hjw * nx + hiw;
-        for (int a = 0; a < 3; ++a) hcur[a] = gv[a * g.ncell + hc];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) hr[0][a] = gv[a * g.ncell + hc];
     }
     if (own) {
         const int km = wrap(k0 - 1, nz);
         const int k0p = k0 + 1 == nz ? 0 : k0 + 1;
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
-            vm[a] = gv[a * g.ncell + km * plane + col];
-            v0[a] = gv[a * g.ncell + (long long)k0 * plane + col];
-            vp[a] = gv[a * g.ncell + (long long)k0p * plane + col];
+            vr[0][a] = gv[a * g.ncell + km * plane + col];
+            vr[1][a] = gv[a * g.ncell + (long long)k0 * plane + col];
+            vr[2][a] = gv[a * g.ncell + (long long)k0p * plane + col];
         }
         if (noisy) {
             // W_zz of the odd plane k0 - 1 (C of the previous pair); xz, yz of
@@ -281,163 +283,172 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
         }
     }
 
-    for (int k = k0; k < k1; ++k) {
-        const int kp = k + 1 == nz ? 0 : k + 1;
-        T wxx = 0, wyy = 0, wzz = 0, wxy = 0, wxz_n = 0, wyz_n = 0;
-        if (it_ok) {
-            int ic = k - it_z0;
-            if (ic < 0) ic += nz;
-            if (ic < P) {
-                const double wz = ic == 0 ? wz0 : (ic == 1 ? wz1 : (ic == 2 ? wz2 : wz3));
-                const double dz = ic == 0 ? dz0 : (ic == 1 ? dz1 : (ic == 2 ? dz2 : dz3));
-                atomicAdd(&s_acc[it_a][it_y][it_x], (T)(it_f * wz + it_d * dz));
-            }
-        }
-        // further items (tiles met by more than 10 blobs) read their data here
-        for (int it = tid + blockDim.x; it < nloc * 3 * 16; it += blockDim.x) {
-            const int lb = it / 48, rem = it - 48 * lb;
-            const int a = rem >> 4, r = rem & 15;
-            if (r >= P * P) continue;
-            const int b = s_blobs[lb];
-            gptr<const double> o = gstc + ((long long)b * 3 + a) * kStcPerComp;
-            int ic = k - (int)o[2];
-            if (ic < 0) ic += nz;
-            if (ic >= P) continue;
-            const int ia = r % P, ib = r / P;
-            int x = (int)o[0] + ia, y = (int)o[1] + ib;
-            if (x >= nx) x -= nx;
-            if (y >= ny) y -= ny;
-            if (x < i0 || x >= i0 + wx || y < j0 || y >= j0 + wy) continue;
-            const double v = tap_value<T>(rb, o, b, a, ia, ib, ic, inv_h3);
-            atomicAdd(&s_acc[a][y - j0][x - i0], (T)v);
-        }
-        const bool more = k + 1 < k1;
-        T vq[3] = {0, 0, 0}, hq[3] = {0, 0, 0};
-        if (own && more) {
-            const int kq = kp + 1 == nz ? 0 : kp + 1;
-            for (int a = 0; a < 3; ++a) vq[a] = gv[a * g.ncell + (long long)kq * plane + col];
-        }
-        if (hvalid && more) {
-            const long long hn = (long long)kp * plane + (long long)hjw * nx + hiw;
-            for (int a = 0; a < 3; ++a) hq[a] = gv[a * g.ncell + hn];
-        }
-        if (own) {
-            if (noisy) {
-                if ((k & 1) == 0) {
-                    const uint32_t ctr = (uint32_t)(k / 2) * pairs_plane + (uint32_t)col;
-                    const u32x4 wa = noise_words(nk, ctr, 0);
-                    const NormalPair<T> p0 = bm<T>(wa.x, wa.y), p1 = bm<T>(wa.z, wa.w);
-                    wxx = p0.a;
-                    wyy = p0.b;
-                    wzz = p1.a;
-                    wxy = p1.b;
-                    const u32x4 wc = noise_words(nk, ctr, 2);
-                    const NormalPair<T> p2 = bm<T>(wc.x, wc.y), p3 = bm<T>(wc.z, wc.w);
-                    up_zz = p2.a;
-                    up_xy = p2.b;
-                    wxz_n = p3.a;
-                    wyz_n = p3.b;
-                } else {
-                    wxx = up_xx;
-                    wyy = up_yy;
-                    wzz = up_zz;
-                    wxy = up_xy;
-                    const uint32_t ctr = (uint32_t)(kp / 2) * pairs_plane + (uint32_t)col;
-                    const u32x4 wb = noise_words(nk, ctr, 1);
-                    const NormalPair<T> p0 = bm<T>(wb.x, wb.y), p1 = bm<T>(wb.z, wb.w);
-                    wxz_n = p0.a;
-                    wyz_n = p0.b;
-                    up_xx = p1.a;
-                    up_yy = p1.b;
+    // The march is unrolled by four so that the prefetch ring rotates by
+    // renaming, not by register moves: plane k reads vm, v0, vp from three
+    // slots of vr and loads plane k + 2 into the fourth, the halo values
+    // alternate between the two slots of hr. A move would have to wait for
+    // the load just issued; renamed, each load has a whole plane of work to
+    // land. The planes past the chunk's end (uniform over the block) stop.
+    for (int kb = k0; kb < k1; kb += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = kb + u;
+            if (k >= k1) break;
+            T(&vm)[3] = vr[u];
+            T(&v0)[3] = vr[(u + 1) & 3];
+            T(&vp)[3] = vr[(u + 2) & 3];
+            T(&vq)[3] = vr[(u + 3) & 3];
+            T(&hcur)[3] = hr[u & 1];
+            T(&hq)[3] = hr[(u + 1) & 1];
+            const int kp = k + 1 == nz ? 0 : k + 1;
+            T wxx = 0, wyy = 0, wzz = 0, wxy = 0, wxz_n = 0, wyz_n = 0;
+            if (it_ok) {
+                int ic = k - it_z0;
+                if (ic < 0) ic += nz;
+                if (ic < P) {
+                    const double wz = ic == 0 ? wz0 : (ic == 1 ? wz1 : (ic == 2 ? wz2 : wz3));
+                    const double dz = ic == 0 ? dz0 : (ic == 1 ? dz1 : (ic == 2 ? dz2 : dz3));
+                    atomicAdd(&s_acc[it_a][it_y][it_x], (T)(it_f * wz + it_d * dz));
                 }
             }
-            for (int a = 0; a < 3; ++a) sv[a][ty + 1][tx + 1] = v0[a];
-            sxx[ty][tx + 1] = wxx;
-            sxy[ty][tx] = wxy;
-            sxz[ty][tx] = wxz_c;
-            syy[ty + 1][tx] = wyy;
-            syz[ty][tx] = wyz_c;
-        }
-        if (hvalid) {
-            // LDS slot of the halo cell (column/row index within the tile + 1)
-            const int sy = hkind <= 1 ? hj - j0 + 1 : (hkind == 2 ? 0 : wy + 1);
-            const int sx = hkind == 0 ? 0 : (hkind == 1 ? wx + 1 : hi - i0 + 1);
-            for (int a = 0; a < 3; ++a) sv[a][sy][sx] = hcur[a];
-            if (noisy) {
-                // the halo cell's pair counter; which words hold its normals
-                // depends on the parity of k (see the pair layout above)
-                const uint32_t hctr = (uint32_t)(k / 2) * pairs_plane + (uint32_t)((long long)hjw * nx + hiw);
-                const bool odd = (k & 1) != 0;
-                if (hkind == 0 || hkind == 2) {
-                    // xx (left) or yy (bottom): A(0,1) on even planes, B(2,3) on odd
-                    const u32x4 w = noise_words(nk, hctr, odd ? 1 : 0);
-                    const NormalPair<T> pr = odd ? bm<T>(w.z, w.w) : bm<T>(w.x, w.y);
-                    if (hkind == 0)
-                        sxx[hj - j0][0] = pr.a;
-                    else
-                        syy[0][hi - i0] = pr.b;
-                } else {
-                    // right: xy and xz; top: xy and yz. Even planes: xy from
-                    // A(2,3), xz / yz from B(0,1); odd planes: all from C.
-                    T exy, ez;
-                    if (odd) {
-                        const u32x4 w = noise_words(nk, hctr, 2);
-                        exy = bm<T>(w.x, w.y).b;
-                        const NormalPair<T> q = bm<T>(w.z, w.w);
-                        ez = hkind == 1 ? q.a : q.b;
+            // further items (tiles met by more than 10 blobs) read their data here
+            for (int it = tid + blockDim.x; it < nloc * 3 * 16; it += blockDim.x) {
+                const int lb = it / 48, rem = it - 48 * lb;
+                const int a = rem >> 4, r = rem & 15;
+                if (r >= P * P) continue;
+                const int b = s_blobs[lb];
+                gptr<const double> o = gstc + ((long long)b * 3 + a) * kStcPerComp;
+                int ic = k - (int)o[2];
+                if (ic < 0) ic += nz;
+                if (ic >= P) continue;
+                const int ia = r % P, ib = r / P;
+                int x = (int)o[0] + ia, y = (int)o[1] + ib;
+                if (x >= nx) x -= nx;
+                if (y >= ny) y -= ny;
+                if (x < i0 || x >= i0 + wx || y < j0 || y >= j0 + wy) continue;
+                const double v = tap_value<T>(rb, o, b, a, ia, ib, ic, inv_h3);
+                atomicAdd(&s_acc[a][y - j0][x - i0], (T)v);
+            }
+            const bool more = k + 1 < k1;
+            if (own && more) {
+                const int kq = kp + 1 == nz ? 0 : kp + 1;
+                for (int a = 0; a < 3; ++a) vq[a] = gv[a * g.ncell + (long long)kq * plane + col];
+            }
+            if (hvalid && more) {
+                const long long hn = (long long)kp * plane + (long long)hjw * nx + hiw;
+                for (int a = 0; a < 3; ++a) hq[a] = gv[a * g.ncell + hn];
+            }
+            if (own) {
+                if (noisy) {
+                    if ((k & 1) == 0) {
+                        const uint32_t ctr = (uint32_t)(k / 2) * pairs_plane + (uint32_t)col;
+                        const u32x4 wa = noise_words(nk, ctr, 0);
+                        const NormalPair<T> p0 = bm<T>(wa.x, wa.y), p1 = bm<T>(wa.z, wa.w);
+                        wxx = p0.a;
+                        wyy = p0.b;
+                        wzz = p1.a;
+                        wxy = p1.b;
+                        const u32x4 wc = noise_words(nk, ctr, 2);
+                        const NormalPair<T> p2 = bm<T>(wc.x, wc.y), p3 = bm<T>(wc.z, wc.w);
+                        up_zz = p2.a;
+                        up_xy = p2.b;
+                        wxz_n = p3.a;
+                        wyz_n = p3.b;
                     } else {
-                        const u32x4 w = noise_words(nk, hctr, 0);
-                        exy = bm<T>(w.z, w.w).b;
-                        const u32x4 w1 = noise_words(nk, hctr, 1);
-                        const NormalPair<T> q = bm<T>(w1.x, w1.y);
-                        ez = hkind == 1 ? q.a : q.b;
+                        wxx = up_xx;
+                        wyy = up_yy;
+                        wzz = up_zz;
+                        wxy = up_xy;
+                        const uint32_t ctr = (uint32_t)(kp / 2) * pairs_plane + (uint32_t)col;
+                        const u32x4 wb = noise_words(nk, ctr, 1);
+                        const NormalPair<T> p0 = bm<T>(wb.x, wb.y), p1 = bm<T>(wb.z, wb.w);
+                        wxz_n = p0.a;
+                        wyz_n = p0.b;
+                        up_xx = p1.a;
+                        up_yy = p1.b;
                     }
-                    if (hkind == 1) {
-                        sxy[hj - j0][wx] = exy;
-                        sxz[hj - j0][wx] = ez;
+                }
+                for (int a = 0; a < 3; ++a) sv[a][ty + 1][tx + 1] = v0[a];
+                sxx[ty][tx + 1] = wxx;
+                sxy[ty][tx] = wxy;
+                sxz[ty][tx] = wxz_c;
+                syy[ty + 1][tx] = wyy;
+                syz[ty][tx] = wyz_c;
+            }
+            if (hvalid) {
+                // LDS slot of the halo cell (column/row index within the tile + 1)
+                const int sy = hkind <= 1 ? hj - j0 + 1 : (hkind == 2 ? 0 : wy + 1);
+                const int sx = hkind == 0 ? 0 : (hkind == 1 ? wx + 1 : hi - i0 + 1);
+                for (int a = 0; a < 3; ++a) sv[a][sy][sx] = hcur[a];
+                if (noisy) {
+                    // the halo cell's pair counter; which words hold its normals
+                    // depends on the parity of k (see the pair layout above)
+                    const uint32_t hctr = (uint32_t)(k / 2) * pairs_plane + (uint32_t)((long long)hjw * nx + hiw);
+                    const bool odd = (k & 1) != 0;
+                    if (hkind == 0 || hkind == 2) {
+                        // xx (left) or yy (bottom): A(0,1) on even planes, B(2,3) on odd
+                        const u32x4 w = noise_words(nk, hctr, odd ? 1 : 0);
+                        const NormalPair<T> pr = odd ? bm<T>(w.z, w.w) : bm<T>(w.x, w.y);
+                        if (hkind == 0)
+                            sxx[hj - j0][0] = pr.a;
+                        else
+                            syy[0][hi - i0] = pr.b;
                     } else {
-                        sxy[wy][hi - i0] = exy;
-                        syz[wy][hi - i0] = ez;
+                        // right: xy and xz; top: xy and yz. Even planes: xy from
+                        // A(2,3), xz / yz from B(0,1); odd planes: all from C.
+                        T exy, ez;
+                        if (odd) {
+                            const u32x4 w = noise_words(nk, hctr, 2);
+                            exy = bm<T>(w.x, w.y).b;
+                            const NormalPair<T> q = bm<T>(w.z, w.w);
+                            ez = hkind == 1 ? q.a : q.b;
+                        } else {
+                            const u32x4 w = noise_words(nk, hctr, 0);
+                            exy = bm<T>(w.z, w.w).b;
+                            const u32x4 w1 = noise_words(nk, hctr, 1);
+                            const NormalPair<T> q = bm<T>(w1.x, w1.y);
+                            ez = hkind == 1 ? q.a : q.b;
+                        }
+                        if (hkind == 1) {
+                            sxy[hj - j0][wx] = exy;
+                            sxz[hj - j0][wx] = ez;
+                        } else {
+                            sxy[wy][hi - i0] = exy;
+                            syz[wy][hi - i0] = ez;
+                        }
                     }
                 }
             }
-        }
-        __syncthreads();
-        if (own) {
-            T out[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const T lap = sv[a][ty + 1][tx] + sv[a][ty + 1][tx + 2] + sv[a][ty][tx + 1] + sv[a][ty + 2][tx + 1] +
-                              vm[a] + vp[a] - (T)6 * v0[a];
-                out[a] = (T)c.rho_dt * v0[a] + (T)c.half_eta_h2 * lap + (T)c.body[a];
+            __syncthreads();
+            if (own) {
+                T out[3];
+    #pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const T lap = sv[a][ty + 1][tx] + sv[a][ty + 1][tx + 2] + sv[a][ty][tx + 1] + sv[a][ty + 2][tx + 1] +
+                                  vm[a] + vp[a] - (T)6 * v0[a];
+                    out[a] = (T)c.rho_dt * v0[a] + (T)c.half_eta_h2 * lap + (T)c.body[a];
+                }
+                if (noisy) {
+                    const T s = (T)c.noise;
+                    const T dx = (T)2 * (wxx - sxx[ty][tx]) + r2 * (sxy[ty + 1][tx] - wxy) + r2 * (wxz_n - wxz_c);
+                    const T dy = r2 * (sxy[ty][tx + 1] - wxy) + (T)2 * (wyy - syy[ty][tx]) + r2 * (wyz_n - wyz_c);
+                    const T dz = r2 * (sxz[ty][tx + 1] - wxz_c) + r2 * (syz[ty + 1][tx] - wyz_c) + (T)2 * (wzz - wzz_m);
+                    out[0] += s * dx;
+                    out[1] += s * dy;
+                    out[2] += s * dz;
+                }
+                const long long cell = (long long)k * plane + col;
+    #pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    out[a] += s_acc[a][ty][tx];
+                    s_acc[a][ty][tx] = (T)0;
+                    grhs[a * g.ncell + cell] = out[a];
+                }
             }
-            if (noisy) {
-                const T s = (T)c.noise;
-                const T dx = (T)2 * (wxx - sxx[ty][tx]) + r2 * (sxy[ty + 1][tx] - wxy) + r2 * (wxz_n - wxz_c);
-                const T dy = r2 * (sxy[ty][tx + 1] - wxy) + (T)2 * (wyy - syy[ty][tx]) + r2 * (wyz_n - wyz_c);
-                const T dz = r2 * (sxz[ty][tx + 1] - wxz_c) + r2 * (syz[ty + 1][tx] - wyz_c) + (T)2 * (wzz - wzz_m);
-                out[0] += s * dx;
-                out[1] += s * dy;
-                out[2] += s * dz;
-            }
-            const long long cell = (long long)k * plane + col;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                out[a] += s_acc[a][ty][tx];
-                s_acc[a][ty][tx] = (T)0;
-                grhs[a * g.ncell + cell] = out[a];
-            }
-        }
-        __syncthreads();
-        wzz_m = wzz;
-        wxz_c = wxz_n;
-        wyz_c = wyz_n;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            vm[a] = v0[a];
-            v0[a] = vp[a];
-            vp[a] = vq[a];
-            hcur[a] = hq[a];
+            __syncthreads();
+            wzz_m = wzz;
+            wxz_c = wxz_n;
+            wyz_c = wyz_n;
         }
     }
 }
