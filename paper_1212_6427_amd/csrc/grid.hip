@@ -114,13 +114,17 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
                                                         int ntz) {
     __shared__ int s_blobs[kRhsTileCap];   // blobs of this z-chunk meeting the tile
     __shared__ int s_nblobs;
-    __shared__ T s_acc[3][RTY][RTX];       // spread accumulated for the current plane
-    __shared__ T sv[3][RTY + 2][RTX + 2];  // velocity of plane k with halo
-    __shared__ T sxx[RTY][RTX + 1];        // W_xx, column 0 = i0 - 1
-    __shared__ T sxy[RTY + 1][RTX + 1];    // W_xy, row RTY = j0 + TY, column RTX = i0 + TX
-    __shared__ T sxz[RTY][RTX + 1];        // W_xz, column RTX = i0 + TX
-    __shared__ T syy[RTY + 1][RTX];        // W_yy, row 0 = j0 - 1
-    __shared__ T syz[RTY + 1][RTX];        // W_yz, row RTY = j0 + TY
+    // Plane buffers, two of each: plane k uses buffer k - k0 mod 2, so the
+    // next plane's writes never meet this plane's reads and one barrier per
+    // plane suffices (plane k + 2 writes only after every thread has passed
+    // the barrier of plane k + 1, hence finished reading plane k).
+    __shared__ T s_acc2[2][3][RTY][RTX];       // spread accumulated for a plane
+    __shared__ T sv2[2][3][RTY + 2][RTX + 2];  // velocity of a plane with halo
+    __shared__ T sxx2[2][RTY][RTX + 1];        // W_xx, column 0 = i0 - 1
+    __shared__ T sxy2[2][RTY + 1][RTX + 1];    // W_xy, row RTY = j0 + TY, column RTX = i0 + TX
+    __shared__ T sxz2[2][RTY][RTX + 1];        // W_xz, column RTX = i0 + TX
+    __shared__ T syy2[2][RTY + 1][RTX];        // W_yy, row 0 = j0 - 1
+    __shared__ T syz2[2][RTY + 1][RTX];        // W_yz, row RTY = j0 + TY
     const int tx = threadIdx.x % RTX, ty = threadIdx.x / RTX;
     // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs,
     // so give XCD j a contiguous run of tiles (x fastest, then y, then z,
@@ -217,7 +221,7 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
     }
     // blobs of this z-chunk whose stencil meets the tile
     if (tid == 0) s_nblobs = 0;
-    for (int a = 0; a < 3; ++a) s_acc[a][ty][tx] = (T)0;
+    for (int a = 0; a < 3; ++a) s_acc2[0][a][ty][tx] = s_acc2[1][a][ty][tx] = (T)0;
     __syncthreads();
     const int P = rb.kernel;
     if (rb.nb > 0) {
@@ -300,6 +304,13 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
             T(&vq)[3] = vr[(u + 3) & 3];
             T(&hcur)[3] = hr[u & 1];
             T(&hq)[3] = hr[(u + 1) & 1];
+            auto& s_acc = s_acc2[u & 1];
+            auto& sv = sv2[u & 1];
+            auto& sxx = sxx2[u & 1];
+            auto& sxy = sxy2[u & 1];
+            auto& sxz = sxz2[u & 1];
+            auto& syy = syy2[u & 1];
+            auto& syz = syz2[u & 1];
             const int kp = k + 1 == nz ? 0 : k + 1;
             T wxx = 0, wyy = 0, wzz = 0, wxy = 0, wxz_n = 0, wyz_n = 0;
             if (it_ok) {
@@ -422,7 +433,7 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
             __syncthreads();
             if (own) {
                 T out[3];
-    #pragma unroll
+#pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const T lap = sv[a][ty + 1][tx] + sv[a][ty + 1][tx + 2] + sv[a][ty][tx + 1] + sv[a][ty + 2][tx + 1] +
                                   vm[a] + vp[a] - (T)6 * v0[a];
@@ -438,14 +449,13 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
                     out[2] += s * dz;
                 }
                 const long long cell = (long long)k * plane + col;
-    #pragma unroll
+#pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     out[a] += s_acc[a][ty][tx];
                     s_acc[a][ty][tx] = (T)0;
                     grhs[a * g.ncell + cell] = out[a];
                 }
             }
-            __syncthreads();
             wzz_m = wzz;
             wxz_c = wxz_n;
             wyz_c = wyz_n;
