@@ -234,7 +234,35 @@ __device__ __forceinline__ void load_tw(cplx<T>* dst, const cplx<T>* src, int n)
 // Spectrum layout: rows of W = nx/2 + 1 complex values at pitch Wp (a
 // multiple of 128 bytes), rows ordered (c, z, y). The y and z passes work in
 // place on column tiles of B consecutive kx; each access of a wave is a run
-// of B complex values.
+// of B complex values. In the z pass, column tiles cover kx < nx/2 only:
+// the last column (kx = nx/2) would fill one of B columns of a tile of its
+// own and cost a whole tile's transforms, so it goes to tail blocks (grid
+// column ceil((nx/2) / B)), each of which takes that column in B consecutive
+// ky rows. The y pass, bound by memory rather than arithmetic, keeps the
+// partial last tile: its reads of that column stay coalesced there, while
+// tail blocks would read it scattered over B planes (measured slower).
+
+// Column of thread b in the z pass: kx, the ky row it works on, and whether
+// that column exists. Returns false for a tail block with no rows left (the
+// whole block leaves).
+struct PassCol {
+    int kx, row;
+    bool ok;
+};
+__device__ __forceinline__ bool pass_col(int W, int B, int b, int nrow, PassCol& pc) {
+    const int nmain = (W - 1 + B - 1) / B;
+    if ((int)blockIdx.x < nmain) {
+        pc.kx = (int)blockIdx.x * B + b;
+        pc.row = (int)blockIdx.y;
+        pc.ok = pc.kx < W - 1;
+        return true;
+    }
+    if ((int)blockIdx.y * B >= nrow) return false;
+    pc.kx = W - 1;
+    pc.row = (int)blockIdx.y * B + b;
+    pc.ok = pc.row < nrow;
+    return true;
+}
 
 // ------------------------------------------------------------------ y pass
 // Block: B consecutive kx columns of one (z, component) plane of replica
@@ -278,10 +306,10 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
     const GridDesc<T> g = rd[blockIdx.z].g;
     const SolveCoef sc = rd[blockIdx.z].solve[solve];
     const int b = threadIdx.x % B, t = threadIdx.x / B;
-    const int kx0 = blockIdx.x * B;
-    const int kx = kx0 + b;
-    const bool ok = kx < g.W;
-    const int y = blockIdx.y;
+    PassCol pc;
+    if (!pass_col(g.W, B, b, g.ny, pc)) return;
+    const int kx = pc.kx, y = pc.row;
+    const bool ok = pc.ok;
     load_tw(tws, g.twz, N);
     constexpr int TL = N / E;
     // Buffer accesses: one 32-bit per-thread offset (column, first plane); the
@@ -294,9 +322,9 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
     // Loads are issued component by component, so that the transform of
     // component 0 can start while those of components 1 and 2 are still in
     // flight (the load counter retires in order). They are unconditional:
-    // a column past W reads row padding, the next row or (past the buffer's
-    // end) zero, transforms it on its own and is never stored, so no select
-    // has to wait for the loads.
+    // a column that does not exist reads row padding, another row or (past
+    // the buffer's end) zero, transforms it on its own and is never stored,
+    // so no select has to wait for the loads.
     cplx<T> a0[E], a1[E], a2[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) a0[i] = sb.load(vo, (uint32_t)(TL * i) * zb);
@@ -615,7 +643,7 @@ bool z_fast_plan(const Batch<T>& Bt, int solve, bool project, hipStream_t s) {
         constexpr int TL = N / Pl::E;
         int B = g.Bz;
         while (B > 1 && B * TL > 512) B /= 2;
-        const dim3 grid((unsigned)((g.W + B - 1) / B), g.ny, Bt.nrep);
+        const dim3 grid((unsigned)((g.W - 1 + B - 1) / B + 1), g.ny, Bt.nrep);
         const size_t lds = (size_t)N * (B + 1) * sizeof(cplx<T>);
         allow_lds(k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>, lds);
         hipLaunchKernelGGL((k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>), grid, dim3(B * TL), lds, s, Bt.d, B,
