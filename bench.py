@@ -770,6 +770,9 @@ def ensemble_vacf_leg(I, torch, stream, steps, per_shape=4, tune=True):
             if both:
                 c32 = np.mean([vacf(ub[r], lags) for r in both], axis=0)
                 c64 = np.mean([vacf(us[r], lags) for r in both], axis=0)
+                # both lists over the replicas run on both paths (the FP32
+                # list above averages every replica of the class)
+                entry["vacf_fp32_batched_same_replicas"] = [float(x * mt / kT) for x in c32]
                 entry["vacf_fp64_single_same_replicas"] = [float(x * mt / kT) for x in c64]
                 d = float(np.max(np.abs(c32 - c64)) / abs(c64[0]))
                 entry["max_diff_rel_c0"] = d
