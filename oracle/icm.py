@@ -13,6 +13,9 @@ fluid") step by step:
   tensor product of one-dimensional Peskin kernels, S = (dV_f)^-1 J*.
 * Sec. III.A.1, Eq. (JS_invariance): kernel moment conditions; the 3-point
   kernel gives dV = 8 dV_f.
+* Sec. III.A.2: the split (shifted) three-point kernel, the mean of two
+  copies shifted by -s/2 and +s/2 per axis; its dV uses the cell average of
+  sum phi^2, whose sum over nodes depends on the blob position.
 * Sec. III.B.2: Crank-Nicolson viscosity and the stochastic flux
   Sigma^n = (kT eta / (dV_f dt))^(1/2) (W^n + W^n^T).
 * Sec. III.C (Summary of Algorithm), steps 1-9, with the slip-correction
@@ -147,6 +150,64 @@ def sum_phi_sq(kernel):
 
 
 # --------------------------------------------------------------------------
+# Split (shifted) kernels (Sec. III.A.2)
+# --------------------------------------------------------------------------
+def split_phi3(r, sigma):
+    """Split three-point kernel of Sec. III.A.2 along one axis: the mean of
+    phi3 shifted by -sigma/2 and by +sigma/2, sigma = s / h (grid units).
+    The d-dimensional kernel is the product of these over the axes, which
+    is the paper's 2^-d times the product of the shifted sums."""
+    r = np.asarray(r, dtype=np.float64)
+    return 0.5 * (phi3(r - 0.5 * sigma) + phi3(r + 0.5 * sigma))
+
+
+def dsplit_phi3(r, sigma):
+    """Derivative of split_phi3 with respect to its argument."""
+    r = np.asarray(r, dtype=np.float64)
+    return 0.5 * (dphi3(r - 0.5 * sigma) + dphi3(r + 0.5 * sigma))
+
+
+def phi3_autocorrelation(sigma):
+    """A(sigma) = integral over t of phi3(t) phi3(t + sigma), by adaptive
+    quadrature with the kinks of both factors as break points."""
+    from scipy.integrate import quad
+    sigma = float(sigma)
+    lo, hi = max(-1.5, -1.5 - sigma), min(1.5, 1.5 - sigma)
+    if hi <= lo:
+        return 0.0
+    kinks = [-0.5, 0.5, -0.5 - sigma, 0.5 - sigma, -1.5 - sigma, 1.5 - sigma]
+    pts = sorted({b for b in kinks if lo < b < hi})
+    f = lambda t: float(phi3(np.array([t]))[0] * phi3(np.array([t + sigma]))[0])
+    val, _ = quad(f, lo, hi, points=pts or None, epsabs=1e-14, epsrel=1e-13, limit=200)
+    return val
+
+
+def mean_sum_phi_sq(kernel, sigma=0.0):
+    """Sum over nodes of phi^2, averaged over the blob position within a
+    cell. For the Peskin kernels it is the constant of Eq. (JS_invariance).
+    For the split kernel the sum depends on the position; expanding the
+    square of the mean of the two shifted copies, each copy contributes the
+    constant 1/2 and the cross term averages to the autocorrelation of phi3
+    at lag sigma: (1 + 2 A(sigma)) / 4."""
+    if sigma == 0.0:
+        return sum_phi_sq(kernel)
+    return 0.25 * (1.0 + 2.0 * phi3_autocorrelation(sigma))
+
+
+def kernel_of(p):
+    """(phi, dphi, node layout) of the kernel of p: the split three-point
+    kernel runs on the four-node layout floor(x) + {-1, 0, 1, 2}, which holds
+    its support |d| < 3/2 + sigma/2 for sigma <= 1."""
+    sigma = float(p.kernel_shift)
+    if sigma == 0.0:
+        phi, dphi = kernel_fns(p.kernel)
+        return phi, dphi, p.kernel
+    if p.kernel != 3 or not (0.0 < sigma <= 1.0):
+        raise ValueError("the split kernel needs kernel 3 and 0 < s/h <= 1")
+    return (lambda r: split_phi3(r, sigma)), (lambda r: dsplit_phi3(r, sigma)), 4
+
+
+# --------------------------------------------------------------------------
 # Parameters and state
 # --------------------------------------------------------------------------
 @dataclass
@@ -168,6 +229,8 @@ class Params:
     spring_k: float = 0.0           # 0 disables the tether spring
     spring_center: tuple = (0.0, 0.0, 0.0)
     advection: bool = False         # include -D.(rho v v^T) in step 2
+    kernel_shift: float = 0.0       # s / h of the split three-point kernel
+                                    # (Sec. III.A.2); 0: the plain kernel
 
     @property
     def cell_volume(self):
@@ -176,8 +239,9 @@ class Params:
     @property
     def blob_volume(self):
         """dV = (J S 1)^-1 = dV_f / (sum phi^2)^3 (Eq. (dV_JS) with the
-        discrete S of Sec. III.A.1)."""
-        return self.h ** 3 / sum_phi_sq(self.kernel) ** 3
+        discrete S of Sec. III.A.1). With a split kernel, J S 1 depends on
+        the blob position; dV then uses its average over the cell."""
+        return self.h ** 3 / mean_sum_phi_sq(self.kernel, float(self.kernel_shift)) ** 3
 
     @property
     def m_f(self):
@@ -239,12 +303,12 @@ def _component_weights(p, q, alpha, deriv_axis=None):
     o = 0 if beta == alpha else 1/2. If deriv_axis is given, that axis uses
     phi'(d)/h in place of phi(d).
     """
-    phi, dphi = kernel_fns(p.kernel)
+    phi, dphi, layout = kernel_of(p)
     out = []
     for beta in range(3):
         o = 0.0 if beta == alpha else 0.5
         x = q[:, beta] / p.h - o
-        nodes, d = stencil_nodes(p.kernel, x)
+        nodes, d = stencil_nodes(layout, x)
         if deriv_axis == beta:
             w = dphi(d) / p.h
         else:

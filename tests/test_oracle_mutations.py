@@ -142,3 +142,34 @@ def test_advection_without_the_lagged_term(monkeypatch):
         return orig(p, st)
     monkeypatch.setattr(icm, "step", euler)
     assert _fails(pins.test_advection_adams_bashforth_is_second_order)
+
+
+# ------------------------------------------------------------ split kernel
+import tests.test_oracle_split as split_pins
+
+
+def test_split_kernel_both_copies_shifted_one_way(monkeypatch):
+    monkeypatch.setattr(icm, "split_phi3",
+                        lambda r, s: 0.5 * (icm.phi3(np.asarray(r) - 0.5 * s) + icm.phi3(np.asarray(r) - 0.5 * s)))
+    assert _fails(split_pins.test_unity_and_first_moment_at_every_position, 0.5)
+
+
+def test_split_kernel_without_the_half(monkeypatch):
+    monkeypatch.setattr(icm, "split_phi3",
+                        lambda r, s: icm.phi3(np.asarray(r) - 0.5 * s) + icm.phi3(np.asarray(r) + 0.5 * s))
+    assert _fails(split_pins.test_unity_and_first_moment_at_every_position, 0.5)
+
+
+def test_split_blob_volume_without_the_cross_term(monkeypatch):
+    monkeypatch.setattr(icm, "phi3_autocorrelation", lambda s: 0.5)
+    assert _fails(split_pins.test_blob_volume_is_the_position_average, 0.5)
+
+
+def test_split_kernel_on_the_three_node_layout(monkeypatch):
+    orig = icm.kernel_of
+
+    def bad(p):
+        phi, dphi, layout = orig(p)
+        return phi, dphi, 3
+    monkeypatch.setattr(icm, "kernel_of", bad)
+    assert _fails(split_pins.test_interp_of_a_locally_linear_field_is_exact)
