@@ -592,7 +592,7 @@ def jps_leg(I, stream_handle):
     return out
 
 
-def mobility_columns(I, stream_handle, n, kernel, qs, F=1e-8, dt=1e6):
+def mobility_columns(I, stream_handle, n, kernel, qs, F=1e-8, dt=1e6, kernel_shift=0.0):
     """Periodic steady Stokes mobility of one blob per configuration on the
     GPU (FP64): the blob at q pushed by F e_b, the fluid by -F e_b / V (zero
     net force, so no mean flow), one deterministic step from rest. With
@@ -607,7 +607,7 @@ def mobility_columns(I, stream_handle, n, kernel, qs, F=1e-8, dt=1e6):
             body = [0.0, 0.0, 0.0]
             body[b] = -F / vol
             params.append(I.make_params(n, eta=1.0, rho=1.0, kT=0.0, dt=dt, kernel=kernel, body_force=body,
-                                        replica_id=3 * c + b))
+                                        replica_id=3 * c + b, kernel_shift=kernel_shift))
     sim = I.Sim(params, [1] * (3 * nq), I.FP64, stream=stream_handle)
     try:
         for c, q in enumerate(qs):
@@ -647,6 +647,15 @@ def hydrodynamic_radius_leg(I, stream_handle):
             r = np.array([hydrodynamic_radius(np.trace(m) / 3.0, float(N)) for m in mu])
             rows[str(N)] = {"R_H_mean": float(r.mean()), "R_H_min": float(r.min()), "R_H_max": float(r.max())}
         out["kernels"]["%d-point" % kernel] = rows
+    # split three-point kernel (Sec. III.A.2): R_H against the shift s / h
+    rows = {}
+    N = 32
+    for s in (0.0, 0.25, 0.5, 0.75, 1.0):
+        qs = [rng.uniform(0.0, N, 3) for _ in range(16)]
+        mu = mobility_columns(I, stream_handle, (N, N, N), 3, qs, kernel_shift=s)
+        r = np.array([hydrodynamic_radius(np.trace(m) / 3.0, float(N)) for m in mu])
+        rows["%g" % s] = {"R_H_mean": float(r.mean()), "R_H_min": float(r.min()), "R_H_max": float(r.max())}
+    out["split_3pt_vs_shift_32"] = rows
     out["wall_s"] = time.perf_counter() - t0
     return out
 
@@ -963,10 +972,12 @@ def main():
         log("jps: %s" % {k: (round(v["diag_dev_max"], 4), round(v["offdiag_max"], 5))
                          for k, v in out["jps_32"]["kernels"].items()})
     if not args.no_jps:
-        log("hydrodynamic radius against box size and position (both kernels)")
+        log("hydrodynamic radius against box size and position (both kernels, split kernel shifts)")
         out["hydrodynamic_radius"] = hydrodynamic_radius_leg(I, stream.cuda_stream)
         log("R_H: %s" % {k: {n: round(v["R_H_mean"], 4) for n, v in rows.items()}
                          for k, rows in out["hydrodynamic_radius"]["kernels"].items()})
+        log("R_H of the split three-point kernel against s/h (32^3): %s" % {
+            s: round(v["R_H_mean"], 4) for s, v in out["hydrodynamic_radius"]["split_3pt_vs_shift_32"].items()})
     if not args.no_convergence:
         log("temporal convergence study (spring test, FP64)")
         out["convergence"] = convergence_leg(I, stream)

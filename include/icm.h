@@ -115,6 +115,19 @@ typedef struct {
     double wca_sigma;        /* WCA diameter; cutoff 2^(1/6) sigma < N h / 2 */
     double spring_k;         /* tether spring -k (q - c) per blob (0 = off)  */
     double spring_center[3];
+    double kernel_shift;     /* s / h of the split (shifted) three-point
+                                kernel of Sec. III.A.2, whose factor per axis
+                                is the mean of phi3 shifted by -s/2 and +s/2:
+                                a wider blob (larger hydrodynamic radius) on
+                                the same grid. In (0, 1] with kernel 3 (the
+                                support then spans four nodes); 0: the plain
+                                kernel (default); other values, or a nonzero
+                                shift with kernel 4: ICM_E_INVALID. The blob
+                                volume dV = h^3 / <sum phi^2>^3 uses the
+                                average of sum phi^2 over the blob position
+                                within a cell, (1 + 2 A(s/h)) / 4 with A the
+                                autocorrelation of phi3, since for the split
+                                kernel that sum depends on the position     */
 } icm_replica_params;
 
 /* FP64 diagnostics of one replica. */

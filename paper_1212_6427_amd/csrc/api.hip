@@ -121,7 +121,66 @@ bool factor_plan(int n, icm::FFTPlan& pl) {
     return m == 1;
 }
 
-double sum_phi_sq(int kernel) { return kernel == 3 ? 0.5 : 0.375; }
+// Nodes per axis of a replica's stencil: the split three-point kernel
+// (kernel_shift > 0) runs on the four-node layout.
+int stencil_width(const icm_replica_params& p) { return p.kernel == 3 && p.kernel_shift > 0 ? 4 : p.kernel; }
+
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on the
+// Legendre polynomial from the Chebyshev-like first guess
+// cos(pi (i + 3/4) / (n + 1/2)), the recurrence
+// (k + 1) P_{k+1} = (2k + 1) x P_k - k P_{k-1}, and w = 2 / ((1 - x^2) P_n'^2).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 1; k < n; ++k) {
+                const double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Sum over nodes of phi^2 averaged over the blob position in a cell (the
+// constant of Eq. (JS_invariance) for the Peskin kernels). For the split
+// kernel (Sec. III.A.2) the square of the mean of the two shifted copies
+// averages to (1 + 2 A(sigma)) / 4, A(sigma) the integral of
+// phi3(t) phi3(t + sigma) over t, integrated here by 24-point Gauss-Legendre
+// on each interval between the kinks of the two factors (smooth inside).
+double mean_sum_phi_sq(const icm_replica_params& p) {
+    if (stencil_width(p) == p.kernel) return p.kernel == 3 ? 0.5 : 0.375;
+    const double sg = p.kernel_shift;
+    const double lo = std::max(-1.5, -1.5 - sg), hi = std::min(1.5, 1.5 - sg);
+    std::vector<double> cut = {lo, hi};
+    for (double b : {-0.5, 0.5, -0.5 - sg, 0.5 - sg})
+        if (b > lo && b < hi) cut.push_back(b);
+    std::sort(cut.begin(), cut.end());
+    std::vector<double> gx, gw;
+    gauss_legendre(24, gx, gw);
+    double A = 0.0;
+    for (size_t i = 0; i + 1 < cut.size(); ++i) {
+        const double a = cut[i], b = cut[i + 1], m = 0.5 * (a + b), r = 0.5 * (b - a);
+        if (r <= 0) continue;
+        double s = 0.0;
+        for (int k = 0; k < (int)gx.size(); ++k) {
+            const double t = m + r * gx[k];
+            s += gw[k] * icm::phi3(t) * icm::phi3(t + sg);
+        }
+        A += r * s;
+    }
+    return 0.25 * (1.0 + 2.0 * A);
+}
 
 icm_status validate(int32_t n_rep, const icm_replica_params* p, const int32_t* max_blobs, int32_t precision) {
     if (n_rep < 1) return fail(nullptr, ICM_E_INVALID, "n_rep must be >= 1 (got %d)", n_rep);
@@ -139,6 +198,9 @@ icm_status validate(int32_t n_rep, const icm_replica_params* p, const int32_t* m
                             a, n);
         }
         if (q.kernel != 3 && q.kernel != 4) return fail(nullptr, ICM_E_INVALID, "replica %d: kernel must be 3 or 4", r);
+        if (!(q.kernel_shift >= 0 && q.kernel_shift <= 1) || (q.kernel == 4 && q.kernel_shift != 0))
+            return fail(nullptr, ICM_E_INVALID,
+                        "replica %d: kernel_shift must be in [0, 1], and 0 with the four-point kernel", r);
         if (!(q.h > 0) || !(q.rho > 0) || !(q.eta >= 0) || !(q.kT >= 0) || !(q.dt > 0))
             return fail(nullptr, ICM_E_INVALID, "replica %d: need h > 0, rho > 0, eta >= 0, kT >= 0, dt > 0", r);
         if (q.slip < ICM_SLIP_NONE || q.slip > ICM_SLIP_FULL)
@@ -192,6 +254,7 @@ void carve_grid(Carver& cv, const icm_replica_params& p, icm::GridDesc<T>& g) {
     g.Wp = (g.W + align - 1) / align * align;
     g.nspec = (long long)g.nz * g.ny * g.Wp;
     g.h = p.h;
+    g.hs = stencil_width(p) == p.kernel ? 0.0 : 0.5 * p.kernel_shift;
     g.v = cv.take<T>(3 * g.ncell);
     g.rhs = cv.take<T>(3 * g.ncell);
     g.aux = cv.take<T>(3 * g.ncell);
@@ -429,7 +492,7 @@ icm::RepDesc<T> build_desc(const Replica& R) {
     const icm::BlobBufs& b = R.bb;
     const int nchunks = (g.nz + icm::kRhsZChunk - 1) / icm::kRhsZChunk;
     d.rb.nb = R.nb;
-    d.rb.kernel = p.kernel;
+    d.rb.kernel = stencil_width(p);
     d.rb.cap = R.max_nb;
     d.rb.stc = b.stc;
     d.rb.F = b.F;
@@ -469,13 +532,13 @@ icm_status sync_batches_t(icm_ctx* c) {
         const Replica& R = c->reps[r];
         BatchInfo* hit = nullptr;
         for (BatchInfo& B : c->batches)
-            if (B.n[0] == R.p.n[0] && B.n[1] == R.p.n[1] && B.n[2] == R.p.n[2] && B.kernel == R.p.kernel &&
+            if (B.n[0] == R.p.n[0] && B.n[1] == R.p.n[1] && B.n[2] == R.p.n[2] && B.kernel == stencil_width(R.p) &&
                 B.any_me == R.any_me && B.adv == (R.p.advection != 0))
                 hit = &B;
         if (!hit) {
             BatchInfo B{};
             for (int a = 0; a < 3; ++a) B.n[a] = R.p.n[a];
-            B.kernel = R.p.kernel;
+            B.kernel = stencil_width(R.p);
             B.any_me = R.any_me;
             B.adv = R.p.advection != 0;
             c->batches.push_back(B);
@@ -518,7 +581,7 @@ icm::Batch<T> batch_view(icm_ctx* c, int first, int count, const Replica& R0, in
     B.d = static_cast<const icm::RepDesc<T>*>(c->d_desc) + first;
     B.nrep = count;
     B.g = grid_of<T>(const_cast<Replica&>(R0));
-    B.kernel = R0.p.kernel;
+    B.kernel = stencil_width(R0.p);
     B.max_nb = max_nb;
     B.any_cells = cells;
     B.any_all_pairs = all_pairs;
@@ -864,7 +927,7 @@ icm_status icm_create(int32_t n_rep, const icm_replica_params* p, const int32_t*
         R.max_nb = max_blobs[r];
         R.nb = 0;
         R.step = 0;
-        R.m_f = p[r].rho * std::pow(p[r].h, 3) / std::pow(sum_phi_sq(p[r].kernel), 3);
+        R.m_f = p[r].rho * std::pow(p[r].h, 3) / std::pow(mean_sum_phi_sq(p[r]), 3);
         R.mt_f = 1.5 * R.m_f;
         st = (precision == ICM_FP64) ? upload_tables(c, R.gd) : upload_tables(c, R.gf);
         if (st != ICM_OK) {

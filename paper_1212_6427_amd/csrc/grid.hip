@@ -598,11 +598,11 @@ __global__ void __launch_bounds__(kThreads) k_spread(const RepDesc<T>* __restric
     const double inv_h = 1.0 / g.h;
     const double val = F[3 * b + a] * (coef ? coef[b] : 1.0) * inv_h * inv_h * inv_h;
     AxisStencil<P> sx;
-    axis_stencil<P>(q[3 * b + 0] * inv_h - comp_offset(0, a), g.nx, false, inv_h, sx);
+    axis_stencil<P>(q[3 * b + 0] * inv_h - comp_offset(0, a), g.nx, false, inv_h, g.hs, sx);
     int ny_, nz_;
     double wy, wz;
-    axis_tap<P>(q[3 * b + 1] * inv_h - comp_offset(1, a), g.ny, cy, false, inv_h, ny_, wy);
-    axis_tap<P>(q[3 * b + 2] * inv_h - comp_offset(2, a), g.nz, cz, false, inv_h, nz_, wz);
+    axis_tap<P>(q[3 * b + 1] * inv_h - comp_offset(1, a), g.ny, cy, false, inv_h, g.hs, ny_, wy);
+    axis_tap<P>(q[3 * b + 2] * inv_h - comp_offset(2, a), g.nz, cz, false, inv_h, g.hs, nz_, wz);
     T* f = field + a * g.ncell + ((long long)nz_ * g.ny + ny_) * g.nx;
     const double wzy = wz * wy * val;
 #pragma unroll
@@ -620,11 +620,11 @@ __device__ __forceinline__ double gather_group(const GridDesc<T>& g, const T* __
         const int cz = r / P, cy = r - P * (r / P);
         const double inv_h = 1.0 / g.h;
         AxisStencil<P> sx;
-        axis_stencil<P>(q3[0] * inv_h - comp_offset(0, a), g.nx, false, inv_h, sx);
+        axis_stencil<P>(q3[0] * inv_h - comp_offset(0, a), g.nx, false, inv_h, g.hs, sx);
         int j, k;
         double wy, wz;
-        axis_tap<P>(q3[1] * inv_h - comp_offset(1, a), g.ny, cy, false, inv_h, j, wy);
-        axis_tap<P>(q3[2] * inv_h - comp_offset(2, a), g.nz, cz, false, inv_h, k, wz);
+        axis_tap<P>(q3[1] * inv_h - comp_offset(1, a), g.ny, cy, false, inv_h, g.hs, j, wy);
+        axis_tap<P>(q3[2] * inv_h - comp_offset(2, a), g.nz, cz, false, inv_h, g.hs, k, wz);
         const T* f = field + a * g.ncell + ((long long)k * g.ny + j) * g.nx;
         double s = 0.0;
 #pragma unroll
@@ -710,8 +710,8 @@ __global__ void __launch_bounds__(kThreads) k_gather_bins(const RepDesc<T>* __re
         o[ax] = (double)wrap_node(base, n[ax]);
         for (int tt = 0; tt < 4; ++tt) {
             const double d = x - (double)(base + tt);
-            o[3 + 4 * ax + tt] = (tt < P) ? ((P == 3) ? phi3(d) : phi4(d)) : 0.0;
-            if (ax == a) o[15 + tt] = (tt < P) ? ((P == 3) ? dphi3(d) : dphi4(d)) * inv_h : 0.0;
+            o[3 + 4 * ax + tt] = (tt < P) ? kern_w<P>(d, g.hs) : 0.0;
+            if (ax == a) o[15 + tt] = (tt < P) ? kern_dw<P>(d, g.hs) * inv_h : 0.0;
         }
     }
 }
@@ -810,11 +810,11 @@ __global__ void __launch_bounds__(kThreads) k_gather(const RepDesc<T>* __restric
         const int cz = r / P, cy = r - P * (r / P);
         const double inv_h = 1.0 / g.h;
         AxisStencil<P> sx;
-        axis_stencil<P>(q[3 * b + 0] * inv_h - comp_offset(0, a), g.nx, false, inv_h, sx);
+        axis_stencil<P>(q[3 * b + 0] * inv_h - comp_offset(0, a), g.nx, false, inv_h, g.hs, sx);
         int j, k;
         double wy, wz;
-        axis_tap<P>(q[3 * b + 1] * inv_h - comp_offset(1, a), g.ny, cy, false, inv_h, j, wy);
-        axis_tap<P>(q[3 * b + 2] * inv_h - comp_offset(2, a), g.nz, cz, false, inv_h, k, wz);
+        axis_tap<P>(q[3 * b + 1] * inv_h - comp_offset(1, a), g.ny, cy, false, inv_h, g.hs, j, wy);
+        axis_tap<P>(q[3 * b + 2] * inv_h - comp_offset(2, a), g.nz, cz, false, inv_h, g.hs, k, wz);
         const T* f = field + a * g.ncell;
         const int nx = g.nx, ny = g.ny, nz = g.nz;
         const long long row = ((long long)k * ny + j) * nx;

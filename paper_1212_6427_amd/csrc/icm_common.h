@@ -114,7 +114,7 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z0, 
 // Three-point kernel: minimal support with sum phi = 1, zero first moment and
 // sum phi^2 = 1/2 (Sec. III.A.1); four-point kernel of Peskin (2002): support 4
 // with the even/odd sums 1/2, zero first moment and sum phi^2 = 3/8.
-__device__ __forceinline__ double phi3(double r) {
+__host__ __device__ __forceinline__ double phi3(double r) {
     const double s = fabs(r);
     if (s <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * s * s)) / 3.0;
     if (s <= 1.5) {
@@ -173,8 +173,24 @@ __device__ __forceinline__ int wrap_node(int node, int n) {
     return node < 0 ? node + n : (node >= n ? node - n : node);
 }
 
+// Weight (and derivative) of the node at offset d for the P-node layout.
+// P = 4 with hs > 0 is the split three-point kernel of Sec. III.A.2: the
+// mean of phi3 shifted by -hs and +hs (hs = s / (2h)); its support
+// |d| < 3/2 + hs lies inside the four nodes for s <= h.
 template <int P>
-__device__ __forceinline__ void axis_stencil(double x, int n, bool deriv, double inv_h, AxisStencil<P>& st) {
+__device__ __forceinline__ double kern_w(double d, double hs) {
+    if (P == 3) return phi3(d);
+    return hs > 0.0 ? 0.5 * (phi3(d - hs) + phi3(d + hs)) : phi4(d);
+}
+template <int P>
+__device__ __forceinline__ double kern_dw(double d, double hs) {
+    if (P == 3) return dphi3(d);
+    return hs > 0.0 ? 0.5 * (dphi3(d - hs) + dphi3(d + hs)) : dphi4(d);
+}
+
+template <int P>
+__device__ __forceinline__ void axis_stencil(double x, int n, bool deriv, double inv_h, double hs,
+                                             AxisStencil<P>& st) {
     x = fold_coord(x, n);
     const int mi = (int)((P == 3) ? floor(x + 0.5) : floor(x));
 #pragma unroll
@@ -182,25 +198,20 @@ __device__ __forceinline__ void axis_stencil(double x, int n, bool deriv, double
         const int node = mi - 1 + a;
         const double d = x - (double)node;
         st.node[a] = wrap_node(node, n);
-        if (P == 3)
-            st.w[a] = deriv ? dphi3(d) * inv_h : phi3(d);
-        else
-            st.w[a] = deriv ? dphi4(d) * inv_h : phi4(d);
+        st.w[a] = deriv ? kern_dw<P>(d, hs) * inv_h : kern_w<P>(d, hs);
     }
 }
 
 // Node and weight of tap a (0 <= a < P) of one axis, without arrays (so a
 // runtime tap index stays in registers).
 template <int P>
-__device__ __forceinline__ void axis_tap(double x, int n, int a, bool deriv, double inv_h, int& node, double& w) {
+__device__ __forceinline__ void axis_tap(double x, int n, int a, bool deriv, double inv_h, double hs, int& node,
+                                         double& w) {
     x = fold_coord(x, n);
     const int nd = (int)((P == 3) ? floor(x + 0.5) : floor(x)) - 1 + a;
     const double d = x - (double)nd;
     node = wrap_node(nd, n);
-    if (P == 3)
-        w = deriv ? dphi3(d) * inv_h : phi3(d);
-    else
-        w = deriv ? dphi4(d) * inv_h : phi4(d);
+    w = deriv ? kern_dw<P>(d, hs) * inv_h : kern_w<P>(d, hs);
 }
 
 __host__ __device__ __forceinline__ int wrap(int i, int n) {

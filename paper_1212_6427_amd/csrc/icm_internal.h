@@ -33,6 +33,8 @@ struct GridDesc {
     long long ncell;   // nx * ny * nz
     long long nspec;   // nz * ny * Wp
     double h;
+    double hs;         // half shift s / (2h) of the split three-point kernel
+                       // (four-node layout); 0: the plain kernel
     T* v;              // fluid velocity v^n / v^{n+1}
     T* rhs;            // right-hand side / spread scratch field
     T* aux;            // inertial-correction field (dv~, dv)

@@ -59,6 +59,7 @@ class icm_replica_params(ctypes.Structure):
         ("wca_sigma", ctypes.c_double),
         ("spring_k", ctypes.c_double),
         ("spring_center", ctypes.c_double * 3),
+        ("kernel_shift", ctypes.c_double),
     ]
 
 
@@ -141,7 +142,7 @@ def _check(status, ctx=None):
 
 def make_params(n, h=1.0, rho=1.0, eta=1.0, kT=0.0, dt=0.1, kernel=3, slip=SLIP_VISCOUS, thermal_drift=True,
                 seed=0, replica_id=0, body_force=(0.0, 0.0, 0.0), wca_eps=0.0, wca_sigma=0.0, spring_k=0.0,
-                spring_center=(0.0, 0.0, 0.0), advection=False):
+                spring_center=(0.0, 0.0, 0.0), advection=False, kernel_shift=0.0):
     p = icm_replica_params()
     p.n[:] = [int(x) for x in n]
     p.kernel = int(kernel)
@@ -155,6 +156,7 @@ def make_params(n, h=1.0, rho=1.0, eta=1.0, kT=0.0, dt=0.1, kernel=3, slip=SLIP_
     p.wca_eps, p.wca_sigma = float(wca_eps), float(wca_sigma)
     p.spring_k = float(spring_k)
     p.spring_center[:] = [float(x) for x in spring_center]
+    p.kernel_shift = float(kernel_shift)
     return p
 
 

@@ -16,17 +16,19 @@ def banner(msg):
 
 def oracle_params(n, kernel=4, kT=0.0, dt=0.2, slip=O.SLIP_VISCOUS, drift=True, seed=7, replica=0, h=1.0, rho=1.0,
                   eta=1.0, body=(0.0, 0.0, 0.0), wca_eps=0.0, wca_sigma=0.0, spring_k=0.0, spring_c=(0.0, 0.0, 0.0),
-                  advection=False):
+                  advection=False, kernel_shift=0.0):
     return O.Params(n=tuple(n), h=h, rho=rho, eta=eta, kT=kT, dt=dt, kernel=kernel, slip=slip, thermal_drift=drift,
                     seed=seed, replica=replica, body_force=tuple(body), wca_eps=wca_eps, wca_sigma=wca_sigma,
-                    spring_k=spring_k, spring_center=tuple(spring_c), advection=advection)
+                    spring_k=spring_k, spring_center=tuple(spring_c), advection=advection,
+                    kernel_shift=kernel_shift)
 
 
 def gpu_params(I, p):
     return I.make_params(p.n, h=p.h, rho=p.rho, eta=p.eta, kT=p.kT, dt=p.dt, kernel=p.kernel, slip=p.slip,
                          thermal_drift=p.thermal_drift, seed=p.seed, replica_id=p.replica,
                          body_force=p.body_force, wca_eps=p.wca_eps, wca_sigma=p.wca_sigma,
-                         spring_k=p.spring_k, spring_center=p.spring_center, advection=p.advection)
+                         spring_k=p.spring_k, spring_center=p.spring_center, advection=p.advection,
+                         kernel_shift=p.kernel_shift)
 
 
 def initial_state(p, nb, me_ratios=(0.0,), seed=0, min_sep=3.0, force_scale=0.01, velocity_field_scale=None):

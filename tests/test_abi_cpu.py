@@ -26,9 +26,37 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(I.icm_replica_params) == 152
+    assert ctypes.sizeof(I.icm_replica_params) == 160
     assert ctypes.sizeof(I.icm_diag) == 56
     assert ctypes.sizeof(I.icm_tune_result) == 48
+
+
+def test_struct_offsets_match_the_c_compiler(tmp_path):
+    """Every field of the ctypes mirrors sits at the offset gcc gives the
+    header's struct (and the sizes agree)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not found")
+    structs = [I.icm_replica_params, I.icm_diag, I.icm_tune_result]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "icm.h"', "int main(void) {"]
+    for st in structs:
+        name = st.__name__
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
+        for fname, _ in st._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, fname, name, fname))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                    text=True).stdout.splitlines())
+    for st in structs:
+        name = st.__name__
+        assert int(got[name]) == ctypes.sizeof(st), name
+        for fname, _ in st._fields_:
+            assert int(got["%s.%s" % (name, fname)]) == getattr(st, fname).offset, (name, fname)
 
 
 @pytest.mark.parametrize("n,ok", [((32, 32, 32), True), ((48, 36, 24), True), ((6, 12, 18), True),
@@ -52,6 +80,21 @@ def test_parameter_validation(field, val):
     with pytest.raises(I.ICMError) as e:
         I.icm_workspace_bytes([p], [1], I.FP64)
     assert e.value.status == I.E_INVALID
+
+
+@pytest.mark.parametrize("kernel,shift,ok", [(3, 0.0, True), (3, 0.5, True), (3, 1.0, True), (4, 0.0, True),
+                                              (4, 0.5, False), (3, 1.5, False), (3, -0.1, False),
+                                              (3, float("nan"), False)])
+def test_kernel_shift_validation(kernel, shift, ok):
+    """The split kernel (Sec. III.A.2) is the three-point kernel's, for
+    shifts up to one grid spacing."""
+    p = I.make_params((16, 16, 16), kernel=kernel, kernel_shift=shift)
+    if ok:
+        assert I.icm_workspace_bytes([p], [2], I.FP64) > 0
+    else:
+        with pytest.raises(I.ICMError) as e:
+            I.icm_workspace_bytes([p], [2], I.FP64)
+        assert e.value.status == I.E_INVALID
 
 
 def test_wca_cutoff_must_fit_half_box():
