@@ -250,8 +250,11 @@ void carve_grid(Carver& cv, const icm_replica_params& p, icm::GridDesc<T>& g) {
     g.xt = 256;
     g.zsmall = 1;
     g.ncell = (long long)g.nx * g.ny * g.nz;
+    // rows of the fast path hold kx < nx/2 (the Nyquist column has an array
+    // of its own), so that at nx = 256 they carry no padding
     const int align = 128 / (int)sizeof(cplx<T>);
-    g.Wp = (g.W + align - 1) / align * align;
+    const int cols = g.fast ? g.nx / 2 : g.W;
+    g.Wp = (cols + align - 1) / align * align;
     g.nspec = (long long)g.nz * g.ny * g.Wp;
     g.h = p.h;
     g.hs = stencil_width(p) == p.kernel ? 0.0 : 0.5 * p.kernel_shift;
@@ -259,6 +262,7 @@ void carve_grid(Carver& cv, const icm_replica_params& p, icm::GridDesc<T>& g) {
     g.rhs = cv.take<T>(3 * g.ncell);
     g.aux = cv.take<T>(3 * g.ncell);
     g.spec = cv.take<cplx<T>>(3 * g.nspec);
+    g.nyq = g.fast ? cv.take<cplx<T>>(3 * (long long)g.nz * g.ny) : nullptr;
     g.adv = p.advection ? cv.take<T>(3 * g.ncell) : nullptr;
     g.adv_hist = p.advection ? cv.take<unsigned int>(1) : nullptr;
     factor_plan(g.nx, g.px);

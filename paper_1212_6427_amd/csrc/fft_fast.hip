@@ -192,10 +192,8 @@ constexpr int xline() { return N + N / 16 + 1; }
 template <typename T>
 struct SpecBuf {
     __amdgpu_buffer_rsrc_t r;
-    __device__ explicit SpecBuf(const GridDesc<T>& g)
-        : r(__builtin_amdgcn_make_buffer_rsrc(g.spec, (short)0,
-                                              (int)(uint32_t)(3ull * (unsigned long long)g.nspec * sizeof(cplx<T>)),
-                                              0x00020000)) {}
+    __device__ SpecBuf(cplx<T>* base, unsigned long long bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)(uint32_t)bytes, 0x00020000)) {}
     __device__ cplx<T> load(uint32_t vo, uint32_t so) const {
         if constexpr (sizeof(T) == 4)
             return __builtin_bit_cast(cplx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
@@ -231,38 +229,14 @@ __device__ __forceinline__ void load_tw(cplx<T>* dst, const cplx<T>* src, int n)
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = gs[i];
 }
 
-// Spectrum layout: rows of W = nx/2 + 1 complex values at pitch Wp (a
-// multiple of 128 bytes), rows ordered (c, z, y). The y and z passes work in
-// place on column tiles of B consecutive kx; each access of a wave is a run
-// of B complex values. In the z pass, column tiles cover kx < nx/2 only:
-// the last column (kx = nx/2) would fill one of B columns of a tile of its
-// own and cost a whole tile's transforms, so it goes to tail blocks (grid
-// column ceil((nx/2) / B)), each of which takes that column in B consecutive
-// ky rows. The y pass, bound by memory rather than arithmetic, keeps the
-// partial last tile: its reads of that column stay coalesced there, while
-// tail blocks would read it scattered over B planes (measured slower).
-
-// Column of thread b in the z pass: kx, the ky row it works on, and whether
-// that column exists. Returns false for a tail block with no rows left (the
-// whole block leaves).
-struct PassCol {
-    int kx, row;
-    bool ok;
-};
-__device__ __forceinline__ bool pass_col(int W, int B, int b, int nrow, PassCol& pc) {
-    const int nmain = (W - 1 + B - 1) / B;
-    if ((int)blockIdx.x < nmain) {
-        pc.kx = (int)blockIdx.x * B + b;
-        pc.row = (int)blockIdx.y;
-        pc.ok = pc.kx < W - 1;
-        return true;
-    }
-    if ((int)blockIdx.y * B >= nrow) return false;
-    pc.kx = W - 1;
-    pc.row = (int)blockIdx.y * B + b;
-    pc.ok = pc.row < nrow;
-    return true;
-}
+// Spectrum layout of the fast passes: rows of the nx/2 modes kx < nx/2 at
+// pitch Wp (a multiple of 128 bytes), rows ordered (c, z, y); the Nyquist
+// column kx = nx/2 in its own array nyq, ordered (c, z, y). At nx = 256 the
+// rows then carry no padding, and the y and z passes work on full column
+// tiles of B consecutive kx (each access of a wave a run of B complex
+// values); tail blocks (grid column ceil((nx/2) / B)) transform the Nyquist
+// column of B planes (y pass) or B ky rows (z pass) from the contiguous
+// nyq array.
 
 // ------------------------------------------------------------------ y pass
 // Block: B consecutive kx columns of one (z, component) plane of replica
@@ -273,21 +247,41 @@ __global__ void __launch_bounds__(512) k_y_fast(const RepDesc<T>* __restrict__ r
     cplx<T>* tws = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* lds = tws + N;
     const GridDesc<T> g = rd[blockIdx.z / 3].g;
-    const int b = threadIdx.x % B, t = threadIdx.x / B;
-    const int kx0 = blockIdx.x * B;
-    const bool ok = kx0 + b < g.W;
-    const int comp = (int)(blockIdx.z % 3);
-    const gptr<cplx<T>> base = as_global(g.spec) + (long long)comp * g.nspec + (long long)blockIdx.y * N * g.Wp + kx0 + b;
-    load_tw(tws, g.twy, N);
     constexpr int TL = N / E;
+    const int H = g.nx / 2;
+    const int comp = (int)(blockIdx.z % 3);
+    int b, t;
+    bool ok;
+    gptr<cplx<T>> base;
+    long long stride;
+    if ((int)blockIdx.x < (H + B - 1) / B) {
+        // B consecutive kx < nx/2 of plane z = blockIdx.y
+        b = threadIdx.x % B;
+        t = threadIdx.x / B;
+        const int kx = blockIdx.x * B + b;
+        ok = kx < H;
+        base = as_global(g.spec) + (long long)comp * g.nspec + (long long)blockIdx.y * N * g.Wp + kx;
+        stride = g.Wp;
+    } else {
+        // tail: the Nyquist column of planes blockIdx.y B + b, contiguous
+        // along y in nyq, so consecutive lanes take consecutive y
+        if ((int)blockIdx.y * B >= g.nz) return;
+        b = threadIdx.x / TL;
+        t = threadIdx.x % TL;
+        const int z = blockIdx.y * B + b;
+        ok = z < g.nz;
+        base = as_global(g.nyq) + ((long long)comp * g.nz + z) * N;
+        stride = 1;
+    }
+    load_tw(tws, g.twy, N);
     cplx<T> a[E];
 #pragma unroll
-    for (int i = 0; i < E; ++i) a[i] = ok ? base[(long long)(t + TL * i) * g.Wp] : cplx<T>{0, 0};
+    for (int i = 0; i < E; ++i) a[i] = ok ? base[(long long)(t + TL * i) * stride] : cplx<T>{0, 0};
     __syncthreads();
     reg_fft<T, N, E, R0, R1, R2, DIR>(a, t, lds, B, b, tws);
     if (ok) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) base[(long long)(t + TL * i) * g.Wp] = a[i];
+        for (int i = 0; i < E; ++i) base[(long long)(t + TL * i) * stride] = a[i];
     }
 }
 
@@ -306,19 +300,26 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
     const GridDesc<T> g = rd[blockIdx.z].g;
     const SolveCoef sc = rd[blockIdx.z].solve[solve];
     const int b = threadIdx.x % B, t = threadIdx.x / B;
-    PassCol pc;
-    if (!pass_col(g.W, B, b, g.ny, pc)) return;
-    const int kx = pc.kx, y = pc.row;
-    const bool ok = pc.ok;
+    const int H = g.nx / 2;
+    const bool tail = (int)blockIdx.x >= (H + B - 1) / B;
+    if (tail && (int)blockIdx.y * B >= g.ny) return;
+    // main blocks: B consecutive kx < nx/2 of ky row blockIdx.y; tail
+    // blocks: the Nyquist column of ky rows blockIdx.y B + b (nyq array)
+    const int kx = tail ? H : (int)blockIdx.x * B + b;
+    const int y = tail ? (int)blockIdx.y * B + b : (int)blockIdx.y;
+    const bool ok = tail ? y < g.ny : kx < H;
     load_tw(tws, g.twz, N);
     constexpr int TL = N / E;
     // Buffer accesses: one 32-bit per-thread offset (column, first plane); the
     // plane and component offsets are uniform and go in the scalar offset, so
     // the 3E loads and stores need no per-access address registers.
-    const SpecBuf<T> sb(g);
-    const uint32_t zb = (uint32_t)(g.ny * g.Wp) * (uint32_t)sizeof(cplx<T>);  // bytes between z planes
-    const uint32_t cb = (uint32_t)g.nspec * (uint32_t)sizeof(cplx<T>);       // bytes between components
-    const uint32_t vo = ((uint32_t)t * (uint32_t)(g.ny * g.Wp) + (uint32_t)(y * g.Wp + kx)) * (uint32_t)sizeof(cplx<T>);
+    constexpr uint32_t cs = (uint32_t)sizeof(cplx<T>);
+    const unsigned long long ncol = (unsigned long long)g.nz * g.ny;  // Nyquist values per component
+    const SpecBuf<T> sb(tail ? g.nyq : g.spec, 3ull * (tail ? ncol : (unsigned long long)g.nspec) * cs);
+    const uint32_t zb = (uint32_t)(tail ? g.ny : g.ny * g.Wp) * cs;       // bytes between z planes
+    const uint32_t cb = (uint32_t)(tail ? ncol : (unsigned long long)g.nspec) * cs;  // between components
+    const uint32_t vo = tail ? ((uint32_t)t * (uint32_t)g.ny + (uint32_t)y) * cs
+                             : ((uint32_t)t * (uint32_t)(g.ny * g.Wp) + (uint32_t)(y * g.Wp + kx)) * cs;
     // Loads are issued component by component, so that the transform of
     // component 0 can start while those of components 1 and 2 are still in
     // flight (the load counter retires in order). They are unconditional:
@@ -404,7 +405,7 @@ __global__ void __launch_bounds__(512) k_xfwd_fast(const RepDesc<T>* __restrict_
     const int c = (int)(blockIdx.y % 3);
     constexpr int TL = N / E;
     const int t = threadIdx.x % TL, l = threadIdx.x / TL;
-    const int W = g.W;
+    constexpr int H = N / 2;
     const long long npairs = (long long)g.ny * g.nz / 2;
     const long long p = (long long)blockIdx.x * P + l;
     const bool ok = p < npairs;
@@ -438,26 +439,29 @@ __global__ void __launch_bounds__(512) k_xfwd_fast(const RepDesc<T>* __restrict_
     __syncthreads();
     if (!ok) return;
     const gptr<cplx<T>> d0 = as_global(g.spec) + (long long)c * g.nspec + 2 * p * g.Wp;
-    // two consecutive modes per thread (16-byte stores for FP32); W is odd,
-    // so the last pair holds the Nyquist mode alone
-    for (int k = 2 * t; k < W; k += 2 * TL) {
+    // modes kx < N/2, two consecutive per thread (16-byte stores for FP32;
+    // N/2 is even); the Nyquist mode kx = N/2 of both rows goes to nyq
+    for (int k = 2 * t; k < H; k += 2 * TL) {
         CPair<T> ea, eb;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const int kk = k + q < W ? k + q : k;
+            const int kk = k + q;
             const cplx<T> zk = lds[l * LS + skew<4>(kk)];
             const cplx<T> zc = cconj(lds[l * LS + skew<4>((N - kk) % N)]);
             const cplx<T> s = cadd(zk, zc), d = csub(zk, zc);
             ea.v[q] = {(T)0.5 * s.x, (T)0.5 * s.y};
             eb.v[q] = {(T)0.5 * d.y, (T)-0.5 * d.x};
         }
-        if (k + 1 < W) {
-            *(gptr<CPair<T>>)(d0 + k) = ea;
-            *(gptr<CPair<T>>)(d0 + g.Wp + k) = eb;
-        } else {
-            d0[k] = ea.v[0];
-            d0[g.Wp + k] = eb.v[0];
-        }
+        *(gptr<CPair<T>>)(d0 + k) = ea;
+        *(gptr<CPair<T>>)(d0 + g.Wp + k) = eb;
+    }
+    if (t == 0) {
+        const cplx<T> zk = lds[l * LS + skew<4>(H)];
+        const cplx<T> zc = cconj(zk);
+        const cplx<T> s = cadd(zk, zc), d = csub(zk, zc);
+        const gptr<cplx<T>> nq = as_global(g.nyq) + (long long)c * g.nz * g.ny + 2 * p;
+        nq[0] = cplx<T>{(T)0.5 * s.x, (T)0.5 * s.y};
+        nq[1] = cplx<T>{(T)0.5 * d.y, (T)-0.5 * d.x};
     }
 }
 
@@ -473,7 +477,6 @@ __global__ void __launch_bounds__(512) k_xinv_fast(const RepDesc<T>* __restrict_
     constexpr int TL = N / E;
     constexpr int H = N / 2;
     const int t = threadIdx.x % TL, l = threadIdx.x / TL;
-    const int W = g.W;
     const long long npairs = (long long)g.ny * g.nz / 2;
     const long long p = (long long)blockIdx.x * P + l;
     const bool ok = p < npairs;
@@ -481,30 +484,34 @@ __global__ void __launch_bounds__(512) k_xinv_fast(const RepDesc<T>* __restrict_
     const long long rp = g.Wp;
     const gptr<const cplx<T>> s0 = as_global((const cplx<T>*)g.spec) + (long long)c * g.nspec + 2 * p * rp;
     constexpr int LS = xline<N>();
-    // two consecutive modes per thread (16-byte loads for FP32)
-    for (int k = 2 * t; k < W; k += 2 * TL) {
+    // modes kx < N/2, two consecutive per thread (16-byte loads for FP32)
+    for (int k = 2 * t; k < H; k += 2 * TL) {
         CPair<T> ea{}, eb{};
         if (ok) {
-            if (k + 1 < W) {
-                ea = *(gptr<const CPair<T>>)(s0 + k);
-                eb = *(gptr<const CPair<T>>)(s0 + rp + k);
-            } else {
-                ea.v[0] = s0[k];
-                eb.v[0] = s0[rp + k];
-            }
+            ea = *(gptr<const CPair<T>>)(s0 + k);
+            eb = *(gptr<const CPair<T>>)(s0 + rp + k);
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int kk = k + q;
-            if (kk >= W) break;
             cplx<T> A = ea.v[q], Bv = eb.v[q];
-            if (kk == 0 || kk == H) {
+            if (kk == 0) {
                 A.y = 0;
                 Bv.y = 0;
             }
             lds[l * LS + skew<4>(kk)] = {A.x - Bv.y, A.y + Bv.x};
-            if (kk > 0 && kk < H) lds[l * LS + skew<4>(N - kk)] = {A.x + Bv.y, -A.y + Bv.x};
+            if (kk > 0) lds[l * LS + skew<4>(N - kk)] = {A.x + Bv.y, -A.y + Bv.x};
         }
+    }
+    // the Nyquist mode of both rows, from nyq (real parts only)
+    if (t == 0) {
+        cplx<T> A{0, 0}, Bv{0, 0};
+        if (ok) {
+            const gptr<const cplx<T>> nq = as_global((const cplx<T>*)g.nyq) + (long long)c * g.nz * g.ny + 2 * p;
+            A = nq[0];
+            Bv = nq[1];
+        }
+        lds[l * LS + skew<4>(H)] = {A.x, Bv.x};
     }
     __syncthreads();
     cplx<T> a[E];
@@ -619,7 +626,7 @@ bool y_fast(const Batch<T>& Bt, int dir, hipStream_t s) {
         constexpr int TL = N / Pl::E;
         int B = g.By;
         while (B > 1 && B * TL > 512) B /= 2;
-        const dim3 grid((unsigned)((g.W + B - 1) / B), g.nz, 3 * Bt.nrep);
+        const dim3 grid((unsigned)((g.nx / 2 + B - 1) / B + 1), g.nz, 3 * Bt.nrep);
         const size_t lds = (size_t)N * (B + 1) * sizeof(cplx<T>);
         if (dir < 0) {
             allow_lds(k_y_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, -1>, lds);
@@ -643,7 +650,7 @@ bool z_fast_plan(const Batch<T>& Bt, int solve, bool project, hipStream_t s) {
         constexpr int TL = N / Pl::E;
         int B = g.Bz;
         while (B > 1 && B * TL > 512) B /= 2;
-        const dim3 grid((unsigned)((g.W - 1 + B - 1) / B + 1), g.ny, Bt.nrep);
+        const dim3 grid((unsigned)((g.nx / 2 + B - 1) / B + 1), g.ny, Bt.nrep);
         const size_t lds = (size_t)N * (B + 1) * sizeof(cplx<T>);
         allow_lds(k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>, lds);
         hipLaunchKernelGGL((k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>), grid, dim3(B * TL), lds, s, Bt.d, B,

@@ -21,17 +21,20 @@ struct FFTPlan {
 
 // Field buffers of one replica. Real face fields hold 3 components of
 // ncell values (x fastest); the spectrum holds 3 components of
-// nz * ny rows of W = nx/2 + 1 complex values (kx fastest) at row pitch Wp.
+// nz * ny rows of W = nx/2 + 1 complex values (kx fastest) at row pitch Wp,
+// except on the fast FFT path, whose rows hold the nx/2 modes kx < nx/2 and
+// whose Nyquist column kx = nx/2 is the separate array nyq (c, z, y).
 template <typename T>
 struct GridDesc {
     int nx, ny, nz, W;
-    int Wp;            // spectrum row pitch (>= W, a multiple of 128 bytes)
+    int Wp;            // spectrum row pitch (a multiple of 128 bytes; >= W, or
+                       // >= nx/2 on the fast path)
     int fast;          // 1: register-resident FFT passes (all three N supported)
     int By, Bz;        // kx columns per block of the fast y and z passes
     int xt;            // threads per block of the fast x passes
     int zsmall;        // 1: the z pass holds the smaller per-thread plan (FP32)
     long long ncell;   // nx * ny * nz
-    long long nspec;   // nz * ny * Wp
+    long long nspec;   // nz * ny * Wp (per component)
     double h;
     double hs;         // half shift s / (2h) of the split three-point kernel
                        // (four-node layout); 0: the plain kernel
@@ -39,6 +42,7 @@ struct GridDesc {
     T* rhs;            // right-hand side / spread scratch field
     T* aux;            // inertial-correction field (dv~, dv)
     cplx<T>* spec;     // spectral work buffer
+    cplx<T>* nyq;      // fast path: Nyquist column, 3 x nz x ny; else null
     // FFT plans and twiddles exp(-2 pi i m / N), m < N, per axis
     FFTPlan px, py, pz;
     const cplx<T>* twx;
