@@ -414,18 +414,31 @@ __global__ void __launch_bounds__(512) k_xfwd_fast(const RepDesc<T>* __restrict_
     const long long row0 = (long long)c * g.ncell + 2 * ((long long)blockIdx.x * P) * N;
     const long long lim = (long long)c * g.ncell + 2 * npairs * N;
     constexpr int LS = xline<N>();
-    // 16-byte loads: V consecutive values of both rows per thread
+    // 16-byte loads: V consecutive values of both rows per thread; each
+    // thread takes NL such pieces (blockDim = P TL), all loads issued before
+    // the first is consumed
     constexpr int V = 16 / (int)sizeof(T);
-    for (int idx = threadIdx.x; idx < P * (N / V); idx += blockDim.x) {
+    static_assert((N / V) % TL == 0, "row pieces per thread");
+    constexpr int NL = (N / V) / TL;
+    Vec16<T> ra[NL], rb[NL];
+#pragma unroll
+    for (int m = 0; m < NL; ++m) {
+        const int idx = threadIdx.x + m * blockDim.x;
         const int ll = idx / (N / V), x = (idx - ll * (N / V)) * V;
         const long long o = row0 + 2LL * ll * N + x;
-        Vec16<T> ra{}, rb{};
+        ra[m] = Vec16<T>{};
+        rb[m] = Vec16<T>{};
         if (o < lim) {
-            ra = *(gptr<const Vec16<T>>)(in + o);
-            rb = *(gptr<const Vec16<T>>)(in + o + N);
+            ra[m] = *(gptr<const Vec16<T>>)(in + o);
+            rb[m] = *(gptr<const Vec16<T>>)(in + o + N);
         }
+    }
 #pragma unroll
-        for (int q = 0; q < V; ++q) lds[ll * LS + skew<4>(x + q)] = cplx<T>{ra.v[q], rb.v[q]};
+    for (int m = 0; m < NL; ++m) {
+        const int idx = threadIdx.x + m * blockDim.x;
+        const int ll = idx / (N / V), x = (idx - ll * (N / V)) * V;
+#pragma unroll
+        for (int q = 0; q < V; ++q) lds[ll * LS + skew<4>(x + q)] = cplx<T>{ra[m].v[q], rb[m].v[q]};
     }
     __syncthreads();
     cplx<T> a[E];
@@ -484,17 +497,29 @@ __global__ void __launch_bounds__(512) k_xinv_fast(const RepDesc<T>* __restrict_
     const long long rp = g.Wp;
     const gptr<const cplx<T>> s0 = as_global((const cplx<T>*)g.spec) + (long long)c * g.nspec + 2 * p * rp;
     constexpr int LS = xline<N>();
-    // modes kx < N/2, two consecutive per thread (16-byte loads for FP32)
-    for (int k = 2 * t; k < H; k += 2 * TL) {
-        CPair<T> ea{}, eb{};
+    // modes kx < N/2, two consecutive per thread (16-byte loads for FP32):
+    // pairs k = 2t + 2 TL m, m < E/4, all loads issued before the first is
+    // consumed
+    static_assert(E % 4 == 0 && 2 * TL * (E / 4) == H, "mode pairs per thread");
+    constexpr int NP = E / 4;
+    CPair<T> ea[NP], eb[NP];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+        const int k = 2 * t + 2 * TL * m;
+        ea[m] = CPair<T>{};
+        eb[m] = CPair<T>{};
         if (ok) {
-            ea = *(gptr<const CPair<T>>)(s0 + k);
-            eb = *(gptr<const CPair<T>>)(s0 + rp + k);
+            ea[m] = *(gptr<const CPair<T>>)(s0 + k);
+            eb[m] = *(gptr<const CPair<T>>)(s0 + rp + k);
         }
+    }
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+        const int k = 2 * t + 2 * TL * m;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int kk = k + q;
-            cplx<T> A = ea.v[q], Bv = eb.v[q];
+            cplx<T> A = ea[m].v[q], Bv = eb[m].v[q];
             if (kk == 0) {
                 A.y = 0;
                 Bv.y = 0;
