@@ -239,8 +239,10 @@ __device__ __forceinline__ void load_tw(cplx<T>* dst, const cplx<T>* src, int n)
 // nyq array.
 
 // ------------------------------------------------------------------ y pass
-// Block: B consecutive kx columns of one (z, component) plane of replica
-// blockIdx.z / 3; thread (b = tid mod B, t = tid / B).
+// Block: B consecutive kx < nx/2 of one (z, component) plane of replica
+// blockIdx.z / 3, thread (b = tid mod B, t = tid / B); or, in the tail
+// column of the grid, the Nyquist column of B planes, thread
+// (b = tid / TL, t = tid mod TL) so that lanes read consecutive y.
 template <typename T, int N, int E, int R0, int R1, int R2, int DIR>
 __global__ void __launch_bounds__(512) k_y_fast(const RepDesc<T>* __restrict__ rd, int B) {
     extern __shared__ unsigned char smem_raw[];
@@ -286,11 +288,11 @@ __global__ void __launch_bounds__(512) k_y_fast(const RepDesc<T>* __restrict__ r
 }
 
 // --------------------------------------------------------- z pass + solve
-// Block: B consecutive kx columns of one ky row of replica blockIdx.z; each
-// thread (b = tid mod B,
-// t = tid / B) holds all three components of its column, so the Helmholtz
-// divide and the 3 x 3 projection of every mode happen in registers between
-// the forward and inverse transforms.
+// Block: B consecutive kx < nx/2 of one ky row of replica blockIdx.z, or, in
+// the tail column of the grid, the Nyquist column of B ky rows; each thread
+// (b = tid mod B, t = tid / B) holds all three components of its column, so
+// the Helmholtz divide and the 3 x 3 projection of every mode happen in
+// registers between the forward and inverse transforms.
 template <typename T, int N, int E, int R0, int R1, int R2>
 __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ rd, int B, int solve,
                                                  int project) {
