@@ -48,7 +48,7 @@ typedef struct icm_ctx icm_ctx;
 typedef enum {
     ICM_OK = 0,
     ICM_E_INVALID = -1,     /* bad argument or parameter                    */
-    ICM_E_UNSUPPORTED = -2, /* valid request this build does not handle     */
+    ICM_E_UNSUPPORTED = -2, /* valid request the library does not handle    */
     ICM_E_NOMEM = -3,       /* workspace too small or device allocation failed */
     ICM_E_DEVICE = -4,      /* a HIP call failed                            */
     ICM_E_STATE = -5,       /* context in error state / call out of order   */

@@ -1,5 +1,7 @@
 """CPU checks of the analysis helpers the statistical GPU tests rely on
 (bench.py): they must find a planted signal and nothing in its absence."""
+import os
+
 import numpy as np
 
 import bench
@@ -39,3 +41,15 @@ def test_pair_histogram_uses_minimum_image():
     c = bench.pair_histogram(q, L, 5.0, 50)
     assert c[3] == 1.0                       # the pair 0.35 apart across the boundary
     assert c.sum() == 3.0                    # 4.75 and 4.9 apart: also within 5
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asking for more exits with status 2
+    and says so, before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU only" in (r.stdout + r.stderr)
