@@ -42,8 +42,8 @@ def log(msg):
 
 
 def algorithmic_bytes(phase, n, nb, kernel, w):
-    """Algorithmic HBM bytes of one launch of a phase:
-    each field or spectrum element read once and written once."""
+    """Algorithmic HBM bytes of one launch of a phase: each field or
+    spectrum element read once and written once."""
     nx, ny, nz = n
     ncell = nx * ny * nz
     nspec = nz * ny * (nx // 2 + 1)
@@ -104,6 +104,34 @@ def measured_traffic(phase):
     if at_hash != source_hash():
         return None
     return traffic.get(kernel)
+
+
+# Kernels of one step of the 256^3 FP32 workload (all blobs neutrally
+# buoyant, so no inertial-correction launches), each launched once per step.
+STEP_KERNELS = ("k_gather_predict<", "k_gather_bins<", "k_pairs_cells<", "k_bins<", "k_rhs_march<",
+                "k_spread_overflow<", "k_xfwd_fast<", "k_y_fast<", "k_z_fast<", "k_xinv_fast<", "k_gather_final<")
+
+
+def measured_step_traffic():
+    """HBM bytes of one whole step from the committed counter summary: the
+    scaled FETCH_SIZE + WRITE_SIZE of every kernel the step launches (both y
+    passes), or None when the sources changed after the counters were
+    taken."""
+    if not os.path.exists(PROFILE):
+        return None
+    at_hash, total, seen = None, 0.0, 0
+    with open(PROFILE) as fh:
+        for line in fh:
+            if line.startswith("source hash"):
+                at_hash = line.split()[-1]
+            elif line.startswith("traffic "):
+                name, val = line[len("traffic "):].rsplit(" ", 1)
+                if name.startswith(STEP_KERNELS):
+                    total += float(val)
+                    seen += 1
+    if at_hash != source_hash() or seen < len(STEP_KERNELS) + 1:
+        return None
+    return total
 
 
 def setup(I, torch, wl, precision, stream, advection=False):
@@ -900,6 +928,7 @@ def main():
                         unit="GB/s", frac=dom_v["achieved_GBs"] / HBM_PEAK_GBS, traffic=measured_traffic(dom_name),
                         alg_bytes_per_launch=dom_v["alg_bytes_per_launch"], avg_launch_us=dom_v["avg_launch_us"])
     step_alg_bytes = 12 * ncell * 4
+    step_traffic = measured_step_traffic()
     out = {
         "metric": METRIC,
         "value": value,
@@ -922,6 +951,10 @@ def main():
         "ms_per_step_repeats": repeats,
         "ms_per_step_median_of_5": float(np.median(repeats)),
         "step_hbm_fraction": step_alg_bytes / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        # counted HBM traffic of all the step's kernels over the step time
+        "step_traffic": (None if step_traffic is None else {
+            "bytes_per_step": step_traffic, "achieved_GBs": step_traffic / (ms_per_step * 1e-3) / 1e9,
+            "frac_of_peak": step_traffic / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)}),
         "roofline": roofline,
         "phases": phases,
         "momentum_after": list(diag["momentum"]),
