@@ -636,6 +636,35 @@ __device__ __forceinline__ double gather_group(const GridDesc<T>& g, const T* __
     return acc;
 }
 
+// gather_group at the positions whose stencil records k_gather_bins wrote
+// (o: the record of component a): the same wrapped nodes and weights, read
+// instead of recomputed, so the result is the same to the bit.
+template <typename T, int P>
+__device__ __forceinline__ double gather_group_rec(const GridDesc<T>& g, const T* __restrict__ field,
+                                                   gptr<const double> o, int a, int r, bool active) {
+    double acc = 0.0;
+    if (active && r < P * P) {
+        const int cz = r / P, cy = r - P * (r / P);
+        const int i0 = (int)o[0];
+        int j = (int)o[1] + cy, k = (int)o[2] + cz;
+        if (j >= g.ny) j -= g.ny;
+        if (k >= g.nz) k -= g.nz;
+        const double wy = o[7 + cy], wz = o[11 + cz];
+        const T* f = field + a * g.ncell + ((long long)k * g.ny + j) * g.nx;
+        double s = 0.0;
+#pragma unroll
+        for (int aa = 0; aa < P; ++aa) {
+            int x = i0 + aa;
+            if (x >= g.nx) x -= g.nx;
+            s += o[3 + aa] * (double)f[x];
+        }
+        acc = wz * wy * s;
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+    return acc;
+}
+
 // Step 1 fused: Jn = J(q^n) v^n, q^{n+1/2} = q^n + dt/2 Jn, the one-body
 // forces at q^{n+1/2} and the folded positions.
 template <typename T, int P>
@@ -777,7 +806,9 @@ __global__ void __launch_bounds__(kThreads) k_gather_final(const RepDesc<T>* __r
     const int grp = t >> 4, r = t & 15;
     const int b = grp / 3, a = grp - 3 * (grp / 3);
     const bool active = b < bp.nb;
-    const double J = gather_group<T, P>(g, g.v, active ? bb.qh + 3 * b : bb.qh, a, r, active);
+    // J(q^{n+1/2}) v^{n+1} from the stencil records of this step's positions
+    const gptr<const double> o = as_global((const double*)bb.stc) + ((long long)(active ? b : 0) * 3 + a) * kStcPerComp;
+    const double J = gather_group_rec<T, P>(g, g.v, o, a, r, active);
     if (active && r == 0) {
         const int i = 3 * b + a;
         bb.Jhvnew[i] = J;
