@@ -708,9 +708,62 @@ __global__ void __launch_bounds__(kThreads) k_gather_bins(const RepDesc<T>* __re
     const int grp = t >> 4, r = t & 15;
     const int b = grp / 3, a = grp - 3 * (grp / 3);
     const bool active = b < bp.nb;
-    const double J = gather_group<T, P>(g, g.v, active ? bb.qh + 3 * b : bb.qh, a, r, active);
+    const double inv_h = 1.0 / g.h;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    // lanes 1..3 compute (and store) the stencil record of axis ax = r - 1:
+    // the wrapped base node, the P weights (zero beyond P) and, along axis
+    // a, the derivative weights; the group's gather below reads the weights
+    // from those lanes instead of evaluating the kernel again
+    int rb_node = 0;
+    double rw[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active && r >= 1 && r <= 3) {
+        const int ax = r - 1;
+        double* o = bb.stc + ((long long)b * 3 + a) * kStcPerComp;
+        const double x = fold_coord(bb.qh[3 * b + ax] * inv_h - (ax == a ? 0.0 : 0.5), n[ax]);
+        const int base = (int)((P == 3) ? floor(x + 0.5) : floor(x)) - 1;
+        rb_node = wrap_node(base, n[ax]);
+        o[ax] = (double)rb_node;
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            const double d = x - (double)(base + tt);
+            rw[tt] = (tt < P) ? kern_w<P>(d, g.hs) : 0.0;
+            o[3 + 4 * ax + tt] = rw[tt];
+            if (ax == a) o[15 + tt] = (tt < P) ? kern_dw<P>(d, g.hs) * inv_h : 0.0;
+        }
+    }
+    // every lane of the group takes the three axes' records (lanes 1, 2, 3)
+    double wx[4], wy4[4], wz4[4];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+        wx[tt] = __shfl(rw[tt], 1, 16);
+        wy4[tt] = __shfl(rw[tt], 2, 16);
+        wz4[tt] = __shfl(rw[tt], 3, 16);
+    }
+    const int bx = __shfl(rb_node, 1, 16), by = __shfl(rb_node, 2, 16), bz = __shfl(rb_node, 3, 16);
+    // Jhvn = J(q^{n+1/2}) v^n: lane r < P^2 sums the x-row of z-tap r / P and
+    // y-tap r mod P, as gather_group does, with the same nodes and weights
+    double acc = 0.0;
+    if (active && r < P * P) {
+        const int cz = r / P, cy = r - P * (r / P);
+        int j = by + cy, k = bz + cz;
+        if (j >= g.ny) j -= g.ny;
+        if (k >= g.nz) k -= g.nz;
+        const double wy = cy == 0 ? wy4[0] : (cy == 1 ? wy4[1] : (cy == 2 ? wy4[2] : wy4[3]));
+        const double wz = cz == 0 ? wz4[0] : (cz == 1 ? wz4[1] : (cz == 2 ? wz4[2] : wz4[3]));
+        const T* f = g.v + a * g.ncell + ((long long)k * g.ny + j) * g.nx;
+        double sx = 0.0;
+#pragma unroll
+        for (int aa = 0; aa < P; ++aa) {
+            int x = bx + aa;
+            if (x >= g.nx) x -= g.nx;
+            sx += wx[aa] * (double)f[x];
+        }
+        acc = wz * wy * sx;
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
     if (!active) return;
-    if (r == 0) bb.Jhvn[3 * b + a] = J;
+    if (r == 0) bb.Jhvn[3 * b + a] = acc;
     // the blob's insertion into its cell's list for the pair forces: a head
     // holds (stamp << kHeadBlobBits | blob) with the step's stamp, so heads
     // left by earlier steps read as empty and are never cleared
@@ -727,21 +780,6 @@ __global__ void __launch_bounds__(kThreads) k_gather_bins(const RepDesc<T>* __re
         const unsigned long long mine = (stamp << kHeadBlobBits) | (unsigned long long)b;
         const unsigned long long old = atomicExch(&cg.heads[cell], mine);
         cg.next[b] = ((old >> kHeadBlobBits) == stamp) ? (int)(old & ((1u << kHeadBlobBits) - 1)) : -1;
-    }
-    const double inv_h = 1.0 / g.h;
-    const int n[3] = {g.nx, g.ny, g.nz};
-    double* o = bb.stc + ((long long)b * 3 + a) * kStcPerComp;
-    // lanes 1..3 write the record of axis ax = r - 1
-    if (r >= 1 && r <= 3) {
-        const int ax = r - 1;
-        const double x = fold_coord(bb.qh[3 * b + ax] * inv_h - (ax == a ? 0.0 : 0.5), n[ax]);
-        const int base = (int)((P == 3) ? floor(x + 0.5) : floor(x)) - 1;
-        o[ax] = (double)wrap_node(base, n[ax]);
-        for (int tt = 0; tt < 4; ++tt) {
-            const double d = x - (double)(base + tt);
-            o[3 + 4 * ax + tt] = (tt < P) ? kern_w<P>(d, g.hs) : 0.0;
-            if (ax == a) o[15 + tt] = (tt < P) ? kern_dw<P>(d, g.hs) * inv_h : 0.0;
-        }
     }
 }
 
