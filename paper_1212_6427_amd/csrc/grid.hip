@@ -609,26 +609,49 @@ __global__ void __launch_bounds__(kThreads) k_spread(const RepDesc<T>* __restric
     for (int aa = 0; aa < P; ++aa) atomicAdd(&f[sx.node[aa]], (T)(wzy * sx.w[aa]));
 }
 
-// One 16-lane group's share of J for component a at position (qx,qy,qz):
-// lane r < P^2 sums the x-row of z-tap r / P and y-tap r mod P; the group
-// total is returned to every lane of the group.
+// One 16-lane group's J for component a at position (qx,qy,qz), returned to
+// every lane of the group: lanes 1..3 evaluate the kernel weights of axis
+// r - 1 and share them through shuffles, and lane r < P^2 sums the x-row of
+// z-tap r / P and y-tap r mod P.
 template <typename T, int P>
 __device__ __forceinline__ double gather_group(const GridDesc<T>& g, const T* __restrict__ field, const double* q3,
                                                int a, int r, bool active) {
+    const double inv_h = 1.0 / g.h;
+    int rb_node = 0;
+    double rw[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active && r >= 1 && r <= 3) {
+        const int ax = r - 1;
+        const int nax = ax == 0 ? g.nx : (ax == 1 ? g.ny : g.nz);
+        const double x = fold_coord(q3[ax] * inv_h - comp_offset(ax, a), nax);
+        const int base = (int)((P == 3) ? floor(x + 0.5) : floor(x)) - 1;
+        rb_node = wrap_node(base, nax);
+#pragma unroll
+        for (int tt = 0; tt < P; ++tt) rw[tt] = kern_w<P>(x - (double)(base + tt), g.hs);
+    }
+    double wx[4], wy4[4], wz4[4];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+        wx[tt] = __shfl(rw[tt], 1, 16);
+        wy4[tt] = __shfl(rw[tt], 2, 16);
+        wz4[tt] = __shfl(rw[tt], 3, 16);
+    }
+    const int bx = __shfl(rb_node, 1, 16), by = __shfl(rb_node, 2, 16), bz = __shfl(rb_node, 3, 16);
     double acc = 0.0;
     if (active && r < P * P) {
         const int cz = r / P, cy = r - P * (r / P);
-        const double inv_h = 1.0 / g.h;
-        AxisStencil<P> sx;
-        axis_stencil<P>(q3[0] * inv_h - comp_offset(0, a), g.nx, false, inv_h, g.hs, sx);
-        int j, k;
-        double wy, wz;
-        axis_tap<P>(q3[1] * inv_h - comp_offset(1, a), g.ny, cy, false, inv_h, g.hs, j, wy);
-        axis_tap<P>(q3[2] * inv_h - comp_offset(2, a), g.nz, cz, false, inv_h, g.hs, k, wz);
+        int j = by + cy, k = bz + cz;
+        if (j >= g.ny) j -= g.ny;
+        if (k >= g.nz) k -= g.nz;
+        const double wy = cy == 0 ? wy4[0] : (cy == 1 ? wy4[1] : (cy == 2 ? wy4[2] : wy4[3]));
+        const double wz = cz == 0 ? wz4[0] : (cz == 1 ? wz4[1] : (cz == 2 ? wz4[2] : wz4[3]));
         const T* f = field + a * g.ncell + ((long long)k * g.ny + j) * g.nx;
         double s = 0.0;
 #pragma unroll
-        for (int aa = 0; aa < P; ++aa) s += sx.w[aa] * (double)f[sx.node[aa]];
+        for (int aa = 0; aa < P; ++aa) {
+            int x = bx + aa;
+            if (x >= g.nx) x -= g.nx;
+            s += wx[aa] * (double)f[x];
+        }
         acc = wz * wy * s;
     }
 #pragma unroll
