@@ -53,3 +53,17 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU only" in (r.stdout + r.stderr)
+
+
+def test_profile_summary_lists_every_step_kernel():
+    """The committed counter summary that the benchmark's roofline traffic
+    and step traffic are read from names its source hash and carries a
+    traffic line for every kernel of the step (both y passes)."""
+    with open(bench.PROFILE) as fh:
+        lines = fh.read().splitlines()
+    assert any(l.startswith("source hash") and len(l.split()[-1]) == 16 for l in lines)
+    names = [l[len("traffic "):].rsplit(" ", 1)[0] for l in lines if l.startswith("traffic ")]
+    for prefix in bench.STEP_KERNELS:
+        hits = [n for n in names if n.startswith(prefix)]
+        assert len(hits) == (2 if prefix == "k_y_fast<" else 1), prefix
+    assert bench.PHASE_KERNEL["rhs"] in names
