@@ -559,8 +559,34 @@ def thermal_drift_coef(p, m_e):
     return p.kT * p.mt_f / (m_e + p.mt_f)
 
 
-def step(p, st):
+def slip_correction(p, lag_c, Jn_vn, Jh_vn):
+    """The slip velocity delta-u^{n+1/2} of Sec. III.C step 4.
+
+    FULL, Eq. (delta_u_nph): (J^{n+1/2} - J^n) v^n plus the viscous term;
+    VISCOUS, Eq. (delta_u_nph_visc): the viscous term alone,
+    (nu dt / 2) J^{n-1/2} L dv^{n-1/2} with nu = eta / rho, where lag_c holds
+    J^{n-1/2} L dv^{n-1/2} from the previous step; NONE: zero.
+    """
+    du = np.zeros_like(np.asarray(lag_c, dtype=np.float64))
+    if p.slip == SLIP_FULL:
+        du += Jh_vn - Jn_vn
+    if p.slip in (SLIP_VISCOUS, SLIP_FULL):
+        du += 0.5 * (p.eta / p.rho) * p.dt * lag_c
+    return du
+
+
+def lagged_viscous_term(p, dv, q_h):
+    """J^{n+1/2} L dv^{n+1/2}: the term of Eq. (Florens_trick) that App. C
+    lags to the next step's slip correction (7-point Laplacian, then J)."""
+    return interp(p, laplacian(p, dv), q_h)
+
+
+def step(p, st, trace=None):
     """Advance one time step. Returns a new State (the input is untouched).
+
+    If trace is a dict, the step stores its intermediate quantities there
+    under the paper's names (rhs, v_tilde, du, dp, dv_tilde, g, dv), so that
+    tests can check each against what the paper fixes for it.
 
     Steps follow Sec. III.C. Readings applied here:
     * m_e = 0 blobs report u^{n+1} = J^{n+1/2} v^{n+1} (the m_e -> 0 limit of
@@ -600,6 +626,11 @@ def step(p, st):
         if coef is not None:
             spread(p, coef[:, None] * np.ones((nb, 3)), q_h, deriv=True, out=rhs)
     v_t = helmholtz_project(p, rhs, rho / dt, 0.5 * eta)
+    if trace is not None:
+        trace["rhs"] = rhs.copy()
+        trace["v_tilde"] = v_t.copy()
+        trace["q_half"] = q_h.copy()
+        trace["F"] = F.copy()
 
     Jh_vn = interp(p, v_n, q_h) if nb else np.zeros((0, 3))
     inertial = nb > 0 and np.any(st.m_e != 0.0)
@@ -608,11 +639,7 @@ def step(p, st):
     if inertial:
         m_e = st.m_e
         # Step 4: slip correction and excess-momentum change.
-        du = np.zeros((nb, 3))
-        if p.slip == SLIP_FULL:
-            du += Jh_vn - Jn_vn
-        if p.slip in (SLIP_VISCOUS, SLIP_FULL):
-            du += 0.5 * (eta / rho) * dt * st.lag_c
+        du = slip_correction(p, st.lag_c, Jn_vn, Jh_vn)
         Jh_vt = interp(p, v_t, q_h)
         dp = m_e[:, None] * (st.u - Jh_vt - du)
         # Step 5: dv~ = m~_f / (rho m~) P S dp, Eq. (dv_tilde_sol).
@@ -626,7 +653,9 @@ def step(p, st):
         v_new = v_t + dv
         # Step 8, Eq. (update_u) / (u_np1_modified).
         u_new = Jh_vt + g + du
-        lag_new = interp(p, laplacian(p, dv), q_h)
+        lag_new = lagged_viscous_term(p, dv, q_h)
+        if trace is not None:
+            trace.update(du=du, dp=dp, dv_tilde=dvt, g=g, dv=dv)
     else:
         v_new = v_t
 

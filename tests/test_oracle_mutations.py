@@ -173,3 +173,58 @@ def test_split_kernel_on_the_three_node_layout(monkeypatch):
         return phi, dphi, 3
     monkeypatch.setattr(icm, "kernel_of", bad)
     assert _fails(split_pins.test_interp_of_a_locally_linear_field_is_exact)
+
+
+# --------------------------------------------- slip correction, thermal drift
+import tests.test_oracle_slip_drift as slip_pins
+
+
+def _slip_with(viscous_coef=None, full_sign=1.0):
+    """A slip_correction with a planted mistake in one of its two terms."""
+    def bad(p, lag_c, Jn_vn, Jh_vn):
+        du = np.zeros_like(np.asarray(lag_c, dtype=np.float64))
+        if p.slip == icm.SLIP_FULL:
+            du += full_sign * (Jh_vn - Jn_vn)
+        if p.slip in (icm.SLIP_VISCOUS, icm.SLIP_FULL):
+            c = 0.5 * (p.eta / p.rho) * p.dt if viscous_coef is None else viscous_coef(p)
+            du += c * lag_c
+        return du
+    return bad
+
+
+def test_viscous_slip_with_eta_dt_instead_of_half_nu_dt(monkeypatch):
+    monkeypatch.setattr(icm, "slip_correction", _slip_with(viscous_coef=lambda p: p.eta * p.dt))
+    assert _fails(slip_pins.test_no_slip_residual_of_the_inertial_correction, 3, icm.SLIP_VISCOUS, 1.0)
+    assert _fails(slip_pins.test_viscous_slip_restores_second_order)
+
+
+def test_lagged_term_without_the_laplacian(monkeypatch):
+    monkeypatch.setattr(icm, "lagged_viscous_term", lambda p, dv, q_h: icm.interp(p, dv, q_h))
+    assert _fails(slip_pins.test_no_slip_residual_of_the_inertial_correction, 4, icm.SLIP_VISCOUS, 1.0)
+    assert _fails(slip_pins.test_viscous_slip_restores_second_order)
+
+
+def test_full_slip_term_with_the_wrong_sign(monkeypatch):
+    monkeypatch.setattr(icm, "slip_correction", _slip_with(full_sign=-1.0))
+    assert _fails(slip_pins.test_no_slip_residual_of_the_inertial_correction, 3, icm.SLIP_FULL, 1.0)
+    assert _fails(slip_pins.test_full_slip_term_on_a_shear_flow, 4)
+
+
+def test_thermal_drift_coefficient_with_the_wrong_sign(monkeypatch):
+    orig = icm.thermal_drift_coef
+
+    def bad(p, m_e):
+        c = orig(p, m_e)
+        return None if c is None else -c
+    monkeypatch.setattr(icm, "thermal_drift_coef", bad)
+    assert _fails(slip_pins.test_thermal_drift_is_the_random_finite_difference, 3, 0.0)
+
+
+def test_thermal_drift_coefficient_without_the_mass_ratio(monkeypatch):
+    def bad(p, m_e):
+        if p.kT == 0.0 or not p.thermal_drift:
+            return None
+        return p.kT * np.ones_like(np.asarray(m_e, dtype=np.float64))
+    monkeypatch.setattr(icm, "thermal_drift_coef", bad)
+    assert _fails(slip_pins.test_thermal_drift_is_the_random_finite_difference, 4, 1.0)
+    assert _fails(slip_pins.test_thermal_drift_is_the_random_finite_difference, 3, -0.5)
