@@ -7,11 +7,13 @@ minimum separation 2h, Peskin 4-point kernel, WCA soft-sphere repulsion
 from the discrete equilibrium. Inputs are synthetic and resident in HBM when
 the timed region starts.
 
-Prints one JSON line: the throughput of the whole hot path, the roofline of
-its dominant kernel (average launch duration from HIP events on the launch
-stream), an FP64 run of the same workload, and the FP64 CPU oracle timed on a
-bounded sample (two full steps) of the same workload, and the further legs
-(advection, batched ensemble, 512^3, statistics, J P S, convergence study).
+The last stdout line is one compact JSON record: the throughput of the whole
+hot path, the roofline of its dominant kernel (average launch duration from
+HIP events on the launch stream), the FP64 CPU oracle timed on a bounded
+sample (two full steps) of the same workload, and one-line summaries of the
+FP64, batched-ensemble and 512^3 legs. The full record of every leg
+(advection, statistics, J P S, convergence study, per-kernel phases) is
+written to --full-record; progress goes to stderr.
 """
 import argparse
 import json
@@ -70,6 +72,9 @@ def algorithmic_bytes(phase, n, nb, kernel, w):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "many_blobs_256_fp32.md")
+# every leg's full results (arrays, statistics) go to this file by default;
+# stdout ends with a compact line
+FULL_RECORD = os.path.join(ROOT, "bench_results", "bench_full.json")
 PHASE_KERNEL = {"rhs": "k_rhs_march<float, true>", "fft_z_solve": "k_z_fast<float, 256, 8, 8, 8, 4>",
                 "fft_x_fwd": "k_xfwd_fast<float, 256, 16, 16, 16, 1>",
                 "fft_x_inv": "k_xinv_fast<float, 256, 16, 16, 16, 1>"}
@@ -820,26 +825,85 @@ def ensemble_vacf_leg(I, torch, stream, steps, per_shape=4, tune=True):
     return out
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, seed_positions, steps=2):
-    """The FP64 oracle, untuned, on `steps` full steps of the same workload
-    (about 10 s of CPU work)."""
+    """The FP64 oracle, untuned, on `steps` full steps of the same workload,
+    timed twice: with scipy.fft's transforms spread over every host core the
+    process may use (numpy's element-wise work stays on one thread), and on
+    one core. About 10 s of CPU work each."""
+    import scipy.fft as sfft
     from oracle import icm as O
     n = tuple(wl["n"])
     sigma = wl["wca_cutoff"] / 2 ** (1.0 / 6.0)
     p = O.Params(n=n, h=wl["h"], rho=wl["rho"], eta=wl["eta"], kT=wl["kT"], dt=wl["dt"], kernel=wl["kernel"],
                  seed=wl["seed"], wca_eps=wl["wca_eps"], wca_sigma=sigma)
-    st = O.new_state(p, seed_positions)
-    st.v = O.equilibrium_field(p)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        st = O.step(p, st)
-    dt = time.perf_counter() - t0
+    st0 = O.new_state(p, seed_positions)
+    st0.v = O.equilibrium_field(p)
+    cores = len(os.sched_getaffinity(0))
     ncell = int(np.prod(n))
-    return dict(value=ncell * steps / dt, unit="cell-steps/s", cores=1, kind="oracle",
-                sample="%d full steps of %s (%dx%dx%d, %d blobs) in the FP64 numpy/scipy oracle, %.1f s; "
-                       "blob-steps/s %.3g; numpy and scipy.fft run single-threaded here"
-                       % (steps, "many_blobs_256", n[0], n[1], n[2], wl["n_blobs"], dt, wl["n_blobs"] * steps / dt),
-                seconds=dt)
+    runs = {}
+    for name, workers in (("all_cores", cores), ("one_core", 1)):
+        st = st0
+        with sfft.set_workers(workers):
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                st = O.step(p, st)
+            dt = time.perf_counter() - t0
+        runs[name] = dict(value=ncell * steps / dt, seconds=dt, fft_workers=workers,
+                          blob_steps_per_s=wl["n_blobs"] * steps / dt)
+    a = runs["all_cores"]
+    return dict(value=a["value"], unit="cell-steps/s", cores=cores, kind="oracle",
+                sample="%d full steps of %s (%dx%dx%d, %d blobs) in the FP64 numpy/scipy oracle, %.1f s with "
+                       "scipy.fft on %d worker threads (element-wise numpy on one), %.1f s on one core"
+                       % (steps, "many_blobs_256", n[0], n[1], n[2], wl["n_blobs"], a["seconds"], cores,
+                          runs["one_core"]["seconds"]),
+                cpu_model=cpu_model(), one_core=runs["one_core"], all_cores=a)
+
+
+def compact_record(out):
+    """The headline keys plus one-line summaries of the other legs: the last
+    stdout line, a few KB."""
+    keep = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+            "vs_baseline", "dtype", "data", "config", "blob_steps_per_s", "ms_per_step_median_of_5",
+            "step_hbm_fraction", "step_traffic")
+    c = {k: out[k] for k in keep if k in out}
+    r = out["roofline"]
+    c["roofline"] = {k: r[k] for k in ("bound", "kernel", "achieved", "peak", "unit", "frac", "traffic",
+                                       "avg_launch_us", "hbm_achieved_GBs") if k in r}
+    if "cpu_baseline" in out:
+        cb = out["cpu_baseline"]
+        c["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "cpu_model")}
+        c["cpu_baseline"]["one_core_value"] = cb["one_core"]["value"]
+    c["phases_us"] = {k: round(v["avg_launch_us"], 1) for k, v in out.get("phases", {}).items()}
+    if "fp64" in out:
+        f = out["fp64"]
+        c["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "steps": f["steps"],
+                     "step_hbm_fraction": f.get("step_hbm_fraction")}
+    if "ensemble" in out:
+        e = out["ensemble"]
+        c["ensemble"] = {"replicas": e["replicas"], "cells": e["cells"],
+                         "batched_ms_per_step": e["batched"]["ms_per_step"], "batched_value": e["batched"]["value"],
+                         "single_ms_per_step": e["single"]["ms_per_step"],
+                         "speedup_batched_vs_single": e["speedup_batched_vs_single"]}
+    if "scale_512" in out:
+        s = out["scale_512"]
+        c["scale_512"] = {"fp32_ms_per_step": s["fp32"]["ms_per_step"], "fp64_ms_per_step": s["fp64"]["ms_per_step"],
+                          "max_rel_err_v": s["max_rel_err_v"], "max_rel_err_u": s["max_rel_err_u"],
+                          "momentum_drift_rel_fp32": s["fp32"]["momentum_drift_rel"],
+                          "momentum_drift_rel_fp64": s["fp64"]["momentum_drift_rel"]}
+    if "advection" in out:
+        c["advection_ms_per_step"] = out["advection"]["ms_per_step"]
+    return c
 
 
 def main():
@@ -866,6 +930,7 @@ def main():
     ap.add_argument("--no-jps", action="store_true", help="skip the J P S invariance diagnostics")
     ap.add_argument("--advection-steps", type=int, default=100)
     ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--full-record", default=FULL_RECORD, help="file for the full record of every leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device tensor copy first (counter calibration)")
     args = ap.parse_args()
@@ -970,7 +1035,8 @@ def main():
         sec64, _ = time_steps(torch, sim64, stream, k64, step_flags)
         sim64.close()
         out["fp64"] = {"value": ncell * k64 / sec64, "ms_per_step": sec64 * 1000.0 / k64, "steps": k64,
-                       "blob_steps_per_s": nb * k64 / sec64}
+                       "blob_steps_per_s": nb * k64 / sec64,
+                       "step_hbm_fraction": 12 * ncell * 8 / sec64 * k64 / (HBM_PEAK_GBS * 1e9)}
         log("FP64: %.3f ms/step" % out["fp64"]["ms_per_step"])
     if not args.no_advection:
         log("advection on: %d steps" % args.advection_steps)
@@ -1019,10 +1085,15 @@ def main():
              for r, v in out["convergence"]["by_me_over_mf"].items()},
             out["convergence"]["wall_s"]))
     if not args.no_cpu_baseline:
-        log("CPU oracle: two steps of the same workload")
+        log("CPU oracle: two steps of the same workload, all host cores and one core")
         out["cpu_baseline"] = cpu_baseline(wl, q)
-        log("CPU oracle: %.1f s" % out["cpu_baseline"]["seconds"])
-    print(json.dumps(out), flush=True)
+        log("CPU oracle: %s" % out["cpu_baseline"]["sample"])
+    path = os.path.abspath(args.full_record)
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    log("full record written to %s" % path)
+    print(json.dumps(compact_record(out)), flush=True)
 
 
 if __name__ == "__main__":

@@ -112,7 +112,11 @@ typedef struct {
                                 face field of workspace. 0: off (default)  */
     double body_force[3];    /* uniform force density on the fluid           */
     double wca_eps;          /* WCA pair potential of Sec. IV.A (0 = off)    */
-    double wca_sigma;        /* WCA diameter; cutoff 2^(1/6) sigma < N h / 2 */
+    double wca_sigma;        /* WCA diameter sigma of Eq. (WCA), the
+                                parameter the paper's potential is written
+                                in; the cutoff is 2^(1/6) sigma (a cutoff of
+                                2h means sigma = 2h / 2^(1/6)) and must stay
+                                below N h / 2 on every axis                  */
     double spring_k;         /* tether spring -k (q - c) per blob (0 = off)  */
     double spring_center[3];
     double kernel_shift;     /* s / h of the split (shifted) three-point
@@ -130,23 +134,35 @@ typedef struct {
                                 kernel that sum depends on the position     */
 } icm_replica_params;
 
-/* FP64 diagnostics of one replica. */
+/* FP64 diagnostics of one replica, reduced on the device. */
 typedef struct {
-    double momentum[3];  /* rho h^3 sum v + sum m_e u (Sec. II)                 */
+    double momentum[3];  /* rho h^3 sum v + sum m_e u: the total momentum that
+                            the step conserves (Sec. II, after Eq. (no_slip);
+                            App. C)                                          */
     double ke_fluid;     /* rho h^3 sum v^2 / 2                                 */
     double ke_blob;      /* sum m_e u^2 / 2                                     */
-    double max_div;      /* max |D v| h / max |v| (0 for v = 0)                 */
-    int64_t step;        /* steps taken since the state was set                */
+    double max_div;      /* max |D v| h / max |v| (0 for v = 0): the discrete
+                            divergence the projection removes (Sec. III.D)   */
+    double max_alpha;    /* advective CFL number alpha = V dt / h of
+                            Eq. (alpha_beta), with V the largest magnitude of
+                            any face velocity or blob velocity component     */
+    int64_t step;        /* step counter n (feeds the Philox counter)          */
 } icm_diag;
 
-/* Bytes of device workspace icm_create needs for these replicas.
- * p: n_rep parameter blocks; max_blobs: n_rep capacities in [0, 2^24).     */
+/* Bytes of device workspace icm_create needs for these replicas: the state
+ * of the method at step n (the staggered face field v of Sec. III.A and the
+ * blob positions, velocities and lagged slip terms of Sec. III.C), the
+ * right-hand side and spectrum of the FFT solves of Sec. III.D, the
+ * inertial-correction field of App. C, and per-blob stencil and cell-list
+ * arrays. p: n_rep parameter blocks; max_blobs: n_rep capacities in
+ * [0, 2^24). Writes *bytes; no device work.                                */
 icm_status icm_workspace_bytes(int32_t n_rep, const icm_replica_params* p,
                                const int32_t* max_blobs, int32_t precision,
                                size_t* bytes);
 
 /* Create a context of n_rep independent replicas (uneven grids allowed) that
- * are stepped together. precision: ICM_FP64 or ICM_FP32_GRID (blob state is
+ * are stepped together, each a periodic box of Sec. III.A advanced by the
+ * step of Sec. III.C. precision: ICM_FP64 or ICM_FP32_GRID (blob state is
  * FP64 in both). workspace/bytes: device memory of at least
  * icm_workspace_bytes, owned by the caller and kept alive until
  * icm_destroy; NULL makes the library allocate (and free) it. stream: a
@@ -166,7 +182,10 @@ icm_status icm_set_blobs(icm_ctx* ctx, int32_t replica, int32_t n_blobs,
                          const double* q, const double* u, const double* m_e,
                          const double* f_const, uint32_t flags);
 
-/* Overwrite parts of a replica's state (checkpoint restore / test input).
+/* Overwrite parts of a replica's state (checkpoint restore / test input):
+ * the step-n quantities v^n, q^n, u^n and the lagged term
+ * J^{n-1/2} L dv^{n-1/2} of Eq. (delta_u_nph_visc) that Sec. III.C step 4
+ * reads.
  * v: face field in the context precision (NULL = keep); q, u, lag_c:
  * n_blobs x 3 blob arrays for the installed blobs (NULL = keep); step: the
  * step counter n that feeds the Philox counter (negative = keep).
@@ -219,7 +238,9 @@ icm_status icm_autotune(icm_ctx* ctx, icm_tune_result* results, int32_t capacity
  * A recorded step graph is dropped.                                        */
 icm_status icm_set_fft_shapes(icm_ctx* ctx, const icm_tune_result* shapes, int32_t count);
 
-/* Read a replica's state. Any output may be NULL. v: face field in the
+/* Read a replica's state at the current step n (v^n, q^n, u^n and the
+ * lagged slip term of Sec. III.C) and its diagnostics. Any output may be
+ * NULL. v: face field in the
  * context precision; q, u, lag_c: n_blobs x 3; diag: FP64 diagnostics.     */
 icm_status icm_get_state(icm_ctx* ctx, int32_t replica, void* v, double* q,
                          double* u, double* lag_c, icm_diag* diag,

@@ -718,6 +718,16 @@ def kinetic_energy(p, st):
     return ke_f, ke_b
 
 
+def advective_cfl(p, st):
+    """The advective CFL number alpha = V dt / dx of Eq. (alpha_beta), with V
+    the largest magnitude of any face velocity or blob velocity component
+    (the speed at which something crosses a cell along one axis)."""
+    V = float(np.max(np.abs(st.v))) if st.v.size else 0.0
+    if st.u.size:
+        V = max(V, float(np.max(np.abs(st.u))))
+    return V * p.dt / p.h
+
+
 def max_divergence(p, v):
     """max |D v| h / max |v| (0 for a zero field)."""
     vm = float(np.max(np.abs(v)))

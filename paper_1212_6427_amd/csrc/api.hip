@@ -1095,6 +1095,13 @@ icm_status icm_set_state(icm_ctx* c, int32_t replica, const void* v, const doubl
         R.step = step;
         const unsigned long long st64 = (unsigned long long)step;
         HIP_TRY(c, hipMemcpyAsync(R.d_step, &st64, sizeof(st64), hipMemcpyHostToDevice, s));
+        // The cell-list heads carry the stamp of the step that wrote them.
+        // After a rewind, heads written by the earlier pass over the same
+        // step numbers would read as live; clear them all.
+        if (R.cells.heads)
+            HIP_TRY(c, hipMemsetAsync(R.cells.heads, 0,
+                                      sizeof(unsigned long long) * (size_t)R.cells.n[0] * R.cells.n[1] * R.cells.n[2],
+                                      s));
     }
     HIP_TRY(c, hipMemsetAsync(R.bb.flag, 0, sizeof(unsigned int), s));
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -1168,6 +1175,7 @@ icm_status icm_get_state(icm_ctx* c, int32_t replica, void* v, double* q, double
         d->ke_fluid = acc[3];
         d->ke_blob = acc[11];
         d->max_div = acc[4] > 0 ? acc[5] / acc[4] : 0.0;
+        d->max_alpha = R.p.dt / R.p.h * std::max(acc[4], acc[12]);
         d->step = R.step;
     }
     HIP_TRY(c, hipStreamSynchronize(s));

@@ -187,25 +187,30 @@ __global__ void k_inertial_u(const RepDesc<T>* __restrict__ rd) {
 }
 
 __global__ void k_blob_diag(int nb, const double* me, const double* u, double* acc) {
-    // single block: sum m_e u (3) and sum m_e u^2 / 2
-    __shared__ double red[4][kThreads];
-    double s[4] = {0, 0, 0, 0};
+    // single block: sum m_e u (3), sum m_e u^2 / 2, and the largest velocity
+    // component max |u_a| (for the advective CFL number)
+    __shared__ double red[5][kThreads];
+    double s[5] = {0, 0, 0, 0, 0};
     for (int i = threadIdx.x; i < nb; i += blockDim.x) {
         const double m = me[i];
-        s[0] += m * u[3 * i];
-        s[1] += m * u[3 * i + 1];
-        s[2] += m * u[3 * i + 2];
-        s[3] += 0.5 * m * (u[3 * i] * u[3 * i] + u[3 * i + 1] * u[3 * i + 1] + u[3 * i + 2] * u[3 * i + 2]);
+        const double ux = u[3 * i], uy = u[3 * i + 1], uz = u[3 * i + 2];
+        s[0] += m * ux;
+        s[1] += m * uy;
+        s[2] += m * uz;
+        s[3] += 0.5 * m * (ux * ux + uy * uy + uz * uz);
+        s[4] = fmax(s[4], fmax(fabs(ux), fmax(fabs(uy), fabs(uz))));
     }
-    for (int m = 0; m < 4; ++m) red[m][threadIdx.x] = s[m];
+    for (int m = 0; m < 5; ++m) red[m][threadIdx.x] = s[m];
     __syncthreads();
     for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off)
+        if ((int)threadIdx.x < off) {
             for (int m = 0; m < 4; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + off];
+            red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + off]);
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int m = 0; m < 4; ++m) acc[m] = red[m][0];
+        for (int m = 0; m < 5; ++m) acc[m] = red[m][0];
 }
 
 dim3 grid3(const int nb, int nrep) { return dim3((unsigned)((3 * nb + kThreads - 1) / kThreads), nrep); }

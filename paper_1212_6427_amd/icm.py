@@ -69,6 +69,7 @@ class icm_diag(ctypes.Structure):
         ("ke_fluid", ctypes.c_double),
         ("ke_blob", ctypes.c_double),
         ("max_div", ctypes.c_double),
+        ("max_alpha", ctypes.c_double),
         ("step", ctypes.c_int64),
     ]
 
@@ -251,7 +252,7 @@ def icm_get_state(ctx, replica, n, field_dtype=np.float64, want_v=True, want_dia
     diag = None
     if want_diag:
         diag = dict(momentum=np.array(d.momentum[:]), ke_fluid=d.ke_fluid, ke_blob=d.ke_blob,
-                    max_div=d.max_div, step=d.step)
+                    max_div=d.max_div, max_alpha=d.max_alpha, step=d.step)
     return dict(v=v, q=q, u=u, lag_c=lag, diag=diag)
 
 

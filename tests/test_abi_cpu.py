@@ -27,7 +27,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(I.icm_replica_params) == 160
-    assert ctypes.sizeof(I.icm_diag) == 56
+    assert ctypes.sizeof(I.icm_diag) == 64
     assert ctypes.sizeof(I.icm_tune_result) == 48
 
 

@@ -67,3 +67,38 @@ def test_profile_summary_lists_every_step_kernel():
         hits = [n for n in names if n.startswith(prefix)]
         assert len(hits) == (2 if prefix == "k_y_fast<" else 1), prefix
     assert bench.PHASE_KERNEL["rhs"] in names
+
+
+def test_compact_record_is_small_and_carries_the_headline():
+    """The benchmark's last stdout line must survive a tail of a few KB: the
+    compact record keeps the headline keys, the roofline and the CPU
+    baseline, and summarises the other legs in a line each."""
+    import json
+    ph = {k: dict(avg_launch_us=10.0 + i, total_ms_per_step=0.01) for i, k in enumerate(
+        ("rhs", "fft_x_fwd", "fft_y_fwd", "fft_z_solve", "fft_y_inv", "fft_x_inv", "gather", "forces"))}
+    big = list(np.linspace(0, 1, 5000))
+    out = dict(metric=bench.METRIC, value=2.9e10, unit="cell-steps/s", n_gpus=1, steps=200, warmup=20,
+               ms_per_step=0.58, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+               data="synthetic", config={"workload": "many_blobs_256", "grid": [256] * 3},
+               blob_steps_per_s=7e6, step_hbm_fraction=0.17, step_traffic=None,
+               roofline=dict(bound="alu", kernel="k_rhs_march", achieved=17.0, peak=39.3, unit="TOP/s",
+                             frac=0.43, traffic=None, avg_launch_us=170.0, alg_ops_per_launch=1e9),
+               phases=ph,
+               cpu_baseline=dict(value=3e6, unit="cell-steps/s", cores=16, kind="oracle", sample="two steps",
+                                 cpu_model="x", one_core=dict(value=2e6), all_cores=dict(value=3e6)),
+               fp64=dict(value=1e10, ms_per_step=1.4, steps=50, step_hbm_fraction=0.14),
+               ensemble=dict(replicas=96, cells=12976128, batched=dict(ms_per_step=1.0, value=1.3e10),
+                             single=dict(ms_per_step=12.0), speedup_batched_vs_single=12.0),
+               scale_512=dict(fp32=dict(ms_per_step=5.7, momentum_drift_rel=1e-9),
+                              fp64=dict(ms_per_step=13.8, momentum_drift_rel=1e-18),
+                              max_rel_err_v=3e-5, max_rel_err_u=8e-6),
+               single_blob_128=dict(vacf=big), convergence=dict(errors=big))
+    line = json.dumps(bench.compact_record(out))
+    assert len(line) < 4096
+    c = json.loads(line)
+    for k in ("metric", "value", "unit", "steps", "warmup", "ms_per_step", "dtype", "config", "roofline",
+              "cpu_baseline"):
+        assert k in c, k
+    assert c["config"]["workload"] == "many_blobs_256"
+    assert c["cpu_baseline"]["cores"] == 16 and c["cpu_baseline"]["kind"] == "oracle"
+    assert c["ensemble"]["batched_ms_per_step"] == 1.0 and c["scale_512"]["max_rel_err_v"] == 3e-5

@@ -46,6 +46,9 @@ def run_parity(I, p, st, steps, precision, tol, name):
         print("errors:", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
         assert not bad, bad
         assert got["diag"]["step"] == st.step + steps
+        # the advective CFL number of the new state, reduced on the device
+        alpha = O.advective_cfl(p, ref)
+        assert abs(got["diag"]["max_alpha"] - alpha) <= tol * alpha
         return got, ref
     finally:
         sim.close()
@@ -351,6 +354,43 @@ def test_checkpoint_restart_continues_exactly(I, precision):
     for k in ("v", "u", "lag_c"):
         assert rel_err(got[k], ref[k]) < tol, k
     assert rel_err(got["q"] - ck["q"], ref["q"] - ck["q"]) < tol
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_rewind_in_the_same_context_with_wca(I, graph):
+    """icm_set_state with step = 0 after three steps, in the same context,
+    with the blobs moved by about one pair-force cell: the cell-list heads
+    of the first pass (stamped with the same step numbers) must not be read
+    as live, or pairs near the old cells are counted twice. The second pass
+    matches the oracle run from the new state."""
+    p = oracle_params((32, 32, 32), kernel=3, kT=1e-3, dt=0.2, seed=141, wca_eps=1e-2,
+                      wca_sigma=2.0 / 2 ** (1 / 6))
+    nb = 48
+    st1 = initial_state(p, nb, (0.0,), seed=21, min_sep=1.8)
+    # a cluster in a 10^3 sub-box so that many pairs lie within the cutoff
+    st1.q = icm_inputs.separated_positions(nb, (10, 10, 10), 1.0, min_sep=1.8, seed=21) + 9.0
+    st1.u = O.interp(p, st1.v, st1.q)
+    st2 = st1.copy()
+    st2.q = st1.q + np.array([2.3, 1.1, -0.7])
+    st2.u = O.interp(p, st2.v, st2.q)
+    banner("rewind with wca graph=%s" % graph)
+    flags = I.STEP_GRAPH if graph else 0
+    sim = I.Sim([gpu_params(I, p)], [nb], I.FP64)
+    try:
+        load_into_gpu(I, sim, 0, st1, np.float64)
+        sim.step(3, flags)
+        load_into_gpu(I, sim, 0, st2, np.float64)
+        sim.step(3, flags)
+        got = sim.get_state(0)
+    finally:
+        sim.close()
+    ref = O.run(p, st2, 3)
+    errs, bad = compare(got, ref, st2.q, TOL64)
+    print("errors:", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    assert not bad, bad
+    # the pair forces matter in this case
+    pairs = O.wca_forces(p, st2.q)
+    assert np.count_nonzero(np.any(pairs != 0.0, axis=1)) >= 4
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

@@ -672,3 +672,15 @@ def test_monte_carlo_low_density_limit_is_the_boltzmann_factor():
     sel = (r > 0.85) & (r < 1.55)
     assert np.max(np.abs(g[sel] - ref[sel])) < 0.06
     assert np.all(g[r < 0.8] == 0.0)
+
+
+def test_advective_cfl_number():
+    """Eq. (alpha_beta): alpha = V dt / dx with V the largest velocity
+    magnitude; a uniform flow sets it, and a faster blob takes over."""
+    p = P(n=(8, 8, 8), dt=0.3, h=0.5)
+    st = icm.new_state(p, [[1.0, 2.0, 3.0]])
+    st.v[1] = -0.2
+    st.v[0] = 0.1
+    assert icm.advective_cfl(p, st) == pytest.approx(0.2 * 0.3 / 0.5, rel=1e-15)
+    st.u[0] = [0.0, 0.0, 0.7]
+    assert icm.advective_cfl(p, st) == pytest.approx(0.7 * 0.3 / 0.5, rel=1e-15)
