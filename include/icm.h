@@ -289,6 +289,33 @@ icm_status icm_set_timing(icm_ctx* ctx, int32_t enable);
 /* Copy the accumulated timing into *out; reset != 0 clears it afterwards.  */
 icm_status icm_get_timing(icm_ctx* ctx, icm_timing* out, int32_t reset);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * spectral solve of icm_step and of icm_set_state(ICM_STATE_PROJECT) on
+ * caller-owned fields, with no context and no allocation. It computes
+ *   out = P (a + b lambda)^-1 rhs,
+ * i.e. solves (a - b L) w + G pi = rhs, D w = 0 by Fourier diagonalisation
+ * followed by projection (Sec. III.D), lambda = -L-hat >= 0 being the
+ * symbol of minus the 7-point Laplacian; the k = 0 mode is divided by a and
+ * not projected. a = rho/dt, b = eta/2 is step 2's Helmholtz operator, and
+ * a = 1, b = 0 the projection of ICM_STATE_PROJECT.
+ * n: Nx, Ny, Nz (even, 4..512, prime factors 2 and 3); h > 0; a > 0;
+ * b >= 0. precision: ICM_FP64 (rhs, out are double) or ICM_FP32_GRID
+ * (float). rhs, out: device face fields on the current device (3 arrays of
+ * Nx*Ny*Nz values, x fastest, as v); out may equal rhs. stream: hipStream_t
+ * of the current device (NULL: null stream). Work is enqueued only; the
+ * call does not synchronise.
+ * Every intermediate (spectrum, twiddle and symbol tables, descriptor) lives
+ * in a 64 MiB device array that the library holds on each GPU it runs on
+ * until the process ends: a grid whose spectrum needs more (above 128^3 in
+ * FP64, about 4.5 M cells in FP32) is rejected with ICM_E_INVALID and a
+ * message in icm_last_error(NULL), as are bad arguments. All calls on one
+ * GPU share that array: calls that overlap on one GPU (two streams, two
+ * host threads) race and must be serialised by the caller. Nothing in the
+ * array needs to start at zero; each call rewrites what it reads.          */
+icm_status icm_solve_noalloc(const int32_t n[3], double h, double a, double b, int32_t precision,
+                             const void* rhs, void* out, void* stream);
+
 /* Number of blobs currently installed in a replica (or -1 on a bad call). */
 int32_t icm_num_blobs(const icm_ctx* ctx, int32_t replica);
 

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libicm.so")
-SOURCES = ["api.hip", "fft.hip", "fft_fast.hip", "grid.hip", "blobs.hip"]
+SOURCES = ["api.hip", "fft.hip", "fft_fast.hip", "grid.hip", "blobs.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

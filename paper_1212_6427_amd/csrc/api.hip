@@ -22,7 +22,11 @@ using icm::cplx;
 
 namespace {
 
-thread_local std::string g_last_error = "no error";
+// message of the last failing call without a context: a fixed buffer, so
+// that recording an error allocates nothing
+thread_local char g_last_error[512] = "no error";
+
+void set_last_error(const char* msg) { snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
 
 struct Replica {
     icm_replica_params p;
@@ -96,7 +100,7 @@ icm_status fail(icm_ctx* c, icm_status st, const char* fmt, ...) {
     if (c)
         c->err = buf;
     else
-        g_last_error = buf;
+        set_last_error(buf);
     return st;
 }
 
@@ -110,16 +114,7 @@ icm_status fail(icm_ctx* c, icm_status st, const char* fmt, ...) {
     } while (0)
 
 // ------------------------------------------------------------ validation
-bool factor_plan(int n, icm::FFTPlan& pl) {
-    pl.n = n;
-    pl.nst = 0;
-    int m = n;
-    while (m % 8 == 0 && pl.nst < icm::kMaxStages) { pl.radix[pl.nst++] = 8; m /= 8; }
-    while (m % 4 == 0 && pl.nst < icm::kMaxStages) { pl.radix[pl.nst++] = 4; m /= 4; }
-    while (m % 2 == 0 && pl.nst < icm::kMaxStages) { pl.radix[pl.nst++] = 2; m /= 2; }
-    while (m % 3 == 0 && pl.nst < icm::kMaxStages) { pl.radix[pl.nst++] = 3; m /= 3; }
-    return m == 1;
-}
+using icm::factor_plan;
 
 // Nodes per axis of a replica's stencil: the split three-point kernel
 // (kernel_shift > 0) runs on the four-node layout.
@@ -237,26 +232,7 @@ struct Carver {
 
 template <typename T>
 void carve_grid(Carver& cv, const icm_replica_params& p, icm::GridDesc<T>& g) {
-    g.nx = p.n[0];
-    g.ny = p.n[1];
-    g.nz = p.n[2];
-    g.W = g.nx / 2 + 1;
-    g.fast = icm::fast_fft_available<T>(g.nx, g.ny, g.nz) ? 1 : 0;
-    // Launch shapes of the fast FFT passes (icm_autotune may change them):
-    // 128 bytes of kx columns per y / z block, 256 threads per x block, the
-    // smaller per-thread z plan.
-    g.By = 128 / (int)sizeof(cplx<T>);
-    g.Bz = 128 / (int)sizeof(cplx<T>);
-    g.xt = 256;
-    g.zsmall = 1;
-    g.ncell = (long long)g.nx * g.ny * g.nz;
-    // rows of the fast path hold kx < nx/2 (the Nyquist column has an array
-    // of its own), so that at nx = 256 they carry no padding
-    const int align = 128 / (int)sizeof(cplx<T>);
-    const int cols = g.fast ? g.nx / 2 : g.W;
-    g.Wp = (cols + align - 1) / align * align;
-    g.nspec = (long long)g.nz * g.ny * g.Wp;
-    g.h = p.h;
+    icm::grid_shape(g, p.n, p.h);
     g.hs = stencil_width(p) == p.kernel ? 0.0 : 0.5 * p.kernel_shift;
     g.v = cv.take<T>(3 * g.ncell);
     g.rhs = cv.take<T>(3 * g.ncell);
@@ -265,9 +241,6 @@ void carve_grid(Carver& cv, const icm_replica_params& p, icm::GridDesc<T>& g) {
     g.nyq = g.fast ? cv.take<cplx<T>>(3 * (long long)g.nz * g.ny) : nullptr;
     g.adv = p.advection ? cv.take<T>(3 * g.ncell) : nullptr;
     g.adv_hist = p.advection ? cv.take<unsigned int>(1) : nullptr;
-    factor_plan(g.nx, g.px);
-    factor_plan(g.ny, g.py);
-    factor_plan(g.nz, g.pz);
     g.twx = cv.take<cplx<T>>(g.nx);
     g.twy = cv.take<cplx<T>>(g.ny);
     g.twz = cv.take<cplx<T>>(g.nz);
@@ -935,7 +908,7 @@ icm_status icm_create(int32_t n_rep, const icm_replica_params* p, const int32_t*
         R.mt_f = 1.5 * R.m_f;
         st = (precision == ICM_FP64) ? upload_tables(c, R.gd) : upload_tables(c, R.gf);
         if (st != ICM_OK) {
-            g_last_error = c->err;
+            set_last_error(c->err.c_str());
             icm_destroy(c);
             return st;
         }
@@ -953,19 +926,19 @@ icm_status icm_create(int32_t n_rep, const icm_replica_params* p, const int32_t*
         if (e == hipSuccess && adv_hist_of(c, R))
             e = hipMemsetAsync(adv_hist_of(c, R), 0, sizeof(unsigned int), c->stream);
         if (e != hipSuccess) {
-            g_last_error = std::string("hipMemsetAsync failed: ") + hipGetErrorString(e);
+            snprintf(g_last_error, sizeof(g_last_error), "hipMemsetAsync failed: %s", hipGetErrorString(e));
             icm_destroy(c);
             return ICM_E_DEVICE;
         }
     }
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
-        g_last_error = "stream synchronisation failed after create";
+        set_last_error("stream synchronisation failed after create");
         icm_destroy(c);
         return ICM_E_DEVICE;
     }
     st = sync_batches(c);
     if (st != ICM_OK) {
-        g_last_error = c->err;
+        set_last_error(c->err.c_str());
         icm_destroy(c);
         return st;
     }
@@ -1300,6 +1273,17 @@ void icm_destroy(icm_ctx* c) {
     delete c;
 }
 
-const char* icm_last_error(const icm_ctx* c) { return c ? c->err.c_str() : g_last_error.c_str(); }
+const char* icm_last_error(const icm_ctx* c) { return c ? c->err.c_str() : g_last_error; }
 
 }  // extern "C"
+
+namespace icm {
+icm_status fail_without_context(icm_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return st;
+}
+}  // namespace icm
+

@@ -61,6 +61,51 @@ struct GridDesc {
     unsigned int* adv_hist;
 };
 
+// Mixed-radix plan of one FFT length (radix 8, then 4, 2, 3); false if N
+// has another prime factor or needs more than kMaxStages stages.
+inline bool factor_plan(int n, FFTPlan& pl) {
+    pl.n = n;
+    pl.nst = 0;
+    int m = n;
+    while (m % 8 == 0 && pl.nst < kMaxStages) { pl.radix[pl.nst++] = 8; m /= 8; }
+    while (m % 4 == 0 && pl.nst < kMaxStages) { pl.radix[pl.nst++] = 4; m /= 4; }
+    while (m % 2 == 0 && pl.nst < kMaxStages) { pl.radix[pl.nst++] = 2; m /= 2; }
+    while (m % 3 == 0 && pl.nst < kMaxStages) { pl.radix[pl.nst++] = 3; m /= 3; }
+    return m == 1;
+}
+
+template <typename T>
+bool fast_fft_available(int nx, int ny, int nz);
+
+// Shape fields of a grid descriptor (sizes, spectrum pitch, FFT plans and
+// the default launch shapes); the buffer and table pointers are left alone.
+template <typename T>
+void grid_shape(GridDesc<T>& g, const int32_t n[3], double h) {
+    g.nx = n[0];
+    g.ny = n[1];
+    g.nz = n[2];
+    g.W = g.nx / 2 + 1;
+    g.fast = fast_fft_available<T>(g.nx, g.ny, g.nz) ? 1 : 0;
+    // Launch shapes of the fast FFT passes (icm_autotune may change them):
+    // 128 bytes of kx columns per y / z block, 256 threads per x block, the
+    // smaller per-thread z plan.
+    g.By = 128 / (int)sizeof(cplx<T>);
+    g.Bz = 128 / (int)sizeof(cplx<T>);
+    g.xt = 256;
+    g.zsmall = 1;
+    g.ncell = (long long)g.nx * g.ny * g.nz;
+    // rows of the fast path hold kx < nx/2 (the Nyquist column has an array
+    // of its own), so that at nx = 256 they carry no padding
+    const int align = 128 / (int)sizeof(cplx<T>);
+    const int cols = g.fast ? g.nx / 2 : g.W;
+    g.Wp = (cols + align - 1) / align * align;
+    g.nspec = (long long)g.nz * g.ny * g.Wp;
+    g.h = h;
+    factor_plan(g.nx, g.px);
+    factor_plan(g.ny, g.py);
+    factor_plan(g.nz, g.pz);
+}
+
 // Spectral multiplier applied between the forward and inverse transforms:
 // w = P-hat( R-hat * scale / (a + b lambda) ), lambda = -L-hat >= 0.
 struct SolveCoef {

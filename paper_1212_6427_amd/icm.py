@@ -124,6 +124,9 @@ _lib.icm_set_timing.argtypes = [_p, ctypes.c_int32]
 _lib.icm_set_timing.restype = ctypes.c_int
 _lib.icm_get_timing.argtypes = [_p, ctypes.POINTER(icm_timing), ctypes.c_int32]
 _lib.icm_get_timing.restype = ctypes.c_int
+_lib.icm_solve_noalloc.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_int32, _p, _p, _p]
+_lib.icm_solve_noalloc.restype = ctypes.c_int
 _lib.icm_destroy.argtypes = [_p]
 _lib.icm_destroy.restype = None
 _lib.icm_last_error.argtypes = [_p]
@@ -229,6 +232,15 @@ def icm_autotune(ctx, capacity=64):
 
 def icm_step(ctx, n_steps, flags=0):
     _check(_lib.icm_step(ctx, int(n_steps), int(flags)), ctx)
+
+
+def icm_solve_noalloc(n, h, a, b, precision, rhs_ptr, out_ptr, stream=None):
+    """out = P (a + b lambda)^-1 rhs on device fields given by address
+    (e.g. torch data_ptr()), enqueued on `stream` (a hipStream_t handle);
+    no context and no allocation (see include/icm.h)."""
+    nn = (ctypes.c_int32 * 3)(*[int(x) for x in n])
+    _check(_lib.icm_solve_noalloc(nn, float(h), float(a), float(b), int(precision), ctypes.c_void_p(rhs_ptr),
+                                  ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream or 0)))
 
 
 def icm_num_blobs(ctx, replica):

@@ -124,3 +124,20 @@ def test_advection_adds_one_face_field_of_workspace(prec, w):
     on = I.icm_workspace_bytes([I.make_params(n, advection=True)], [4], getattr(I, prec))
     field = 3 * 32 * 24 * 16 * w
     assert field <= on - off <= field + 512
+
+
+def test_solve_noalloc_validates_before_touching_the_device():
+    """Bad sizes, coefficients, precision or NULL fields are refused with
+    ICM_E_INVALID and a message, before any HIP call (so also without a GPU)."""
+    bad = [((16, 16, 15), 1.0, 1.0, 0.0, I.FP64), ((16, 16, 1024), 1.0, 1.0, 0.0, I.FP64),
+           ((16, 14, 16), 1.0, 1.0, 0.0, I.FP64), ((16, 16, 16), 0.0, 1.0, 0.0, I.FP64),
+           ((16, 16, 16), 1.0, 0.0, 0.0, I.FP64), ((16, 16, 16), 1.0, 1.0, -1.0, I.FP64),
+           ((16, 16, 16), 1.0, 1.0, 0.0, 7)]
+    for n, h, a, b, prec in bad:
+        with pytest.raises(I.ICMError) as e:
+            I.icm_solve_noalloc(n, h, a, b, prec, 1 << 20, 1 << 20, 0)
+        assert e.value.status == I.E_INVALID, (n, h, a, b, prec)
+        assert "icm_solve_noalloc" in str(e.value)
+    with pytest.raises(I.ICMError) as e:
+        I.icm_solve_noalloc((16, 16, 16), 1.0, 1.0, 0.0, I.FP64, 0, 1 << 20, 0)
+    assert e.value.status == I.E_INVALID
