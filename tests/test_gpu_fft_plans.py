@@ -82,3 +82,46 @@ def test_single_blob_128_fp32(I):
     errs, bad = compare(got, ref, st.q, TOL32)
     print("errors:", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
     assert not bad, bad
+
+
+# ------------------------------------------- the benchmark's 256 x 256 planes
+# The x and y passes of the 256^3 benchmark (FP32), with a short z axis so
+# that the oracle stays cheap.
+@pytest.mark.parametrize("n", [(256, 256, 16), (256, 256, 48)])
+def test_256_planes_fp32(I, n):
+    p, st = _case(n, seed=260 + n[2])
+    st.v = st.v.astype(np.float32).astype(np.float64)
+    banner("256 planes fp32 n=%s" % (n,))
+    got = _run(I, p, st, 1, I.FP32_GRID)
+    ref = O.step(p, st)
+    errs, bad = compare(got, ref, st.q, TOL32)
+    print("errors:", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    assert not bad, bad
+
+
+def test_256_planes_kick_and_projection_fp32(I):
+    """The inverse x pass adding to the field (the t = 0 impulse of
+    ICM_BLOBS_KICK) and the projection initialiser on 256 x 256 planes. The
+    projected base field is small (max ~0.05) and the impulse of order one,
+    so both a lost base and a wrong impulse exceed the tolerance."""
+    from tests.parity_cases import rel_err
+    import icm_inputs
+    n = (256, 256, 16)
+    p = oracle_params(n, kernel=3, kT=0.0, dt=0.2, seed=271)
+    q = icm_inputs.separated_positions(3, n, min_sep=4.0, seed=272)
+    u0 = icm_inputs.random_forces(3, seed=273, scale=0.5)
+    w = icm_inputs.random_field(n, seed=274, scale=0.01).astype(np.float32).astype(np.float64)
+    banner("256 planes kick and projection fp32")
+    sim = I.Sim([gpu_params(I, p)], [3], I.FP32_GRID)
+    try:
+        sim.set_state(0, v=w.astype(np.float32), flags=I.STATE_PROJECT)
+        pw = O.project(p, w)
+        got = sim.get_state(0)["v"]
+        assert rel_err(got, pw) < TOL32
+        sim.set_blobs(0, q, u0, flags=I.BLOBS_KICK)
+        got = sim.get_state(0)["v"]
+        kick = O.kick_field(p, q, u0, np.zeros(3))
+        assert np.max(np.abs(kick)) > 10 * np.max(np.abs(pw))
+        assert rel_err(got, pw + kick) < TOL32
+    finally:
+        sim.close()
