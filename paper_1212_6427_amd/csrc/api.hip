@@ -241,6 +241,8 @@ void carve_grid(Carver& cv, const icm_replica_params& p, icm::GridDesc<T>& g) {
     g.nyq = g.fast ? cv.take<cplx<T>>(3 * (long long)g.nz * g.ny) : nullptr;
     g.adv = p.advection ? cv.take<T>(3 * g.ncell) : nullptr;
     g.adv_hist = p.advection ? cv.take<unsigned int>(1) : nullptr;
+    // FP32 grids carry the mean velocity (the k = 0 mode) in FP64
+    g.k0 = sizeof(T) == 4 ? cv.take<double>(9) : nullptr;
     g.twx = cv.take<cplx<T>>(g.nx);
     g.twy = cv.take<cplx<T>>(g.ny);
     g.twz = cv.take<cplx<T>>(g.nz);
@@ -492,6 +494,16 @@ icm::RepDesc<T> build_desc(const Replica& R) {
     return d;
 }
 
+// FP32-grid replicas carry their mean velocity in FP64; after the field
+// was set from outside the step, re-derive it from the stored field.
+icm_status reset_carry(icm_ctx* c, Replica& R, hipStream_t s) {
+    if (c->precision == ICM_FP64) return ICM_OK;
+    HIP_TRY(c, hipMemsetAsync(R.diag, 0, 16 * sizeof(double), s));
+    icm::launch_carry_init(R.gf, R.p.rho, R.diag, s);
+    HIP_TRY(c, hipGetLastError());
+    return ICM_OK;
+}
+
 void drop_graph(icm_ctx* c) {
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -583,7 +595,8 @@ void enqueue_fft_solve(icm_ctx* c, const icm::Batch<T>& B, int in, int out, bool
                        hipStream_t s) {
     timed(c, ICM_PHASE_FFT_X_FWD, s, [&] { icm::launch_fft_x_forward(B, in, s); });
     timed(c, ICM_PHASE_FFT_Y_FWD, s, [&] { icm::launch_fft_y(B, -1, s); });
-    timed(c, ICM_PHASE_FFT_Z_SOLVE, s, [&] { icm::launch_fft_z_solve(B, solve, true, s); });
+    timed(c, ICM_PHASE_FFT_Z_SOLVE, s,
+          [&] { icm::launch_fft_z_solve(B, solve, true, s, solve == icm::kSolveH1 || solve == icm::kSolveH2); });
     timed(c, ICM_PHASE_FFT_Y_INV, s, [&] { icm::launch_fft_y(B, 1, s); });
     timed(c, ICM_PHASE_FFT_X_INV, s, [&] { icm::launch_fft_x_inverse(B, out, accumulate, s); });
 }
@@ -923,6 +936,8 @@ icm_status icm_create(int32_t n_rep, const icm_replica_params* p, const int32_t*
             e = hipMemsetAsync(R.bb.chunk_count, 0,
                                sizeof(int) * ((p[r].n[2] + icm::kRhsZChunk - 1) / icm::kRhsZChunk + 1), c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(R.d_step, 0, sizeof(unsigned long long), c->stream);
+        if (e == hipSuccess && R.gf.k0 && precision == ICM_FP32_GRID)
+            e = hipMemsetAsync(R.gf.k0, 0, 9 * sizeof(double), c->stream);
         if (e == hipSuccess && adv_hist_of(c, R))
             e = hipMemsetAsync(adv_hist_of(c, R), 0, sizeof(unsigned int), c->stream);
         if (e != hipSuccess) {
@@ -995,6 +1010,8 @@ icm_status icm_set_blobs(icm_ctx* c, int32_t replica, int32_t n_blobs, const dou
     }
     R.nb = n_blobs;
     R.any_me = any;
+    if (c->precision == ICM_FP32_GRID)  // force sums of the carried mean (recomputed every step with blobs)
+        HIP_TRY(c, hipMemsetAsync(R.gf.k0 + 3, 0, 6 * sizeof(double), s));
     st = sync_batches(c);
     if (st != ICM_OK) return st;
     if ((flags & ICM_BLOBS_KICK) && n_blobs) {
@@ -1016,6 +1033,8 @@ icm_status icm_set_blobs(icm_ctx* c, int32_t replica, int32_t n_blobs, const dou
             kick<float>(c, R, s);
         HIP_TRY(c, hipGetLastError());
         if (adv_hist_of(c, R)) HIP_TRY(c, hipMemsetAsync(adv_hist_of(c, R), 0, sizeof(unsigned int), s));
+        st = reset_carry(c, R, s);
+        if (st != ICM_OK) return st;
     }
     HIP_TRY(c, hipStreamSynchronize(s));
     return ICM_OK;
@@ -1056,6 +1075,10 @@ icm_status icm_set_state(icm_ctx* c, int32_t replica, const void* v, const doubl
     // a new field starts the advective history again (first step: Euler)
     if (((flags & ICM_STATE_EQUILIBRIUM) || v) && adv_hist_of(c, R))
         HIP_TRY(c, hipMemsetAsync(adv_hist_of(c, R), 0, sizeof(unsigned int), s));
+    if ((flags & ICM_STATE_EQUILIBRIUM) || v) {
+        st = reset_carry(c, R, s);
+        if (st != ICM_OK) return st;
+    }
     if (q && n3) HIP_TRY(c, hipMemcpyAsync(R.bb.q, q, n3 * sizeof(double), kind, s));
     if (u && n3) HIP_TRY(c, hipMemcpyAsync(R.bb.u, u, n3 * sizeof(double), kind, s));
     if (lag_c && n3) {
@@ -1145,6 +1168,13 @@ icm_status icm_get_state(icm_ctx* c, int32_t replica, void* v, double* q, double
         HIP_TRY(c, hipMemcpyAsync(acc, R.diag, sizeof(acc), hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
         for (int a = 0; a < 3; ++a) d->momentum[a] = acc[a] + acc[8 + a];
+        if (R.gf.k0 && c->precision == ICM_FP32_GRID) {
+            // the fluid's momentum is the carried FP64 mean velocity times rho V
+            double k0[3];
+            HIP_TRY(c, hipMemcpy(k0, R.gf.k0, sizeof(k0), hipMemcpyDeviceToHost));
+            const double rv = R.p.rho * R.p.h * R.p.h * R.p.h * (double)R.gf.ncell;
+            for (int a = 0; a < 3; ++a) d->momentum[a] = rv * k0[a] + acc[8 + a];
+        }
         d->ke_fluid = acc[3];
         d->ke_blob = acc[11];
         d->max_div = acc[4] > 0 ? acc[5] / acc[4] : 0.0;

@@ -166,11 +166,17 @@ __global__ void k_inertial_dp(const RepDesc<T>* __restrict__ rd) {
     b.dp[t] = b.me[t / 3] * (b.u[t] - b.Jhvt[t] - du);
 }
 
-// Step 6 right-hand side: dp - m_e J dv~.
+// Step 6 right-hand side: dp - m_e J dv~. With the mean velocity carried
+// in FP64, an extra last block sums it over the replica's blobs (it forms
+// the same values itself, in a fixed order).
 template <typename T>
 __global__ void k_inertial_dp2(const RepDesc<T>* __restrict__ rd) {
     const BlobParams bp = rd[blockIdx.y].bp;
     const BlobBufs b = rd[blockIdx.y].bb;
+    if (rd[blockIdx.y].g.k0 && blockIdx.x == gridDim.x - 1) {
+        block_sum3(bp.nb, b.dp, b.me, b.g, rd[blockIdx.y].g.k0 + 6);
+        return;
+    }
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 3 * bp.nb) return;
     b.dp2[t] = b.dp[t] - b.me[t / 3] * b.g[t];
@@ -237,7 +243,10 @@ void launch_inertial_dp(const Batch<T>& B, hipStream_t s) {
 }
 template <typename T>
 void launch_inertial_dp2(const Batch<T>& B, hipStream_t s) {
-    if (B.max_nb > 0) hipLaunchKernelGGL(k_inertial_dp2<T>, grid3(B.max_nb, B.nrep), dim3(kThreads), 0, s, B.d);
+    if (B.max_nb <= 0) return;
+    dim3 grid = grid3(B.max_nb, B.nrep);
+    if (B.g.k0) grid.x += 1;  // the sum of dp - m_e g for the carried mean
+    hipLaunchKernelGGL(k_inertial_dp2<T>, grid, dim3(kThreads), 0, s, B.d);
 }
 template <typename T>
 void launch_inertial_u(const Batch<T>& B, hipStream_t s) {

@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(kThreads) k_zsolve(const RepDesc<T>* __restric
         w0 = {w0.x * f, w0.y * f};
         w1 = {w1.x * f, w1.y * f};
         w2 = {w2.x * f, w2.y * f};
-        if (project && lam > (T)0) {
+        if ((project & 1) && lam > (T)0) {
             const cplx<T> dx = g.dx_hat[kx], dz = g.dz_hat[z];
             const cplx<T> d = cadd(cadd(cmul(dx, w0), cmul(dy, w1)), cmul(dz, w2));
             const T il = (T)1 / lam;
@@ -304,6 +304,7 @@ __global__ void __launch_bounds__(kThreads) k_zsolve(const RepDesc<T>* __restric
             w1 = csub(w1, cmul(cconj(dy), dd));
             w2 = csub(w2, cmul(cconj(dz), dd));
         }
+        if ((project & 2) && g.k0 && kx == 0 && y == 0 && z == 0) carry_mean_mode(rd[blockIdx.z], solve, w0, w1, w2);
         e[0] = w0;
         e[B] = w1;
         e[2 * B] = w2;
@@ -369,15 +370,15 @@ void launch_fft_y(const Batch<T>& B, int dir, hipStream_t s) {
 }
 
 template <typename T>
-void launch_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s) {
+void launch_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s, bool carry) {
     const GridDesc<T>& g = B.g;
-    if (g.fast && fast_fft_z_solve(B, solve, project, s)) return;
+    if (g.fast && fast_fft_z_solve(B, solve, project, s, carry)) return;
     const size_t cs = sizeof(cplx<T>);
     const int N = g.nz;
     const int Bz = zpass_width(N, cs);
     const dim3 grid((unsigned)((g.W + Bz - 1) / Bz), g.ny, B.nrep);
     const size_t lds = (size_t)(N + 6 * N * Bz) * cs;
-    hipLaunchKernelGGL(k_zsolve<T>, grid, dim3(kThreads), lds, s, B.d, Bz, solve, project ? 1 : 0);
+    hipLaunchKernelGGL(k_zsolve<T>, grid, dim3(kThreads), lds, s, B.d, Bz, solve, (project ? 1 : 0) | (carry ? 2 : 0));
 }
 
 template <typename T>
@@ -396,7 +397,7 @@ void launch_fft_x_inverse(const Batch<T>& B, int out, bool accumulate, hipStream
 #define ICM_INST(T)                                                                     \
     template void launch_fft_x_forward<T>(const Batch<T>&, int, hipStream_t);           \
     template void launch_fft_y<T>(const Batch<T>&, int, hipStream_t);                   \
-    template void launch_fft_z_solve<T>(const Batch<T>&, int, bool, hipStream_t);       \
+    template void launch_fft_z_solve<T>(const Batch<T>&, int, bool, hipStream_t, bool); \
     template void launch_fft_x_inverse<T>(const Batch<T>&, int, bool, hipStream_t);
 ICM_INST(float)
 ICM_INST(double)

@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
             cplx<T> w0 = {a0[i].x * f, a0[i].y * f};
             cplx<T> w1 = {a1[i].x * f, a1[i].y * f};
             cplx<T> w2 = {a2[i].x * f, a2[i].y * f};
-            if (project && lam > (T)0) {
+            if ((project & 1) && lam > (T)0) {
                 const cplx<T> dz = gdz[kz];
                 const cplx<T> d = cadd(cadd(cmul(dx, w0), cmul(dy, w1)), cmul(dz, w2));
                 T il;
@@ -373,6 +373,9 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
             a1[i] = w1;
             a2[i] = w2;
         }
+        // mode k = 0 (kx = ky = kz = 0: thread t = 0, register 0 of column 0)
+        if ((project & 2) && g.k0 && !tail && kx == 0 && y == 0 && t == 0)
+            carry_mean_mode(rd[blockIdx.z], solve, a0[0], a1[0], a2[0]);
     }
     // each component is stored as soon as its inverse transform is done
     reg_fft<T, N, E, R0, R1, R2, 1>(a0, t, lds, B, b, tws);
@@ -669,7 +672,7 @@ bool y_fast(const Batch<T>& Bt, int dir, hipStream_t s) {
 }
 
 template <typename T, int N, typename Pl>
-bool z_fast_plan(const Batch<T>& Bt, int solve, bool project, hipStream_t s) {
+bool z_fast_plan(const Batch<T>& Bt, int solve, bool project, hipStream_t s, bool carry) {
     if constexpr (!Pl::ok) {
         return false;
     } else {
@@ -681,15 +684,15 @@ bool z_fast_plan(const Batch<T>& Bt, int solve, bool project, hipStream_t s) {
         const size_t lds = (size_t)N * (B + 1) * sizeof(cplx<T>);
         allow_lds(k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>, lds);
         hipLaunchKernelGGL((k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>), grid, dim3(B * TL), lds, s, Bt.d, B,
-                           solve, project ? 1 : 0);
+                           solve, (project ? 1 : 0) | (carry ? 2 : 0));
         return true;
     }
 }
 
 template <typename T, int N>
-bool z_fast(const Batch<T>& Bt, int solve, bool project, hipStream_t s) {
-    if (Bt.g.zsmall) return z_fast_plan<T, N, PlanZ<T, N>>(Bt, solve, project, s);
-    return z_fast_plan<T, N, Plan<T, N>>(Bt, solve, project, s);
+bool z_fast(const Batch<T>& Bt, int solve, bool project, hipStream_t s, bool carry) {
+    if (Bt.g.zsmall) return z_fast_plan<T, N, PlanZ<T, N>>(Bt, solve, project, s, carry);
+    return z_fast_plan<T, N, Plan<T, N>>(Bt, solve, project, s, carry);
 }
 
 template <typename T, int N>
@@ -766,8 +769,8 @@ bool fast_fft_y(const Batch<T>& B, int dir, hipStream_t s) {
 #undef C
 }
 template <typename T>
-bool fast_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s) {
-#define C(NN) z_fast<T, NN>(B, solve, project, s)
+bool fast_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s, bool carry) {
+#define C(NN) z_fast<T, NN>(B, solve, project, s, carry)
     ICM_SWITCH_N(B.g.nz, C)
 #undef C
 }
@@ -787,7 +790,7 @@ bool fast_fft_x_inverse(const Batch<T>& B, int out, bool acc, hipStream_t s) {
 #define ICM_INST(T)                                                                \
     template bool fast_fft_available<T>(int, int, int);                            \
     template bool fast_fft_y<T>(const Batch<T>&, int, hipStream_t);                \
-    template bool fast_fft_z_solve<T>(const Batch<T>&, int, bool, hipStream_t);    \
+    template bool fast_fft_z_solve<T>(const Batch<T>&, int, bool, hipStream_t, bool); \
     template bool fast_fft_x_forward<T>(const Batch<T>&, int, hipStream_t);        \
     template bool fast_fft_x_inverse<T>(const Batch<T>&, int, bool, hipStream_t);
 ICM_INST(float)

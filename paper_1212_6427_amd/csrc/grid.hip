@@ -815,6 +815,12 @@ template <typename T, int P>
 __global__ void __launch_bounds__(kThreads) k_bins(const RepDesc<T>* __restrict__ rd) {
     __shared__ int s_cnt[kMaxChunks];
     __shared__ int s_base[kMaxChunks];
+    if (rd[blockIdx.y].g.k0 && blockIdx.x == gridDim.x - 1) {
+        // the extra last block: the replica's total blob force, for the
+        // FP64-carried mean velocity (fixed summation order)
+        block_sum3(rd[blockIdx.y].bp.nb, rd[blockIdx.y].bb.F, nullptr, nullptr, rd[blockIdx.y].g.k0 + 3);
+        return;
+    }
     const int nb = rd[blockIdx.y].bp.nb, nz = rd[blockIdx.y].g.nz;
     const double h = rd[blockIdx.y].g.h;
     const double* __restrict__ qh = rd[blockIdx.y].bb.qh;
@@ -1095,7 +1101,8 @@ void launch_gather_bins(const Batch<T>& B, hipStream_t s) {
 template <typename T>
 void launch_bins(const Batch<T>& B, hipStream_t s) {
     if (B.max_nb <= 0) return;
-    const dim3 grid((unsigned)((B.max_nb + kThreads - 1) / kThreads), B.nrep);
+    // one more block when the mean velocity is carried (the force sum)
+    const dim3 grid((unsigned)((B.max_nb + kThreads - 1) / kThreads + (B.g.k0 ? 1 : 0)), B.nrep);
     if (B.kernel == 3)
         hipLaunchKernelGGL((k_bins<T, 3>), grid, dim3(kThreads), 0, s, B.d);
     else
@@ -1111,6 +1118,18 @@ void launch_gather_final(const Batch<T>& B, hipStream_t s) {
         hipLaunchKernelGGL((k_gather_final<T, 3>), grid, dim3(kThreads), 0, s, B.d, n_clear);
     else
         hipLaunchKernelGGL((k_gather_final<T, 4>), grid, dim3(kThreads), 0, s, B.d, n_clear);
+}
+
+__global__ void k_carry_from_sum(double* k0, const double* acc, double inv) {
+    if (threadIdx.x < 3) k0[threadIdx.x] = acc[threadIdx.x] * inv;
+}
+
+template <typename T>
+void launch_carry_init(const GridDesc<T>& g, double rho, double* acc, hipStream_t s) {
+    if (!g.k0) return;
+    launch_field_diag(g, rho, acc, s);
+    hipLaunchKernelGGL(k_carry_from_sum, dim3(1), dim3(64), 0, s, g.k0, acc,
+                       1.0 / (rho * g.h * g.h * g.h * (double)g.ncell));
 }
 
 template <typename T>
@@ -1129,6 +1148,7 @@ void launch_field_diag(const GridDesc<T>& g, double rho, double* acc, hipStream_
     template void launch_spread<T>(const Batch<T>&, int, int, int, int, hipStream_t);            \
     template void launch_gather<T>(const Batch<T>&, int, int, int, bool, hipStream_t);           \
     template void launch_field_diag<T>(const GridDesc<T>&, double, double*, hipStream_t);        \
+    template void launch_carry_init<T>(const GridDesc<T>&, double, double*, hipStream_t);        \
     template void launch_gather_predict<T>(const Batch<T>&, hipStream_t);                        \
     template void launch_gather_bins<T>(const Batch<T>&, hipStream_t);                           \
     template void launch_bins<T>(const Batch<T>&, hipStream_t);                                  \

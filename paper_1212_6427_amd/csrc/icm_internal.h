@@ -59,6 +59,10 @@ struct GridDesc {
     // and a flag that is 1 once it holds one
     T* adv;
     unsigned int* adv_hist;
+    // FP32-grid replicas: the k = 0 mode (mean velocity) carried in FP64.
+    // k0[0..2] mean of v, k0[3..5] sum of the blob forces F of the step,
+    // k0[6..8] sum of dp - m_e g (step 6); NULL in FP64 replicas
+    double* k0;
 };
 
 // Mixed-radix plan of one FFT length (radix 8, then 4, 2, 3); false if N
@@ -228,6 +232,57 @@ struct RepDesc {
     unsigned long long* step;   // step counter n (incremented at the end of the step)
 };
 
+// Sum over nb blobs of a 3-vector per blob, a[3i + c], or a[3i + c] -
+// m[i] b[3i + c] when m is given, by one workgroup of 256 threads in a fixed
+// order (so the same inputs give the same sum); thread 0 writes out[0..2].
+__device__ inline void block_sum3(int nb, const double* a, const double* m, const double* b, double* out) {
+    __shared__ double red[3][256];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+        for (int c = 0; c < 3; ++c) s[c] += m ? a[3 * i + c] - m[i] * b[3 * i + c] : a[3 * i + c];
+    for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = s[c];
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) out[c] = red[c][0];
+}
+
+// The k = 0 mode of a step's solve when the replica carries its mean
+// velocity in FP64 (called by the one thread that holds mode 0, after the
+// solve, before the inverse transforms; the inverse transforms are
+// unnormalised, so mode 0 becomes the mean of the output field).
+//   H1 (step 2): the mean of v~ is the mean of v^n plus (dt/rho)(sum F / V +
+//                f_body): spread forces keep their sum, while the viscous,
+//                stochastic, drift and advective terms have none.
+//   H2 (step 6): the mean of dv is sum (dp - m_e J dv~) / (rho V).
+// In both cases the carried mean advances by the same amount, so the total
+// momentum rho V mean + sum m_e u changes by exactly dt (sum F + V f_body).
+template <typename T>
+__device__ __forceinline__ void carry_mean_mode(const RepDesc<T>& R, int solve, cplx<T>& w0, cplx<T>& w1,
+                                                cplx<T>& w2) {
+    double* k0 = R.g.k0;
+    const double vol = (double)R.g.ncell * R.g.h * R.g.h * R.g.h;
+    double m[3];
+    if (solve == kSolveH1) {
+        for (int c = 0; c < 3; ++c) {
+            m[c] = k0[c] + (k0[3 + c] / vol + R.rc.body[c]) / R.rc.rho_dt;
+            k0[c] = m[c];
+        }
+    } else {
+        for (int c = 0; c < 3; ++c) {
+            m[c] = k0[6 + c] / (R.bp.rho * vol);
+            k0[c] += m[c];
+        }
+    }
+    w0 = cplx<T>{(T)m[0], (T)0};
+    w1 = cplx<T>{(T)m[1], (T)0};
+    w2 = cplx<T>{(T)m[2], (T)0};
+}
+
 // Host view of a batch: the device descriptors and the shape they share.
 template <typename T>
 struct Batch {
@@ -248,8 +303,11 @@ template <typename T>
 void launch_fft_x_forward(const Batch<T>& B, int in, hipStream_t s);
 template <typename T>
 void launch_fft_y(const Batch<T>& B, int dir, hipStream_t s);
+// carry: the solve of a step (H1 or H2) in a replica whose mean velocity is
+// carried in FP64 (GridDesc::k0): the k = 0 mode is set from the carried
+// mean and the exactly known change of total momentum, and the carry advanced.
 template <typename T>
-void launch_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s);
+void launch_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s, bool carry = false);
 template <typename T>
 void launch_fft_x_inverse(const Batch<T>& B, int out, bool accumulate, hipStream_t s);
 
@@ -260,7 +318,7 @@ bool fast_fft_available(int nx, int ny, int nz);
 template <typename T>
 bool fast_fft_y(const Batch<T>& B, int dir, hipStream_t s);
 template <typename T>
-bool fast_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s);
+bool fast_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s, bool carry = false);
 template <typename T>
 bool fast_fft_x_forward(const Batch<T>& B, int in, hipStream_t s);
 template <typename T>
@@ -313,6 +371,10 @@ void launch_bins(const Batch<T>& B, hipStream_t s);
 // acc[4] = max |v| (as bits), acc[5] = max |Dv| (as bits)
 template <typename T>
 void launch_field_diag(const GridDesc<T>& g, double rho, double* acc, hipStream_t s);
+// g.k0[0..2] = mean of g.v, reduced in FP64 (acc: 16 zeroed doubles of
+// scratch); nothing for replicas without the carry.
+template <typename T>
+void launch_carry_init(const GridDesc<T>& g, double rho, double* acc, hipStream_t s);
 
 // ----------------------------------------------------------- blob kernels
 template <typename T>
