@@ -42,6 +42,7 @@ struct Replica {
     double* diag = nullptr;  // 16 doubles
     unsigned long long* d_step = nullptr;  // device step counter
     int slot = 0;            // index of the replica's descriptor in the device array
+    bool tab_owner = false;  // builds the projection-kernel table of its grid shape
 };
 
 // Replicas stepped by the same launches: equal grid shape and kernel, the
@@ -55,6 +56,7 @@ struct BatchInfo {
     int first, count;
     int max_nb;
     bool any_cells, any_all_pairs;
+    bool table;              // step 5 through the projection-kernel table
     std::vector<int> reps;
 };
 
@@ -333,6 +335,35 @@ size_t layout(int32_t n_rep, const icm_replica_params* p, const int32_t* max_blo
         carve_blobs(cv, max_blobs[r], p[r].n[2], R.bb, R.diag);
         carve_cells(cv, p[r], max_blobs[r], R.cells);
     }
+    // projection-kernel tables, one per grid shape that holds a replica of at
+    // most kTabMaxBlobs blobs and at most kTabMaxCells cells
+    const size_t word = precision == ICM_FP64 ? sizeof(double) : sizeof(float);
+    std::vector<std::pair<std::array<int, 3>, void*>> shapes;
+    for (int r = 0; r < n_rep; ++r) {
+        const long long nc = (long long)p[r].n[0] * p[r].n[1] * p[r].n[2];
+        if (max_blobs[r] > icm::kTabMaxBlobs || nc > icm::kTabMaxCells) continue;
+        const std::array<int, 3> key = {p[r].n[0], p[r].n[1], p[r].n[2]};
+        void* tab = nullptr;
+        bool found = false;
+        for (auto& s : shapes)
+            if (s.first == key) {
+                tab = s.second;
+                found = true;
+            }
+        const bool owner = !found;
+        if (owner) {
+            tab = cv.take<unsigned char>(9 * (size_t)nc * word);
+            shapes.push_back({key, tab});
+        }
+        if (reps) {
+            Replica& R = (*reps)[r];
+            R.tab_owner = owner;
+            if (precision == ICM_FP64)
+                R.gd.ptab = static_cast<const double*>(tab);
+            else
+                R.gf.ptab = static_cast<const float*>(tab);
+        }
+    }
     return (cv.off + 255) & ~size_t(255);
 }
 
@@ -542,10 +573,12 @@ icm_status sync_batches_t(icm_ctx* c) {
         B.count = (int)B.reps.size();
         B.max_nb = 0;
         B.any_cells = B.any_all_pairs = false;
+        B.table = true;
         for (int r : B.reps) {
             Replica& R = c->reps[r];
             R.slot = slot;
             h[slot] = build_desc<T>(R);
+            B.table = B.table && h[slot].g.ptab != nullptr;
             B.max_nb = std::max(B.max_nb, R.nb);
             B.any_cells = B.any_cells || h[slot].pair_mode == 1;
             B.any_all_pairs = B.any_all_pairs || h[slot].pair_mode == 2;
@@ -624,11 +657,16 @@ void enqueue_step(icm_ctx* c, const BatchInfo& bi, hipStream_t s) {
         // Step 4: slip correction and excess-momentum change.
         timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather(B, kFieldV, kBlobQh, kBlobJhvt, false, s); });
         timed(c, ICM_PHASE_BLOB, s, [&] { launch_inertial_dp(B, s); });
-        // Step 5: dv~ = m~_f/(rho m~) P S dp.
-        timed(c, ICM_PHASE_FIELD_OPS, s, [&] { launch_zero(B, kFieldRhs, s); });
-        timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread(B, kFieldRhs, kBlobQh, kBlobDp, kBlobC5, s); });
-        enqueue_fft_solve(c, B, kFieldRhs, kFieldAux, false, kSolveP, s);
-        timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather(B, kFieldAux, kBlobQh, kBlobG, false, s); });
+        // Step 5: dv~ = m~_f/(rho m~) P S dp, needed only as g = J dv~: for
+        // few blobs through the projection-kernel table, else as a field.
+        if (bi.table && bi.max_nb <= kTabMaxBlobs) {
+            timed(c, ICM_PHASE_BLOB, s, [&] { launch_jps_table(B, s); });
+        } else {
+            timed(c, ICM_PHASE_FIELD_OPS, s, [&] { launch_zero(B, kFieldRhs, s); });
+            timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread(B, kFieldRhs, kBlobQh, kBlobDp, kBlobC5, s); });
+            enqueue_fft_solve(c, B, kFieldRhs, kFieldAux, false, kSolveP, s);
+            timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather(B, kFieldAux, kBlobQh, kBlobG, false, s); });
+        }
         // Step 6: (rho - dt/2 eta L) dv + dt G dpi = S (dp - m_e J dv~).
         timed(c, ICM_PHASE_BLOB, s, [&] { launch_inertial_dp2(B, s); });
         timed(c, ICM_PHASE_FIELD_OPS, s, [&] { launch_zero(B, kFieldRhs, s); });
@@ -666,6 +704,37 @@ void kick(icm_ctx* c, const Replica& R, hipStream_t s) {
     icm::launch_zero(B, icm::kFieldRhs, s);
     icm::launch_spread(B, icm::kFieldRhs, icm::kBlobQ, icm::kBlobDp, icm::kBlobNone, s);
     enqueue_project<T>(c, R, icm::kFieldRhs, true, s);
+}
+
+// The projection-kernel tables: for each grid shape that has one, its first
+// replica projects the unit impulse on face 0 of each component b with its
+// own scratch fields (the fluid is at rest right after create), and the
+// result, (P e_b)_a for a = x, y, z, is copied into the table.
+template <typename T>
+icm_status build_tables_t(icm_ctx* c) {
+    hipStream_t s = c->stream;
+    for (Replica& R : c->reps) {
+        if (!R.tab_owner) continue;
+        icm::GridDesc<T>& g = grid_of<T>(R);
+        const size_t fb = 3 * (size_t)g.ncell * sizeof(T);
+        const T one = 1;
+        for (int b = 0; b < 3; ++b) {
+            HIP_TRY(c, hipMemsetAsync(g.rhs, 0, fb, s));
+            HIP_TRY(c, hipMemcpyAsync(g.rhs + (size_t)b * g.ncell, &one, sizeof(T), hipMemcpyHostToDevice, s));
+            enqueue_project<T>(c, R, icm::kFieldRhs, false, s);
+            HIP_TRY(c, hipGetLastError());
+            HIP_TRY(c, hipMemcpyAsync(const_cast<T*>(g.ptab) + (size_t)b * 3 * g.ncell, g.v, fb,
+                                      hipMemcpyDeviceToDevice, s));
+            HIP_TRY(c, hipStreamSynchronize(s));  // `one` lives on the stack
+        }
+        HIP_TRY(c, hipMemsetAsync(g.v, 0, fb, s));
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return ICM_OK;
+}
+
+icm_status build_tables(icm_ctx* c) {
+    return c->precision == ICM_FP64 ? build_tables_t<double>(c) : build_tables_t<float>(c);
 }
 
 // Record one step of every batch into a graph (kernel launches only; the
@@ -952,6 +1021,7 @@ icm_status icm_create(int32_t n_rep, const icm_replica_params* p, const int32_t*
         return ICM_E_DEVICE;
     }
     st = sync_batches(c);
+    if (st == ICM_OK) st = build_tables(c);
     if (st != ICM_OK) {
         set_last_error(c->err.c_str());
         icm_destroy(c);

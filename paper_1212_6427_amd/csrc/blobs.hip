@@ -182,6 +182,75 @@ __global__ void k_inertial_dp2(const RepDesc<T>* __restrict__ rd) {
     b.dp2[t] = b.dp[t] - b.me[t / 3] * b.g[t];
 }
 
+// Step 5 for replicas with at most kTabMaxBlobs blobs: g_i = J_i dv~ with
+// dv~ = P S (c5 dp). Since dv~ enters the step only through J, it is never
+// formed: with K the tabulated real-space kernel of the discrete
+// projection, g_i,a = sum_j sum_b sum_{nodes x of J_i,a, y of S_j,b}
+// w(x) w(y) h^-3 K_ab[x - y] c5_j dp_j,b, the same linear map as spreading,
+// projecting and interpolating. One workgroup per replica; each output is
+// summed in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_jps_table(const RepDesc<T>* __restrict__ rd) {
+    __shared__ double red[kThreads];
+    const GridDesc<T> g = rd[blockIdx.x].g;
+    const BlobBufs b = rd[blockIdx.x].bb;
+    const int nb = rd[blockIdx.x].bp.nb;
+    const int P = rd[blockIdx.x].rb.kernel, P3 = P * P * P;
+    const double ih3 = 1.0 / (g.h * g.h * g.h);
+    const gptr<const T> K = as_global(g.ptab);
+    const gptr<const double> stc = as_global((const double*)b.stc);
+    for (int o = 0; o < 3 * nb; ++o) {
+        const int i = o / 3, al = o - 3 * (o / 3);
+        const gptr<const double> oi = stc + ((long long)i * 3 + al) * kStcPerComp;
+        double part = 0.0;
+        for (int it = threadIdx.x; it < nb * 3 * P3; it += blockDim.x) {
+            const int j = it / (3 * P3), rem = it - j * 3 * P3, be = rem / P3, a = rem - be * P3;
+            const double fj = b.c5[j] * b.dp[3 * j + be] * ih3;
+            if (fj == 0.0) continue;
+            const int ax = a % P, ay = (a / P) % P, az = a / (P * P);
+            int xa = (int)oi[0] + ax, ya = (int)oi[1] + ay, za = (int)oi[2] + az;
+            if (xa >= g.nx) xa -= g.nx;
+            if (ya >= g.ny) ya -= g.ny;
+            if (za >= g.nz) za -= g.nz;
+            const double wa = oi[3 + ax] * oi[7 + ay] * oi[11 + az];
+            const gptr<const double> oj = stc + ((long long)j * 3 + be) * kStcPerComp;
+            const gptr<const T> Kab = K + (long long)(be * 3 + al) * g.ncell;
+            double s = 0.0;
+            // node and offset both wrapped into [0, N): the source node
+            // base + b can pass N, and x_a - x_b then lies in (-N, N)
+            for (int bz = 0; bz < P; ++bz) {
+                int zb = (int)oj[2] + bz;
+                if (zb >= g.nz) zb -= g.nz;
+                int dz = za - zb;
+                if (dz < 0) dz += g.nz;
+                for (int by = 0; by < P; ++by) {
+                    int yb = (int)oj[1] + by;
+                    if (yb >= g.ny) yb -= g.ny;
+                    int dy = ya - yb;
+                    if (dy < 0) dy += g.ny;
+                    const double wyz = oj[7 + by] * oj[11 + bz];
+                    for (int bx = 0; bx < P; ++bx) {
+                        int xb = (int)oj[0] + bx;
+                        if (xb >= g.nx) xb -= g.nx;
+                        int dx = xa - xb;
+                        if (dx < 0) dx += g.nx;
+                        s += oj[3 + bx] * wyz * (double)Kab[((long long)dz * g.ny + dy) * g.nx + dx];
+                    }
+                }
+            }
+            part += wa * fj * s;
+        }
+        red[threadIdx.x] = part;
+        __syncthreads();
+        for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+            if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) b.g[o] = red[0];
+        __syncthreads();
+    }
+}
+
 // Step 8: u^{n+1} = J (v~ + dv~) + du for blobs with m_e != 0.
 template <typename T>
 __global__ void k_inertial_u(const RepDesc<T>* __restrict__ rd) {
@@ -249,6 +318,10 @@ void launch_inertial_dp2(const Batch<T>& B, hipStream_t s) {
     hipLaunchKernelGGL(k_inertial_dp2<T>, grid, dim3(kThreads), 0, s, B.d);
 }
 template <typename T>
+void launch_jps_table(const Batch<T>& B, hipStream_t s) {
+    if (B.max_nb > 0) hipLaunchKernelGGL(k_jps_table<T>, dim3(B.nrep), dim3(kThreads), 0, s, B.d);
+}
+template <typename T>
 void launch_inertial_u(const Batch<T>& B, hipStream_t s) {
     if (B.max_nb > 0) hipLaunchKernelGGL(k_inertial_u<T>, grid3(B.max_nb, B.nrep), dim3(kThreads), 0, s, B.d);
 }
@@ -260,7 +333,8 @@ void launch_blob_diag(int nb, const double* me, const double* u, double* acc, hi
     template void launch_forces<T>(const Batch<T>&, hipStream_t);            \
     template void launch_inertial_dp<T>(const Batch<T>&, hipStream_t);       \
     template void launch_inertial_dp2<T>(const Batch<T>&, hipStream_t);      \
-    template void launch_inertial_u<T>(const Batch<T>&, hipStream_t);
+    template void launch_inertial_u<T>(const Batch<T>&, hipStream_t);        \
+    template void launch_jps_table<T>(const Batch<T>&, hipStream_t);
 ICM_INST(float)
 ICM_INST(double)
 #undef ICM_INST

@@ -63,6 +63,11 @@ struct GridDesc {
     // k0[0..2] mean of v, k0[3..5] sum of the blob forces F of the step,
     // k0[6..8] sum of dp - m_e g (step 6); NULL in FP64 replicas
     double* k0;
+    // Few-blob replicas on grids up to 128^3: the real-space kernel of the
+    // discrete projection, K[(b * 3 + a) * ncell + cell] = (P e_b)_a at cell,
+    // e_b the unit impulse on face 0 of component b (shared by the replicas
+    // of one grid shape; P does not depend on h); NULL otherwise
+    const T* ptab;
 };
 
 // Mixed-radix plan of one FFT length (radix 8, then 4, 2, 3); false if N
@@ -383,6 +388,12 @@ template <typename T>
 void launch_inertial_dp(const Batch<T>& B, hipStream_t s);
 template <typename T>
 void launch_inertial_dp2(const Batch<T>& B, hipStream_t s);
+// Step 5 through the projection-kernel table: g = J P S (c5 dp) for every
+// blob, without forming the field (batches whose replicas have ptab).
+template <typename T>
+void launch_jps_table(const Batch<T>& B, hipStream_t s);
+constexpr int kTabMaxBlobs = 8;
+constexpr long long kTabMaxCells = 128LL * 128 * 128;
 template <typename T>
 void launch_inertial_u(const Batch<T>& B, hipStream_t s);
 void launch_blob_diag(int nb, const double* me, const double* u, double* acc, hipStream_t s);
