@@ -258,7 +258,7 @@ void carve_grid(Carver& cv, const icm_replica_params& p, icm::GridDesc<T>& g) {
 
 void carve_blobs(Carver& cv, int max_nb, int nz, icm::BlobBufs& b, double*& diag) {
     const size_t n3 = 3 * (size_t)max_nb;
-    const int nchunks = (nz + icm::kRhsZChunk - 1) / icm::kRhsZChunk;
+    const int nchunks = icm::max_chunks(nz);
     b.stc = cv.take<double>((size_t)max_nb * 3 * icm::kStcPerComp);
     b.chunk_count = cv.take<int>(nchunks + 1);
     b.chunk_list = cv.take<int>((size_t)nchunks * max_nb);
@@ -500,7 +500,7 @@ icm::RepDesc<T> build_desc(const Replica& R) {
     for (int a = 0; a < 3; ++a) d.rc.body[a] = p.body_force[a];
     d.rc.key = noise_key(R, 0);
     const icm::BlobBufs& b = R.bb;
-    const int nchunks = (g.nz + icm::kRhsZChunk - 1) / icm::kRhsZChunk;
+    const int nchunks = icm::max_chunks(g.nz);  // the overflow count follows the finest chunking's slots
     d.rb.nb = R.nb;
     d.rb.kernel = stencil_width(p);
     d.rb.cap = R.max_nb;
@@ -565,6 +565,15 @@ icm_status sync_batches_t(icm_ctx* c) {
             hit = &c->batches.back();
         }
         hit->reps.push_back(r);
+    }
+    // z-chunk of the RHS kernel per batch: the longest of 16, 8, 4 planes
+    // that still gives the batch's launch at least 512 workgroups (two per
+    // compute unit); the 16-plane chunk amortises each chunk's prologue best
+    for (BatchInfo& B : c->batches) {
+        const long long tiles = (long long)((B.n[0] + 31) / 32) * ((B.n[1] + 15) / 16) * (long long)B.reps.size();
+        int zc = icm::kRhsZChunk;
+        while (zc > icm::kRhsZChunkMin && tiles * ((B.n[2] + zc - 1) / zc) < 512) zc /= 2;
+        for (int r : B.reps) grid_of<T>(c->reps[r]).zc = zc;
     }
     std::vector<icm::RepDesc<T>> h(c->reps.size());
     int slot = 0;
@@ -1003,7 +1012,7 @@ icm_status icm_create(int32_t n_rep, const icm_replica_params* p, const int32_t*
                                c->stream);
         if (e == hipSuccess)
             e = hipMemsetAsync(R.bb.chunk_count, 0,
-                               sizeof(int) * ((p[r].n[2] + icm::kRhsZChunk - 1) / icm::kRhsZChunk + 1), c->stream);
+                               sizeof(int) * (icm::max_chunks(p[r].n[2]) + 1), c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(R.d_step, 0, sizeof(unsigned long long), c->stream);
         if (e == hipSuccess && R.gf.k0 && precision == ICM_FP32_GRID)
             e = hipMemsetAsync(R.gf.k0, 0, 9 * sizeof(double), c->stream);

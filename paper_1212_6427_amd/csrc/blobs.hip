@@ -187,67 +187,64 @@ __global__ void k_inertial_dp2(const RepDesc<T>* __restrict__ rd) {
 // formed: with K the tabulated real-space kernel of the discrete
 // projection, g_i,a = sum_j sum_b sum_{nodes x of J_i,a, y of S_j,b}
 // w(x) w(y) h^-3 K_ab[x - y] c5_j dp_j,b, the same linear map as spreading,
-// projecting and interpolating. One workgroup per replica; each output is
-// summed in a fixed order.
+// projecting and interpolating. The node weights are products over the
+// axes, so the double sum over nodes is a sum over the (2P - 1)^3 offsets s
+// of K_ab[base_i - base_j + s] times the product of the three 1-D
+// correlations c(s) = sum_m w_i[m] w_j[m - s] of the two stencils' weights.
+// One workgroup per replica; each output is summed in a fixed order.
+__device__ __forceinline__ double stencil_corr(gptr<const double> wa, gptr<const double> wb, int s, int P) {
+    double c = 0.0;
+    for (int m = 0; m < P; ++m) {
+        const int n = m - s;
+        if (n >= 0 && n < P) c += wa[m] * wb[n];
+    }
+    return c;
+}
+
+__device__ __forceinline__ int wrap_offset(int d, int n) {
+    d %= n;
+    return d < 0 ? d + n : d;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_jps_table(const RepDesc<T>* __restrict__ rd) {
-    __shared__ double red[kThreads];
     const GridDesc<T> g = rd[blockIdx.x].g;
     const BlobBufs b = rd[blockIdx.x].bb;
     const int nb = rd[blockIdx.x].bp.nb;
-    const int P = rd[blockIdx.x].rb.kernel, P3 = P * P * P;
+    const int P = rd[blockIdx.x].rb.kernel, Q = 2 * P - 1;
     const double ih3 = 1.0 / (g.h * g.h * g.h);
     const gptr<const T> K = as_global(g.ptab);
     const gptr<const double> stc = as_global((const double*)b.stc);
-    for (int o = 0; o < 3 * nb; ++o) {
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, nwaves = blockDim.x / 64;
+    // one wave per output (i, a); its lanes take the items (j, b, z offset,
+    // y offset), the x offsets run inside an item
+    for (int o = wave; o < 3 * nb; o += nwaves) {
         const int i = o / 3, al = o - 3 * (o / 3);
         const gptr<const double> oi = stc + ((long long)i * 3 + al) * kStcPerComp;
         double part = 0.0;
-        for (int it = threadIdx.x; it < nb * 3 * P3; it += blockDim.x) {
-            const int j = it / (3 * P3), rem = it - j * 3 * P3, be = rem / P3, a = rem - be * P3;
+        for (int it = lane; it < nb * 3 * Q * Q; it += 64) {
+            const int j = it / (3 * Q * Q), rem = it - j * 3 * Q * Q, be = rem / (Q * Q);
+            const int tz = (rem - be * Q * Q) / Q, ty = rem - be * Q * Q - tz * Q;
             const double fj = b.c5[j] * b.dp[3 * j + be] * ih3;
             if (fj == 0.0) continue;
-            const int ax = a % P, ay = (a / P) % P, az = a / (P * P);
-            int xa = (int)oi[0] + ax, ya = (int)oi[1] + ay, za = (int)oi[2] + az;
-            if (xa >= g.nx) xa -= g.nx;
-            if (ya >= g.ny) ya -= g.ny;
-            if (za >= g.nz) za -= g.nz;
-            const double wa = oi[3 + ax] * oi[7 + ay] * oi[11 + az];
             const gptr<const double> oj = stc + ((long long)j * 3 + be) * kStcPerComp;
-            const gptr<const T> Kab = K + (long long)(be * 3 + al) * g.ncell;
+            const double cyz = stencil_corr(oi + 11, oj + 11, tz - (P - 1), P) *
+                               stencil_corr(oi + 7, oj + 7, ty - (P - 1), P);
+            if (cyz == 0.0) continue;
+            const int dz = wrap_offset((int)oi[2] - (int)oj[2] + tz - (P - 1), g.nz);
+            const int dy = wrap_offset((int)oi[1] - (int)oj[1] + ty - (P - 1), g.ny);
+            const gptr<const T> row = K + (long long)(be * 3 + al) * g.ncell + ((long long)dz * g.ny + dy) * g.nx;
+            const int dx0 = (int)oi[0] - (int)oj[0] - (P - 1);
             double s = 0.0;
-            // node and offset both wrapped into [0, N): the source node
-            // base + b can pass N, and x_a - x_b then lies in (-N, N)
-            for (int bz = 0; bz < P; ++bz) {
-                int zb = (int)oj[2] + bz;
-                if (zb >= g.nz) zb -= g.nz;
-                int dz = za - zb;
-                if (dz < 0) dz += g.nz;
-                for (int by = 0; by < P; ++by) {
-                    int yb = (int)oj[1] + by;
-                    if (yb >= g.ny) yb -= g.ny;
-                    int dy = ya - yb;
-                    if (dy < 0) dy += g.ny;
-                    const double wyz = oj[7 + by] * oj[11 + bz];
-                    for (int bx = 0; bx < P; ++bx) {
-                        int xb = (int)oj[0] + bx;
-                        if (xb >= g.nx) xb -= g.nx;
-                        int dx = xa - xb;
-                        if (dx < 0) dx += g.nx;
-                        s += oj[3 + bx] * wyz * (double)Kab[((long long)dz * g.ny + dy) * g.nx + dx];
-                    }
-                }
+            for (int tx = 0; tx < Q; ++tx) {
+                const double cx = stencil_corr(oi + 3, oj + 3, tx - (P - 1), P);
+                if (cx != 0.0) s += cx * (double)row[wrap_offset(dx0 + tx, g.nx)];
             }
-            part += wa * fj * s;
+            part += fj * cyz * s;
         }
-        red[threadIdx.x] = part;
-        __syncthreads();
-        for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-            if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) b.g[o] = red[0];
-        __syncthreads();
+        // butterfly sum over the wave (the same order on every run)
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        if (lane == 0) b.g[o] = part;
     }
 }
 

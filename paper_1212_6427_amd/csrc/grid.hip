@@ -75,14 +75,14 @@ __global__ void __launch_bounds__(kThreads) k_spread_overflow(const RepDesc<T>* 
         if (r >= P * P) continue;
         const int b = rb.ovf_list[2 * pr], tile = rb.ovf_list[2 * pr + 1];
         const int txi = tile % tiles_x, tyi = (tile / tiles_x) % tiles_y, tzi = tile / (tiles_x * tiles_y);
-        const int i0 = txi * rtx, j0 = tyi * rty, k0 = tzi * kRhsZChunk;
+        const int i0 = txi * rtx, j0 = tyi * rty, k0 = tzi * g.zc;
         gptr<const double> o = as_global(rb.stc) + ((long long)b * 3 + a) * kStcPerComp;
         const int ib = r / P;
         const int y = ((int)o[1] + ib) % g.ny;
         if (y < j0 || y >= j0 + rty) continue;
         for (int ic = 0; ic < P; ++ic) {
             const int z = ((int)o[2] + ic) % g.nz;
-            if (z < k0 || z >= k0 + kRhsZChunk) continue;
+            if (z < k0 || z >= k0 + g.zc) continue;
             const int ia = r % P;
             const int x = ((int)o[0] + ia) % g.nx;
             if (x < i0 || x >= i0 + rtx) continue;
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(kThreads) k_spread_overflow(const RepDesc<T>* 
 // W_zz of plane k-1 is carried in a register, and the in-plane neighbours'
 // stresses and velocities are shared through LDS. Only the tile's one-cell
 // halo ring regenerates the few normals it needs.
-constexpr int RTX = 32, RTY = 16, RZC = kRhsZChunk;
+constexpr int RTX = 32, RTY = 16;
 
 // ONE: a batch of one replica whose descriptor comes by value in the kernel
 // arguments (constant memory the compiler may re-read at will); otherwise the
@@ -147,8 +147,8 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
     const gptr<const double> gstc = as_global(rb.stc);
     const gptr<const double> gF = as_global(rb.F);
     const int i0 = tile_x * RTX, j0 = tile_y * RTY;
-    const int k0 = tile_z * RZC;
-    const int k1 = min(k0 + RZC, nz);
+    const int k0 = tile_z * g.zc;
+    const int k1 = min(k0 + g.zc, nz);
     const int i = i0 + tx, j = j0 + ty;
     const bool own = (i < nx) && (j < ny);
     const long long plane = (long long)nx * ny;
@@ -810,7 +810,7 @@ __global__ void __launch_bounds__(kThreads) k_gather_bins(const RepDesc<T>* __re
 // chunks met by the planes of any component grid along z are counted per
 // workgroup in LDS and reserved in the global lists with one atomic per
 // (workgroup, chunk), which keeps same-address contention low.
-constexpr int kMaxChunks = 512 / kRhsZChunk;
+constexpr int kMaxChunks = 512 / kRhsZChunkMin;
 template <typename T, int P>
 __global__ void __launch_bounds__(kThreads) k_bins(const RepDesc<T>* __restrict__ rd) {
     __shared__ int s_cnt[kMaxChunks];
@@ -828,7 +828,8 @@ __global__ void __launch_bounds__(kThreads) k_bins(const RepDesc<T>* __restrict_
     int* __restrict__ chunk_count = rd[blockIdx.y].bb.chunk_count;
     int* __restrict__ chunk_list = rd[blockIdx.y].bb.chunk_list;
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nchunks = (nz + kRhsZChunk - 1) / kRhsZChunk;
+    const int zc = rd[blockIdx.y].g.zc;
+    const int nchunks = (nz + zc - 1) / zc;
     for (int i = threadIdx.x; i < nchunks; i += blockDim.x) s_cnt[i] = 0;
     __syncthreads();
     int c0 = -1, c1 = -1, s0 = 0, s1 = 0;
@@ -838,8 +839,8 @@ __global__ void __launch_bounds__(kThreads) k_bins(const RepDesc<T>* __restrict_
         const long long lo1 = (long long)((P == 3) ? floor(z) : floor(z - 0.5)) - 1;
         const long long zlo = lo0 < lo1 ? lo0 : lo1;
         const long long zhi = (lo0 > lo1 ? lo0 : lo1) + P - 1;
-        c0 = (int)(((zlo % nz) + nz) % nz) / kRhsZChunk;
-        c1 = (int)(((zhi % nz) + nz) % nz) / kRhsZChunk;
+        c0 = (int)(((zlo % nz) + nz) % nz) / zc;
+        c1 = (int)(((zhi % nz) + nz) % nz) / zc;
         if (c1 == c0 || nchunks == 1) c1 = -1;
         s0 = atomicAdd(&s_cnt[c0], 1);
         if (c1 >= 0) s1 = atomicAdd(&s_cnt[c1], 1);
@@ -1007,7 +1008,7 @@ unsigned grid_for(long long n) {
 template <typename T>
 void launch_rhs(const Batch<T>& B, hipStream_t s) {
     const GridDesc<T>& g = B.g;
-    const int ntz = (g.nz + RZC - 1) / RZC;
+    const int ntz = (g.nz + g.zc - 1) / g.zc;
     const dim3 grid((unsigned)((g.nx + RTX - 1) / RTX), (unsigned)((g.ny + RTY - 1) / RTY), (unsigned)(ntz * B.nrep));
     if (B.nrep == 1 && B.one)
         hipLaunchKernelGGL((k_rhs_march<T, true>), grid, dim3(RTX * RTY), 0, s, B.d, *B.one, ntz);
@@ -1112,7 +1113,7 @@ void launch_bins(const Batch<T>& B, hipStream_t s) {
 template <typename T>
 void launch_gather_final(const Batch<T>& B, hipStream_t s) {
     // always launched: its first block per replica advances the step counter
-    const int n_clear = (B.g.nz + kRhsZChunk - 1) / kRhsZChunk + 1;
+    const int n_clear = max_chunks(B.g.nz) + 1;  // every chunk count and the overflow count
     const dim3 grid(grid_for(48LL * (B.max_nb > 0 ? B.max_nb : 1)), B.nrep);
     if (B.kernel == 3)
         hipLaunchKernelGGL((k_gather_final<T, 3>), grid, dim3(kThreads), 0, s, B.d, n_clear);

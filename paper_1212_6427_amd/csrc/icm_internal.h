@@ -12,6 +12,14 @@ namespace icm {
 
 constexpr int kMaxStages = 16;
 
+// z-chunks of the right-hand-side kernel (see RhsBlobs)
+constexpr int kRhsZChunk = 16;    // default z-chunk (planes)
+constexpr int kRhsZChunkMin = 4;  // smallest z-chunk: sizes the bins; a stencil
+                                  // (at most 5 planes over the components)
+                                  // then meets at most two chunks
+// bin slots: chunk counts of the finest chunking, then the overflow count
+__host__ __device__ inline int max_chunks(int nz) { return (nz + kRhsZChunkMin - 1) / kRhsZChunkMin; }
+
 // Mixed-radix (2, 3, 4, 8) Stockham plan of one FFT length.
 struct FFTPlan {
     int n;
@@ -33,6 +41,8 @@ struct GridDesc {
     int By, Bz;        // kx columns per block of the fast y and z passes
     int xt;            // threads per block of the fast x passes
     int zsmall;        // 1: the z pass holds the smaller per-thread plan (FP32)
+    int zc;            // z planes per chunk of the right-hand-side kernel and its
+                       // blob bins (4, 8 or 16; chosen per batch)
     long long ncell;   // nx * ny * nz
     long long nspec;   // nz * ny * Wp (per component)
     double h;
@@ -102,6 +112,7 @@ void grid_shape(GridDesc<T>& g, const int32_t n[3], double h) {
     g.Bz = 128 / (int)sizeof(cplx<T>);
     g.xt = 256;
     g.zsmall = 1;
+    g.zc = kRhsZChunk;
     g.ncell = (long long)g.nx * g.ny * g.nz;
     // rows of the fast path hold kx < nx/2 (the Nyquist column has an array
     // of its own), so that at nx = 256 they carry no padding
@@ -135,11 +146,11 @@ struct RhsCoef {
 // component a, the wrapped base nodes (as doubles) of the P-tap stencil on
 // the a-component grid, the P weights of each axis, and the P derivative
 // weights phi'(d)/h along axis a (kStcPerComp values per component).
-// Blobs are binned by z-chunk of kRhsZChunk planes: chunk_count[c] blobs of
+// Blobs are binned by z-chunk of GridDesc::zc planes: chunk_count[c] blobs of
 // chunk c are listed at chunk_list[c * cap]. A tile that meets more than
 // kRhsTileCap blobs appends the excess (blob, tile) pairs to the overflow
 // list, which launch_spread_overflow spreads with atomics.
-constexpr int kRhsZChunk = 16;
+
 constexpr int kRhsTileCap = 128;
 constexpr int kStcPerComp = 3 + 4 * 4;
 struct RhsBlobs {
