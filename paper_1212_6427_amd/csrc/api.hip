@@ -45,19 +45,22 @@ struct Replica {
     bool tab_owner = false;  // builds the projection-kernel table of its grid shape
 };
 
-// Replicas stepped by the same launches: equal grid shape and kernel, the
-// same inertial path (all m_e = 0 or not) and advection setting. Their
-// descriptors occupy slots [first, first + count) of the device array.
+// Replicas stepped by the same launches: equal grid shape, kernel and
+// advection setting. Their descriptors occupy slots [first, first + count)
+// of the device array, the n_me replicas with a blob of nonzero excess mass
+// first: the inertial correction (steps 4-8) is launched over those slots
+// only, every other launch of the step over all of them.
 struct BatchInfo {
     int n[3];
     int kernel;
-    bool any_me;
     bool adv;
     int first, count;
     int max_nb;
     bool any_cells, any_all_pairs;
-    bool table;              // step 5 through the projection-kernel table
-    std::vector<int> reps;
+    int n_me;                // leading replicas on the inertial path
+    int me_max_nb;           // their largest blob count
+    bool table;              // their step 5 through the projection-kernel table
+    std::vector<int> reps;   // inertial replicas first
 };
 
 }  // namespace
@@ -553,19 +556,21 @@ icm_status sync_batches_t(icm_ctx* c) {
         BatchInfo* hit = nullptr;
         for (BatchInfo& B : c->batches)
             if (B.n[0] == R.p.n[0] && B.n[1] == R.p.n[1] && B.n[2] == R.p.n[2] && B.kernel == stencil_width(R.p) &&
-                B.any_me == R.any_me && B.adv == (R.p.advection != 0))
+                B.adv == (R.p.advection != 0))
                 hit = &B;
         if (!hit) {
             BatchInfo B{};
             for (int a = 0; a < 3; ++a) B.n[a] = R.p.n[a];
             B.kernel = stencil_width(R.p);
-            B.any_me = R.any_me;
             B.adv = R.p.advection != 0;
             c->batches.push_back(B);
             hit = &c->batches.back();
         }
         hit->reps.push_back(r);
     }
+    // inertial replicas first (a stable order within each part)
+    for (BatchInfo& B : c->batches)
+        std::stable_partition(B.reps.begin(), B.reps.end(), [c](int r) { return c->reps[r].any_me; });
     // z-chunk of the RHS kernel per batch: the longest of 16, 8, 4 planes
     // that still gives the batch's launch at least 512 workgroups (two per
     // compute unit); the 16-plane chunk amortises each chunk's prologue best
@@ -580,17 +585,21 @@ icm_status sync_batches_t(icm_ctx* c) {
     for (BatchInfo& B : c->batches) {
         B.first = slot;
         B.count = (int)B.reps.size();
-        B.max_nb = 0;
+        B.max_nb = B.me_max_nb = B.n_me = 0;
         B.any_cells = B.any_all_pairs = false;
         B.table = true;
         for (int r : B.reps) {
             Replica& R = c->reps[r];
             R.slot = slot;
             h[slot] = build_desc<T>(R);
-            B.table = B.table && h[slot].g.ptab != nullptr;
             B.max_nb = std::max(B.max_nb, R.nb);
             B.any_cells = B.any_cells || h[slot].pair_mode == 1;
             B.any_all_pairs = B.any_all_pairs || h[slot].pair_mode == 2;
+            if (R.any_me) {
+                ++B.n_me;
+                B.me_max_nb = std::max(B.me_max_nb, R.nb);
+                B.table = B.table && h[slot].g.ptab != nullptr;
+            }
             ++slot;
         }
     }
@@ -662,13 +671,15 @@ void enqueue_step(icm_ctx* c, const BatchInfo& bi, hipStream_t s) {
     timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread_overflow(B, s); });
     if (bi.adv) timed(c, ICM_PHASE_ADVECTION, s, [&] { launch_advect(B, s); });
     enqueue_fft_solve(c, B, kFieldRhs, kFieldV, false, kSolveH1, s);
-    if (bi.any_me) {
+    if (bi.n_me > 0) {
+        // steps 4-8 over the leading replicas with excess mass only
+        const icm::Batch<T> B = batch_view<T>(c, bi.first, bi.n_me, c->reps[bi.reps[0]], bi.me_max_nb, false, false);
         // Step 4: slip correction and excess-momentum change.
         timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather(B, kFieldV, kBlobQh, kBlobJhvt, false, s); });
         timed(c, ICM_PHASE_BLOB, s, [&] { launch_inertial_dp(B, s); });
         // Step 5: dv~ = m~_f/(rho m~) P S dp, needed only as g = J dv~: for
         // few blobs through the projection-kernel table, else as a field.
-        if (bi.table && bi.max_nb <= kTabMaxBlobs) {
+        if (bi.table && bi.me_max_nb <= kTabMaxBlobs) {
             timed(c, ICM_PHASE_BLOB, s, [&] { launch_jps_table(B, s); });
         } else {
             timed(c, ICM_PHASE_FIELD_OPS, s, [&] { launch_zero(B, kFieldRhs, s); });
@@ -748,7 +759,8 @@ icm_status build_tables(icm_ctx* c) {
 
 // Record one step of every batch into a graph (kernel launches only; the
 // step counters and all per-replica data live in device memory). Batches
-// touch disjoint memory, so each is its own branch of the graph: the first
+// (one per grid shape, kernel and advection setting) touch disjoint memory,
+// so each is its own branch of the graph: the first
 // on the capture stream, the others on branch streams forked from it by an
 // event and joined back at the end.
 icm_status capture_step(icm_ctx* c) {

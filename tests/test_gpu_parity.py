@@ -207,7 +207,9 @@ def test_batched_uneven_replicas_match_single(I, precision):
 
 def _batch_cases():
     """Six replicas, two grid shapes; one shape mixes m_e = 0 and m_e != 0
-    replicas (two batches), the other takes the generic FFT path."""
+    replicas (one batch whose inertial correction runs over its replicas
+    1-3 only, ordered before replica 0), the other takes the generic FFT
+    path."""
     cases = []
     mes = [(0.0,), (1.0,), (-0.5,), (0.0, 1.0)]
     for i, me in enumerate(mes):
