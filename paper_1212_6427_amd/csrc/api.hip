@@ -642,7 +642,7 @@ icm::Batch<T> single(icm_ctx* c, const Replica& R) {
 
 // Forward transform, spectral solve, inverse transform.
 template <typename T>
-void enqueue_fft_solve(icm_ctx* c, const icm::Batch<T>& B, int in, int out, bool accumulate, int solve,
+void enqueue_fft_solve(icm_ctx* c, const icm::Batch<T>& B, int in, int out, int accumulate, int solve,
                        hipStream_t s) {
     timed(c, ICM_PHASE_FFT_X_FWD, s, [&] { icm::launch_fft_x_forward(B, in, s); });
     timed(c, ICM_PHASE_FFT_Y_FWD, s, [&] { icm::launch_fft_y(B, -1, s); });
@@ -661,8 +661,7 @@ void enqueue_step(icm_ctx* c, const BatchInfo& bi, hipStream_t s) {
     // Step 1: midpoint predictor with the one-body forces; J^{n+1/2} v^n (for
     // step 9) with the spread stencils and the cell lists; pair forces;
     // z-chunk bins of the spread.
-    timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather_predict(B, s); });
-    timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather_bins(B, s); });
+    timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather_step1(B, s); });
     timed(c, ICM_PHASE_FORCES, s, [&] { launch_forces(B, s); });
     timed(c, ICM_PHASE_SPREAD, s, [&] { launch_bins(B, s); });
     // Step 2: unperturbed fluid solve; S F and the thermal drift are spread
@@ -670,35 +669,34 @@ void enqueue_step(icm_ctx* c, const BatchInfo& bi, hipStream_t s) {
     timed(c, ICM_PHASE_RHS, s, [&] { launch_rhs(B, s); });
     timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread_overflow(B, s); });
     if (bi.adv) timed(c, ICM_PHASE_ADVECTION, s, [&] { launch_advect(B, s); });
-    enqueue_fft_solve(c, B, kFieldRhs, kFieldV, false, kSolveH1, s);
+    enqueue_fft_solve(c, B, kFieldRhs, kFieldV, 0, kSolveH1, s);
     if (bi.n_me > 0) {
         // steps 4-8 over the leading replicas with excess mass only
         const icm::Batch<T> B = batch_view<T>(c, bi.first, bi.n_me, c->reps[bi.reps[0]], bi.me_max_nb, false, false);
-        // Step 4: slip correction and excess-momentum change.
-        timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather(B, kFieldV, kBlobQh, kBlobJhvt, false, s); });
-        timed(c, ICM_PHASE_BLOB, s, [&] { launch_inertial_dp(B, s); });
+        // Step 4: J^{n+1/2} v~, the slip correction and the excess momentum.
+        timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather(B, kFieldV, kBlobQh, kBlobJhvt, false, s, kEpiDp); });
         // Step 5: dv~ = m~_f/(rho m~) P S dp, needed only as g = J dv~: for
-        // few blobs through the projection-kernel table, else as a field.
+        // few blobs through the projection-kernel table, else as a field;
+        // with g, the step-6 source dp - m_e J dv~ and u^{n+1} (step 8).
         if (bi.table && bi.me_max_nb <= kTabMaxBlobs) {
             timed(c, ICM_PHASE_BLOB, s, [&] { launch_jps_table(B, s); });
         } else {
             timed(c, ICM_PHASE_FIELD_OPS, s, [&] { launch_zero(B, kFieldRhs, s); });
             timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread(B, kFieldRhs, kBlobQh, kBlobDp, kBlobC5, s); });
-            enqueue_fft_solve(c, B, kFieldRhs, kFieldAux, false, kSolveP, s);
-            timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather(B, kFieldAux, kBlobQh, kBlobG, false, s); });
+            enqueue_fft_solve(c, B, kFieldRhs, kFieldAux, 0, kSolveP, s);
+            timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather(B, kFieldAux, kBlobQh, kBlobG, false, s, kEpiDp2); });
+            timed(c, ICM_PHASE_BLOB, s, [&] { launch_dp2_sum(B, s); });
         }
-        // Step 6: (rho - dt/2 eta L) dv + dt G dpi = S (dp - m_e J dv~).
-        timed(c, ICM_PHASE_BLOB, s, [&] { launch_inertial_dp2(B, s); });
+        // Step 6: (rho - dt/2 eta L) dv + dt G dpi = S (dp - m_e J dv~);
+        // step 7: v^{n+1} = v~ + dv, written by the last pass with dv itself
+        // (kept in aux for the lagged term gathered in step 9).
         timed(c, ICM_PHASE_FIELD_OPS, s, [&] { launch_zero(B, kFieldRhs, s); });
         timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread(B, kFieldRhs, kBlobQh, kBlobDp2, kBlobNone, s); });
-        enqueue_fft_solve(c, B, kFieldRhs, kFieldAux, false, kSolveH2, s);
-        // Step 7, lagged J L dv, step 8.
-        timed(c, ICM_PHASE_FIELD_OPS, s, [&] { launch_axpy(B, kFieldV, kFieldAux, s); });
-        timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather(B, kFieldAux, kBlobQh, kBlobLag, true, s); });
-        timed(c, ICM_PHASE_BLOB, s, [&] { launch_inertial_u(B, s); });
+        enqueue_fft_solve(c, B, kFieldRhs, kFieldAux, kXinvAlsoV, kSolveH2, s);
     }
-    // Step 9 (also advances the device step counters).
-    timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather_final(B, s); });
+    // Step 9 (also the lagged term of the inertial replicas and the device
+    // step counters).
+    timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather_final(B, bi.n_me, s); });
 }
 
 template <typename T>

@@ -151,35 +151,13 @@ __global__ void __launch_bounds__(kThreads) k_pairs(const RepDesc<T>* __restrict
     }
 }
 
-// Step 4: du = [FULL] (J^{n+1/2} - J^n) v^n + [VISCOUS|FULL] (nu dt/2) c_lag;
-// dp = m_e (u^n - J^{n+1/2} v~ - du).
+// With the mean velocity carried in FP64: the sum over a replica's blobs of
+// the step-6 source dp - m_e g, formed again here in a fixed order (one
+// workgroup per replica).
 template <typename T>
-__global__ void k_inertial_dp(const RepDesc<T>* __restrict__ rd) {
-    const BlobParams bp = rd[blockIdx.y].bp;
-    const BlobBufs b = rd[blockIdx.y].bb;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * bp.nb) return;
-    double du = 0.0;
-    if (bp.slip == 2) du += b.Jhvn[t] - b.Jn[t];
-    if (bp.slip >= 1) du += 0.5 * (bp.eta / bp.rho) * bp.dt * b.lag[t];
-    b.du[t] = du;
-    b.dp[t] = b.me[t / 3] * (b.u[t] - b.Jhvt[t] - du);
-}
-
-// Step 6 right-hand side: dp - m_e J dv~. With the mean velocity carried
-// in FP64, an extra last block sums it over the replica's blobs (it forms
-// the same values itself, in a fixed order).
-template <typename T>
-__global__ void k_inertial_dp2(const RepDesc<T>* __restrict__ rd) {
-    const BlobParams bp = rd[blockIdx.y].bp;
-    const BlobBufs b = rd[blockIdx.y].bb;
-    if (rd[blockIdx.y].g.k0 && blockIdx.x == gridDim.x - 1) {
-        block_sum3(bp.nb, b.dp, b.me, b.g, rd[blockIdx.y].g.k0 + 6);
-        return;
-    }
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * bp.nb) return;
-    b.dp2[t] = b.dp[t] - b.me[t / 3] * b.g[t];
+__global__ void __launch_bounds__(kThreads) k_dp2_sum(const RepDesc<T>* __restrict__ rd) {
+    const BlobBufs b = rd[blockIdx.x].bb;
+    block_sum3(rd[blockIdx.x].bp.nb, b.dp, b.me, b.g, rd[blockIdx.x].g.k0 + 6);
 }
 
 // Step 5 for replicas with at most kTabMaxBlobs blobs: g_i = J_i dv~ with
@@ -191,7 +169,9 @@ __global__ void k_inertial_dp2(const RepDesc<T>* __restrict__ rd) {
 // axes, so the double sum over nodes is a sum over the (2P - 1)^3 offsets s
 // of K_ab[base_i - base_j + s] times the product of the three 1-D
 // correlations c(s) = sum_m w_i[m] w_j[m - s] of the two stencils' weights.
-// One workgroup per replica; each output is summed in a fixed order.
+// One workgroup per replica; each output is summed in a fixed order. Then
+// the step-6 source dp2 = dp - m_e g, u^{n+1} = J v~ + g + du for m_e != 0
+// (step 8) and, with the mean velocity carried in FP64, the sum of dp2.
 __device__ __forceinline__ double stencil_corr(gptr<const double> wa, gptr<const double> wb, int s, int P) {
     double c = 0.0;
     for (int m = 0; m < P; ++m) {
@@ -246,16 +226,13 @@ __global__ void __launch_bounds__(kThreads) k_jps_table(const RepDesc<T>* __rest
         for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
         if (lane == 0) b.g[o] = part;
     }
-}
-
-// Step 8: u^{n+1} = J (v~ + dv~) + du for blobs with m_e != 0.
-template <typename T>
-__global__ void k_inertial_u(const RepDesc<T>* __restrict__ rd) {
-    const BlobParams bp = rd[blockIdx.y].bp;
-    const BlobBufs b = rd[blockIdx.y].bb;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * bp.nb) return;
-    if (b.me[t / 3] != 0.0) b.u[t] = b.Jhvt[t] + b.g[t] + b.du[t];
+    __syncthreads();
+    for (int t = threadIdx.x; t < 3 * nb; t += blockDim.x) {
+        const double me = b.me[t / 3], gt = b.g[t];
+        b.dp2[t] = b.dp[t] - me * gt;
+        if (me != 0.0) b.u[t] = b.Jhvt[t] + gt + b.du[t];
+    }
+    if (g.k0) block_sum3(nb, b.dp, b.me, b.g, g.k0 + 6);
 }
 
 __global__ void k_blob_diag(int nb, const double* me, const double* u, double* acc) {
@@ -285,8 +262,6 @@ __global__ void k_blob_diag(int nb, const double* me, const double* u, double* a
         for (int m = 0; m < 5; ++m) acc[m] = red[m][0];
 }
 
-dim3 grid3(const int nb, int nrep) { return dim3((unsigned)((3 * nb + kThreads - 1) / kThreads), nrep); }
-
 }  // namespace
 
 template <typename T>
@@ -304,23 +279,12 @@ void launch_forces(const Batch<T>& B, hipStream_t s) {
     }
 }
 template <typename T>
-void launch_inertial_dp(const Batch<T>& B, hipStream_t s) {
-    if (B.max_nb > 0) hipLaunchKernelGGL(k_inertial_dp<T>, grid3(B.max_nb, B.nrep), dim3(kThreads), 0, s, B.d);
-}
-template <typename T>
-void launch_inertial_dp2(const Batch<T>& B, hipStream_t s) {
-    if (B.max_nb <= 0) return;
-    dim3 grid = grid3(B.max_nb, B.nrep);
-    if (B.g.k0) grid.x += 1;  // the sum of dp - m_e g for the carried mean
-    hipLaunchKernelGGL(k_inertial_dp2<T>, grid, dim3(kThreads), 0, s, B.d);
+void launch_dp2_sum(const Batch<T>& B, hipStream_t s) {
+    if (B.max_nb > 0 && B.g.k0) hipLaunchKernelGGL(k_dp2_sum<T>, dim3(B.nrep), dim3(kThreads), 0, s, B.d);
 }
 template <typename T>
 void launch_jps_table(const Batch<T>& B, hipStream_t s) {
     if (B.max_nb > 0) hipLaunchKernelGGL(k_jps_table<T>, dim3(B.nrep), dim3(kThreads), 0, s, B.d);
-}
-template <typename T>
-void launch_inertial_u(const Batch<T>& B, hipStream_t s) {
-    if (B.max_nb > 0) hipLaunchKernelGGL(k_inertial_u<T>, grid3(B.max_nb, B.nrep), dim3(kThreads), 0, s, B.d);
 }
 void launch_blob_diag(int nb, const double* me, const double* u, double* acc, hipStream_t s) {
     hipLaunchKernelGGL(k_blob_diag, dim3(1), dim3(kThreads), 0, s, nb, me, u, acc);
@@ -328,9 +292,7 @@ void launch_blob_diag(int nb, const double* me, const double* u, double* acc, hi
 
 #define ICM_INST(T)                                                          \
     template void launch_forces<T>(const Batch<T>&, hipStream_t);            \
-    template void launch_inertial_dp<T>(const Batch<T>&, hipStream_t);       \
-    template void launch_inertial_dp2<T>(const Batch<T>&, hipStream_t);      \
-    template void launch_inertial_u<T>(const Batch<T>&, hipStream_t);        \
+    template void launch_dp2_sum<T>(const Batch<T>&, hipStream_t);           \
     template void launch_jps_table<T>(const Batch<T>&, hipStream_t);
 ICM_INST(float)
 ICM_INST(double)

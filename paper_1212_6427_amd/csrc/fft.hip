@@ -212,12 +212,18 @@ __global__ void __launch_bounds__(kThreads) k_xinv(const RepDesc<T>* __restrict_
     __syncthreads();
     cplx<T>* r = lds_fft<T, 1>(b0, b1, g.px, pp, N, 1, tw);
     T* dst = out + (long long)c * g.ncell;
+    T* vv = g.v + (long long)c * g.ncell;
     for (int idx = threadIdx.x; idx < pp * N; idx += blockDim.x) {
         const int l = idx / N, x = idx - l * N;
         const long long p = p0 + l;
         if (p >= npairs) continue;
         const cplx<T> z = r[idx];
-        if (accumulate) {
+        if (accumulate == kXinvAlsoV) {
+            dst[(2 * p) * N + x] = z.x;
+            dst[(2 * p + 1) * N + x] = z.y;
+            vv[(2 * p) * N + x] += z.x;
+            vv[(2 * p + 1) * N + x] += z.y;
+        } else if (accumulate) {
             dst[(2 * p) * N + x] += z.x;
             dst[(2 * p + 1) * N + x] += z.y;
         } else {
@@ -382,7 +388,7 @@ void launch_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t 
 }
 
 template <typename T>
-void launch_fft_x_inverse(const Batch<T>& B, int out, bool accumulate, hipStream_t s) {
+void launch_fft_x_inverse(const Batch<T>& B, int out, int accumulate, hipStream_t s) {
     const GridDesc<T>& g = B.g;
     if (g.fast && fast_fft_x_inverse(B, out, accumulate, s)) return;
     const size_t cs = sizeof(cplx<T>);
@@ -391,14 +397,14 @@ void launch_fft_x_inverse(const Batch<T>& B, int out, bool accumulate, hipStream
     const long long npairs = (long long)g.ny * g.nz / 2;
     const dim3 grid((unsigned)((npairs + pp - 1) / pp), 3 * B.nrep);
     const size_t lds = (size_t)(N + 2 * pp * N) * cs;
-    hipLaunchKernelGGL(k_xinv<T>, grid, dim3(kThreads), lds, s, B.d, out, (int)pp, accumulate ? 1 : 0);
+    hipLaunchKernelGGL(k_xinv<T>, grid, dim3(kThreads), lds, s, B.d, out, (int)pp, accumulate);
 }
 
 #define ICM_INST(T)                                                                     \
     template void launch_fft_x_forward<T>(const Batch<T>&, int, hipStream_t);           \
     template void launch_fft_y<T>(const Batch<T>&, int, hipStream_t);                   \
     template void launch_fft_z_solve<T>(const Batch<T>&, int, bool, hipStream_t, bool); \
-    template void launch_fft_x_inverse<T>(const Batch<T>&, int, bool, hipStream_t);
+    template void launch_fft_x_inverse<T>(const Batch<T>&, int, int, hipStream_t);
 ICM_INST(float)
 ICM_INST(double)
 #undef ICM_INST

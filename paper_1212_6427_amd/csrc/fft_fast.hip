@@ -570,6 +570,22 @@ __global__ void __launch_bounds__(512) k_xinv_fast(const RepDesc<T>* __restrict_
         }
         const gptr<Vec16<T>> oa = (gptr<Vec16<T>>)(out + o);
         const gptr<Vec16<T>> ob = (gptr<Vec16<T>>)(out + o + N);
+        if (accumulate == kXinvAlsoV) {
+            // write the field and add it to v (v += dv of step 7)
+            *oa = ra;
+            *ob = rb;
+            const gptr<Vec16<T>> va = (gptr<Vec16<T>>)(g.v + o);
+            const gptr<Vec16<T>> vb = (gptr<Vec16<T>>)(g.v + o + N);
+            Vec16<T> pa = *va, pb = *vb;
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                pa.v[q] += ra.v[q];
+                pb.v[q] += rb.v[q];
+            }
+            *va = pa;
+            *vb = pb;
+            continue;
+        }
         if (accumulate) {
             const Vec16<T> pa = *oa, pb = *ob;
 #pragma unroll
@@ -714,7 +730,7 @@ bool xf_fast(const Batch<T>& Bt, int in, hipStream_t s) {
 }
 
 template <typename T, int N>
-bool xi_fast(const Batch<T>& Bt, int out, bool acc, hipStream_t s) {
+bool xi_fast(const Batch<T>& Bt, int out, int acc, hipStream_t s) {
     using Pl = Plan<T, N>;
     if constexpr (!Pl::ok) {
         return false;
@@ -726,7 +742,7 @@ bool xi_fast(const Batch<T>& Bt, int out, bool acc, hipStream_t s) {
         const dim3 grid((unsigned)((npairs + P - 1) / P), 3 * Bt.nrep);
         const size_t lds = (size_t)(N + P * xline<N>()) * sizeof(cplx<T>);
         hipLaunchKernelGGL((k_xinv_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>), grid, dim3(P * TL), lds, s, Bt.d, out,
-                           P, acc ? 1 : 0);
+                           P, acc);
         return true;
     }
 }
@@ -781,7 +797,7 @@ bool fast_fft_x_forward(const Batch<T>& B, int in, hipStream_t s) {
 #undef C
 }
 template <typename T>
-bool fast_fft_x_inverse(const Batch<T>& B, int out, bool acc, hipStream_t s) {
+bool fast_fft_x_inverse(const Batch<T>& B, int out, int acc, hipStream_t s) {
 #define C(NN) xi_fast<T, NN>(B, out, acc, s)
     ICM_SWITCH_N(B.g.nx, C)
 #undef C
@@ -792,7 +808,7 @@ bool fast_fft_x_inverse(const Batch<T>& B, int out, bool acc, hipStream_t s) {
     template bool fast_fft_y<T>(const Batch<T>&, int, hipStream_t);                \
     template bool fast_fft_z_solve<T>(const Batch<T>&, int, bool, hipStream_t, bool); \
     template bool fast_fft_x_forward<T>(const Batch<T>&, int, hipStream_t);        \
-    template bool fast_fft_x_inverse<T>(const Batch<T>&, int, bool, hipStream_t);
+    template bool fast_fft_x_inverse<T>(const Batch<T>&, int, int, hipStream_t);
 ICM_INST(float)
 ICM_INST(double)
 #undef ICM_INST

@@ -493,17 +493,6 @@ __global__ void k_zero(const RepDesc<T>* __restrict__ rd, int sel) {
         p[i] = (T)0;
 }
 
-template <typename T>
-__global__ void k_axpy(const RepDesc<T>* __restrict__ rd, int ysel, int xsel) {
-    const GridDesc<T> g = rd[blockIdx.y].g;
-    T* y = field_of(rd[blockIdx.y].g, ysel);
-    const T* x = field_of(rd[blockIdx.y].g, xsel);
-    const long long n = 3 * g.ncell;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
-        y[i] += x[i];
-}
-
 // Advective term of step 2 (Eq. (provisional_step-1) with the Adams-Bashforth
 // lag of Eq. (Adams_Bashforth)): A = D.(rho v v^T) at the three faces of cell
 // (i, j, k) in the centred conservative form of the staggered grid. Fluxes:
@@ -688,17 +677,67 @@ __device__ __forceinline__ double gather_group_rec(const GridDesc<T>& g, const T
     return acc;
 }
 
-// Step 1 fused: Jn = J(q^n) v^n, q^{n+1/2} = q^n + dt/2 Jn, the one-body
-// forces at q^{n+1/2} and the folded positions.
+// The same with the field value at each node replaced by its 7-point
+// Laplacian (periodic), for the lagged term J L dv.
 template <typename T, int P>
-__global__ void __launch_bounds__(kThreads) k_gather_predict(const RepDesc<T>* __restrict__ rd) {
+__device__ __forceinline__ double gather_group_rec_lap(const GridDesc<T>& g, const T* __restrict__ field,
+                                                       gptr<const double> o, int a, int r, bool active) {
+    double acc = 0.0;
+    if (active && r < P * P) {
+        const int cz = r / P, cy = r - P * (r / P);
+        const int nx = g.nx, ny = g.ny, nz = g.nz;
+        const int i0 = (int)o[0];
+        int j = (int)o[1] + cy, k = (int)o[2] + cz;
+        if (j >= ny) j -= ny;
+        if (k >= nz) k -= nz;
+        const int jp = j + 1 == ny ? 0 : j + 1, jm = j == 0 ? ny - 1 : j - 1;
+        const int kp = k + 1 == nz ? 0 : k + 1, km = k == 0 ? nz - 1 : k - 1;
+        const double inv_h = 1.0 / g.h;
+        const double wy = o[7 + cy], wz = o[11 + cz];
+        const T* f = field + a * g.ncell;
+        const long long row = ((long long)k * ny + j) * nx;
+        double s = 0.0;
+#pragma unroll
+        for (int aa = 0; aa < P; ++aa) {
+            int i = i0 + aa;
+            if (i >= nx) i -= nx;
+            const int ip = i + 1 == nx ? 0 : i + 1, im = i == 0 ? nx - 1 : i - 1;
+            const double c0 = (double)f[row + i];
+            const double l = ((double)f[row + ip] + (double)f[row + im] + (double)f[((long long)k * ny + jp) * nx + i] +
+                              (double)f[((long long)k * ny + jm) * nx + i] + (double)f[((long long)kp * ny + j) * nx + i] +
+                              (double)f[((long long)km * ny + j) * nx + i] - 6.0 * c0) *
+                             inv_h * inv_h;
+            s += o[3 + aa] * l;
+        }
+        acc = wz * wy * s;
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+    return acc;
+}
+
+// Step 1 fused, one 16-lane group per (blob, component) and five whole
+// blobs per 256-thread workgroup (groups 0..14), so that a blob's three
+// components meet at the workgroup barrier:
+//  (a) Jn = J(q^n) v^n, q^{n+1/2} = q^n + dt/2 Jn, the one-body forces at
+//      q^{n+1/2} and the position folded into the box (for the pair forces);
+//  (b) Jhvn = J(q^{n+1/2}) v^n, with the stencil record of component a at
+//      q^{n+1/2} (wrapped base nodes, the P weights of each axis, the
+//      derivative weights along axis a) for the spread inside the RHS kernel
+//      and the gathers of step 9, and the blob's insertion into its cell's
+//      list for the pair forces.
+constexpr int kStep1Blobs = kThreads / 48;
+template <typename T, int P>
+__global__ void __launch_bounds__(kThreads) k_gather_step1(const RepDesc<T>* __restrict__ rd) {
+    __shared__ double s_qh[3 * kStep1Blobs], s_qw[3 * kStep1Blobs];
     const GridDesc<T> g = rd[blockIdx.y].g;
     const BlobParams bp = rd[blockIdx.y].bp;
     const BlobBufs bb = rd[blockIdx.y].bb;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int grp = t >> 4, r = t & 15;
-    const int b = grp / 3, a = grp - 3 * (grp / 3);
-    const bool active = b < bp.nb;
+    const int grp = (int)threadIdx.x >> 4, r = (int)threadIdx.x & 15;
+    const int lb = grp / 3, a = grp - 3 * (grp / 3);
+    const int b = (int)blockIdx.x * kStep1Blobs + lb;
+    const bool active = grp < 3 * kStep1Blobs && b < bp.nb;
+    // (a)
     const double J = gather_group<T, P>(g, g.v, active ? bb.q + 3 * b : bb.q, a, r, active);
     if (active && r == 0) {
         const int i = 3 * b + a;
@@ -706,8 +745,6 @@ __global__ void __launch_bounds__(kThreads) k_gather_predict(const RepDesc<T>* _
         const double qh = bb.q[i] + 0.5 * bp.dt * J;
         if (!isfinite(qh)) atomicOr(bb.flag, 1u);
         bb.qh[i] = qh;
-        // one-body forces at q^{n+1/2} (constant and tether spring) and the
-        // position folded into the box, for the pair forces
         // (component a's box length and spring centre by select: a runtime
         // index into the parameter copy would put it in scratch memory)
         const double L = a == 0 ? bp.box[0] : (a == 1 ? bp.box[1] : bp.box[2]);
@@ -715,34 +752,22 @@ __global__ void __launch_bounds__(kThreads) k_gather_predict(const RepDesc<T>* _
         double f = bb.fconst[i];
         if (bp.spring_k != 0.0) f -= bp.spring_k * (qh - cs);
         bb.F[i] = f;
-        bb.qw[i] = qh - L * floor(qh / L);
+        const double qw = qh - L * floor(qh / L);
+        bb.qw[i] = qw;
+        s_qh[grp] = qh;
+        s_qw[grp] = qw;
     }
-}
-
-// Jhvn = J(q^{n+1/2}) v^n, plus, for the spread inside the RHS kernel, the
-// stencil record of component a (wrapped base nodes, the P weights of each
-// axis, the derivative weights along axis a).
-template <typename T, int P>
-__global__ void __launch_bounds__(kThreads) k_gather_bins(const RepDesc<T>* __restrict__ rd) {
-    const GridDesc<T> g = rd[blockIdx.y].g;
-    const BlobParams bp = rd[blockIdx.y].bp;
-    const BlobBufs bb = rd[blockIdx.y].bb;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int grp = t >> 4, r = t & 15;
-    const int b = grp / 3, a = grp - 3 * (grp / 3);
-    const bool active = b < bp.nb;
+    __syncthreads();
+    // (b): lanes 1..3 compute (and store) the record of axis ax = r - 1; the
+    // group's gather reads the weights from those lanes
     const double inv_h = 1.0 / g.h;
     const int n[3] = {g.nx, g.ny, g.nz};
-    // lanes 1..3 compute (and store) the stencil record of axis ax = r - 1:
-    // the wrapped base node, the P weights (zero beyond P) and, along axis
-    // a, the derivative weights; the group's gather below reads the weights
-    // from those lanes instead of evaluating the kernel again
     int rb_node = 0;
     double rw[4] = {0.0, 0.0, 0.0, 0.0};
     if (active && r >= 1 && r <= 3) {
         const int ax = r - 1;
         double* o = bb.stc + ((long long)b * 3 + a) * kStcPerComp;
-        const double x = fold_coord(bb.qh[3 * b + ax] * inv_h - (ax == a ? 0.0 : 0.5), n[ax]);
+        const double x = fold_coord(s_qh[3 * lb + ax] * inv_h - (ax == a ? 0.0 : 0.5), n[ax]);
         const int base = (int)((P == 3) ? floor(x + 0.5) : floor(x)) - 1;
         rb_node = wrap_node(base, n[ax]);
         o[ax] = (double)rb_node;
@@ -754,7 +779,6 @@ __global__ void __launch_bounds__(kThreads) k_gather_bins(const RepDesc<T>* __re
             if (ax == a) o[15 + tt] = (tt < P) ? kern_dw<P>(d, g.hs) * inv_h : 0.0;
         }
     }
-    // every lane of the group takes the three axes' records (lanes 1, 2, 3)
     double wx[4], wy4[4], wz4[4];
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
@@ -763,8 +787,8 @@ __global__ void __launch_bounds__(kThreads) k_gather_bins(const RepDesc<T>* __re
         wz4[tt] = __shfl(rw[tt], 3, 16);
     }
     const int bx = __shfl(rb_node, 1, 16), by = __shfl(rb_node, 2, 16), bz = __shfl(rb_node, 3, 16);
-    // Jhvn = J(q^{n+1/2}) v^n: lane r < P^2 sums the x-row of z-tap r / P and
-    // y-tap r mod P, as gather_group does, with the same nodes and weights
+    // lane r < P^2 sums the x-row of z-tap r / P and y-tap r mod P, as
+    // gather_group does, with the same nodes and weights
     double acc = 0.0;
     if (active && r < P * P) {
         const int cz = r / P, cy = r - P * (r / P);
@@ -787,15 +811,14 @@ __global__ void __launch_bounds__(kThreads) k_gather_bins(const RepDesc<T>* __re
     for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
     if (!active) return;
     if (r == 0) bb.Jhvn[3 * b + a] = acc;
-    // the blob's insertion into its cell's list for the pair forces: a head
-    // holds (stamp << kHeadBlobBits | blob) with the step's stamp, so heads
-    // left by earlier steps read as empty and are never cleared
+    // a head holds (stamp << kHeadBlobBits | blob) with the step's stamp, so
+    // heads left by earlier steps read as empty and are never cleared
     if (r == 4 && a == 0 && rd[blockIdx.y].pair_mode == 1) {
         const CellGrid cg = rd[blockIdx.y].cg;
         int ci[3];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            const int cc = (int)(bb.qw[3 * b + ax] * cg.inv_size[ax]);
+            const int cc = (int)(s_qw[3 * lb + ax] * cg.inv_size[ax]);
             ci[ax] = cc >= cg.n[ax] ? cg.n[ax] - 1 : (cc < 0 ? 0 : cc);
         }
         const unsigned long long stamp = cell_stamp(*rd[blockIdx.y].step);
@@ -855,11 +878,14 @@ __global__ void __launch_bounds__(kThreads) k_bins(const RepDesc<T>* __restrict_
 
 // Step 9 fused: Jhvnew = J(q^{n+1/2}) v^{n+1}; q^{n+1} = q^n + dt/2
 // (Jhvnew + Jhvn); u^{n+1} = Jhvnew for m_e = 0 blobs; numeric flag on
-// NaN/Inf or a displacement above h. The first block of a replica clears its
+// NaN/Inf or a displacement above h. In the first n_me replicas (those on
+// the inertial path) also the lagged term J^{n+1/2} L dv of the next step's
+// slip correction, from dv in aux. The first block of a replica clears its
 // z-chunk bins for the next step and advances its step counter (no other
 // kernel of the step reads the counter after the RHS).
 template <typename T, int P>
-__global__ void __launch_bounds__(kThreads) k_gather_final(const RepDesc<T>* __restrict__ rd, int n_clear) {
+__global__ void __launch_bounds__(kThreads) k_gather_final(const RepDesc<T>* __restrict__ rd, int n_clear,
+                                                          int n_me) {
     const GridDesc<T> g = rd[blockIdx.y].g;
     const BlobParams bp = rd[blockIdx.y].bp;
     const BlobBufs bb = rd[blockIdx.y].bb;
@@ -877,8 +903,11 @@ __global__ void __launch_bounds__(kThreads) k_gather_final(const RepDesc<T>* __r
     // J(q^{n+1/2}) v^{n+1} from the stencil records of this step's positions
     const gptr<const double> o = as_global((const double*)bb.stc) + ((long long)(active ? b : 0) * 3 + a) * kStcPerComp;
     const double J = gather_group_rec<T, P>(g, g.v, o, a, r, active);
+    const bool inertial = (int)blockIdx.y < n_me;
+    const double lag = inertial ? gather_group_rec_lap<T, P>(g, g.aux, o, a, r, active) : 0.0;
     if (active && r == 0) {
         const int i = 3 * b + a;
+        if (inertial) bb.lag[i] = lag;
         bb.Jhvnew[i] = J;
         const double dq = 0.5 * bp.dt * (J + bb.Jhvn[i]);
         const double qn = bb.q[i] + dq;
@@ -892,9 +921,14 @@ __global__ void __launch_bounds__(kThreads) k_gather_final(const RepDesc<T>* __r
 // J: out[b][a] = sum phi(dx) phi(dy) phi(dz) f_a (FP64 accumulation), one
 // 16-lane group per (blob, component) reduced with shuffles; with lap = 1 the
 // field value at each node is replaced by its 7-point Laplacian.
+// With epi = kEpiDp (out = J^{n+1/2} v~, step 4): the slip correction du =
+// [FULL] (J^{n+1/2} - J^n) v^n + [VISCOUS|FULL] (nu dt/2) c_lag and the
+// excess momentum dp = m_e (u^n - J^{n+1/2} v~ - du); with epi = kEpiDp2
+// (out = g = J dv~, step 5): the step-6 source dp2 = dp - m_e g and, for
+// m_e != 0, u^{n+1} = J v~ + g + du (step 8).
 template <typename T, int P>
 __global__ void __launch_bounds__(kThreads) k_gather(const RepDesc<T>* __restrict__ rd, int fsel, int qsel, int osel,
-                                                    int lap) {
+                                                    int lap, int epi) {
     const GridDesc<T> g = rd[blockIdx.y].g;
     const BlobBufs bb = rd[blockIdx.y].bb;
     const int nb = rd[blockIdx.y].bp.nb;
@@ -940,7 +974,22 @@ __global__ void __launch_bounds__(kThreads) k_gather(const RepDesc<T>* __restric
     }
 #pragma unroll
     for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
-    if (b < nb && r == 0) out[3 * b + a] = acc;
+    if (b < nb && r == 0) {
+        const int i = 3 * b + a;
+        out[i] = acc;
+        if (epi == kEpiDp) {
+            const BlobParams bp = rd[blockIdx.y].bp;
+            double du = 0.0;
+            if (bp.slip == 2) du += bb.Jhvn[i] - bb.Jn[i];
+            if (bp.slip >= 1) du += 0.5 * (bp.eta / bp.rho) * bp.dt * bb.lag[i];
+            bb.du[i] = du;
+            bb.dp[i] = bb.me[b] * (bb.u[i] - acc - du);
+        } else if (epi == kEpiDp2) {
+            const double me = bb.me[b];
+            bb.dp2[i] = bb.dp[i] - me * acc;
+            if (me != 0.0) bb.u[i] = bb.Jhvt[i] + acc + bb.du[i];
+        }
+    }
 }
 
 __device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
@@ -1043,12 +1092,6 @@ void launch_zero(const Batch<T>& B, int field, hipStream_t s) {
 }
 
 template <typename T>
-void launch_axpy(const Batch<T>& B, int y, int x, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpy<T>, dim3(stream_blocks(3 * B.g.ncell, B.nrep), B.nrep), dim3(kThreads), 0, s, B.d, y,
-                       x);
-}
-
-template <typename T>
 void launch_advect(const Batch<T>& B, hipStream_t s) {
     // gridDim.z = planes x replicas stays within 65535: split large batches
     const int per = std::max(1, 65535 / B.g.nz);
@@ -1070,33 +1113,23 @@ void launch_spread(const Batch<T>& B, int field, int q, int F, int coef, hipStre
 }
 
 template <typename T>
-void launch_gather(const Batch<T>& B, int field, int q, int out, bool laplacian, hipStream_t s) {
+void launch_gather(const Batch<T>& B, int field, int q, int out, bool laplacian, hipStream_t s, int epi) {
     if (B.max_nb <= 0) return;
     const dim3 grid(grid_for(48LL * B.max_nb), B.nrep);
     if (B.kernel == 3)
-        hipLaunchKernelGGL((k_gather<T, 3>), grid, dim3(kThreads), 0, s, B.d, field, q, out, laplacian ? 1 : 0);
+        hipLaunchKernelGGL((k_gather<T, 3>), grid, dim3(kThreads), 0, s, B.d, field, q, out, laplacian ? 1 : 0, epi);
     else
-        hipLaunchKernelGGL((k_gather<T, 4>), grid, dim3(kThreads), 0, s, B.d, field, q, out, laplacian ? 1 : 0);
+        hipLaunchKernelGGL((k_gather<T, 4>), grid, dim3(kThreads), 0, s, B.d, field, q, out, laplacian ? 1 : 0, epi);
 }
 
 template <typename T>
-void launch_gather_predict(const Batch<T>& B, hipStream_t s) {
+void launch_gather_step1(const Batch<T>& B, hipStream_t s) {
     if (B.max_nb <= 0) return;
-    const dim3 grid(grid_for(48LL * B.max_nb), B.nrep);
+    const dim3 grid((unsigned)((B.max_nb + kStep1Blobs - 1) / kStep1Blobs), B.nrep);
     if (B.kernel == 3)
-        hipLaunchKernelGGL((k_gather_predict<T, 3>), grid, dim3(kThreads), 0, s, B.d);
+        hipLaunchKernelGGL((k_gather_step1<T, 3>), grid, dim3(kThreads), 0, s, B.d);
     else
-        hipLaunchKernelGGL((k_gather_predict<T, 4>), grid, dim3(kThreads), 0, s, B.d);
-}
-
-template <typename T>
-void launch_gather_bins(const Batch<T>& B, hipStream_t s) {
-    if (B.max_nb <= 0) return;
-    const dim3 grid(grid_for(48LL * B.max_nb), B.nrep);
-    if (B.kernel == 3)
-        hipLaunchKernelGGL((k_gather_bins<T, 3>), grid, dim3(kThreads), 0, s, B.d);
-    else
-        hipLaunchKernelGGL((k_gather_bins<T, 4>), grid, dim3(kThreads), 0, s, B.d);
+        hipLaunchKernelGGL((k_gather_step1<T, 4>), grid, dim3(kThreads), 0, s, B.d);
 }
 
 template <typename T>
@@ -1111,14 +1144,14 @@ void launch_bins(const Batch<T>& B, hipStream_t s) {
 }
 
 template <typename T>
-void launch_gather_final(const Batch<T>& B, hipStream_t s) {
+void launch_gather_final(const Batch<T>& B, int n_me, hipStream_t s) {
     // always launched: its first block per replica advances the step counter
     const int n_clear = max_chunks(B.g.nz) + 1;  // every chunk count and the overflow count
     const dim3 grid(grid_for(48LL * (B.max_nb > 0 ? B.max_nb : 1)), B.nrep);
     if (B.kernel == 3)
-        hipLaunchKernelGGL((k_gather_final<T, 3>), grid, dim3(kThreads), 0, s, B.d, n_clear);
+        hipLaunchKernelGGL((k_gather_final<T, 3>), grid, dim3(kThreads), 0, s, B.d, n_clear, n_me);
     else
-        hipLaunchKernelGGL((k_gather_final<T, 4>), grid, dim3(kThreads), 0, s, B.d, n_clear);
+        hipLaunchKernelGGL((k_gather_final<T, 4>), grid, dim3(kThreads), 0, s, B.d, n_clear, n_me);
 }
 
 __global__ void k_carry_from_sum(double* k0, const double* acc, double inv) {
@@ -1145,15 +1178,13 @@ void launch_field_diag(const GridDesc<T>& g, double rho, double* acc, hipStream_
     template void launch_spread_overflow<T>(const Batch<T>&, hipStream_t);                       \
     template void launch_equilibrium_noise<T>(const Batch<T>&, double, hipStream_t);             \
     template void launch_zero<T>(const Batch<T>&, int, hipStream_t);                             \
-    template void launch_axpy<T>(const Batch<T>&, int, int, hipStream_t);                        \
     template void launch_spread<T>(const Batch<T>&, int, int, int, int, hipStream_t);            \
-    template void launch_gather<T>(const Batch<T>&, int, int, int, bool, hipStream_t);           \
+    template void launch_gather<T>(const Batch<T>&, int, int, int, bool, hipStream_t, int);      \
     template void launch_field_diag<T>(const GridDesc<T>&, double, double*, hipStream_t);        \
     template void launch_carry_init<T>(const GridDesc<T>&, double, double*, hipStream_t);        \
-    template void launch_gather_predict<T>(const Batch<T>&, hipStream_t);                        \
-    template void launch_gather_bins<T>(const Batch<T>&, hipStream_t);                           \
+    template void launch_gather_step1<T>(const Batch<T>&, hipStream_t);                          \
     template void launch_bins<T>(const Batch<T>&, hipStream_t);                                  \
-    template void launch_gather_final<T>(const Batch<T>&, hipStream_t); \
+    template void launch_gather_final<T>(const Batch<T>&, int, hipStream_t);                     \
     template void launch_advect<T>(const Batch<T>&, hipStream_t);
 ICM_INST(float)
 ICM_INST(double)

@@ -324,8 +324,11 @@ void launch_fft_y(const Batch<T>& B, int dir, hipStream_t s);
 // mean and the exactly known change of total momentum, and the carry advanced.
 template <typename T>
 void launch_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s, bool carry = false);
+// accumulate: 0 writes field `out`, 1 adds to it, kXinvAlsoV (with out =
+// kFieldAux) writes it and also adds the result to v.
+constexpr int kXinvAlsoV = 2;
 template <typename T>
-void launch_fft_x_inverse(const Batch<T>& B, int out, bool accumulate, hipStream_t s);
+void launch_fft_x_inverse(const Batch<T>& B, int out, int accumulate, hipStream_t s);
 
 // Register-resident passes for N in {16, 32, 48, 64, 128, 256, 512};
 // return false (launching nothing) for other sizes.
@@ -338,7 +341,7 @@ bool fast_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s,
 template <typename T>
 bool fast_fft_x_forward(const Batch<T>& B, int in, hipStream_t s);
 template <typename T>
-bool fast_fft_x_inverse(const Batch<T>& B, int out, bool accumulate, hipStream_t s);
+bool fast_fft_x_inverse(const Batch<T>& B, int out, int accumulate, hipStream_t s);
 
 // ------------------------------------------------------------ grid kernels
 template <typename T>
@@ -351,9 +354,6 @@ template <typename T>
 void launch_equilibrium_noise(const Batch<T>& B, double sd, hipStream_t s);
 template <typename T>
 void launch_zero(const Batch<T>& B, int field, hipStream_t s);
-// field y += field x
-template <typename T>
-void launch_axpy(const Batch<T>& B, int y, int x, hipStream_t s);
 // rhs -= 3/2 A^n - 1/2 A^{n-1} with A = D.(rho v v^T) of v; A^n kept in adv
 // (replicas of a batch with advection on).
 template <typename T>
@@ -364,20 +364,23 @@ void launch_advect(const Batch<T>& B, hipStream_t s);
 template <typename T>
 void launch_spread(const Batch<T>& B, int field, int q, int F, int coef, hipStream_t s);
 // gather: out[b][a] = sum prod(phi) f_a (or of (L f)_a with laplacian = true)
-// at positions q.
+// at positions q; epi = kEpiDp / kEpiDp2 adds the per-component work of the
+// inertial correction that uses the gathered value (step 4: du and dp;
+// step 5: dp2 and, for m_e != 0, u^{n+1}).
+enum GatherEpi { kEpiNone = 0, kEpiDp = 1, kEpiDp2 = 2 };
 template <typename T>
-void launch_gather(const Batch<T>& B, int field, int q, int out, bool laplacian, hipStream_t s);
+void launch_gather(const Batch<T>& B, int field, int q, int out, bool laplacian, hipStream_t s,
+                   int epi = kEpiNone);
 
-// Fused gathers of the step (one 16-lane group per blob component):
-// J^n v^n with the predictor; J^{n+1/2} v^n with the RHS stencils; J^{n+1/2}
-// v^{n+1} with the position update (which also clears the z-chunk bin
-// counters and advances the step counter).
+// Fused gathers of the step (one 16-lane group per blob component): J^n v^n
+// with the predictor and J^{n+1/2} v^n with the stencil records of
+// q^{n+1/2} (step 1); J^{n+1/2} v^{n+1} with the position update (step 9,
+// which also clears the z-chunk bin counters, advances the step counter and,
+// in the first n_me replicas, gathers the lagged term J L dv from aux).
 template <typename T>
-void launch_gather_predict(const Batch<T>& B, hipStream_t s);
+void launch_gather_step1(const Batch<T>& B, hipStream_t s);
 template <typename T>
-void launch_gather_bins(const Batch<T>& B, hipStream_t s);
-template <typename T>
-void launch_gather_final(const Batch<T>& B, hipStream_t s);
+void launch_gather_final(const Batch<T>& B, int n_me, hipStream_t s);
 // z-chunk bins of the RHS spread (positions qh); counters must start at zero.
 template <typename T>
 void launch_bins(const Batch<T>& B, hipStream_t s);
@@ -395,18 +398,17 @@ void launch_carry_init(const GridDesc<T>& g, double rho, double* acc, hipStream_
 // ----------------------------------------------------------- blob kernels
 template <typename T>
 void launch_forces(const Batch<T>& B, hipStream_t s);
+// With the FP64-carried mean velocity: the sum of dp - m_e g per replica
+// (after g came from the field path of step 5).
 template <typename T>
-void launch_inertial_dp(const Batch<T>& B, hipStream_t s);
-template <typename T>
-void launch_inertial_dp2(const Batch<T>& B, hipStream_t s);
+void launch_dp2_sum(const Batch<T>& B, hipStream_t s);
 // Step 5 through the projection-kernel table: g = J P S (c5 dp) for every
-// blob, without forming the field (batches whose replicas have ptab).
+// blob, without forming the field (batches whose replicas have ptab); then
+// dp2, u^{n+1} of the blobs with m_e != 0 and the carried sum of dp2.
 template <typename T>
 void launch_jps_table(const Batch<T>& B, hipStream_t s);
 constexpr int kTabMaxBlobs = 8;
 constexpr long long kTabMaxCells = 128LL * 128 * 128;
-template <typename T>
-void launch_inertial_u(const Batch<T>& B, hipStream_t s);
 void launch_blob_diag(int nb, const double* me, const double* u, double* acc, hipStream_t s);
 
 }  // namespace icm
