@@ -16,9 +16,9 @@ struct NormalPair {
 };
 
 template <typename T>
-__device__ __forceinline__ NormalPair<T> bm(uint32_t wa, uint32_t wb) {
+__device__ __forceinline__ NormalPair<T> bm(const LogTab& lt, uint32_t wa, uint32_t wb) {
     NormalPair<T> r;
-    box_muller(wa, wb, r.a, r.b);
+    box_muller(wa, wb, r.a, r.b, lt);
     return r;
 }
 
@@ -125,6 +125,15 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
     __shared__ T sxz2[2][RTY][RTX + 1];        // W_xz, column RTX = i0 + TX
     __shared__ T syy2[2][RTY + 1][RTX];        // W_yy, row 0 = j0 - 1
     __shared__ T syz2[2][RTY + 1][RTX];        // W_yz, row RTY = j0 + TY
+    // the FP64 transform's logarithm table (the FP32 one uses the hardware
+    // logarithm)
+    LogTab lt{nullptr, nullptr};
+    if constexpr (sizeof(T) == 8) {
+        __shared__ double s_linv[kLogTab], s_lnf[kLogTab];
+        fill_log_tab(s_linv, s_lnf);
+        __syncthreads();
+        lt = LogTab{s_linv, s_lnf};
+    }
     const int tx = threadIdx.x % RTX, ty = threadIdx.x / RTX;
     // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs,
     // so give XCD j a contiguous run of tiles (x fastest, then y, then z,
@@ -210,9 +219,9 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
             // plane k0 and xx, yy of plane k0 + 1 (B of the first pair)
             const uint32_t mprev = (uint32_t)(km / 2), m0 = (uint32_t)(k0 / 2);
             const u32x4 wc = noise_words(nk, mprev * pairs_plane + (uint32_t)col, 2);
-            wzz_m = bm<T>(wc.x, wc.y).a;
+            wzz_m = bm<T>(lt, wc.x, wc.y).a;
             const u32x4 wb = noise_words(nk, m0 * pairs_plane + (uint32_t)col, 1);
-            const NormalPair<T> q = bm<T>(wb.x, wb.y), r = bm<T>(wb.z, wb.w);
+            const NormalPair<T> q = bm<T>(lt, wb.x, wb.y), r = bm<T>(lt, wb.z, wb.w);
             wxz_c = q.a;
             wyz_c = q.b;
             up_xx = r.a;
@@ -354,13 +363,13 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
                     if ((k & 1) == 0) {
                         const uint32_t ctr = (uint32_t)(k / 2) * pairs_plane + (uint32_t)col;
                         const u32x4 wa = noise_words(nk, ctr, 0);
-                        const NormalPair<T> p0 = bm<T>(wa.x, wa.y), p1 = bm<T>(wa.z, wa.w);
+                        const NormalPair<T> p0 = bm<T>(lt, wa.x, wa.y), p1 = bm<T>(lt, wa.z, wa.w);
                         wxx = p0.a;
                         wyy = p0.b;
                         wzz = p1.a;
                         wxy = p1.b;
                         const u32x4 wc = noise_words(nk, ctr, 2);
-                        const NormalPair<T> p2 = bm<T>(wc.x, wc.y), p3 = bm<T>(wc.z, wc.w);
+                        const NormalPair<T> p2 = bm<T>(lt, wc.x, wc.y), p3 = bm<T>(lt, wc.z, wc.w);
                         up_zz = p2.a;
                         up_xy = p2.b;
                         wxz_n = p3.a;
@@ -372,7 +381,7 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
                         wxy = up_xy;
                         const uint32_t ctr = (uint32_t)(kp / 2) * pairs_plane + (uint32_t)col;
                         const u32x4 wb = noise_words(nk, ctr, 1);
-                        const NormalPair<T> p0 = bm<T>(wb.x, wb.y), p1 = bm<T>(wb.z, wb.w);
+                        const NormalPair<T> p0 = bm<T>(lt, wb.x, wb.y), p1 = bm<T>(lt, wb.z, wb.w);
                         wxz_n = p0.a;
                         wyz_n = p0.b;
                         up_xx = p1.a;
@@ -399,7 +408,7 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
                     if (hkind == 0 || hkind == 2) {
                         // xx (left) or yy (bottom): A(0,1) on even planes, B(2,3) on odd
                         const u32x4 w = noise_words(nk, hctr, odd ? 1 : 0);
-                        const NormalPair<T> pr = odd ? bm<T>(w.z, w.w) : bm<T>(w.x, w.y);
+                        const NormalPair<T> pr = odd ? bm<T>(lt, w.z, w.w) : bm<T>(lt, w.x, w.y);
                         if (hkind == 0)
                             sxx[hj - j0][0] = pr.a;
                         else
@@ -410,14 +419,14 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
                         T exy, ez;
                         if (odd) {
                             const u32x4 w = noise_words(nk, hctr, 2);
-                            exy = bm<T>(w.x, w.y).b;
-                            const NormalPair<T> q = bm<T>(w.z, w.w);
+                            exy = bm<T>(lt, w.x, w.y).b;
+                            const NormalPair<T> q = bm<T>(lt, w.z, w.w);
                             ez = hkind == 1 ? q.a : q.b;
                         } else {
                             const u32x4 w = noise_words(nk, hctr, 0);
-                            exy = bm<T>(w.z, w.w).b;
+                            exy = bm<T>(lt, w.z, w.w).b;
                             const u32x4 w1 = noise_words(nk, hctr, 1);
-                            const NormalPair<T> q = bm<T>(w1.x, w1.y);
+                            const NormalPair<T> q = bm<T>(lt, w1.x, w1.y);
                             ez = hkind == 1 ? q.a : q.b;
                         }
                         if (hkind == 1) {
@@ -472,12 +481,16 @@ __global__ void __launch_bounds__(kThreads) k_eq_noise(const RepDesc<T>* __restr
     NoiseKey nk = rd[blockIdx.y].rc.key;
     nk.step_lo = 0;
     nk.step_hi = 0;
+    __shared__ double s_linv[kLogTab], s_lnf[kLogTab];
+    fill_log_tab(s_linv, s_lnf);
+    __syncthreads();
+    const LogTab lt{s_linv, s_lnf};
     const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= g.ncell) return;
     const u32x4 w = noise_words(nk, (uint32_t)cell, 3);
     double a, b, cz, unused;
-    box_muller(w.x, w.y, a, b);
-    box_muller(w.z, w.w, cz, unused);
+    box_muller(w.x, w.y, a, b, lt);
+    box_muller(w.z, w.w, cz, unused, lt);
     g.rhs[cell] = (T)(sd * a);
     g.rhs[g.ncell + cell] = (T)(sd * b);
     g.rhs[2 * g.ncell + cell] = (T)(sd * cz);

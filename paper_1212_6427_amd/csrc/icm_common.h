@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "normal64.h"
+
 namespace icm {
 
 // Global-memory pointers. Pointers read from a device-resident descriptor are
@@ -88,18 +90,23 @@ __device__ __forceinline__ u32x4 noise_words(const NoiseKey& nk, uint32_t index,
 }
 
 // Box-Muller: first word -> radius via u1 = (w+1) 2^-32 in (0,1], second word
-// -> angle 2 pi u2 with u2 = w 2^-32 in [0,1).
-__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& z0, double& z1) {
-    const double u1 = ((double)wa + 1.0) * 2.3283064365386963e-10;
-    const double u2 = (double)wb * 2.3283064365386963e-10;
-    const double r = sqrt(-2.0 * log(u1));
-    double s, c;
-    sincospi(2.0 * u2, &s, &c);
-    z0 = r * c;
-    z1 = r * s;
+// -> angle 2 pi u2 with u2 = w 2^-32 in [0,1). The FP64 transform takes the
+// logarithm table of normal64.h, kept in the calling kernel's LDS and filled
+// by fill_log_tab before its first use.
+struct LogTab {
+    const double* inv;
+    const double* lnf;
+};
+
+__device__ __forceinline__ void fill_log_tab(double* inv, double* lnf) {
+    for (int j = threadIdx.x; j < kLogTab; j += blockDim.x) log_table_entry(j, inv, lnf);
 }
 
-__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z0, float& z1) {
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& z0, double& z1, const LogTab& lt) {
+    box_muller64(wa, wb, lt.inv, lt.lnf, z0, z1);
+}
+
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z0, float& z1, const LogTab&) {
     // FP32 transform of the same words with the hardware log2, square root
     // (-2 ln u1 lies in [0, 44.4], no denormals) and sine/cosine, which take
     // their argument in revolutions.
