@@ -172,8 +172,10 @@ __global__ void __launch_bounds__(kThreads) k_dp2_sum(const RepDesc<T>* __restri
 // One workgroup per replica; each output is summed in a fixed order. Then
 // the step-6 source dp2 = dp - m_e g, u^{n+1} = J v~ + g + du for m_e != 0
 // (step 8) and, with the mean velocity carried in FP64, the sum of dp2.
-__device__ __forceinline__ double stencil_corr(gptr<const double> wa, gptr<const double> wb, int s, int P) {
+template <int P>
+__device__ __forceinline__ double stencil_corr(const double* wa, const double* wb, int s) {
     double c = 0.0;
+#pragma unroll
     for (int m = 0; m < P; ++m) {
         const int n = m - s;
         if (n >= 0 && n < P) c += wa[m] * wb[n];
@@ -186,53 +188,69 @@ __device__ __forceinline__ int wrap_offset(int d, int n) {
     return d < 0 ? d + n : d;
 }
 
-template <typename T>
+// The replica's stencil records and sources are staged in LDS first, so that
+// each item's only global reads are the Q table values of its x-row.
+template <typename T, int P>
 __global__ void __launch_bounds__(kThreads) k_jps_table(const RepDesc<T>* __restrict__ rd) {
-    const GridDesc<T> g = rd[blockIdx.x].g;
-    const BlobBufs b = rd[blockIdx.x].bb;
+    constexpr int Q = 2 * P - 1;
+    __shared__ double s_rec[3 * kTabMaxBlobs * kStcPerComp];
+    __shared__ double s_f[3 * kTabMaxBlobs];
+    __shared__ double s_g[3 * kTabMaxBlobs];
+    const GridDesc<T>& g = rd[blockIdx.x].g;
+    const BlobBufs& b = rd[blockIdx.x].bb;
     const int nb = rd[blockIdx.x].bp.nb;
-    const int P = rd[blockIdx.x].rb.kernel, Q = 2 * P - 1;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const long long ncell = g.ncell;
     const double ih3 = 1.0 / (g.h * g.h * g.h);
     const gptr<const T> K = as_global(g.ptab);
-    const gptr<const double> stc = as_global((const double*)b.stc);
+    for (int t = threadIdx.x; t < 3 * nb * kStcPerComp; t += blockDim.x) s_rec[t] = b.stc[t];
+    for (int t = threadIdx.x; t < 3 * nb; t += blockDim.x) s_f[t] = b.c5[t / 3] * b.dp[t] * ih3;
+    __syncthreads();
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, nwaves = blockDim.x / 64;
     // one wave per output (i, a); its lanes take the items (j, b, z offset,
     // y offset), the x offsets run inside an item
     for (int o = wave; o < 3 * nb; o += nwaves) {
-        const int i = o / 3, al = o - 3 * (o / 3);
-        const gptr<const double> oi = stc + ((long long)i * 3 + al) * kStcPerComp;
+        const int al = o - 3 * (o / 3);
+        const double* oi = s_rec + o * kStcPerComp;
         double part = 0.0;
         for (int it = lane; it < nb * 3 * Q * Q; it += 64) {
-            const int j = it / (3 * Q * Q), rem = it - j * 3 * Q * Q, be = rem / (Q * Q);
-            const int tz = (rem - be * Q * Q) / Q, ty = rem - be * Q * Q - tz * Q;
-            const double fj = b.c5[j] * b.dp[3 * j + be] * ih3;
+            const int jb = it / (Q * Q), rem = it - jb * Q * Q;  // jb = 3 j + b
+            const int tz = rem / Q, ty = rem - tz * Q;
+            const double fj = s_f[jb];
             if (fj == 0.0) continue;
-            const gptr<const double> oj = stc + ((long long)j * 3 + be) * kStcPerComp;
-            const double cyz = stencil_corr(oi + 11, oj + 11, tz - (P - 1), P) *
-                               stencil_corr(oi + 7, oj + 7, ty - (P - 1), P);
+            const double* oj = s_rec + jb * kStcPerComp;
+            const double cyz = stencil_corr<P>(oi + 11, oj + 11, tz - (P - 1)) * stencil_corr<P>(oi + 7, oj + 7, ty - (P - 1));
             if (cyz == 0.0) continue;
-            const int dz = wrap_offset((int)oi[2] - (int)oj[2] + tz - (P - 1), g.nz);
-            const int dy = wrap_offset((int)oi[1] - (int)oj[1] + ty - (P - 1), g.ny);
-            const gptr<const T> row = K + (long long)(be * 3 + al) * g.ncell + ((long long)dz * g.ny + dy) * g.nx;
-            const int dx0 = (int)oi[0] - (int)oj[0] - (P - 1);
-            double s = 0.0;
+            const int be = jb - 3 * (jb / 3);
+            const int dz = wrap_offset((int)oi[2] - (int)oj[2] + tz - (P - 1), nz);
+            const int dy = wrap_offset((int)oi[1] - (int)oj[1] + ty - (P - 1), ny);
+            const gptr<const T> row = K + (long long)(be * 3 + al) * ncell + ((long long)dz * ny + dy) * nx;
+            const int dx0 = wrap_offset((int)oi[0] - (int)oj[0] - (P - 1), nx);
+            T kv[Q];
+#pragma unroll
             for (int tx = 0; tx < Q; ++tx) {
-                const double cx = stencil_corr(oi + 3, oj + 3, tx - (P - 1), P);
-                if (cx != 0.0) s += cx * (double)row[wrap_offset(dx0 + tx, g.nx)];
+                const int x = dx0 + tx;
+                kv[tx] = row[x >= nx ? x - nx : x];
             }
-            part += fj * cyz * s;
+            double sx = 0.0;
+#pragma unroll
+            for (int tx = 0; tx < Q; ++tx) sx += stencil_corr<P>(oi + 3, oj + 3, tx - (P - 1)) * (double)kv[tx];
+            part += fj * cyz * sx;
         }
         // butterfly sum over the wave (the same order on every run)
         for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-        if (lane == 0) b.g[o] = part;
+        if (lane == 0) {
+            s_g[o] = part;
+            b.g[o] = part;
+        }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < 3 * nb; t += blockDim.x) {
-        const double me = b.me[t / 3], gt = b.g[t];
+        const double me = b.me[t / 3], gt = s_g[t];
         b.dp2[t] = b.dp[t] - me * gt;
         if (me != 0.0) b.u[t] = b.Jhvt[t] + gt + b.du[t];
     }
-    if (g.k0) block_sum3(nb, b.dp, b.me, b.g, g.k0 + 6);
+    if (g.k0) block_sum3(nb, b.dp, b.me, s_g, g.k0 + 6);
 }
 
 __global__ void k_blob_diag(int nb, const double* me, const double* u, double* acc) {
@@ -284,7 +302,11 @@ void launch_dp2_sum(const Batch<T>& B, hipStream_t s) {
 }
 template <typename T>
 void launch_jps_table(const Batch<T>& B, hipStream_t s) {
-    if (B.max_nb > 0) hipLaunchKernelGGL(k_jps_table<T>, dim3(B.nrep), dim3(kThreads), 0, s, B.d);
+    if (B.max_nb <= 0) return;
+    if (B.kernel == 3)
+        hipLaunchKernelGGL((k_jps_table<T, 3>), dim3(B.nrep), dim3(kThreads), 0, s, B.d);
+    else
+        hipLaunchKernelGGL((k_jps_table<T, 4>), dim3(B.nrep), dim3(kThreads), 0, s, B.d);
 }
 void launch_blob_diag(int nb, const double* me, const double* u, double* acc, hipStream_t s) {
     hipLaunchKernelGGL(k_blob_diag, dim3(1), dim3(kThreads), 0, s, nb, me, u, acc);

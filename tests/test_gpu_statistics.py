@@ -7,9 +7,15 @@ invariance error of a few percent and, for m_e != 0, a dt-dependent bias)."""
 import numpy as np
 import pytest
 
+import json
+import os
+
 import icm_inputs
 
 from .parity_cases import banner
+
+with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_values.json")) as _fh:
+    GOLDEN = json.load(_fh)
 
 pytestmark = pytest.mark.gpu
 
@@ -63,6 +69,7 @@ def test_equipartition_fluid_and_blobs(I):
     # 24 steps apart are close to independent at these wavelengths only for
     # the short modes, so the bound allows for correlated samples
     assert np.all(np.abs(v2 / expect_v - 1.0) < 0.01)
+    jps_dev = GOLDEN["jps_diag_max_dev"]["value"]
     for cls, me in ((0, 0.0), (1, m_f)):
         a = np.concatenate(u2[cls])
         expect_u = kT / (me + mt_f)
@@ -70,7 +77,14 @@ def test_equipartition_fluid_and_blobs(I):
         ratio = a.mean() / expect_u
         print("blob m_e = %g m_f: <u_a^2> / (kT/m~) = %.4f (sd of the mean %.3f, %d samples)"
               % (me / m_f, ratio, rel_sd, a.size), flush=True)
-        assert abs(ratio - 1.0) < 4 * rel_sd + 0.06
+        if me == 0.0:
+            # u = J v: its variance follows the diagonal of J P S, which the
+            # paper bounds within a few percent of its translation-invariant
+            # value (Sec. III.A.2)
+            assert abs(ratio - 1.0) < 4 * rel_sd + jps_dev
+    # the m_e = m_f class (samples 8 steps apart, well inside the blob's
+    # velocity correlation time, so the sd above understates the error) is
+    # checked against the paper's intercept by the heavy-blob test below
 
 
 def test_thermal_drift_removes_the_grid_bias(I):
@@ -125,6 +139,43 @@ def test_wca_suspension_reproduces_the_gibbs_boltzmann_structure(I):
         print(np.c_[r[sel], gm[sel], g_mc[sel], se[sel]].round(4), flush=True)
         assert np.max(np.abs(gm - g_mc)[sel]) < 0.03
         assert z.max() < 5.0
+
+
+def test_heavy_blob_velocity_variance_reaches_the_paper_intercept(I):
+    """Sec. IV.B: the velocity autocorrelation of a blob with m_e = m_f starts
+    at C(0+) = kT / m~ = 0.8 kT / m (m = m_e + m_f). <u_a^2> m / kT must
+    match the paper's 0.8 within 3% (plus three standard errors of the
+    replica mean) at beta = 1/4, 1/8 and 1/16, and within 3% at beta = 1/16
+    (64^3, 16 replicas, one blob each). A heavy blob's time-step bias is
+    small (measured below 1% at beta = 1/4, against +11% for the light blob
+    of the next test)."""
+    n, kT = (64, 64, 64), 1e-3
+    m_f = 1.0 / 0.375 ** 3
+    m = 2.0 * m_f
+    target = GOLDEN["vacf_intercept_me_eq_mf"]["value"]
+    R = 16
+    c0 = {}
+    for dt in (0.25, 0.125, 0.0625):
+        banner("heavy-blob velocity variance dt=%g" % dt)
+        params = [I.make_params(n, kT=kT, dt=dt, kernel=4, seed=78, replica_id=r) for r in range(R)]
+        sim = I.Sim(params, [1] * R, I.FP32_GRID)
+        try:
+            for r in range(R):
+                sim.set_blobs(r, icm_inputs.uniform_positions(1, n, 1.0, seed=700 + r), m_e=np.array([m_f]))
+                sim.set_state(r, flags=I.STATE_EQUILIBRIUM)
+            sim.step(int(50 / dt), I.STEP_GRAPH)
+            acc = []
+            for _ in range(int(500 / dt) // 5):
+                sim.step(5, I.STEP_GRAPH)
+                acc.append([sim.get_state(r, want_v=False, want_diag=False)["u"][0] ** 2 for r in range(R)])
+        finally:
+            sim.close()
+        per = np.asarray(acc).mean(axis=(0, 2)) * m / kT
+        c0[dt] = (per.mean(), per.std(ddof=1) / np.sqrt(R))
+        print("dt=%g: C(0+) m / kT = %.4f +- %.4f (paper %.2f)" % (dt, *c0[dt], target), flush=True)
+    for dt, (mean, se) in c0.items():
+        assert abs(mean - target) < 0.03 * target + 3 * se, dt
+    assert abs(c0[0.0625][0] - target) < 0.03 * target
 
 
 def test_light_blob_equipartition_bias_vanishes_with_the_time_step(I):
