@@ -109,6 +109,25 @@ def test_thermal_drift_removes_the_grid_bias(I):
     assert abs(on["corner_over_centre_minus_1"]) < 0.015
 
 
+def test_four_point_kernel_bias_has_the_sign_of_its_jps_variation(I):
+    """The same ideal gas with the four-point kernel, whose J P S is larger at
+    the grid nodes than at the cell centres (opposite to the three-point
+    kernel; pinned on the CPU from the oracle): without the thermal drift
+    the node harmonic is negative (blobs avoid the nodes), smaller than the
+    three-point kernel's since the four-point kernel's J P S varies three
+    times less; with the drift it vanishes within the statistical error."""
+    import bench
+    wl = icm_inputs.WORKLOADS["drift_bias_16"]
+    banner("thermal drift bias, four-point kernel: %d replicas of %d blobs" % (wl["replicas"], wl["n_blobs"]))
+    per = bench.drift_bias_run(I, None, wl, 4, 20000, wl["every"], wl["replicas"])
+    on, off = bench.drift_bias_summary(per[0::2]), bench.drift_bias_summary(per[1::2])
+    print("with drift:", on, flush=True)
+    print("without drift:", off, flush=True)
+    assert off["node_harmonic"] + 2 * off["node_harmonic_se"] < 0.0
+    assert off["node_harmonic"] > -0.006
+    assert abs(on["node_harmonic"]) < 4 * on["node_harmonic_se"] + 0.001
+
+
 def test_wca_suspension_reproduces_the_gibbs_boltzmann_structure(I):
     """Sec. IV.A, Table RDF: the radial distribution function of 1000 WCA
     blobs (kT = eps = 1e-3, sigma = 2, 32^3, dt = 1, i.e. viscous CFL 1)

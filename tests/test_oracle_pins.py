@@ -145,6 +145,34 @@ def test_JPS_translational_invariance_bounds():
     assert ratio == pytest.approx(0.125, rel=0.05)
 
 
+def test_JPS_variation_within_a_cell_has_opposite_signs_for_the_two_kernels():
+    """The position dependence of J P S within a cell (the translational
+    invariance error of Sec. III.A.2) is what the thermal drift of App. B.2
+    corrects: without the drift, blobs linger where J P S is small. Its trace
+    is, to within a few percent of the harmonic, 1/3 tr(JPS) = A + B sum_a
+    cos(2 pi f_a) (f: position within the cell). For the three-point kernel
+    B < 0 (J P S 3.2% smaller at the grid nodes than at the cell centres);
+    for the four-point kernel B > 0 (1.1% larger): so the no-drift density
+    excess at the nodes has opposite signs for the two kernels, as the GPU
+    statistics test measures."""
+    out = {}
+    for kernel in (3, 4):
+        p = P(n=(16, 16, 16), kernel=kernel)
+        tr = {}
+        for name, f in (("node", (0, 0, 0)), ("edge", (0.5, 0, 0)), ("face", (0.5, 0.5, 0)),
+                        ("centre", (0.5, 0.5, 0.5))):
+            q = (np.array([[8.0, 8.0, 8.0]]) + np.asarray(f)[None]) * p.h
+            tr[name] = np.trace(icm.jps_matrix(p, q)) / 3.0
+        A = 0.5 * (tr["node"] + tr["centre"])
+        B = (tr["node"] - tr["centre"]) / 6.0
+        # the edge and face points (sum cos = +1, -1) follow the same harmonic
+        assert tr["edge"] == pytest.approx(A + B, abs=0.05 * abs(B))
+        assert tr["face"] == pytest.approx(A - B, abs=0.05 * abs(B))
+        out[kernel] = (tr["node"] / tr["centre"] - 1.0, B / A)
+    assert out[3][0] == pytest.approx(-0.0318, abs=0.002) and out[3][1] < 0
+    assert out[4][0] == pytest.approx(0.0107, abs=0.002) and out[4][1] > 0
+
+
 # --------------------------------------------------------- projection, solve
 def test_projection_divergence_idempotence_mean():
     p = P(n=(16, 12, 10), h=0.8)
