@@ -689,10 +689,22 @@ void enqueue_step(icm_ctx* c, const BatchInfo& bi, hipStream_t s) {
         }
         // Step 6: (rho - dt/2 eta L) dv + dt G dpi = S (dp - m_e J dv~);
         // step 7: v^{n+1} = v~ + dv, written by the last pass with dv itself
-        // (kept in aux for the lagged term gathered in step 9).
-        timed(c, ICM_PHASE_FIELD_OPS, s, [&] { launch_zero(B, kFieldRhs, s); });
-        timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread(B, kFieldRhs, kBlobQh, kBlobDp2, kBlobNone, s); });
-        enqueue_fft_solve(c, B, kFieldRhs, kFieldAux, kXinvAlsoV, kSolveH2, s);
+        // (kept in aux for the lagged term gathered in step 9). For few blobs
+        // on a register-resident plan, the z pass forms the transform of the
+        // spread source from the stencil records itself.
+        const bool carry = true;
+        bool src = false;
+        if (bi.table && bi.me_max_nb <= kTabMaxBlobs && B.g.fast) {
+            timed(c, ICM_PHASE_FFT_Z_SOLVE, s, [&] { src = fast_fft_z_solve_from_blobs(B, kSolveH2, s, carry); });
+        }
+        if (src) {
+            timed(c, ICM_PHASE_FFT_Y_INV, s, [&] { launch_fft_y(B, 1, s); });
+            timed(c, ICM_PHASE_FFT_X_INV, s, [&] { launch_fft_x_inverse(B, kFieldAux, kXinvAlsoV, s); });
+        } else {
+            timed(c, ICM_PHASE_FIELD_OPS, s, [&] { launch_zero(B, kFieldRhs, s); });
+            timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread(B, kFieldRhs, kBlobQh, kBlobDp2, kBlobNone, s); });
+            enqueue_fft_solve(c, B, kFieldRhs, kFieldAux, kXinvAlsoV, kSolveH2, s);
+        }
     }
     // Step 9 (also the lagged term of the inertial replicas and the device
     // step counters).

@@ -293,7 +293,75 @@ __global__ void __launch_bounds__(512) k_y_fast(const RepDesc<T>* __restrict__ r
 // (b = tid mod B, t = tid / B) holds all three components of its column, so
 // the Helmholtz divide and the 3 x 3 projection of every mode happen in
 // registers between the forward and inverse transforms.
-template <typename T, int N, int E, int R0, int R1, int R2>
+// SRC: the input spectrum is not read but formed from the replica's blobs:
+// the field S f (f = dp2, the source of step 6) is a sum of tensor-product
+// stencils, so its discrete Fourier transform over (x, y, z) is, per blob and
+// component c, h^-3 f_c times the product of three one-dimensional sums
+// sum_m w_a[m] exp(-2 pi i k_a (base_a + m) / n_a) over the stencil's nodes
+// (the same nodes and weights as the spread, from the stencil records).
+// This replaces zeroing the field, spreading into it and the x and y
+// forward passes for replicas with few blobs.
+template <typename T, int N, int E>
+__device__ __forceinline__ void spectral_source(const RepDesc<T>& R, int kx, int ky, int t, const cplx<T>* twz,
+                                                cplx<T> (&a0)[E], cplx<T> (&a1)[E], cplx<T> (&a2)[E]) {
+    constexpr int TL = N / E;
+    const GridDesc<T>& g = R.g;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const gptr<const cplx<T>> twx = as_global(g.twx), twy = as_global(g.twy);
+    const gptr<const double> stc = as_global((const double*)R.bb.stc);
+    const gptr<const double> dp2 = as_global((const double*)R.bb.dp2);
+    const double ih3 = 1.0 / (g.h * g.h * g.h);
+#pragma unroll
+    for (int i = 0; i < E; ++i) a0[i] = a1[i] = a2[i] = cplx<T>{0, 0};
+    const int nb = R.bp.nb;
+    for (int b = 0; b < nb; ++b) {
+#pragma unroll 1
+        for (int c = 0; c < 3; ++c) {
+            const double f = dp2[3 * b + c] * ih3;
+            if (f == 0.0) continue;
+            const gptr<const double> o = stc + ((long long)b * 3 + c) * kStcPerComp;
+            // x and y factors: sum over the stencil's four nodes (weights past
+            // the kernel's width are zero)
+            cplx<T> wxs = {0, 0}, wys = {0, 0};
+            int ix = (int)(((long long)kx * (long long)o[0]) % nx), iy = (int)(((long long)ky * (long long)o[1]) % ny);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const T wx = (T)o[3 + m], wy = (T)o[7 + m];
+                const cplx<T> ex = twx[ix], ey = twy[iy];
+                wxs = {wxs.x + wx * ex.x, wxs.y + wx * ex.y};
+                wys = {wys.x + wy * ey.x, wys.y + wy * ey.y};
+                ix += kx;
+                if (ix >= nx) ix -= nx;
+                iy += ky;
+                if (iy >= ny) iy -= ny;
+            }
+            cplx<T> wxy = cmul(wxs, wys);
+            wxy = {(T)f * wxy.x, (T)f * wxy.y};
+            const T wz0 = (T)o[11], wz1 = (T)o[12], wz2 = (T)o[13], wz3 = (T)o[14];
+            const int bz = (int)o[2];
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const int kz = t + TL * i;
+                int iz = (int)(((long long)kz * bz) % nz);
+                cplx<T> wzs = {0, 0};
+                const T wz[4] = {wz0, wz1, wz2, wz3};
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const cplx<T> ez = twz[iz];
+                    wzs = {wzs.x + wz[m] * ez.x, wzs.y + wz[m] * ez.y};
+                    iz += kz;
+                    if (iz >= nz) iz -= nz;
+                }
+                const cplx<T> v = cmul(wxy, wzs);
+                if (c == 0) a0[i] = cadd(a0[i], v);
+                if (c == 1) a1[i] = cadd(a1[i], v);
+                if (c == 2) a2[i] = cadd(a2[i], v);
+            }
+        }
+    }
+}
+
+template <typename T, int N, int E, int R0, int R1, int R2, bool SRC = false>
 __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ rd, int B, int solve,
                                                  int project) {
     extern __shared__ unsigned char smem_raw[];
@@ -329,16 +397,22 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
     // the buffer's end) zero, transforms it on its own and is never stored,
     // so no select has to wait for the loads.
     cplx<T> a0[E], a1[E], a2[E];
+    if constexpr (SRC) {
+        // the transform in (x, y, z) of the spread field, formed directly
+        __syncthreads();  // twiddles in LDS
+        spectral_source<T, N, E>(rd[blockIdx.z], kx, y, t, tws, a0, a1, a2);
+    } else {
 #pragma unroll
-    for (int i = 0; i < E; ++i) a0[i] = sb.load(vo, (uint32_t)(TL * i) * zb);
+        for (int i = 0; i < E; ++i) a0[i] = sb.load(vo, (uint32_t)(TL * i) * zb);
 #pragma unroll
-    for (int i = 0; i < E; ++i) a1[i] = sb.load(vo, (uint32_t)(TL * i) * zb + cb);
+        for (int i = 0; i < E; ++i) a1[i] = sb.load(vo, (uint32_t)(TL * i) * zb + cb);
 #pragma unroll
-    for (int i = 0; i < E; ++i) a2[i] = sb.load(vo, (uint32_t)(TL * i) * zb + 2 * cb);
-    __syncthreads();
-    reg_fft<T, N, E, R0, R1, R2, -1>(a0, t, lds, B, b, tws);
-    reg_fft<T, N, E, R0, R1, R2, -1>(a1, t, lds, B, b, tws);
-    reg_fft<T, N, E, R0, R1, R2, -1>(a2, t, lds, B, b, tws);
+        for (int i = 0; i < E; ++i) a2[i] = sb.load(vo, (uint32_t)(TL * i) * zb + 2 * cb);
+        __syncthreads();
+        reg_fft<T, N, E, R0, R1, R2, -1>(a0, t, lds, B, b, tws);
+        reg_fft<T, N, E, R0, R1, R2, -1>(a1, t, lds, B, b, tws);
+        reg_fft<T, N, E, R0, R1, R2, -1>(a2, t, lds, B, b, tws);
+    }
     if (ok) {
         const gptr<const T> glz = as_global(g.lz);
         const gptr<const cplx<T>> gdz = as_global(g.dz_hat);
@@ -687,7 +761,7 @@ bool y_fast(const Batch<T>& Bt, int dir, hipStream_t s) {
     }
 }
 
-template <typename T, int N, typename Pl>
+template <typename T, int N, typename Pl, bool SRC = false>
 bool z_fast_plan(const Batch<T>& Bt, int solve, bool project, hipStream_t s, bool carry) {
     if constexpr (!Pl::ok) {
         return false;
@@ -698,9 +772,9 @@ bool z_fast_plan(const Batch<T>& Bt, int solve, bool project, hipStream_t s, boo
         while (B > 1 && B * TL > 512) B /= 2;
         const dim3 grid((unsigned)((g.nx / 2 + B - 1) / B + 1), g.ny, Bt.nrep);
         const size_t lds = (size_t)N * (B + 1) * sizeof(cplx<T>);
-        allow_lds(k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>, lds);
-        hipLaunchKernelGGL((k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2>), grid, dim3(B * TL), lds, s, Bt.d, B,
-                           solve, (project ? 1 : 0) | (carry ? 2 : 0));
+        allow_lds(k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, SRC>, lds);
+        hipLaunchKernelGGL((k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, SRC>), grid, dim3(B * TL), lds, s, Bt.d,
+                           B, solve, (project ? 1 : 0) | (carry ? 2 : 0));
         return true;
     }
 }
@@ -709,6 +783,12 @@ template <typename T, int N>
 bool z_fast(const Batch<T>& Bt, int solve, bool project, hipStream_t s, bool carry) {
     if (Bt.g.zsmall) return z_fast_plan<T, N, PlanZ<T, N>>(Bt, solve, project, s, carry);
     return z_fast_plan<T, N, Plan<T, N>>(Bt, solve, project, s, carry);
+}
+
+template <typename T, int N>
+bool z_fast_src(const Batch<T>& Bt, int solve, hipStream_t s, bool carry) {
+    if (Bt.g.zsmall) return z_fast_plan<T, N, PlanZ<T, N>, true>(Bt, solve, true, s, carry);
+    return z_fast_plan<T, N, Plan<T, N>, true>(Bt, solve, true, s, carry);
 }
 
 template <typename T, int N>
@@ -791,6 +871,13 @@ bool fast_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s,
 #undef C
 }
 template <typename T>
+bool fast_fft_z_solve_from_blobs(const Batch<T>& B, int solve, hipStream_t s, bool carry) {
+    if (!B.g.fast) return false;
+#define C(NN) z_fast_src<T, NN>(B, solve, s, carry)
+    ICM_SWITCH_N(B.g.nz, C)
+#undef C
+}
+template <typename T>
 bool fast_fft_x_forward(const Batch<T>& B, int in, hipStream_t s) {
 #define C(NN) xf_fast<T, NN>(B, in, s)
     ICM_SWITCH_N(B.g.nx, C)
@@ -807,6 +894,7 @@ bool fast_fft_x_inverse(const Batch<T>& B, int out, int acc, hipStream_t s) {
     template bool fast_fft_available<T>(int, int, int);                            \
     template bool fast_fft_y<T>(const Batch<T>&, int, hipStream_t);                \
     template bool fast_fft_z_solve<T>(const Batch<T>&, int, bool, hipStream_t, bool); \
+    template bool fast_fft_z_solve_from_blobs<T>(const Batch<T>&, int, hipStream_t, bool); \
     template bool fast_fft_x_forward<T>(const Batch<T>&, int, hipStream_t);        \
     template bool fast_fft_x_inverse<T>(const Batch<T>&, int, int, hipStream_t);
 ICM_INST(float)

@@ -338,6 +338,12 @@ template <typename T>
 bool fast_fft_y(const Batch<T>& B, int dir, hipStream_t s);
 template <typename T>
 bool fast_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s, bool carry = false);
+// The z pass and solve with its input spectrum formed from the blobs instead
+// of read: the transform of S dp2 (step 6), so that no field is zeroed and
+// spread and no x or y forward pass runs. False (launching nothing) without a
+// register-resident plan for the grid.
+template <typename T>
+bool fast_fft_z_solve_from_blobs(const Batch<T>& B, int solve, hipStream_t s, bool carry);
 template <typename T>
 bool fast_fft_x_forward(const Batch<T>& B, int in, hipStream_t s);
 template <typename T>

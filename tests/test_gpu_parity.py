@@ -477,22 +477,26 @@ def test_set_fft_shapes_rejects_bad_values(I):
         sim.close()
 
 
+@pytest.mark.parametrize("grid", [(32, 24, 36), (32, 48, 64)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_step5_table_and_field_paths_match_the_oracle(I, precision):
+def test_step5_table_and_field_paths_match_the_oracle(I, precision, grid):
     """Step 5's g = J P S (c5 dp) for replicas of at most 8 blobs comes from
     the tabulated projection kernel; with a capacity above 8 blobs (or 12
     blobs) it is formed as a field and interpolated. Both paths against the
-    oracle, same state, mixed excess masses and both kernels."""
+    oracle, same state, mixed excess masses and both kernels. On the grid
+    with register-resident FFT plans (32 x 48 x 64) the table cases also
+    take step 6's source transform from the blobs inside the z pass; on
+    the other (generic FFT) they spread it into a field."""
     prec = I.FP64 if precision == "fp64" else I.FP32_GRID
     tol = TOL64 if precision == "fp64" else TOL32
     steps = 3 if precision == "fp64" else 1
     dtype = np.float64 if prec == I.FP64 else np.float32
     for kernel, nb, cap in ((4, 5, 5), (4, 5, 9), (3, 7, 7), (3, 12, 12)):
-        p = oracle_params((32, 24, 36), kernel=kernel, kT=1e-3, dt=0.3, seed=150 + nb, rho=1.3, eta=0.8)
+        p = oracle_params(grid, kernel=kernel, kT=1e-3, dt=0.3, seed=150 + nb, rho=1.3, eta=0.8)
         st = initial_state(p, nb, (1.0, -0.5, 0.0, 3.0), seed=160 + nb, min_sep=3.0)
         if prec == I.FP32_GRID:
             st.v = st.v.astype(np.float32).astype(np.float64)
-        banner("step 5 paths %s kernel=%d nb=%d capacity=%d" % (precision, kernel, nb, cap))
+        banner("step 5 paths %s grid=%s kernel=%d nb=%d capacity=%d" % (precision, grid, kernel, nb, cap))
         sim = I.Sim([gpu_params(I, p)], [cap], prec)
         try:
             load_into_gpu(I, sim, 0, st, dtype)
