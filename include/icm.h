@@ -204,10 +204,12 @@ icm_status icm_set_state(icm_ctx* ctx, int32_t replica, const void* v,
  * raised. Flags: ICM_STEP_GRAPH (other bits: ICM_E_INVALID).               */
 icm_status icm_step(icm_ctx* ctx, int64_t n_steps, uint32_t flags);
 
-/* Launch shapes of the FFT passes for one grid shape, as chosen by
- * icm_autotune. Times are the five passes of one spectral solve (x forward,
- * y forward, z with the solve, y inverse, x inverse) for all replicas of
- * that shape, in microseconds.                                             */
+/* Launch shapes of the FFT passes and of the right-hand-side kernel for
+ * one grid shape, as chosen by icm_autotune. FFT times are the five passes
+ * of one spectral solve (x forward, y forward, z with the solve, y inverse,
+ * x inverse) for all replicas of that shape, RHS times one launch of the
+ * step-2 right-hand side (noise, viscous term, spread forces) followed by
+ * those five passes, in microseconds.                                      */
 typedef struct {
     int32_t n[3];          /* grid shape                                      */
     int32_t y_columns;     /* kx columns per workgroup of the y passes         */
@@ -216,14 +218,21 @@ typedef struct {
     int32_t x_threads;     /* threads per workgroup of the x passes            */
     int32_t tuned;         /* 0: this shape takes the generic passes (nothing
                               to tune)                                        */
+    int32_t rhs_z_chunk;   /* z planes per workgroup of the right-hand-side
+                              kernel (4, 8 or 16; 0: chosen from the batch's
+                              size)                                           */
     double us_default;     /* with the default shapes                         */
     double us_tuned;       /* with the chosen shapes                          */
+    double us_rhs_default; /* RHS kernel and one solve's five passes, with the
+                              size-based z chunk                              */
+    double us_rhs_tuned;   /* the same with the chosen z chunk                */
 } icm_tune_result;
 
-/* Measure the launch-shape variants of the FFT passes on the context's own
- * scratch buffers (right-hand side, spectrum and inertial-correction fields;
- * the state v, q, u is not touched) and keep the fastest for each grid
- * shape. Enqueued on the context stream; synchronises. results: room for
+/* Measure the launch-shape variants of the FFT passes and the z chunk of
+ * the right-hand-side kernel on the context's own scratch buffers
+ * (right-hand side, spectrum and inertial-correction fields, the spread's
+ * z-chunk bins; the state v, q, u is not touched) and keep the fastest for
+ * each grid shape. Enqueued on the context stream; synchronises. results: room for
  * `capacity` entries (may be NULL when capacity is 0); *n_results receives
  * the number of distinct grid shapes. A recorded step graph is dropped.     */
 icm_status icm_autotune(icm_ctx* ctx, icm_tune_result* results, int32_t capacity, int32_t* n_results);
@@ -231,8 +240,8 @@ icm_status icm_autotune(icm_ctx* ctx, icm_tune_result* results, int32_t capacity
 /* Install FFT launch shapes without measuring (for instance results saved
  * from an earlier icm_autotune): for each of the `count` entries, the
  * replicas whose grid shape equals n take y_columns and z_columns (1, 2, 4,
- * ..., 64), z_small_plan (0 or 1) and x_threads (64, 128, 256 or 512); the
- * time and `tuned` fields are ignored. Shapes only change how the passes are
+ * ..., 64), z_small_plan (0 or 1), x_threads (64, 128, 256 or 512) and
+ * rhs_z_chunk (0, 4, 8 or 16); the time and `tuned` fields are ignored. Shapes only change how the passes are
  * launched, not their results beyond rounding. ICM_E_INVALID (context
  * unchanged) for a value outside those sets or a shape no replica has.
  * A recorded step graph is dropped.                                        */

@@ -34,6 +34,7 @@ struct Replica {
     int max_nb = 0;
     int nb = 0;
     int64_t step = 0;
+    int zc_tuned = 0;        // RHS z chunk from the autotuner (0: by batch size)
     bool any_me = false;
     double m_f = 0, mt_f = 0;
     icm::GridDesc<float> gf{};
@@ -545,6 +546,16 @@ void drop_graph(icm_ctx* c) {
     c->graph = nullptr;
 }
 
+// z chunk of the RHS kernel by batch size: the longest of 16, 8, 4 planes
+// that still gives the launch at least 512 workgroups (two per compute
+// unit); the 16-plane chunk amortises each chunk's prologue best.
+int default_zc(const int n[3], int nrep) {
+    const long long tiles = (long long)((n[0] + 31) / 32) * ((n[1] + 15) / 16) * (long long)nrep;
+    int zc = icm::kRhsZChunk;
+    while (zc > icm::kRhsZChunkMin && tiles * ((n[2] + zc - 1) / zc) < 512) zc /= 2;
+    return zc;
+}
+
 // Group the replicas into batches and upload their descriptors (after any
 // change of blob counts or masses). Drops a captured step.
 template <typename T>
@@ -571,13 +582,10 @@ icm_status sync_batches_t(icm_ctx* c) {
     // inertial replicas first (a stable order within each part)
     for (BatchInfo& B : c->batches)
         std::stable_partition(B.reps.begin(), B.reps.end(), [c](int r) { return c->reps[r].any_me; });
-    // z-chunk of the RHS kernel per batch: the longest of 16, 8, 4 planes
-    // that still gives the batch's launch at least 512 workgroups (two per
-    // compute unit); the 16-plane chunk amortises each chunk's prologue best
+    // z chunk of the RHS kernel per batch: the autotuner's, else by size
     for (BatchInfo& B : c->batches) {
-        const long long tiles = (long long)((B.n[0] + 31) / 32) * ((B.n[1] + 15) / 16) * (long long)B.reps.size();
-        int zc = icm::kRhsZChunk;
-        while (zc > icm::kRhsZChunkMin && tiles * ((B.n[2] + zc - 1) / zc) < 512) zc /= 2;
+        int zc = c->reps[B.reps[0]].zc_tuned;
+        if (zc <= 0) zc = default_zc(B.n, (int)B.reps.size());
         for (int r : B.reps) grid_of<T>(c->reps[r]).zc = zc;
     }
     std::vector<icm::RepDesc<T>> h(c->reps.size());
@@ -851,6 +859,47 @@ float time_fft(icm_ctx* c, const icm::Batch<T>& B, hipEvent_t ea, hipEvent_t eb)
     return ms * 1000.f / kReps;
 }
 
+// Average time of one right-hand-side launch of batch b with z chunk zc,
+// each followed by one solve's five FFT passes as in the step (the RHS kernel
+// timed alone finds different data in the caches, and such timings picked
+// chunks that were slower in the step): the chunk is installed, the
+// spread's bins computed for it (from the positions and forces of the last
+// step) and cleared again afterwards.
+template <typename T>
+float time_rhs(icm_ctx* c, size_t b, int zc, hipEvent_t ea, hipEvent_t eb) {
+    for (int r : c->batches[b].reps) c->reps[r].zc_tuned = zc;
+    if (sync_batches(c) != ICM_OK) return -1.f;
+    const BatchInfo& bi = c->batches[b];  // same grouping: the replicas did not change
+    const icm::Batch<T> B = batch_of<T>(c, bi);
+    hipStream_t s = c->stream;
+    auto clear = [&] {
+        for (int r : bi.reps) {
+            const Replica& R = c->reps[r];
+            (void)hipMemsetAsync(R.bb.chunk_count, 0, (size_t)(icm::max_chunks(R.p.n[2]) + 1) * sizeof(int), s);
+        }
+    };
+    clear();
+    icm::launch_bins(B, s);
+    auto once = [&] {
+        icm::launch_rhs(B, s);
+        icm::launch_fft_x_forward(B, icm::kFieldRhs, s);
+        icm::launch_fft_y(B, -1, s);
+        icm::launch_fft_z_solve(B, icm::kSolveP, true, s);
+        icm::launch_fft_y(B, 1, s);
+        icm::launch_fft_x_inverse(B, icm::kFieldAux, 0, s);
+    };
+    once();  // warm-up
+    constexpr int kReps = 10;
+    (void)hipEventRecord(ea, s);
+    for (int r = 0; r < kReps; ++r) once();
+    (void)hipEventRecord(eb, s);
+    clear();
+    if (hipEventSynchronize(eb) != hipSuccess) return -1.f;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ea, eb) != hipSuccess) return -1.f;
+    return ms * 1000.f / kReps;
+}
+
 template <typename T>
 icm_status autotune_t(icm_ctx* c, icm_tune_result* res, int32_t cap, int32_t* nres) {
     hipEvent_t ea = nullptr, eb = nullptr;
@@ -935,6 +984,38 @@ icm_status autotune_t(icm_ctx* c, icm_tune_result* res, int32_t cap, int32_t* nr
         r.x_threads = g.xt;
         if (res && count < cap) res[count] = r;
         ++count;
+    }
+    // RHS z chunk per batch: 16, 8 and 4 planes, each timed with its own
+    // bins (RHS plus a solve's passes); the size-based choice stays unless
+    // another makes that unit at least 1% faster
+    for (size_t b = 0; b < c->batches.size() && st == ICM_OK; ++b) {
+        const std::vector<int> reps = c->batches[b].reps;
+        int n3[3];
+        for (int a = 0; a < 3; ++a) n3[a] = c->batches[b].n[a];
+        const int zdef = default_zc(n3, (int)reps.size());
+        const float t0 = time_rhs<T>(c, b, zdef, ea, eb);
+        if (t0 < 0) {
+            st = fail(c, ICM_E_DEVICE, "autotune timing failed");
+            break;
+        }
+        float best = t0;
+        int bz = zdef;
+        for (int zc : {16, 8, 4}) {
+            if (zc == zdef) continue;
+            const float t = time_rhs<T>(c, b, zc, ea, eb);
+            if (t >= 0 && t < 0.99f * best) {
+                best = t;
+                bz = zc;
+            }
+        }
+        for (int r : reps) c->reps[r].zc_tuned = bz;
+        for (int e = 0; res && e < std::min(count, (int)cap); ++e)
+            if (res[e].n[0] == n3[0] && res[e].n[1] == n3[1] && res[e].n[2] == n3[2] && res[e].rhs_z_chunk == 0) {
+                res[e].rhs_z_chunk = bz;
+                res[e].us_rhs_default = t0;
+                res[e].us_rhs_tuned = best;
+                break;
+            }
     }
     (void)hipEventDestroy(ea);
     (void)hipEventDestroy(eb);
@@ -1293,7 +1374,8 @@ icm_status icm_set_fft_shapes(icm_ctx* c, const icm_tune_result* shapes, int32_t
     for (int e = 0; e < count; ++e) {
         const icm_tune_result& r = shapes[e];
         if (!pow2(r.y_columns) || !pow2(r.z_columns) || (r.z_small_plan != 0 && r.z_small_plan != 1) ||
-            !(r.x_threads == 64 || r.x_threads == 128 || r.x_threads == 256 || r.x_threads == 512))
+            !(r.x_threads == 64 || r.x_threads == 128 || r.x_threads == 256 || r.x_threads == 512) ||
+            !(r.rhs_z_chunk == 0 || r.rhs_z_chunk == 4 || r.rhs_z_chunk == 8 || r.rhs_z_chunk == 16))
             return fail(c, ICM_E_INVALID, "entry %d: launch shape out of range", e);
         bool any = false;
         for (const Replica& R : c->reps)
@@ -1305,6 +1387,7 @@ icm_status icm_set_fft_shapes(icm_ctx* c, const icm_tune_result* shapes, int32_t
         const icm_tune_result& r = shapes[e];
         for (Replica& R : c->reps) {
             if (R.p.n[0] != r.n[0] || R.p.n[1] != r.n[1] || R.p.n[2] != r.n[2]) continue;
+            R.zc_tuned = r.rhs_z_chunk;
             auto apply = [&](auto& g) {
                 g.By = r.y_columns;
                 g.Bz = r.z_columns;

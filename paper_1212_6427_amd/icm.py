@@ -86,8 +86,11 @@ class icm_tune_result(ctypes.Structure):
         ("z_small_plan", ctypes.c_int32),
         ("x_threads", ctypes.c_int32),
         ("tuned", ctypes.c_int32),
+        ("rhs_z_chunk", ctypes.c_int32),
         ("us_default", ctypes.c_double),
         ("us_tuned", ctypes.c_double),
+        ("us_rhs_default", ctypes.c_double),
+        ("us_rhs_tuned", ctypes.c_double),
     ]
 
 
@@ -226,7 +229,9 @@ def icm_autotune(ctx, capacity=64):
     out = []
     for r in res[:min(n.value, capacity)]:
         out.append(dict(n=tuple(r.n), y_columns=r.y_columns, z_columns=r.z_columns, z_small_plan=r.z_small_plan,
-                        x_threads=r.x_threads, tuned=bool(r.tuned), us_default=r.us_default, us_tuned=r.us_tuned))
+                        x_threads=r.x_threads, rhs_z_chunk=r.rhs_z_chunk, tuned=bool(r.tuned),
+                        us_default=r.us_default, us_tuned=r.us_tuned, us_rhs_default=r.us_rhs_default,
+                        us_rhs_tuned=r.us_rhs_tuned))
     return out
 
 
@@ -289,8 +294,9 @@ def icm_set_advection_lag(ctx, replica, lag, field_dtype=np.float64):
 
 
 def icm_set_fft_shapes(ctx, shapes):
-    """Install FFT launch shapes: a list of dicts with n, y_columns,
-    z_columns, z_small_plan and x_threads (as icm_autotune returns them)."""
+    """Install launch shapes: a list of dicts with n, y_columns, z_columns,
+    z_small_plan, x_threads and optionally rhs_z_chunk (as icm_autotune
+    returns them)."""
     arr = (icm_tune_result * max(len(shapes), 1))()
     for i, sh in enumerate(shapes):
         arr[i].n[:] = [int(x) for x in sh["n"]]
@@ -298,6 +304,7 @@ def icm_set_fft_shapes(ctx, shapes):
         arr[i].z_columns = int(sh["z_columns"])
         arr[i].z_small_plan = int(sh["z_small_plan"])
         arr[i].x_threads = int(sh["x_threads"])
+        arr[i].rhs_z_chunk = int(sh.get("rhs_z_chunk", 0))
     _check(_lib.icm_set_fft_shapes(ctx, arr, len(shapes)), ctx)
 
 

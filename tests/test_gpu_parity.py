@@ -309,6 +309,7 @@ def test_autotuned_launch_shapes_keep_parity(I, precision):
             assert r["y_columns"] in (8, 16, 32) and r["z_columns"] in (8, 16, 32)
             assert r["x_threads"] in (128, 256, 512) and r["z_small_plan"] in (0, 1)
             assert r["us_default"] > 0 and r["us_tuned"] > 0
+            assert r["rhs_z_chunk"] in (4, 8, 16) and r["us_rhs_default"] > 0 and r["us_rhs_tuned"] > 0
         # the state is not touched by the measurements
         for r in range(len(cases)):
             after = sim.get_state(r, want_diag=False)
@@ -445,19 +446,21 @@ def test_every_fft_launch_shape_keeps_parity(I, precision):
         for st in states:
             st.v = st.v.astype(np.float32).astype(np.float64)
     refs = [O.step(p, st) for (p, _, _), st in zip(cases, states)]
-    combos = [(1, 4, 4, 64), (0, 16, 64, 512), (1, 64, 16, 128), (0, 1, 2, 256), (1, 32, 32, 512), (0, 8, 1, 64)]
-    for zs, by, bz, xt in combos:
-        banner("fft shapes %s zsmall=%d By=%d Bz=%d xt=%d" % (precision, zs, by, bz, xt))
+    # (z plan, y columns, z columns, x threads, RHS z chunk; 0: by batch size)
+    combos = [(1, 4, 4, 64, 0), (0, 16, 64, 512, 4), (1, 64, 16, 128, 16), (0, 1, 2, 256, 8), (1, 32, 32, 512, 0),
+              (0, 8, 1, 64, 16)]
+    for zs, by, bz, xt, zc in combos:
+        banner("fft shapes %s zsmall=%d By=%d Bz=%d xt=%d zc=%d" % (precision, zs, by, bz, xt, zc))
         sim = I.Sim([gpu_params(I, p) for p, _, _ in cases], [nb for _, _, nb in cases], prec)
         try:
             for r, st in enumerate(states):
                 load_into_gpu(I, sim, r, st, dtype)
-            sim.set_fft_shapes([dict(n=p.n, y_columns=by, z_columns=bz, z_small_plan=zs, x_threads=xt)
+            sim.set_fft_shapes([dict(n=p.n, y_columns=by, z_columns=bz, z_small_plan=zs, x_threads=xt, rhs_z_chunk=zc)
                                 for p, _, _ in cases])
             sim.step(1, I.STEP_GRAPH)
             for r, (ref, st) in enumerate(zip(refs, states)):
                 errs, bad = compare(sim.get_state(r), ref, st.q, tol)
-                assert not bad, (zs, by, bz, xt, r, bad)
+                assert not bad, (zs, by, bz, xt, zc, r, bad)
         finally:
             sim.close()
 
@@ -469,6 +472,7 @@ def test_set_fft_shapes_rejects_bad_values(I):
         for bad in (dict(n=(16, 16, 16), y_columns=3, z_columns=8, z_small_plan=1, x_threads=256),
                     dict(n=(16, 16, 16), y_columns=8, z_columns=8, z_small_plan=2, x_threads=256),
                     dict(n=(16, 16, 16), y_columns=8, z_columns=8, z_small_plan=1, x_threads=1024),
+                    dict(n=(16, 16, 16), y_columns=8, z_columns=8, z_small_plan=1, x_threads=256, rhs_z_chunk=5),
                     dict(n=(32, 16, 16), y_columns=8, z_columns=8, z_small_plan=1, x_threads=256)):
             with pytest.raises(I.ICMError) as e:
                 sim.set_fft_shapes([bad])
