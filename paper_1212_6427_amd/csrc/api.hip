@@ -285,6 +285,7 @@ void carve_blobs(Carver& cv, int max_nb, int nz, icm::BlobBufs& b, double*& diag
     b.dp2 = cv.take<double>(n3);
     b.g = cv.take<double>(n3);
     b.Jhvnew = cv.take<double>(n3);
+    b.JLvt = cv.take<double>(n3);
     b.me = cv.take<double>(max_nb);
     b.c5 = cv.take<double>(max_nb);
     b.cdrift = cv.take<double>(max_nb);
@@ -677,12 +678,33 @@ void enqueue_step(icm_ctx* c, const BatchInfo& bi, hipStream_t s) {
     timed(c, ICM_PHASE_RHS, s, [&] { launch_rhs(B, s); });
     timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread_overflow(B, s); });
     if (bi.adv) timed(c, ICM_PHASE_ADVECTION, s, [&] { launch_advect(B, s); });
-    enqueue_fft_solve(c, B, kFieldRhs, kFieldV, 0, kSolveH1, s);
+    // Replicas with excess mass and at most kTabMaxBlobs blobs on a
+    // register-resident grid keep the first solve in the spectrum: step 4
+    // reads J v~ (and J L v~) from it, step 6's solve adds its own result to
+    // it, and one inverse y and x pass then gives v^{n+1}.
+    const bool spectral = bi.n_me > 0 && bi.table && bi.me_max_nb <= kTabMaxBlobs && B.g.fast;
+    if (!spectral) {
+        enqueue_fft_solve(c, B, kFieldRhs, kFieldV, 0, kSolveH1, s);
+    } else {
+        timed(c, ICM_PHASE_FFT_X_FWD, s, [&] { launch_fft_x_forward(B, kFieldRhs, s); });
+        timed(c, ICM_PHASE_FFT_Y_FWD, s, [&] { launch_fft_y(B, -1, s); });
+        timed(c, ICM_PHASE_FFT_Z_SOLVE, s, [&] { launch_fft_z_solve(B, kSolveH1, true, s, true); });
+        if (bi.n_me < bi.count) {
+            // the replicas without excess mass finish the solve now
+            const icm::Batch<T> Bn = batch_view<T>(c, bi.first + bi.n_me, bi.count - bi.n_me,
+                                                   c->reps[bi.reps[bi.n_me]], bi.max_nb, false, false);
+            timed(c, ICM_PHASE_FFT_Y_INV, s, [&] { launch_fft_y(Bn, 1, s); });
+            timed(c, ICM_PHASE_FFT_X_INV, s, [&] { launch_fft_x_inverse(Bn, kFieldV, 0, s); });
+        }
+    }
     if (bi.n_me > 0) {
         // steps 4-8 over the leading replicas with excess mass only
         const icm::Batch<T> B = batch_view<T>(c, bi.first, bi.n_me, c->reps[bi.reps[0]], bi.me_max_nb, false, false);
         // Step 4: J^{n+1/2} v~, the slip correction and the excess momentum.
-        timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather(B, kFieldV, kBlobQh, kBlobJhvt, false, s, kEpiDp); });
+        if (spectral)
+            timed(c, ICM_PHASE_GATHER, s, [&] { launch_spectral_gather(B, s); });
+        else
+            timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather(B, kFieldV, kBlobQh, kBlobJhvt, false, s, kEpiDp); });
         // Step 5: dv~ = m~_f/(rho m~) P S dp, needed only as g = J dv~: for
         // few blobs through the projection-kernel table, else as a field;
         // with g, the step-6 source dp - m_e J dv~ and u^{n+1} (step 8).
@@ -696,19 +718,16 @@ void enqueue_step(icm_ctx* c, const BatchInfo& bi, hipStream_t s) {
             timed(c, ICM_PHASE_BLOB, s, [&] { launch_dp2_sum(B, s); });
         }
         // Step 6: (rho - dt/2 eta L) dv + dt G dpi = S (dp - m_e J dv~);
-        // step 7: v^{n+1} = v~ + dv, written by the last pass with dv itself
-        // (kept in aux for the lagged term gathered in step 9). For few blobs
-        // on a register-resident plan, the z pass forms the transform of the
-        // spread source from the stencil records itself.
-        const bool carry = true;
-        bool src = false;
-        if (bi.table && bi.me_max_nb <= kTabMaxBlobs && B.g.fast) {
-            timed(c, ICM_PHASE_FFT_Z_SOLVE, s, [&] { src = fast_fft_z_solve_from_blobs(B, kSolveH2, s, carry); });
-        }
-        if (src) {
+        // step 7: v^{n+1} = v~ + dv.
+        if (spectral) {
+            // the z pass forms the transform of the spread source from the
+            // stencil records and adds its solve to the first one
+            timed(c, ICM_PHASE_FFT_Z_SOLVE, s, [&] { (void)fast_fft_z_solve_from_blobs(B, kSolveH2, s, true, true); });
             timed(c, ICM_PHASE_FFT_Y_INV, s, [&] { launch_fft_y(B, 1, s); });
-            timed(c, ICM_PHASE_FFT_X_INV, s, [&] { launch_fft_x_inverse(B, kFieldAux, kXinvAlsoV, s); });
+            timed(c, ICM_PHASE_FFT_X_INV, s, [&] { launch_fft_x_inverse(B, kFieldV, 0, s); });
         } else {
+            // dv written to aux by the last pass (for the lagged term of
+            // step 9) and added to v
             timed(c, ICM_PHASE_FIELD_OPS, s, [&] { launch_zero(B, kFieldRhs, s); });
             timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread(B, kFieldRhs, kBlobQh, kBlobDp2, kBlobNone, s); });
             enqueue_fft_solve(c, B, kFieldRhs, kFieldAux, kXinvAlsoV, kSolveH2, s);
@@ -716,7 +735,7 @@ void enqueue_step(icm_ctx* c, const BatchInfo& bi, hipStream_t s) {
     }
     // Step 9 (also the lagged term of the inertial replicas and the device
     // step counters).
-    timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather_final(B, bi.n_me, s); });
+    timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather_final(B, bi.n_me, spectral, s); });
 }
 
 template <typename T>

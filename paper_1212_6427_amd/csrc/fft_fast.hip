@@ -361,7 +361,9 @@ __device__ __forceinline__ void spectral_source(const RepDesc<T>& R, int kx, int
     }
 }
 
-template <typename T, int N, int E, int R0, int R1, int R2, bool SRC = false>
+// SRC 0: the input spectrum read; 1: formed from the blobs; 2: formed from the
+// blobs and the result added to the spectrum already there.
+template <typename T, int N, int E, int R0, int R1, int R2, int SRC = 0>
 __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ rd, int B, int solve,
                                                  int project) {
     extern __shared__ unsigned char smem_raw[];
@@ -397,7 +399,7 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
     // the buffer's end) zero, transforms it on its own and is never stored,
     // so no select has to wait for the loads.
     cplx<T> a0[E], a1[E], a2[E];
-    if constexpr (SRC) {
+    if constexpr (SRC > 0) {
         // the transform in (x, y, z) of the spread field, formed directly
         __syncthreads();  // twiddles in LDS
         spectral_source<T, N, E>(rd[blockIdx.z], kx, y, t, tws, a0, a1, a2);
@@ -452,21 +454,21 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
             carry_mean_mode(rd[blockIdx.z], solve, a0[0], a1[0], a2[0]);
     }
     // each component is stored as soon as its inverse transform is done
+    auto put = [&](cplx<T>(&a)[E], uint32_t co) {
+        if (!ok) return;
+        if constexpr (SRC == 2) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) a[i] = cadd(a[i], sb.load(vo, (uint32_t)(TL * i) * zb + co));
+        }
+#pragma unroll
+        for (int i = 0; i < E; ++i) sb.store(a[i], vo, (uint32_t)(TL * i) * zb + co);
+    };
     reg_fft<T, N, E, R0, R1, R2, 1>(a0, t, lds, B, b, tws);
-    if (ok) {
-#pragma unroll
-        for (int i = 0; i < E; ++i) sb.store(a0[i], vo, (uint32_t)(TL * i) * zb);
-    }
+    put(a0, 0);
     reg_fft<T, N, E, R0, R1, R2, 1>(a1, t, lds, B, b, tws);
-    if (ok) {
-#pragma unroll
-        for (int i = 0; i < E; ++i) sb.store(a1[i], vo, (uint32_t)(TL * i) * zb + cb);
-    }
+    put(a1, cb);
     reg_fft<T, N, E, R0, R1, R2, 1>(a2, t, lds, B, b, tws);
-    if (ok) {
-#pragma unroll
-        for (int i = 0; i < E; ++i) sb.store(a2[i], vo, (uint32_t)(TL * i) * zb + 2 * cb);
-    }
+    put(a2, 2 * cb);
 }
 
 // ------------------------------------------------------------------ x pass
@@ -673,6 +675,109 @@ __global__ void __launch_bounds__(512) k_xinv_fast(const RepDesc<T>* __restrict_
     }
 }
 
+// ------------------------------------------------ step 4 from the spectrum
+// After the first solve's z pass the spectrum holds S(kx, ky, z): z in real
+// space, x and y still transformed (kx < nx/2 in rows, nx/2 in nyq). The
+// field is v(x, y, z) = C2R_x of sum_ky S e^{2 pi i ky y / ny}, so for the
+// tensor-product stencil of a blob component (weights wx, wy, wz on the
+// recorded nodes), J v = sum_z wz(z) Re sum_{kx, ky} c_kx Wx(kx) Wy(ky)
+// S(kx, ky, z), with Wa(k) = sum_m wa[m] exp(+2 pi i k (base_a + m) / n_a)
+// and c = 1 at kx = 0 and nx/2 (real there after the inverse), 2 between.
+// J L v takes -(lam_x + lam_y) S + (S(z + 1) + S(z - 1) - 2 S(z)) / h^2 in
+// place of S (the 7-point Laplacian: its x and y parts diagonal in kx, ky).
+// One workgroup per (blob component, replica), a fixed-order reduction;
+// then du and dp as in the step-4 gather.
+template <typename T>
+__global__ void __launch_bounds__(256) k_spec_gather(const RepDesc<T>* __restrict__ rd) {
+    __shared__ double red[2][256];
+    const RepDesc<T>& R = rd[blockIdx.y];
+    const int o = (int)blockIdx.x;
+    if (o >= 3 * R.bp.nb) return;
+    const int bl = o / 3, a = o - 3 * bl;
+    const GridDesc<T>& g = R.g;
+    const int nx = g.nx, ny = g.ny, nz = g.nz, H = nx / 2, W = H + 1;
+    const gptr<const double> rec = as_global((const double*)R.bb.stc) + (long long)o * kStcPerComp;
+    const int bx = (int)rec[0], by = (int)rec[1], bz = (int)rec[2];
+    double wx[4], wy[4], wz[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        wx[m] = rec[3 + m];
+        wy[m] = rec[7 + m];
+        wz[m] = rec[11 + m];
+    }
+    const double ih2 = 1.0 / (g.h * g.h);
+    const gptr<const cplx<T>> spec = as_global((const cplx<T>*)g.spec) + (long long)a * g.nspec;
+    const gptr<const cplx<T>> nyq = as_global((const cplx<T>*)g.nyq) + (long long)a * nz * ny;
+    const gptr<const cplx<T>> twx = as_global(g.twx), twy = as_global(g.twy);
+    const gptr<const T> lx = as_global(g.lx), ly = as_global(g.ly);
+    int zs[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        int z = bz - 1 + j;
+        z %= nz;
+        zs[j] = z < 0 ? z + nz : z;
+    }
+    double sv = 0.0, sl = 0.0;
+    for (int idx = threadIdx.x; idx < W * ny; idx += blockDim.x) {
+        const int ky = idx / W, kx = idx - ky * W;
+        // Wx(kx) Wy(ky): the forward twiddles exp(-2 pi i j / n), conjugated
+        double xr = 0, xi = 0, yr = 0, yi = 0;
+        int ix = (int)(((long long)kx * bx) % nx), iy = (int)(((long long)ky * by) % ny);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const cplx<T> ex = twx[ix], ey = twy[iy];
+            xr += wx[m] * (double)ex.x;
+            xi -= wx[m] * (double)ex.y;
+            yr += wy[m] * (double)ey.x;
+            yi -= wy[m] * (double)ey.y;
+            ix += kx;
+            if (ix >= nx) ix -= nx;
+            iy += ky;
+            if (iy >= ny) iy -= ny;
+        }
+        const double cw = (kx == 0 || kx == H) ? 1.0 : 2.0;
+        const double cr = cw * (xr * yr - xi * yi), ci = cw * (xr * yi + xi * yr);
+        const double lam = (double)lx[kx] + (double)ly[ky];
+        double sr[6], si[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const cplx<T> v = kx < H ? spec[((long long)zs[j] * ny + ky) * g.Wp + kx] : nyq[(long long)zs[j] * ny + ky];
+            sr[j] = (double)v.x;
+            si[j] = (double)v.y;
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int j = m + 1;
+            sv += wz[m] * (cr * sr[j] - ci * si[j]);
+            const double lr = -lam * sr[j] + (sr[j + 1] + sr[j - 1] - 2.0 * sr[j]) * ih2;
+            const double li = -lam * si[j] + (si[j + 1] + si[j - 1] - 2.0 * si[j]) * ih2;
+            sl += wz[m] * (cr * lr - ci * li);
+        }
+    }
+    red[0][threadIdx.x] = sv;
+    red[1][threadIdx.x] = sl;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + off];
+            red[1][threadIdx.x] += red[1][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const BlobBufs& bb = R.bb;
+        const BlobParams& bp = R.bp;
+        const double J = red[0][0];
+        bb.Jhvt[o] = J;
+        bb.JLvt[o] = red[1][0];
+        double du = 0.0;
+        if (bp.slip == 2) du += bb.Jhvn[o] - bb.Jn[o];
+        if (bp.slip >= 1) du += 0.5 * (bp.eta / bp.rho) * bp.dt * bb.lag[o];
+        bb.du[o] = du;
+        bb.dp[o] = bb.me[bl] * (bb.u[o] - J - du);
+    }
+}
+
 // --------------------------------------------------------------- dispatch
 // Plans: (E, R0, R1, R2) per (precision, N); a radix of 1 ends the list.
 template <typename T, int N>
@@ -761,7 +866,7 @@ bool y_fast(const Batch<T>& Bt, int dir, hipStream_t s) {
     }
 }
 
-template <typename T, int N, typename Pl, bool SRC = false>
+template <typename T, int N, typename Pl, int SRC = 0>
 bool z_fast_plan(const Batch<T>& Bt, int solve, bool project, hipStream_t s, bool carry) {
     if constexpr (!Pl::ok) {
         return false;
@@ -786,9 +891,13 @@ bool z_fast(const Batch<T>& Bt, int solve, bool project, hipStream_t s, bool car
 }
 
 template <typename T, int N>
-bool z_fast_src(const Batch<T>& Bt, int solve, hipStream_t s, bool carry) {
-    if (Bt.g.zsmall) return z_fast_plan<T, N, PlanZ<T, N>, true>(Bt, solve, true, s, carry);
-    return z_fast_plan<T, N, Plan<T, N>, true>(Bt, solve, true, s, carry);
+bool z_fast_src(const Batch<T>& Bt, int solve, hipStream_t s, bool carry, bool acc) {
+    if (acc) {
+        if (Bt.g.zsmall) return z_fast_plan<T, N, PlanZ<T, N>, 2>(Bt, solve, true, s, carry);
+        return z_fast_plan<T, N, Plan<T, N>, 2>(Bt, solve, true, s, carry);
+    }
+    if (Bt.g.zsmall) return z_fast_plan<T, N, PlanZ<T, N>, 1>(Bt, solve, true, s, carry);
+    return z_fast_plan<T, N, Plan<T, N>, 1>(Bt, solve, true, s, carry);
 }
 
 template <typename T, int N>
@@ -871,9 +980,13 @@ bool fast_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s,
 #undef C
 }
 template <typename T>
-bool fast_fft_z_solve_from_blobs(const Batch<T>& B, int solve, hipStream_t s, bool carry) {
+void launch_spectral_gather(const Batch<T>& B, hipStream_t s) {
+    if (B.max_nb > 0) hipLaunchKernelGGL(k_spec_gather<T>, dim3(3 * B.max_nb, B.nrep), dim3(256), 0, s, B.d);
+}
+template <typename T>
+bool fast_fft_z_solve_from_blobs(const Batch<T>& B, int solve, hipStream_t s, bool carry, bool accumulate) {
     if (!B.g.fast) return false;
-#define C(NN) z_fast_src<T, NN>(B, solve, s, carry)
+#define C(NN) z_fast_src<T, NN>(B, solve, s, carry, accumulate)
     ICM_SWITCH_N(B.g.nz, C)
 #undef C
 }
@@ -894,7 +1007,8 @@ bool fast_fft_x_inverse(const Batch<T>& B, int out, int acc, hipStream_t s) {
     template bool fast_fft_available<T>(int, int, int);                            \
     template bool fast_fft_y<T>(const Batch<T>&, int, hipStream_t);                \
     template bool fast_fft_z_solve<T>(const Batch<T>&, int, bool, hipStream_t, bool); \
-    template bool fast_fft_z_solve_from_blobs<T>(const Batch<T>&, int, hipStream_t, bool); \
+    template bool fast_fft_z_solve_from_blobs<T>(const Batch<T>&, int, hipStream_t, bool, bool); \
+    template void launch_spectral_gather<T>(const Batch<T>&, hipStream_t); \
     template bool fast_fft_x_forward<T>(const Batch<T>&, int, hipStream_t);        \
     template bool fast_fft_x_inverse<T>(const Batch<T>&, int, int, hipStream_t);
 ICM_INST(float)

@@ -893,12 +893,13 @@ __global__ void __launch_bounds__(kThreads) k_bins(const RepDesc<T>* __restrict_
 // (Jhvnew + Jhvn); u^{n+1} = Jhvnew for m_e = 0 blobs; numeric flag on
 // NaN/Inf or a displacement above h. In the first n_me replicas (those on
 // the inertial path) also the lagged term J^{n+1/2} L dv of the next step's
-// slip correction, from dv in aux. The first block of a replica clears its
+// slip correction: from dv in aux, or (lag_from_v) as J L v^{n+1} - J L v~
+// with J L v~ from step 4. The first block of a replica clears its
 // z-chunk bins for the next step and advances its step counter (no other
 // kernel of the step reads the counter after the RHS).
 template <typename T, int P>
 __global__ void __launch_bounds__(kThreads) k_gather_final(const RepDesc<T>* __restrict__ rd, int n_clear,
-                                                          int n_me) {
+                                                          int n_me, int lag_from_v) {
     const GridDesc<T> g = rd[blockIdx.y].g;
     const BlobParams bp = rd[blockIdx.y].bp;
     const BlobBufs bb = rd[blockIdx.y].bb;
@@ -917,10 +918,10 @@ __global__ void __launch_bounds__(kThreads) k_gather_final(const RepDesc<T>* __r
     const gptr<const double> o = as_global((const double*)bb.stc) + ((long long)(active ? b : 0) * 3 + a) * kStcPerComp;
     const double J = gather_group_rec<T, P>(g, g.v, o, a, r, active);
     const bool inertial = (int)blockIdx.y < n_me;
-    const double lag = inertial ? gather_group_rec_lap<T, P>(g, g.aux, o, a, r, active) : 0.0;
+    const double lag = inertial ? gather_group_rec_lap<T, P>(g, lag_from_v ? g.v : g.aux, o, a, r, active) : 0.0;
     if (active && r == 0) {
         const int i = 3 * b + a;
-        if (inertial) bb.lag[i] = lag;
+        if (inertial) bb.lag[i] = lag_from_v ? lag - bb.JLvt[i] : lag;
         bb.Jhvnew[i] = J;
         const double dq = 0.5 * bp.dt * (J + bb.Jhvn[i]);
         const double qn = bb.q[i] + dq;
@@ -1157,14 +1158,16 @@ void launch_bins(const Batch<T>& B, hipStream_t s) {
 }
 
 template <typename T>
-void launch_gather_final(const Batch<T>& B, int n_me, hipStream_t s) {
+void launch_gather_final(const Batch<T>& B, int n_me, bool lag_from_v, hipStream_t s) {
     // always launched: its first block per replica advances the step counter
     const int n_clear = max_chunks(B.g.nz) + 1;  // every chunk count and the overflow count
     const dim3 grid(grid_for(48LL * (B.max_nb > 0 ? B.max_nb : 1)), B.nrep);
     if (B.kernel == 3)
-        hipLaunchKernelGGL((k_gather_final<T, 3>), grid, dim3(kThreads), 0, s, B.d, n_clear, n_me);
+        hipLaunchKernelGGL((k_gather_final<T, 3>), grid, dim3(kThreads), 0, s, B.d, n_clear, n_me,
+                           lag_from_v ? 1 : 0);
     else
-        hipLaunchKernelGGL((k_gather_final<T, 4>), grid, dim3(kThreads), 0, s, B.d, n_clear, n_me);
+        hipLaunchKernelGGL((k_gather_final<T, 4>), grid, dim3(kThreads), 0, s, B.d, n_clear, n_me,
+                           lag_from_v ? 1 : 0);
 }
 
 __global__ void k_carry_from_sum(double* k0, const double* acc, double inv) {
@@ -1197,7 +1200,7 @@ void launch_field_diag(const GridDesc<T>& g, double rho, double* acc, hipStream_
     template void launch_carry_init<T>(const GridDesc<T>&, double, double*, hipStream_t);        \
     template void launch_gather_step1<T>(const Batch<T>&, hipStream_t);                          \
     template void launch_bins<T>(const Batch<T>&, hipStream_t);                                  \
-    template void launch_gather_final<T>(const Batch<T>&, int, hipStream_t);                     \
+    template void launch_gather_final<T>(const Batch<T>&, int, bool, hipStream_t);               \
     template void launch_advect<T>(const Batch<T>&, hipStream_t);
 ICM_INST(float)
 ICM_INST(double)

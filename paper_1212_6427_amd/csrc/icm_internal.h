@@ -180,6 +180,7 @@ struct BlobParams {
 struct BlobBufs {
     double *q, *u, *me, *fconst, *lag;     // state
     double *qh, *qw, *F, *Jn, *Jhvn, *Jhvt, *du, *dp, *dp2, *g, *Jhvnew;  // per step
+    double* JLvt;                          // J L v~ (step 4 from the spectrum)
     double *c5, *cdrift;                   // per-blob coefficients
     unsigned int* flag;                    // numeric error flag
     // spread inside the right-hand-side kernel
@@ -340,10 +341,11 @@ template <typename T>
 bool fast_fft_z_solve(const Batch<T>& B, int solve, bool project, hipStream_t s, bool carry = false);
 // The z pass and solve with its input spectrum formed from the blobs instead
 // of read: the transform of S dp2 (step 6), so that no field is zeroed and
-// spread and no x or y forward pass runs. False (launching nothing) without a
+// spread and no x or y forward pass runs; with accumulate, the result is
+// added to the spectrum already there. False (launching nothing) without a
 // register-resident plan for the grid.
 template <typename T>
-bool fast_fft_z_solve_from_blobs(const Batch<T>& B, int solve, hipStream_t s, bool carry);
+bool fast_fft_z_solve_from_blobs(const Batch<T>& B, int solve, hipStream_t s, bool carry, bool accumulate);
 template <typename T>
 bool fast_fft_x_forward(const Batch<T>& B, int in, hipStream_t s);
 template <typename T>
@@ -386,7 +388,7 @@ void launch_gather(const Batch<T>& B, int field, int q, int out, bool laplacian,
 template <typename T>
 void launch_gather_step1(const Batch<T>& B, hipStream_t s);
 template <typename T>
-void launch_gather_final(const Batch<T>& B, int n_me, hipStream_t s);
+void launch_gather_final(const Batch<T>& B, int n_me, bool lag_from_v, hipStream_t s);
 // z-chunk bins of the RHS spread (positions qh); counters must start at zero.
 template <typename T>
 void launch_bins(const Batch<T>& B, hipStream_t s);
@@ -404,6 +406,11 @@ void launch_carry_init(const GridDesc<T>& g, double rho, double* acc, hipStream_
 // ----------------------------------------------------------- blob kernels
 template <typename T>
 void launch_forces(const Batch<T>& B, hipStream_t s);
+// Step 4 from the spectrum the first solve's z pass left (its y and x
+// inverse passes deferred): J v~ and J L v~ of every blob component, with
+// du and dp as the step-4 gather forms them (register-resident grids).
+template <typename T>
+void launch_spectral_gather(const Batch<T>& B, hipStream_t s);
 // With the FP64-carried mean velocity: the sum of dp - m_e g per replica
 // (after g came from the field path of step 5).
 template <typename T>
