@@ -689,13 +689,6 @@ void enqueue_step(icm_ctx* c, const BatchInfo& bi, hipStream_t s) {
         timed(c, ICM_PHASE_FFT_X_FWD, s, [&] { launch_fft_x_forward(B, kFieldRhs, s); });
         timed(c, ICM_PHASE_FFT_Y_FWD, s, [&] { launch_fft_y(B, -1, s); });
         timed(c, ICM_PHASE_FFT_Z_SOLVE, s, [&] { launch_fft_z_solve(B, kSolveH1, true, s, true); });
-        if (bi.n_me < bi.count) {
-            // the replicas without excess mass finish the solve now
-            const icm::Batch<T> Bn = batch_view<T>(c, bi.first + bi.n_me, bi.count - bi.n_me,
-                                                   c->reps[bi.reps[bi.n_me]], bi.max_nb, false, false);
-            timed(c, ICM_PHASE_FFT_Y_INV, s, [&] { launch_fft_y(Bn, 1, s); });
-            timed(c, ICM_PHASE_FFT_X_INV, s, [&] { launch_fft_x_inverse(Bn, kFieldV, 0, s); });
-        }
     }
     if (bi.n_me > 0) {
         // steps 4-8 over the leading replicas with excess mass only
@@ -723,8 +716,6 @@ void enqueue_step(icm_ctx* c, const BatchInfo& bi, hipStream_t s) {
             // the z pass forms the transform of the spread source from the
             // stencil records and adds its solve to the first one
             timed(c, ICM_PHASE_FFT_Z_SOLVE, s, [&] { (void)fast_fft_z_solve_from_blobs(B, kSolveH2, s, true, true); });
-            timed(c, ICM_PHASE_FFT_Y_INV, s, [&] { launch_fft_y(B, 1, s); });
-            timed(c, ICM_PHASE_FFT_X_INV, s, [&] { launch_fft_x_inverse(B, kFieldV, 0, s); });
         } else {
             // dv written to aux by the last pass (for the lagged term of
             // step 9) and added to v
@@ -732,6 +723,13 @@ void enqueue_step(icm_ctx* c, const BatchInfo& bi, hipStream_t s) {
             timed(c, ICM_PHASE_SPREAD, s, [&] { launch_spread(B, kFieldRhs, kBlobQh, kBlobDp2, kBlobNone, s); });
             enqueue_fft_solve(c, B, kFieldRhs, kFieldAux, kXinvAlsoV, kSolveH2, s);
         }
+    }
+    if (spectral) {
+        // one y and x inverse pass for the whole batch: v^{n+1} of the
+        // replicas without excess mass from the first solve's spectrum
+        // (untouched since), of the others from the sum of both solves
+        timed(c, ICM_PHASE_FFT_Y_INV, s, [&] { launch_fft_y(B, 1, s); });
+        timed(c, ICM_PHASE_FFT_X_INV, s, [&] { launch_fft_x_inverse(B, kFieldV, 0, s); });
     }
     // Step 9 (also the lagged term of the inertial replicas and the device
     // step counters).
