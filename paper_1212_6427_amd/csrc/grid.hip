@@ -1081,7 +1081,9 @@ void launch_rhs(const Batch<T>& B, hipStream_t s) {
 
 template <typename T>
 void launch_spread_overflow(const Batch<T>& B, hipStream_t s) {
-    if (B.max_nb <= 0) return;
+    // a tile's list holds kRhsTileCap blobs: with no more blobs in a replica
+    // nothing can overflow, and the launch is skipped
+    if (B.max_nb <= kRhsTileCap) return;
     const int tiles_x = (B.g.nx + RTX - 1) / RTX, tiles_y = (B.g.ny + RTY - 1) / RTY;
     hipLaunchKernelGGL(k_spread_overflow<T>, dim3(B.nrep > 8 ? 8 : 64, B.nrep), dim3(kThreads), 0, s, B.d, tiles_x,
                        tiles_y, RTX, RTY);
