@@ -75,7 +75,7 @@ PROFILE = os.path.join(ROOT, "profiles", "many_blobs_256_fp32.md")
 # every leg's full results (arrays, statistics) go to this file by default;
 # stdout ends with a compact line
 FULL_RECORD = os.path.join(ROOT, "bench_results", "bench_full.json")
-PHASE_KERNEL = {"rhs": "k_rhs_march<float, true>", "fft_z_solve": "k_z_fast<float, 256, 8, 8, 8, 4>",
+PHASE_KERNEL = {"rhs": "k_rhs_march<float, true>", "fft_z_solve": "k_z_fast<float, 256, 8, 8, 8, 4, 0>",
                 "fft_x_fwd": "k_xfwd_fast<float, 256, 16, 16, 16, 1>",
                 "fft_x_inv": "k_xinv_fast<float, 256, 16, 16, 16, 1>"}
 
