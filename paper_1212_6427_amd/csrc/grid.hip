@@ -661,7 +661,7 @@ __device__ __forceinline__ double gather_group(const GridDesc<T>& g, const T* __
     return acc;
 }
 
-// gather_group at the positions whose stencil records k_gather_bins wrote
+// gather_group at the positions whose stencil records k_gather_step1 wrote
 // (o: the record of component a): the same wrapped nodes and weights, read
 // instead of recomputed, so the result is the same to the bit.
 template <typename T, int P>
