@@ -154,10 +154,29 @@ __device__ __forceinline__ int skew(int n) {
     else return n + (n >> SK);
 }
 
-template <typename T, int N, int E, int R, int Ns, int SK>
+// How the exchanges of one transform synchronise (reg_fft's SYNC):
+//   kSyncBlock  workgroup barrier before the writes and after them;
+//   kSyncFresh  as kSyncBlock without the barrier before the first exchange,
+//               for a transform that is the first user of its LDS buffer;
+//   kSyncWave   each line lies within one wave (TL divides 64 and lines are
+//               consecutive lanes), whose LDS accesses complete in program
+//               order: the compiler only must not move them across the wave
+//               barrier.
+constexpr int kSyncBlock = 0, kSyncFresh = 1, kSyncWave = 2;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int N, int E, int R, int Ns, int SK, int SYNC, bool FIRST>
 __device__ __forceinline__ void reg_exchange(cplx<T> (&a)[E], int t, cplx<T>* lds, int ls, int lo) {
     constexpr int TL = N / E, M = E / R;
-    __syncthreads();
+    if constexpr (SYNC == kSyncWave)
+        wave_sync();
+    else if constexpr (SYNC == kSyncBlock || !FIRST)
+        __syncthreads();
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int j = t + TL * m;
@@ -165,19 +184,23 @@ __device__ __forceinline__ void reg_exchange(cplx<T> (&a)[E], int t, cplx<T>* ld
 #pragma unroll
         for (int r = 0; r < R; ++r) lds[skew<SK>(base + r * Ns) * ls + lo] = a[m + M * r];
     }
-    __syncthreads();
+    if constexpr (SYNC == kSyncWave)
+        wave_sync();
+    else
+        __syncthreads();
 #pragma unroll
     for (int i = 0; i < E; ++i) a[i] = lds[skew<SK>(t + TL * i) * ls + lo];
 }
 
-template <typename T, int N, int E, int R0, int R1, int R2, int DIR, int SK = 16>
+template <typename T, int N, int E, int R0, int R1, int R2, int DIR, int SK = 16, int SYNC = kSyncBlock>
 __device__ __forceinline__ void reg_fft(cplx<T> (&a)[E], int t, cplx<T>* lds, int ls, int lo, const cplx<T>* tw) {
+    static_assert(SYNC != kSyncWave || (64 % (N / E) == 0), "a line within one wave");
     reg_stage<T, N, E, R0, 1, DIR>(a, t, tw);
     if constexpr (R1 > 1) {
-        reg_exchange<T, N, E, R0, 1, SK>(a, t, lds, ls, lo);
+        reg_exchange<T, N, E, R0, 1, SK, SYNC, true>(a, t, lds, ls, lo);
         reg_stage<T, N, E, R1, R0, DIR>(a, t, tw);
         if constexpr (R2 > 1) {
-            reg_exchange<T, N, E, R1, R0, SK>(a, t, lds, ls, lo);
+            reg_exchange<T, N, E, R1, R0, SK, SYNC, false>(a, t, lds, ls, lo);
             reg_stage<T, N, E, R2, R0 * R1, DIR>(a, t, tw);
         }
     }
@@ -279,8 +302,9 @@ __global__ void __launch_bounds__(512) k_y_fast(const RepDesc<T>* __restrict__ r
     cplx<T> a[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) a[i] = ok ? base[(long long)(t + TL * i) * stride] : cplx<T>{0, 0};
-    __syncthreads();
-    reg_fft<T, N, E, R0, R1, R2, DIR>(a, t, lds, B, b, tws);
+    // the first stage takes no twiddles; the first exchange's barrier orders
+    // the twiddle writes before the second stage reads them
+    reg_fft<T, N, E, R0, R1, R2, DIR, 16, kSyncFresh>(a, t, lds, B, b, tws);
     if (ok) {
 #pragma unroll
         for (int i = 0; i < E; ++i) base[(long long)(t + TL * i) * stride] = a[i];
@@ -363,12 +387,17 @@ __device__ __forceinline__ void spectral_source(const RepDesc<T>& R, int kx, int
 
 // SRC 0: the input spectrum read; 1: formed from the blobs; 2: formed from the
 // blobs and the result added to the spectrum already there.
+// LDS: twiddles (N), the exchange buffer (N B), then the z symbols of the
+// solve, d_z (N complex) and the Laplacian's eigenvalues (N), so that the
+// solve reads them without a global-memory round trip per mode.
 template <typename T, int N, int E, int R0, int R1, int R2, int SRC = 0>
 __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ rd, int B, int solve,
                                                  int project) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* tws = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* lds = tws + N;
+    cplx<T>* sdz = lds + N * B;
+    T* slz = reinterpret_cast<T*>(sdz + N);
     const GridDesc<T> g = rd[blockIdx.z].g;
     const SolveCoef sc = rd[blockIdx.z].solve[solve];
     const int b = threadIdx.x % B, t = threadIdx.x / B;
@@ -381,6 +410,14 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
     const int y = tail ? (int)blockIdx.y * B + b : (int)blockIdx.y;
     const bool ok = tail ? y < g.ny : kx < H;
     load_tw(tws, g.twz, N);
+    {
+        const gptr<const T> glz = as_global(g.lz);
+        const gptr<const cplx<T>> gdz = as_global(g.dz_hat);
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            sdz[i] = gdz[i];
+            slz[i] = glz[i];
+        }
+    }
     constexpr int TL = N / E;
     // Buffer accesses: one 32-bit per-thread offset (column, first plane); the
     // plane and component offsets are uniform and go in the scalar offset, so
@@ -415,15 +452,15 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
         reg_fft<T, N, E, R0, R1, R2, -1>(a1, t, lds, B, b, tws);
         reg_fft<T, N, E, R0, R1, R2, -1>(a2, t, lds, B, b, tws);
     }
+    // the barrier after the loads (or after the spectral source's twiddles)
+    // has ordered the table writes before these reads
     if (ok) {
-        const gptr<const T> glz = as_global(g.lz);
-        const gptr<const cplx<T>> gdz = as_global(g.dz_hat);
         const T lxy = as_global(g.lx)[kx] + as_global(g.ly)[y];
         const cplx<T> dx = as_global(g.dx_hat)[kx], dy = as_global(g.dy_hat)[y];
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int kz = t + TL * i;
-            const T lam = lxy + glz[kz];
+            const T lam = lxy + slz[kz];
             T f;
             if constexpr (sizeof(T) == 4)  // hardware reciprocal (1 ulp) in FP32
                 f = (T)sc.scale * __builtin_amdgcn_rcpf((T)sc.a + (T)sc.b * lam);
@@ -433,7 +470,7 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
             cplx<T> w1 = {a1[i].x * f, a1[i].y * f};
             cplx<T> w2 = {a2[i].x * f, a2[i].y * f};
             if ((project & 1) && lam > (T)0) {
-                const cplx<T> dz = gdz[kz];
+                const cplx<T> dz = sdz[kz];
                 const cplx<T> d = cadd(cadd(cmul(dx, w0), cmul(dy, w1)), cmul(dz, w2));
                 T il;
                 if constexpr (sizeof(T) == 4)
@@ -522,15 +559,16 @@ __global__ void __launch_bounds__(512) k_xfwd_fast(const RepDesc<T>* __restrict_
         for (int q = 0; q < V; ++q) lds[ll * LS + skew<4>(x + q)] = cplx<T>{ra[m].v[q], rb[m].v[q]};
     }
     __syncthreads();
+    // from here on each line is touched only by its own TL lanes, which lie in
+    // one wave: wave-level synchronisation suffices
     cplx<T> a[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) a[i] = lds[l * LS + skew<4>(t + TL * i)];
-    __syncthreads();
-    reg_fft<T, N, E, R0, R1, R2, -1, 4>(a, t, lds, 1, l * LS, tws);
-    __syncthreads();
+    reg_fft<T, N, E, R0, R1, R2, -1, 4, kSyncWave>(a, t, lds, 1, l * LS, tws);
+    wave_sync();
 #pragma unroll
     for (int i = 0; i < E; ++i) lds[l * LS + skew<4>(t + TL * i)] = a[i];
-    __syncthreads();
+    wave_sync();
     if (!ok) return;
     const gptr<cplx<T>> d0 = as_global(g.spec) + (long long)c * g.nspec + 2 * p * g.Wp;
     // modes kx < N/2, two consecutive per thread (16-byte stores for FP32;
@@ -619,13 +657,14 @@ __global__ void __launch_bounds__(512) k_xinv_fast(const RepDesc<T>* __restrict_
         }
         lds[l * LS + skew<4>(H)] = {A.x, Bv.x};
     }
-    __syncthreads();
+    __syncthreads();  // twiddles
+    // each line is transformed by its own TL lanes, which lie in one wave
     cplx<T> a[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) a[i] = lds[l * LS + skew<4>(t + TL * i)];
-    reg_fft<T, N, E, R0, R1, R2, 1, 4>(a, t, lds, 1, l * LS, tws);
+    reg_fft<T, N, E, R0, R1, R2, 1, 4, kSyncWave>(a, t, lds, 1, l * LS, tws);
     // unstage through LDS so that rows are written with contiguous stores
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int i = 0; i < E; ++i) lds[l * LS + skew<4>(t + TL * i)] = a[i];
     __syncthreads();
@@ -876,7 +915,8 @@ bool z_fast_plan(const Batch<T>& Bt, int solve, bool project, hipStream_t s, boo
         int B = g.Bz;
         while (B > 1 && B * TL > 512) B /= 2;
         const dim3 grid((unsigned)((g.nx / 2 + B - 1) / B + 1), g.ny, Bt.nrep);
-        const size_t lds = (size_t)N * (B + 1) * sizeof(cplx<T>);
+        // twiddles, exchange buffer, d_z and the z eigenvalues
+        const size_t lds = (size_t)N * (B + 2) * sizeof(cplx<T>) + (size_t)N * sizeof(T);
         allow_lds(k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, SRC>, lds);
         hipLaunchKernelGGL((k_z_fast<T, N, Pl::E, Pl::R0, Pl::R1, Pl::R2, SRC>), grid, dim3(B * TL), lds, s, Bt.d,
                            B, solve, (project ? 1 : 0) | (carry ? 2 : 0));

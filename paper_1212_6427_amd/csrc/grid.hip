@@ -199,21 +199,27 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
     const uint32_t pairs_plane = (uint32_t)plane;  // pair counters per pair of planes
     // v is read one plane ahead of its use (vp for plane k + 1 was loaded
     // during plane k - 1; the halo ring's values likewise), so the loads'
-    // latency overlaps a whole plane of work.
-    if (hvalid) {
-        const long long hc = (long long)k0 * plane + (long long)hjw * nx + hiw;
+    // latency overlaps a whole plane of work. Every thread issues these
+    // loads, with no branch around them: a thread outside a ragged tile
+    // reads a clamped column, one without a halo duty the wrapped corner
+    // (nx - 1, ny - 1) (one line for the wave). The compiler's wait counts
+    // then follow the issue order, and a plane's use of its prefetched
+    // values waits for none of the loads issued for later planes.
+    const long long colc = (long long)min(j, ny - 1) * nx + min(i, nx - 1);
+    const long long hcol = (long long)hjw * nx + hiw;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) hr[0][a] = gv[a * g.ncell + hc];
-    }
-    if (own) {
-        const int km = wrap(k0 - 1, nz);
+    for (int a = 0; a < 3; ++a) hr[0][a] = gv[a * g.ncell + (long long)k0 * plane + hcol];
+    const int km = wrap(k0 - 1, nz);
+    {
         const int k0p = k0 + 1 == nz ? 0 : k0 + 1;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            vr[0][a] = gv[a * g.ncell + km * plane + col];
-            vr[1][a] = gv[a * g.ncell + (long long)k0 * plane + col];
-            vr[2][a] = gv[a * g.ncell + (long long)k0p * plane + col];
+            vr[0][a] = gv[a * g.ncell + km * plane + colc];
+            vr[1][a] = gv[a * g.ncell + (long long)k0 * plane + colc];
+            vr[2][a] = gv[a * g.ncell + (long long)k0p * plane + colc];
         }
+    }
+    if (own) {
         if (noisy) {
             // W_zz of the odd plane k0 - 1 (C of the previous pair); xz, yz of
             // plane k0 and xx, yy of plane k0 + 1 (B of the first pair)
@@ -266,7 +272,7 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
     // plane independent apart from its z weight: keep it in registers.
     bool it_ok = false;
     int it_a = 0, it_x = 0, it_y = 0, it_z0 = 0;
-    double it_f = 0, it_d = 0, wz0 = 0, wz1 = 0, wz2 = 0, wz3 = 0, dz0 = 0, dz1 = 0, dz2 = 0, dz3 = 0;
+    T tv0 = 0, tv1 = 0, tv2 = 0, tv3 = 0;
     if (tid < nloc * 48) {
         const int lb = tid / 48, rem = tid - 48 * lb;
         const int a = rem >> 4, r = rem & 15;
@@ -284,14 +290,18 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
                 it_y = y - j0;
                 it_z0 = (int)o[2];
                 const double wxv = o[3 + ia], wyv = o[7 + ib];
-                it_f = gF[3 * b + a] * wxv * wyv * inv_h3;
-                wz0 = o[11]; wz1 = o[12]; wz2 = o[13]; wz3 = o[14];
+                const double it_f = gF[3 * b + a] * wxv * wyv * inv_h3;
+                double it_d = 0, dz0 = 0, dz1 = 0, dz2 = 0, dz3 = 0;
                 if (rb.cdrift) {
                     const double cx = a == 0 ? o[15 + ia] : wxv, cy = a == 1 ? o[15 + ib] : wyv;
                     it_d = as_global(rb.cdrift)[b] * cx * cy * inv_h3;
                     if (a == 2) { dz0 = o[15]; dz1 = o[16]; dz2 = o[17]; dz3 = o[18]; }
-                    else { dz0 = wz0; dz1 = wz1; dz2 = wz2; dz3 = wz3; }
+                    else { dz0 = o[11]; dz1 = o[12]; dz2 = o[13]; dz3 = o[14]; }
                 }
+                tv0 = (T)(it_f * o[11] + it_d * dz0);
+                tv1 = (T)(it_f * o[12] + it_d * dz1);
+                tv2 = (T)(it_f * o[13] + it_d * dz2);
+                tv3 = (T)(it_f * o[14] + it_d * dz3);
             }
         }
     }
@@ -325,11 +335,7 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
             if (it_ok) {
                 int ic = k - it_z0;
                 if (ic < 0) ic += nz;
-                if (ic < P) {
-                    const double wz = ic == 0 ? wz0 : (ic == 1 ? wz1 : (ic == 2 ? wz2 : wz3));
-                    const double dz = ic == 0 ? dz0 : (ic == 1 ? dz1 : (ic == 2 ? dz2 : dz3));
-                    atomicAdd(&s_acc[it_a][it_y][it_x], (T)(it_f * wz + it_d * dz));
-                }
+                if (ic < P) atomicAdd(&s_acc[it_a][it_y][it_x], ic == 0 ? tv0 : (ic == 1 ? tv1 : (ic == 2 ? tv2 : tv3)));
             }
             // further items (tiles met by more than 10 blobs) read their data here
             for (int it = tid + blockDim.x; it < nloc * 3 * 16; it += blockDim.x) {
@@ -349,13 +355,15 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
                 const double v = tap_value<T>(rb, o, b, a, ia, ib, ic, inv_h3);
                 atomicAdd(&s_acc[a][y - j0][x - i0], (T)v);
             }
-            const bool more = k + 1 < k1;
-            if (own && more) {
-                const int kq = kp + 1 == nz ? 0 : kp + 1;
-                for (int a = 0; a < 3; ++a) vq[a] = gv[a * g.ncell + (long long)kq * plane + col];
-            }
-            if (hvalid && more) {
-                const long long hn = (long long)kp * plane + (long long)hjw * nx + hiw;
+            {
+                // the chunk's last plane loads (unused) values of planes
+                // this block has just read, which the cache still holds
+                const bool more = k + 1 < k1;
+                const int kq = !more ? kp : (kp + 1 == nz ? 0 : kp + 1);
+                const long long hn = (long long)(more ? kp : k) * plane + hcol;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) vq[a] = gv[a * g.ncell + (long long)kq * plane + colc];
+#pragma unroll
                 for (int a = 0; a < 3; ++a) hq[a] = gv[a * g.ncell + hn];
             }
             if (own) {
