@@ -260,15 +260,17 @@ void carve_grid(Carver& cv, const icm_replica_params& p, icm::GridDesc<T>& g) {
     g.lz = cv.take<T>(g.nz);
 }
 
-void carve_blobs(Carver& cv, int max_nb, int nz, icm::BlobBufs& b, double*& diag) {
+void carve_blobs(Carver& cv, int max_nb, const int n[3], icm::BlobBufs& b, double*& diag) {
     const size_t n3 = 3 * (size_t)max_nb;
-    const int nchunks = icm::max_chunks(nz);
+    const int nbins = icm::rhs_bins(n[0], n[1], n[2]);
     b.stc = cv.take<double>((size_t)max_nb * 3 * icm::kStcPerComp);
-    b.chunk_count = cv.take<int>(nchunks + 1);
-    b.chunk_list = cv.take<int>((size_t)nchunks * max_nb);
-    // a P <= 4 stencil spans at most two tiles per axis (tiles are at least
-    // 16 cells wide), so a blob can overflow at most 8 tiles
-    b.ovf_cap = 8 * std::max(max_nb, 1);
+    b.bin_count = cv.take<int>(nbins + 1);
+    b.bin_list = cv.take<int>((size_t)nbins * icm::kRhsTileCap);
+    // the stencils of a blob cover at most five nodes per axis, which meet
+    // at most three tiles or chunks (two, unless a short last one lies
+    // between them), so a blob is listed in (and can overflow) at most 27
+    // bins
+    b.ovf_cap = 27 * std::max(max_nb, 1);
     b.ovf_list = cv.take<int>(2 * (size_t)b.ovf_cap);
     b.q = cv.take<double>(n3);
     b.u = cv.take<double>(n3);
@@ -337,7 +339,7 @@ size_t layout(int32_t n_rep, const icm_replica_params* p, const int32_t* max_blo
             carve_grid(cv, p[r], R.gd);
         else
             carve_grid(cv, p[r], R.gf);
-        carve_blobs(cv, max_blobs[r], p[r].n[2], R.bb, R.diag);
+        carve_blobs(cv, max_blobs[r], p[r].n, R.bb, R.diag);
         carve_cells(cv, p[r], max_blobs[r], R.cells);
     }
     // projection-kernel tables, one per grid shape that holds a replica of at
@@ -505,16 +507,15 @@ icm::RepDesc<T> build_desc(const Replica& R) {
     for (int a = 0; a < 3; ++a) d.rc.body[a] = p.body_force[a];
     d.rc.key = noise_key(R, 0);
     const icm::BlobBufs& b = R.bb;
-    const int nchunks = icm::max_chunks(g.nz);  // the overflow count follows the finest chunking's slots
+    const int nbins = icm::rhs_bins(g.nx, g.ny, g.nz);  // the overflow count follows the bins
     d.rb.nb = R.nb;
     d.rb.kernel = stencil_width(p);
-    d.rb.cap = R.max_nb;
     d.rb.stc = b.stc;
     d.rb.F = b.F;
     d.rb.cdrift = (p.kT > 0 && p.thermal_drift) ? b.cdrift : nullptr;
-    d.rb.chunk_count = b.chunk_count;
-    d.rb.chunk_list = b.chunk_list;
-    d.rb.ovf_count = b.chunk_count + nchunks;
+    d.rb.bin_count = b.bin_count;
+    d.rb.bin_list = b.bin_list;
+    d.rb.ovf_count = b.bin_count + nbins;
     d.rb.ovf_list = b.ovf_list;
     d.rb.ovf_cap = b.ovf_cap;
     d.bp = blob_params(R);
@@ -892,7 +893,8 @@ float time_rhs(icm_ctx* c, size_t b, int zc, hipEvent_t ea, hipEvent_t eb) {
     auto clear = [&] {
         for (int r : bi.reps) {
             const Replica& R = c->reps[r];
-            (void)hipMemsetAsync(R.bb.chunk_count, 0, (size_t)(icm::max_chunks(R.p.n[2]) + 1) * sizeof(int), s);
+            (void)hipMemsetAsync(R.bb.bin_count, 0,
+                                 (size_t)(icm::rhs_bins(R.p.n[0], R.p.n[1], R.p.n[2]) + 1) * sizeof(int), s);
         }
     };
     clear();
@@ -1131,8 +1133,8 @@ icm_status icm_create(int32_t n_rep, const icm_replica_params* p, const int32_t*
                                sizeof(unsigned long long) * (size_t)R.cells.n[0] * R.cells.n[1] * R.cells.n[2],
                                c->stream);
         if (e == hipSuccess)
-            e = hipMemsetAsync(R.bb.chunk_count, 0,
-                               sizeof(int) * (icm::max_chunks(p[r].n[2]) + 1), c->stream);
+            e = hipMemsetAsync(R.bb.bin_count, 0,
+                               sizeof(int) * (icm::rhs_bins(p[r].n[0], p[r].n[1], p[r].n[2]) + 1), c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(R.d_step, 0, sizeof(unsigned long long), c->stream);
         if (e == hipSuccess && R.gf.k0 && precision == ICM_FP32_GRID)
             e = hipMemsetAsync(R.gf.k0, 0, 9 * sizeof(double), c->stream);

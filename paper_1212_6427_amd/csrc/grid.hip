@@ -26,20 +26,6 @@ __global__ void k_clear_ints(int* p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
-// Does blob b's a-component stencil touch cells [i0, i0 + wx) x [j0, j0 + wy)?
-__device__ __forceinline__ bool stencil_meets_tile(gptr<const double> o, int P, int nx, int ny, int i0, int wx, int j0,
-                                                   int wy) {
-    const int bx = (int)o[0], by = (int)o[1];
-    bool inx = false, iny = false;
-    for (int t = 0; t < P; ++t) {
-        const int x = bx + t >= nx ? bx + t - nx : bx + t;
-        const int y = by + t >= ny ? by + t - ny : by + t;
-        inx = inx || (x >= i0 && x < i0 + wx);
-        iny = iny || (y >= j0 && y < j0 + wy);
-    }
-    return inx && iny;
-}
-
 // Value spread to one tap (ia, ib, ic) of component a of blob b:
 // (F_a prod w + c_drift prod w') / h^3, w' = phi'/h along axis a.
 template <typename T>
@@ -104,7 +90,7 @@ __global__ void __launch_bounds__(kThreads) k_spread_overflow(const RepDesc<T>* 
 // W_zz of plane k-1 is carried in a register, and the in-plane neighbours'
 // stresses and velocities are shared through LDS. Only the tile's one-cell
 // halo ring regenerates the few normals it needs.
-constexpr int RTX = 32, RTY = 16;
+constexpr int RTX = kRhsTileX, RTY = kRhsTileY;
 
 // ONE: a batch of one replica whose descriptor comes by value in the kernel
 // arguments (constant memory the compiler may re-read at will); otherwise the
@@ -112,8 +98,7 @@ constexpr int RTX = 32, RTY = 16;
 template <typename T, bool ONE>
 __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __restrict__ rd, const RepDesc<T> one,
                                                         int ntz) {
-    __shared__ int s_blobs[kRhsTileCap];   // blobs of this z-chunk meeting the tile
-    __shared__ int s_nblobs;
+    __shared__ int s_blobs[kRhsTileCap];   // blobs of this workgroup's bin
     // Plane buffers, two of each: plane k uses buffer k - k0 mod 2, so the
     // next plane's writes never meet this plane's reads and one barrier per
     // plane suffices (plane k + 2 writes only after every thread has passed
@@ -234,39 +219,17 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
             up_yy = r.b;
         }
     }
-    // blobs of this z-chunk whose stencil meets the tile
-    if (tid == 0) s_nblobs = 0;
+    // the blobs of this workgroup's bin (its tile and z-chunk), which k_bins
+    // listed; those beyond kRhsTileCap are in the overflow list
     for (int a = 0; a < 3; ++a) s_acc2[0][a][ty][tx] = s_acc2[1][a][ty][tx] = (T)0;
-    __syncthreads();
     const int P = rb.kernel;
+    int nloc = 0;
     if (rb.nb > 0) {
-        const int chunk = tile_z;
-        const int cnt = min(as_global(rb.chunk_count)[chunk], rb.cap);
-        const int tile_id = (tile_z * nty + tile_y) * ntx + tile_x;
-        const gptr<const int> glist = as_global(rb.chunk_list);
-        for (int s = tid; s < cnt; s += blockDim.x) {
-            const int b = glist[(long long)chunk * rb.cap + s];
-            bool meets = false;
-            for (int a = 0; a < 3; ++a)
-                meets = meets || stencil_meets_tile(gstc + ((long long)b * 3 + a) * kStcPerComp, P, nx, ny, i0, wx,
-                                                    j0, wy);
-            if (meets) {
-                const int slot = atomicAdd(&s_nblobs, 1);
-                if (slot < kRhsTileCap) {
-                    s_blobs[slot] = b;
-                } else {
-                    const int os = __hip_atomic_fetch_add(as_global(rb.ovf_count), 1, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT);
-                    if (os < rb.ovf_cap) {
-                        as_global(rb.ovf_list)[2 * os] = b;
-                        as_global(rb.ovf_list)[2 * os + 1] = tile_id;
-                    }
-                }
-            }
-        }
+        const int bin = (tile_z * nty + tile_y) * ntx + tile_x;
+        nloc = min(as_global(rb.bin_count)[bin], kRhsTileCap);
+        if (tid < nloc) s_blobs[tid] = as_global(rb.bin_list)[(long long)bin * kRhsTileCap + tid];
     }
     __syncthreads();
-    const int nloc = min(s_nblobs, kRhsTileCap);
     const double inv_h3 = 1.0 / (g.h * g.h * g.h);
     // This thread's first spread item (local blob, component, x-y tap) is
     // plane independent apart from its z weight: keep it in registers.
@@ -850,51 +813,93 @@ __global__ void __launch_bounds__(kThreads) k_gather_step1(const RepDesc<T>* __r
     }
 }
 
-// z-chunk bins of the spread inside the RHS kernel: one thread per blob; the
-// chunks met by the planes of any component grid along z are counted per
-// workgroup in LDS and reserved in the global lists with one atomic per
-// (workgroup, chunk), which keeps same-address contention low.
-constexpr int kMaxChunks = 512 / kRhsZChunkMin;
+// The distinct tiles (runs of `span` nodes, the last run possibly shorter)
+// of an axis of n nodes that the P-node stencil runs from wrapped base nodes
+// b0 and b1 meet. The two runs overlap or touch (b1 is b0 or b0 - 1 modulo
+// n), so together they cover at most P + 1 <= 5 consecutive nodes, which
+// cross at most two tile starts: at most three tiles, and three only when a
+// short last tile lies between them. Unused slots are -1.
+template <int P>
+__device__ __forceinline__ void axis_tiles(int b0, int b1, int n, int span, int& c0, int& c1, int& c2) {
+    c0 = b0 / span;
+    c1 = -1;
+    c2 = -1;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            int node = (r == 0 ? b0 : b1) + t;
+            if (node >= n) node -= n;
+            const int c = node / span;
+            if (c != c0 && c != c1 && c != c2) {
+                if (c1 < 0)
+                    c1 = c;
+                else
+                    c2 = c;
+            }
+        }
+    }
+}
+
+// Bins of the spread inside the RHS kernel, one per RHS workgroup (tile and
+// z-chunk), one thread per blob: the blob is listed in every bin whose tile
+// and chunk meet the nodes of its stencils, read from the records that
+// k_gather_step1 wrote (per axis, the base node of the component grid
+// offset by 0 along it and that of the two offset by h/2); a bin's entries
+// beyond kRhsTileCap go to the overflow list. The counts start at zero: the
+// previous step's k_gather_final (or the host) cleared them.
 template <typename T, int P>
 __global__ void __launch_bounds__(kThreads) k_bins(const RepDesc<T>* __restrict__ rd) {
-    __shared__ int s_cnt[kMaxChunks];
-    __shared__ int s_base[kMaxChunks];
     if (rd[blockIdx.y].g.k0 && blockIdx.x == gridDim.x - 1) {
         // the extra last block: the replica's total blob force, for the
         // FP64-carried mean velocity (fixed summation order)
         block_sum3(rd[blockIdx.y].bp.nb, rd[blockIdx.y].bb.F, nullptr, nullptr, rd[blockIdx.y].g.k0 + 3);
         return;
     }
-    const int nb = rd[blockIdx.y].bp.nb, nz = rd[blockIdx.y].g.nz;
-    const double h = rd[blockIdx.y].g.h;
-    const double* __restrict__ qh = rd[blockIdx.y].bb.qh;
-    const int cap = rd[blockIdx.y].rb.cap;
-    int* __restrict__ chunk_count = rd[blockIdx.y].bb.chunk_count;
-    int* __restrict__ chunk_list = rd[blockIdx.y].bb.chunk_list;
+    const RhsBlobs rb = rd[blockIdx.y].rb;
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= rb.nb) return;
+    const int nx = rd[blockIdx.y].g.nx, ny = rd[blockIdx.y].g.ny, nz = rd[blockIdx.y].g.nz;
     const int zc = rd[blockIdx.y].g.zc;
-    const int nchunks = (nz + zc - 1) / zc;
-    for (int i = threadIdx.x; i < nchunks; i += blockDim.x) s_cnt[i] = 0;
-    __syncthreads();
-    int c0 = -1, c1 = -1, s0 = 0, s1 = 0;
-    if (b < nb) {
-        const double z = qh[3 * b + 2] / h;
-        const long long lo0 = (long long)((P == 3) ? floor(z + 0.5) : floor(z)) - 1;
-        const long long lo1 = (long long)((P == 3) ? floor(z) : floor(z - 0.5)) - 1;
-        const long long zlo = lo0 < lo1 ? lo0 : lo1;
-        const long long zhi = (lo0 > lo1 ? lo0 : lo1) + P - 1;
-        c0 = (int)(((zlo % nz) + nz) % nz) / zc;
-        c1 = (int)(((zhi % nz) + nz) % nz) / zc;
-        if (c1 == c0 || nchunks == 1) c1 = -1;
-        s0 = atomicAdd(&s_cnt[c0], 1);
-        if (c1 >= 0) s1 = atomicAdd(&s_cnt[c1], 1);
+    const int tiles_x = rhs_tiles_x(nx), tiles_y = rhs_tiles_y(ny);
+    // record of component a: o + a kStcPerComp, base node along axis ax at
+    // [ax]; a record the step has not written yet (the autotuner's timing
+    // before a first step) may hold anything, and a value outside the axis
+    // reads as node 0, so that every bin index stays in range
+    const gptr<const double> o = as_global(rb.stc) + (long long)b * 3 * kStcPerComp;
+    auto node = [](double d, int n) { return (d >= 0.0 && d < (double)n) ? (int)d : 0; };
+    int x0, x1, x2, y0, y1, y2, z0, z1, z2;
+    axis_tiles<P>(node(o[0], nx), node(o[kStcPerComp], nx), nx, kRhsTileX, x0, x1, x2);
+    axis_tiles<P>(node(o[kStcPerComp + 1], ny), node(o[2 * kStcPerComp + 1], ny), ny, kRhsTileY, y0, y1, y2);
+    axis_tiles<P>(node(o[2 * kStcPerComp + 2], nz), node(o[2], nz), nz, zc, z0, z1, z2);
+    const gptr<int> count = as_global(rb.bin_count), list = as_global(rb.bin_list);
+#pragma unroll
+    for (int iz = 0; iz < 3; ++iz) {
+        const int cz = iz == 0 ? z0 : (iz == 1 ? z1 : z2);
+        if (cz < 0) continue;
+#pragma unroll
+        for (int iy = 0; iy < 3; ++iy) {
+            const int cy = iy == 0 ? y0 : (iy == 1 ? y1 : y2);
+            if (cy < 0) continue;
+#pragma unroll
+            for (int ix = 0; ix < 3; ++ix) {
+                const int cx = ix == 0 ? x0 : (ix == 1 ? x1 : x2);
+                if (cx < 0) continue;
+                const int bin = (cz * tiles_y + cy) * tiles_x + cx;
+                const int slot = __hip_atomic_fetch_add(&count[bin], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (slot < kRhsTileCap) {
+                    list[(long long)bin * kRhsTileCap + slot] = b;
+                } else {
+                    const int os = __hip_atomic_fetch_add(as_global(rb.ovf_count), 1, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                    if (os < rb.ovf_cap) {
+                        as_global(rb.ovf_list)[2 * os] = b;
+                        as_global(rb.ovf_list)[2 * os + 1] = bin;
+                    }
+                }
+            }
+        }
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nchunks; i += blockDim.x)
-        s_base[i] = s_cnt[i] ? atomicAdd(&chunk_count[i], s_cnt[i]) : 0;
-    __syncthreads();
-    if (c0 >= 0 && s_base[c0] + s0 < cap) chunk_list[(long long)c0 * cap + s_base[c0] + s0] = b;
-    if (c1 >= 0 && s_base[c1] + s1 < cap) chunk_list[(long long)c1 * cap + s_base[c1] + s1] = b;
 }
 
 // Step 9 fused: Jhvnew = J(q^{n+1/2}) v^{n+1}; q^{n+1} = q^n + dt/2
@@ -902,9 +907,9 @@ __global__ void __launch_bounds__(kThreads) k_bins(const RepDesc<T>* __restrict_
 // NaN/Inf or a displacement above h. In the first n_me replicas (those on
 // the inertial path) also the lagged term J^{n+1/2} L dv of the next step's
 // slip correction: from dv in aux, or (lag_from_v) as J L v^{n+1} - J L v~
-// with J L v~ from step 4. The first block of a replica clears its
-// z-chunk bins for the next step and advances its step counter (no other
-// kernel of the step reads the counter after the RHS).
+// with J L v~ from step 4. The replica's blocks clear its RHS bins for the
+// next step, and its first thread advances the step counter (no other kernel
+// of the step reads the counter after the RHS).
 template <typename T, int P>
 __global__ void __launch_bounds__(kThreads) k_gather_final(const RepDesc<T>* __restrict__ rd, int n_clear,
                                                           int n_me, int lag_from_v) {
@@ -912,12 +917,10 @@ __global__ void __launch_bounds__(kThreads) k_gather_final(const RepDesc<T>* __r
     const BlobParams bp = rd[blockIdx.y].bp;
     const BlobBufs bb = rd[blockIdx.y].bb;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (blockIdx.x == 0) {
-        for (int i = threadIdx.x; i < n_clear; i += blockDim.x) bb.chunk_count[i] = 0;
-        if (threadIdx.x == 0) {
-            *rd[blockIdx.y].step += 1;
-            if (g.adv_hist) *g.adv_hist = 1u;  // this step's advective term is the next one's lag
-        }
+    for (int i = t; i < n_clear; i += gridDim.x * blockDim.x) bb.bin_count[i] = 0;
+    if (t == 0) {
+        *rd[blockIdx.y].step += 1;
+        if (g.adv_hist) *g.adv_hist = 1u;  // this step's advective term is the next one's lag
     }
     const int grp = t >> 4, r = t & 15;
     const int b = grp / 3, a = grp - 3 * (grp / 3);
@@ -1170,7 +1173,7 @@ void launch_bins(const Batch<T>& B, hipStream_t s) {
 template <typename T>
 void launch_gather_final(const Batch<T>& B, int n_me, bool lag_from_v, hipStream_t s) {
     // always launched: its first block per replica advances the step counter
-    const int n_clear = max_chunks(B.g.nz) + 1;  // every chunk count and the overflow count
+    const int n_clear = rhs_bins(B.g.nx, B.g.ny, B.g.nz) + 1;  // every bin count and the overflow count
     const dim3 grid(grid_for(48LL * (B.max_nb > 0 ? B.max_nb : 1)), B.nrep);
     if (B.kernel == 3)
         hipLaunchKernelGGL((k_gather_final<T, 3>), grid, dim3(kThreads), 0, s, B.d, n_clear, n_me,

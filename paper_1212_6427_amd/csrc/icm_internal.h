@@ -12,13 +12,19 @@ namespace icm {
 
 constexpr int kMaxStages = 16;
 
-// z-chunks of the right-hand-side kernel (see RhsBlobs)
+// Workgroups of the right-hand-side kernel: a tile of kRhsTileX x kRhsTileY
+// (x, y) columns and a z-chunk of GridDesc::zc planes (see RhsBlobs)
+constexpr int kRhsTileX = 32, kRhsTileY = 16;
 constexpr int kRhsZChunk = 16;    // default z-chunk (planes)
-constexpr int kRhsZChunkMin = 4;  // smallest z-chunk: sizes the bins; a stencil
-                                  // (at most 5 planes over the components)
-                                  // then meets at most two chunks
-// bin slots: chunk counts of the finest chunking, then the overflow count
+constexpr int kRhsZChunkMin = 4;  // smallest z-chunk: sizes the bins
 __host__ __device__ inline int max_chunks(int nz) { return (nz + kRhsZChunkMin - 1) / kRhsZChunkMin; }
+__host__ __device__ inline int rhs_tiles_x(int nx) { return (nx + kRhsTileX - 1) / kRhsTileX; }
+__host__ __device__ inline int rhs_tiles_y(int ny) { return (ny + kRhsTileY - 1) / kRhsTileY; }
+// bin slots: one per (tile, chunk) of the finest chunking, then the overflow
+// count
+__host__ __device__ inline int rhs_bins(int nx, int ny, int nz) {
+    return rhs_tiles_x(nx) * rhs_tiles_y(ny) * max_chunks(nz);
+}
 
 // Mixed-radix (2, 3, 4, 8) Stockham plan of one FFT length.
 struct FFTPlan {
@@ -146,24 +152,24 @@ struct RhsCoef {
 // component a, the wrapped base nodes (as doubles) of the P-tap stencil on
 // the a-component grid, the P weights of each axis, and the P derivative
 // weights phi'(d)/h along axis a (kStcPerComp values per component).
-// Blobs are binned by z-chunk of GridDesc::zc planes: chunk_count[c] blobs of
-// chunk c are listed at chunk_list[c * cap]. A tile that meets more than
-// kRhsTileCap blobs appends the excess (blob, tile) pairs to the overflow
-// list, which launch_spread_overflow spreads with atomics.
+// Blobs are binned by workgroup of the RHS kernel, i.e. by (tile, z-chunk):
+// bin t = (chunk * tiles_y + tile_y) * tiles_x + tile_x lists bin_count[t]
+// blobs at bin_list[t * kRhsTileCap]. A bin's blobs beyond kRhsTileCap go to
+// the overflow list as (blob, bin) pairs, which launch_spread_overflow
+// spreads with atomics.
 
 constexpr int kRhsTileCap = 128;
 constexpr int kStcPerComp = 3 + 4 * 4;
 struct RhsBlobs {
     int nb;
     int kernel;
-    int cap;                 // list capacity per chunk (>= nb)
     const double* stc;       // nb * 3 * kStcPerComp
     const double* F;         // nb * 3 forces (spread with S)
     const double* cdrift;    // nb drift coefficients kT m~_f / m~ (NULL = no drift)
-    const int* chunk_count;  // n_chunks
-    const int* chunk_list;   // n_chunks * cap
+    int* bin_count;          // rhs_bins
+    int* bin_list;           // rhs_bins * kRhsTileCap
     int* ovf_count;          // 1
-    int* ovf_list;           // 2 * ovf_cap ints (blob, tile)
+    int* ovf_list;           // 2 * ovf_cap ints (blob, bin)
     int ovf_cap;
 };
 
@@ -185,8 +191,8 @@ struct BlobBufs {
     unsigned int* flag;                    // numeric error flag
     // spread inside the right-hand-side kernel
     double* stc;                           // max_nb * 3 * kStcPerComp
-    int* chunk_count;                      // n_chunks + 1 (the last is the overflow count)
-    int* chunk_list;                       // n_chunks * max_nb
+    int* bin_count;                        // rhs_bins + 1 (the last is the overflow count)
+    int* bin_list;                         // rhs_bins * kRhsTileCap
     int* ovf_list;                         // 2 * ovf_cap
     int ovf_cap;
 };

@@ -164,6 +164,24 @@ def test_equilibrium_and_projection_initialisers(I):
         sim.close()
 
 
+@pytest.mark.parametrize("kernel", [3, 4])
+def test_stencils_across_short_last_tiles_fp64(I, kernel):
+    """(16, 162, 18): the RHS kernel runs 16-row tiles along y, the last of
+    two rows, and 4-plane z-chunks, the last of two planes. A stencil that
+    wraps around y from row 159 to row 0 meets three tiles, one that wraps
+    around z from plane 15 to plane 0 three chunks; the blob must be spread
+    into every one of them."""
+    p = oracle_params((16, 162, 18), kernel=kernel, kT=1e-3, dt=0.2, seed=151)
+    st = initial_state(p, 5, (0.0, 1.0), seed=43, min_sep=3.0)
+    st.q = np.array([[5.3, 160.6, 16.6],    # three y tiles, three z chunks
+                     [10.7, 40.2, 17.4],    # three z chunks (4-point kernel)
+                     [2.2, 0.6, 1.1],       # wraps below y = 0 and z = 0
+                     [12.0, 20.0, 8.0],
+                     [7.5, 161.5, 15.5]])
+    st.u = O.interp(p, st.v, st.q)
+    run_parity(I, p, st, 2, I.FP64, TOL64, "short last tiles")
+
+
 def test_wca_small_box_all_pairs_fp64(I):
     """A box fewer than three cutoffs wide takes the all-pairs force path."""
     sigma = 3.0 / 2 ** (1 / 6)
