@@ -881,8 +881,9 @@ float time_fft(icm_ctx* c, const icm::Batch<T>& B, hipEvent_t ea, hipEvent_t eb)
 // each followed by one solve's five FFT passes as in the step (the RHS kernel
 // timed alone finds different data in the caches, and such timings picked
 // chunks that were slower in the step): the chunk is installed, the
-// spread's bins computed for it (from the positions and forces of the last
-// step) and cleared again afterwards.
+// spread's bins computed for it (from stencil records at the current
+// positions, which a step has not necessarily written yet, and the last
+// step's forces) and cleared again afterwards.
 template <typename T>
 float time_rhs(icm_ctx* c, size_t b, int zc, hipEvent_t ea, hipEvent_t eb) {
     for (int r : c->batches[b].reps) c->reps[r].zc_tuned = zc;
@@ -898,6 +899,7 @@ float time_rhs(icm_ctx* c, size_t b, int zc, hipEvent_t ea, hipEvent_t eb) {
         }
     };
     clear();
+    icm::launch_stencil_records(B, s);
     icm::launch_bins(B, s);
     auto once = [&] {
         icm::launch_rhs(B, s);

@@ -813,6 +813,34 @@ __global__ void __launch_bounds__(kThreads) k_gather_step1(const RepDesc<T>* __r
     }
 }
 
+// Stencil records at q^n: one thread per (blob, component), the same
+// nodes, weights and derivative weights that k_gather_step1 records at
+// q^{n+1/2}.
+template <typename T, int P>
+__global__ void __launch_bounds__(kThreads) k_stencil_records(const RepDesc<T>* __restrict__ rd) {
+    const GridDesc<T> g = rd[blockIdx.y].g;
+    const BlobParams bp = rd[blockIdx.y].bp;
+    const BlobBufs bb = rd[blockIdx.y].bb;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = t / 3, a = t - 3 * (t / 3);
+    if (b >= bp.nb) return;
+    const double inv_h = 1.0 / g.h;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    double* o = bb.stc + ((long long)b * 3 + a) * kStcPerComp;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const double x = fold_coord(bb.q[3 * b + ax] * inv_h - (ax == a ? 0.0 : 0.5), n[ax]);
+        const int base = (int)((P == 3) ? floor(x + 0.5) : floor(x)) - 1;
+        o[ax] = (double)wrap_node(base, n[ax]);
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            const double d = x - (double)(base + tt);
+            o[3 + 4 * ax + tt] = (tt < P) ? kern_w<P>(d, g.hs) : 0.0;
+            if (ax == a) o[15 + tt] = (tt < P) ? kern_dw<P>(d, g.hs) * inv_h : 0.0;
+        }
+    }
+}
+
 // The distinct tiles (runs of `span` nodes, the last run possibly shorter)
 // of an axis of n nodes that the P-node stencil runs from wrapped base nodes
 // b0 and b1 meet. The two runs overlap or touch (b1 is b0 or b0 - 1 modulo
@@ -1160,6 +1188,16 @@ void launch_gather_step1(const Batch<T>& B, hipStream_t s) {
 }
 
 template <typename T>
+void launch_stencil_records(const Batch<T>& B, hipStream_t s) {
+    if (B.max_nb <= 0) return;
+    const dim3 grid((unsigned)((3 * B.max_nb + kThreads - 1) / kThreads), B.nrep);
+    if (B.kernel == 3)
+        hipLaunchKernelGGL((k_stencil_records<T, 3>), grid, dim3(kThreads), 0, s, B.d);
+    else
+        hipLaunchKernelGGL((k_stencil_records<T, 4>), grid, dim3(kThreads), 0, s, B.d);
+}
+
+template <typename T>
 void launch_bins(const Batch<T>& B, hipStream_t s) {
     if (B.max_nb <= 0) return;
     // one more block when the mean velocity is carried (the force sum)
@@ -1213,6 +1251,7 @@ void launch_field_diag(const GridDesc<T>& g, double rho, double* acc, hipStream_
     template void launch_carry_init<T>(const GridDesc<T>&, double, double*, hipStream_t);        \
     template void launch_gather_step1<T>(const Batch<T>&, hipStream_t);                          \
     template void launch_bins<T>(const Batch<T>&, hipStream_t);                                  \
+    template void launch_stencil_records<T>(const Batch<T>&, hipStream_t);                       \
     template void launch_gather_final<T>(const Batch<T>&, int, bool, hipStream_t);               \
     template void launch_advect<T>(const Batch<T>&, hipStream_t);
 ICM_INST(float)

@@ -389,15 +389,21 @@ void launch_gather(const Batch<T>& B, int field, int q, int out, bool laplacian,
 // Fused gathers of the step (one 16-lane group per blob component): J^n v^n
 // with the predictor and J^{n+1/2} v^n with the stencil records of
 // q^{n+1/2} (step 1); J^{n+1/2} v^{n+1} with the position update (step 9,
-// which also clears the z-chunk bin counters, advances the step counter and,
+// which also clears the RHS bin counters, advances the step counter and,
 // in the first n_me replicas, gathers the lagged term J L dv from aux).
 template <typename T>
 void launch_gather_step1(const Batch<T>& B, hipStream_t s);
 template <typename T>
 void launch_gather_final(const Batch<T>& B, int n_me, bool lag_from_v, hipStream_t s);
-// z-chunk bins of the RHS spread (positions qh); counters must start at zero.
+// Bins of the RHS spread, one per RHS workgroup, from the stencil records;
+// counters must start at zero.
 template <typename T>
 void launch_bins(const Batch<T>& B, hipStream_t s);
+// Stencil records at the positions q^n, as step 1 writes them at q^{n+1/2}:
+// for the autotuner's RHS timing, whose bins need records before a first
+// step has written any (the next step overwrites them).
+template <typename T>
+void launch_stencil_records(const Batch<T>& B, hipStream_t s);
 
 // ------------------------------------------------------------ reductions
 // acc[0..2] += rho h^3 sum v; acc[3] += rho h^3 sum v^2 / 2;
