@@ -261,8 +261,26 @@ struct RepDesc {
 __device__ inline void block_sum3(int nb, const double* a, const double* m, const double* b, double* out) {
     __shared__ double red[3][256];
     double s[3] = {0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < nb; i += blockDim.x)
-        for (int c = 0; c < 3; ++c) s[c] += m ? a[3 * i + c] - m[i] * b[3 * i + c] : a[3 * i + c];
+    // thread t adds blobs t, t + 256, t + 512, ... in that order, sixteen per
+    // pass with all of a pass's loads issued before the first is added (at
+    // clamped indices, so that no branch stands between them)
+    constexpr int U = 16;
+    for (int i0 = 0; i0 < nb; i0 += U * (int)blockDim.x) {
+        double v[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+            const int ic = i < nb ? i : nb - 1;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[u][c] = m ? a[3 * ic + c] - m[ic] * b[3 * ic + c] : a[3 * ic + c];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (i0 + u * (int)blockDim.x + (int)threadIdx.x < nb)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) s[c] += v[u][c];
+        }
+    }
     for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = s[c];
     __syncthreads();
     for (int off = blockDim.x / 2; off > 0; off >>= 1) {
