@@ -583,32 +583,32 @@ __global__ void __launch_bounds__(kThreads) k_spread(const RepDesc<T>* __restric
 }
 
 // One 16-lane group's J for component a at position (qx,qy,qz), returned to
-// every lane of the group: lanes 1..3 evaluate the kernel weights of axis
-// r - 1 and share them through shuffles, and lane r < P^2 sums the x-row of
-// z-tap r / P and y-tap r mod P.
+// every lane of the group: lane 1 + 4 ax + tt (ax < 3, tt < 4) evaluates the
+// kernel weight of tap tt along axis ax (zero past P taps) and shares it
+// through shuffles, and lane r < P^2 sums the x-row of z-tap r / P and y-tap
+// r mod P.
 template <typename T, int P>
 __device__ __forceinline__ double gather_group(const GridDesc<T>& g, const T* __restrict__ field, const double* q3,
                                                int a, int r, bool active) {
     const double inv_h = 1.0 / g.h;
     int rb_node = 0;
-    double rw[4] = {0.0, 0.0, 0.0, 0.0};
-    if (active && r >= 1 && r <= 3) {
-        const int ax = r - 1;
+    double rw = 0.0;
+    if (active && r >= 1 && r <= 12) {
+        const int ax = (r - 1) >> 2, tt = (r - 1) & 3;
         const int nax = ax == 0 ? g.nx : (ax == 1 ? g.ny : g.nz);
         const double x = fold_coord(q3[ax] * inv_h - comp_offset(ax, a), nax);
         const int base = (int)((P == 3) ? floor(x + 0.5) : floor(x)) - 1;
         rb_node = wrap_node(base, nax);
-#pragma unroll
-        for (int tt = 0; tt < P; ++tt) rw[tt] = kern_w<P>(x - (double)(base + tt), g.hs);
+        if (tt < P) rw = kern_w<P>(x - (double)(base + tt), g.hs);
     }
     double wx[4], wy4[4], wz4[4];
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
-        wx[tt] = __shfl(rw[tt], 1, 16);
-        wy4[tt] = __shfl(rw[tt], 2, 16);
-        wz4[tt] = __shfl(rw[tt], 3, 16);
+        wx[tt] = __shfl(rw, 1 + tt, 16);
+        wy4[tt] = __shfl(rw, 5 + tt, 16);
+        wz4[tt] = __shfl(rw, 9 + tt, 16);
     }
-    const int bx = __shfl(rb_node, 1, 16), by = __shfl(rb_node, 2, 16), bz = __shfl(rb_node, 3, 16);
+    const int bx = __shfl(rb_node, 1, 16), by = __shfl(rb_node, 5, 16), bz = __shfl(rb_node, 9, 16);
     double acc = 0.0;
     if (active && r < P * P) {
         const int cz = r / P, cy = r - P * (r / P);
@@ -742,35 +742,32 @@ __global__ void __launch_bounds__(kThreads) k_gather_step1(const RepDesc<T>* __r
         s_qw[grp] = qw;
     }
     __syncthreads();
-    // (b): lanes 1..3 compute (and store) the record of axis ax = r - 1; the
-    // group's gather reads the weights from those lanes
+    // (b): lane 1 + 4 ax + tt computes (and stores) tap tt of axis ax of
+    // the record; the group's gather reads the weights from those lanes
     const double inv_h = 1.0 / g.h;
     const int n[3] = {g.nx, g.ny, g.nz};
     int rb_node = 0;
-    double rw[4] = {0.0, 0.0, 0.0, 0.0};
-    if (active && r >= 1 && r <= 3) {
-        const int ax = r - 1;
+    double rw = 0.0;
+    if (active && r >= 1 && r <= 12) {
+        const int ax = (r - 1) >> 2, tt = (r - 1) & 3;
         double* o = bb.stc + ((long long)b * 3 + a) * kStcPerComp;
         const double x = fold_coord(s_qh[3 * lb + ax] * inv_h - (ax == a ? 0.0 : 0.5), n[ax]);
         const int base = (int)((P == 3) ? floor(x + 0.5) : floor(x)) - 1;
         rb_node = wrap_node(base, n[ax]);
-        o[ax] = (double)rb_node;
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-            const double d = x - (double)(base + tt);
-            rw[tt] = (tt < P) ? kern_w<P>(d, g.hs) : 0.0;
-            o[3 + 4 * ax + tt] = rw[tt];
-            if (ax == a) o[15 + tt] = (tt < P) ? kern_dw<P>(d, g.hs) * inv_h : 0.0;
-        }
+        if (tt == 0) o[ax] = (double)rb_node;
+        const double d = x - (double)(base + tt);
+        rw = (tt < P) ? kern_w<P>(d, g.hs) : 0.0;
+        o[3 + 4 * ax + tt] = rw;
+        if (ax == a) o[15 + tt] = (tt < P) ? kern_dw<P>(d, g.hs) * inv_h : 0.0;
     }
     double wx[4], wy4[4], wz4[4];
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
-        wx[tt] = __shfl(rw[tt], 1, 16);
-        wy4[tt] = __shfl(rw[tt], 2, 16);
-        wz4[tt] = __shfl(rw[tt], 3, 16);
+        wx[tt] = __shfl(rw, 1 + tt, 16);
+        wy4[tt] = __shfl(rw, 5 + tt, 16);
+        wz4[tt] = __shfl(rw, 9 + tt, 16);
     }
-    const int bx = __shfl(rb_node, 1, 16), by = __shfl(rb_node, 2, 16), bz = __shfl(rb_node, 3, 16);
+    const int bx = __shfl(rb_node, 1, 16), by = __shfl(rb_node, 5, 16), bz = __shfl(rb_node, 9, 16);
     // lane r < P^2 sums the x-row of z-tap r / P and y-tap r mod P, as
     // gather_group does, with the same nodes and weights
     double acc = 0.0;
