@@ -10,6 +10,7 @@ namespace icm {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kTabThreads = 1024;  // the projection-table kernel: one workgroup per replica
 
 
 // F += WCA pair forces (Eq. (WCA), minimum image, unordered pairs counted
@@ -157,7 +158,7 @@ __global__ void __launch_bounds__(kThreads) k_pairs(const RepDesc<T>* __restrict
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_dp2_sum(const RepDesc<T>* __restrict__ rd) {
     const BlobBufs b = rd[blockIdx.x].bb;
-    block_sum3(rd[blockIdx.x].bp.nb, b.dp, b.me, b.g, rd[blockIdx.x].g.k0 + 6);
+    block_sum3<true>(rd[blockIdx.x].bp.nb, b.dp, b.me, b.g, rd[blockIdx.x].g.k0 + 6);
 }
 
 // Step 5 for replicas with at most kTabMaxBlobs blobs: g_i = J_i dv~ with
@@ -191,11 +192,13 @@ __device__ __forceinline__ int wrap_offset(int d, int n) {
 // The replica's stencil records and sources are staged in LDS first, so that
 // each item's only global reads are the Q table values of its x-row.
 template <typename T, int P>
-__global__ void __launch_bounds__(kThreads) k_jps_table(const RepDesc<T>* __restrict__ rd) {
+__global__ void __launch_bounds__(kTabThreads) k_jps_table(const RepDesc<T>* __restrict__ rd) {
     constexpr int Q = 2 * P - 1;
+    constexpr int kWaves = kTabThreads / 64;
     __shared__ double s_rec[3 * kTabMaxBlobs * kStcPerComp];
     __shared__ double s_f[3 * kTabMaxBlobs];
     __shared__ double s_g[3 * kTabMaxBlobs];
+    __shared__ double s_part[3 * kTabMaxBlobs][kWaves];
     const GridDesc<T>& g = rd[blockIdx.x].g;
     const BlobBufs& b = rd[blockIdx.x].bb;
     const int nb = rd[blockIdx.x].bp.nb;
@@ -206,14 +209,18 @@ __global__ void __launch_bounds__(kThreads) k_jps_table(const RepDesc<T>* __rest
     for (int t = threadIdx.x; t < 3 * nb * kStcPerComp; t += blockDim.x) s_rec[t] = b.stc[t];
     for (int t = threadIdx.x; t < 3 * nb; t += blockDim.x) s_f[t] = b.c5[t / 3] * b.dp[t] * ih3;
     __syncthreads();
-    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, nwaves = blockDim.x / 64;
-    // one wave per output (i, a); its lanes take the items (j, b, z offset,
-    // y offset), the x offsets run inside an item
-    for (int o = wave; o < 3 * nb; o += nwaves) {
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    // W waves per output (i, a) (several when there are fewer outputs than
+    // waves); their lanes take the items (j, b, z offset, y offset), the x
+    // offsets run inside an item
+    const int nout = 3 * nb;
+    const int W = (nout > 0 && nout < kWaves) ? kWaves / nout : 1;
+    const int ws = wave % W;
+    for (int o = wave / W; o < nout && wave < W * nout; o += kWaves / W) {
         const int al = o - 3 * (o / 3);
         const double* oi = s_rec + o * kStcPerComp;
         double part = 0.0;
-        for (int it = lane; it < nb * 3 * Q * Q; it += 64) {
+        for (int it = lane + 64 * ws; it < nb * 3 * Q * Q; it += 64 * W) {
             const int jb = it / (Q * Q), rem = it - jb * Q * Q;  // jb = 3 j + b
             const int tz = rem / Q, ty = rem - tz * Q;
             const double fj = s_f[jb];
@@ -237,12 +244,18 @@ __global__ void __launch_bounds__(kThreads) k_jps_table(const RepDesc<T>* __rest
             for (int tx = 0; tx < Q; ++tx) sx += stencil_corr<P>(oi + 3, oj + 3, tx - (P - 1)) * (double)kv[tx];
             part += fj * cyz * sx;
         }
-        // butterfly sum over the wave (the same order on every run)
+        // butterfly sum over the wave, then over the output's W waves in
+        // order (the same order on every run)
         for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-        if (lane == 0) {
-            s_g[o] = part;
-            b.g[o] = part;
-        }
+        if (lane == 0) s_part[o][ws] = part;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nout) {
+        const int o = (int)threadIdx.x;
+        double sum = 0.0;
+        for (int k = 0; k < W; ++k) sum += s_part[o][k];
+        s_g[o] = sum;
+        b.g[o] = sum;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < 3 * nb; t += blockDim.x) {
@@ -250,7 +263,7 @@ __global__ void __launch_bounds__(kThreads) k_jps_table(const RepDesc<T>* __rest
         b.dp2[t] = b.dp[t] - me * gt;
         if (me != 0.0) b.u[t] = b.Jhvt[t] + gt + b.du[t];
     }
-    if (g.k0) block_sum3(nb, b.dp, b.me, s_g, g.k0 + 6);
+    if (g.k0) block_sum3<true>(nb, b.dp, b.me, s_g, g.k0 + 6);
 }
 
 __global__ void k_blob_diag(int nb, const double* me, const double* u, double* acc) {
@@ -304,9 +317,9 @@ template <typename T>
 void launch_jps_table(const Batch<T>& B, hipStream_t s) {
     if (B.max_nb <= 0) return;
     if (B.kernel == 3)
-        hipLaunchKernelGGL((k_jps_table<T, 3>), dim3(B.nrep), dim3(kThreads), 0, s, B.d);
+        hipLaunchKernelGGL((k_jps_table<T, 3>), dim3(B.nrep), dim3(kTabThreads), 0, s, B.d);
     else
-        hipLaunchKernelGGL((k_jps_table<T, 4>), dim3(B.nrep), dim3(kThreads), 0, s, B.d);
+        hipLaunchKernelGGL((k_jps_table<T, 4>), dim3(B.nrep), dim3(kTabThreads), 0, s, B.d);
 }
 void launch_blob_diag(int nb, const double* me, const double* u, double* acc, hipStream_t s) {
     hipLaunchKernelGGL(k_blob_diag, dim3(1), dim3(kThreads), 0, s, nb, me, u, acc);

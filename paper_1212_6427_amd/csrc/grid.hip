@@ -878,7 +878,7 @@ __global__ void __launch_bounds__(kThreads) k_bins(const RepDesc<T>* __restrict_
     if (rd[blockIdx.y].g.k0 && blockIdx.x == gridDim.x - 1) {
         // the extra last block: the replica's total blob force, for the
         // FP64-carried mean velocity (fixed summation order)
-        block_sum3(rd[blockIdx.y].bp.nb, rd[blockIdx.y].bb.F, nullptr, nullptr, rd[blockIdx.y].g.k0 + 3);
+        block_sum3<false>(rd[blockIdx.y].bp.nb, rd[blockIdx.y].bb.F, nullptr, nullptr, rd[blockIdx.y].g.k0 + 3);
         return;
     }
     const RhsBlobs rb = rd[blockIdx.y].rb;

@@ -255,40 +255,46 @@ struct RepDesc {
     unsigned long long* step;   // step counter n (incremented at the end of the step)
 };
 
-// Sum over nb blobs of a 3-vector per blob, a[3i + c], or a[3i + c] -
-// m[i] b[3i + c] when m is given, by one workgroup of 256 threads in a fixed
-// order (so the same inputs give the same sum); thread 0 writes out[0..2].
+// Sum over nb blobs of a 3-vector per blob, a[3i + c], or (DIFF) a[3i + c] -
+// m[i] b[3i + c], by the first 256 threads of a workgroup (every thread of
+// it calls this) in a fixed order (so the same inputs give the same sum);
+// thread 0 writes out[0..2]. Thread t adds blobs t, t + 256, t + 512, ...
+// in that order, U per pass with all of a pass's loads issued before the
+// first is added (at clamped indices, so that no branch stands between
+// them).
+template <bool DIFF>
 __device__ inline void block_sum3(int nb, const double* a, const double* m, const double* b, double* out) {
-    __shared__ double red[3][256];
+    constexpr int NT = 256;
+    constexpr int U = DIFF ? 4 : 16;  // 7 or 3 loads per blob in flight
+    __shared__ double red[3][NT];
+    const int tid = (int)threadIdx.x;
     double s[3] = {0.0, 0.0, 0.0};
-    // thread t adds blobs t, t + 256, t + 512, ... in that order, sixteen per
-    // pass with all of a pass's loads issued before the first is added (at
-    // clamped indices, so that no branch stands between them)
-    constexpr int U = 16;
-    for (int i0 = 0; i0 < nb; i0 += U * (int)blockDim.x) {
-        double v[U][3];
+    if (tid < NT) {
+        for (int i0 = 0; i0 < nb; i0 += U * NT) {
+            double v[U][3];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
-            const int ic = i < nb ? i : nb - 1;
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * NT + tid;
+                const int ic = i < nb ? i : nb - 1;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) v[u][c] = m ? a[3 * ic + c] - m[ic] * b[3 * ic + c] : a[3 * ic + c];
+                for (int c = 0; c < 3; ++c) v[u][c] = DIFF ? a[3 * ic + c] - m[ic] * b[3 * ic + c] : a[3 * ic + c];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (i0 + u * NT + tid < nb)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) s[c] += v[u][c];
+            }
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (i0 + u * (int)blockDim.x + (int)threadIdx.x < nb)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) s[c] += v[u][c];
-        }
+        for (int c = 0; c < 3; ++c) red[c][tid] = s[c];
     }
-    for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = s[c];
     __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off)
-            for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + off];
+    for (int off = NT / 2; off > 0; off >>= 1) {
+        if (tid < off)
+            for (int c = 0; c < 3; ++c) red[c][tid] += red[c][tid + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0)
+    if (tid == 0)
         for (int c = 0; c < 3; ++c) out[c] = red[c][0];
 }
 
