@@ -113,7 +113,7 @@ def measured_traffic(phase):
 
 # Kernels of one step of the 256^3 FP32 workload (all blobs neutrally
 # buoyant, so no inertial-correction launches), each launched once per step.
-STEP_KERNELS = ("k_gather_step1<", "k_pairs_cells<", "k_bins<", "k_rhs_march<", "k_spread_overflow<",
+STEP_KERNELS = ("k_gather_step1<", "k_pairs_cells<", "k_rhs_march<", "k_spread_overflow<",
                 "k_xfwd_fast<", "k_y_fast<", "k_z_fast<", "k_xinv_fast<", "k_gather_final<")
 
 

@@ -669,11 +669,10 @@ void enqueue_step(icm_ctx* c, const BatchInfo& bi, hipStream_t s) {
     const icm::Batch<T> B = batch_of<T>(c, bi);
     using namespace icm;
     // Step 1: midpoint predictor with the one-body forces; J^{n+1/2} v^n (for
-    // step 9) with the spread stencils and the cell lists; pair forces;
-    // z-chunk bins of the spread.
+    // step 9) with the spread stencils and the cell lists; pair forces and
+    // the RHS bins of the spread.
     timed(c, ICM_PHASE_GATHER, s, [&] { launch_gather_step1(B, s); });
     timed(c, ICM_PHASE_FORCES, s, [&] { launch_forces(B, s); });
-    timed(c, ICM_PHASE_SPREAD, s, [&] { launch_bins(B, s); });
     // Step 2: unperturbed fluid solve; S F and the thermal drift are spread
     // inside the right-hand-side kernel.
     timed(c, ICM_PHASE_RHS, s, [&] { launch_rhs(B, s); });

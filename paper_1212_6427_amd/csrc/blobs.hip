@@ -17,8 +17,20 @@ constexpr int kTabThreads = 1024;  // the projection-table kernel: one workgroup
 // once) at q^{n+1/2}: each blob walks the lists of the 27 cells around its
 // own (cells are at least one cutoff wide, at least 3 per axis). Replica
 // blockIdx.y.
+// Workgroups from pair_blocks on bin the replica's blobs for the RHS spread
+// instead (any pair mode; width: the stencil width), which needs only the
+// stencil records of the step-1 gather, like the pair walk its positions.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_pairs_cells(const RepDesc<T>* __restrict__ rd) {
+__global__ void __launch_bounds__(kThreads) k_pairs_cells(const RepDesc<T>* __restrict__ rd, int pair_blocks,
+                                                          int width) {
+    if ((int)blockIdx.x >= pair_blocks) {
+        const int b = ((int)blockIdx.x - pair_blocks) * (int)blockDim.x + (int)threadIdx.x;
+        if (width == 3)
+            bin_blob_from_records<T, 3>(rd[blockIdx.y], b);
+        else
+            bin_blob_from_records<T, 4>(rd[blockIdx.y], b);
+        return;
+    }
     if (rd[blockIdx.y].pair_mode != 1) return;
     const BlobParams bp = rd[blockIdx.y].bp;
     const BlobBufs b = rd[blockIdx.y].bb;
@@ -298,10 +310,16 @@ __global__ void k_blob_diag(int nb, const double* me, const double* u, double* a
 template <typename T>
 void launch_forces(const Batch<T>& B, hipStream_t s) {
     if (B.max_nb <= 0) return;
-    // the one-body forces and the cell lists are set by the gathers before
+    // the one-body forces, the cell lists and the stencil records are set by
+    // the gathers before; the cell-list pair walk and the RHS bins share a
+    // launch (the bins get workgroups of their own), else the bins run alone
     if (B.any_cells) {
-        const dim3 g4((unsigned)((4LL * B.max_nb + kThreads - 1) / kThreads), B.nrep);
-        hipLaunchKernelGGL(k_pairs_cells<T>, g4, dim3(kThreads), 0, s, B.d);
+        const unsigned pair_blocks = (unsigned)((4LL * B.max_nb + kThreads - 1) / kThreads);
+        const unsigned bin_blocks = (unsigned)((B.max_nb + kThreads - 1) / kThreads);
+        hipLaunchKernelGGL(k_pairs_cells<T>, dim3(pair_blocks + bin_blocks, B.nrep), dim3(kThreads), 0, s, B.d,
+                           (int)pair_blocks, B.kernel);
+    } else {
+        launch_bins(B, s);
     }
     if (B.any_all_pairs) {
         const unsigned ti = (unsigned)((B.max_nb + kThreads - 1) / kThreads);

@@ -95,9 +95,13 @@ constexpr int RTX = kRhsTileX, RTY = kRhsTileY;
 // ONE: a batch of one replica whose descriptor comes by value in the kernel
 // arguments (constant memory the compiler may re-read at will); otherwise the
 // replica's descriptor is read from the device array.
+// sum_slice: one more z-slice of workgroups (the first), which sum the blob
+// forces of the batch's replicas (fixed order) for the FP64-carried mean
+// velocity of an FP32 grid (the z pass reads them); the pair forces are
+// complete before this launch.
 template <typename T, bool ONE>
 __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __restrict__ rd, const RepDesc<T> one,
-                                                        int ntz) {
+                                                        int ntz, int sum_slice) {
     __shared__ int s_blobs[kRhsTileCap];   // blobs of this workgroup's bin
     // Plane buffers, two of each: plane k uses buffer k - k0 mod 2, so the
     // next plane's writes never meet this plane's reads and one barrier per
@@ -125,8 +129,18 @@ __global__ void __launch_bounds__(RTX * RTY) k_rhs_march(const RepDesc<T>* __res
     // then replica): neighbouring tiles then share their halo lines in that
     // XCD's L2.
     const int ntx = gridDim.x, nty = gridDim.y;
-    const int ntiles = ntx * nty * gridDim.z;
-    int tile = blockIdx.x + ntx * (blockIdx.y + nty * blockIdx.z);
+    const int nzr = (int)gridDim.z - sum_slice;  // z-slices of tiles: chunks x replicas
+    if (sum_slice && blockIdx.z == 0) {
+        // the first slice, dispatched first, so that the sums overlap the tiles
+        const int nrep = nzr / ntz;
+        for (int r = blockIdx.x + ntx * blockIdx.y; r < nrep; r += ntx * nty) {
+            const RepDesc<T>& Rr = ONE ? one : rd[r];
+            block_sum3<false, 4>(Rr.bp.nb, Rr.bb.F, nullptr, nullptr, Rr.g.k0 + 3);  // few registers
+        }
+        return;
+    }
+    const int ntiles = ntx * nty * nzr;
+    int tile = blockIdx.x + ntx * (blockIdx.y + nty * ((int)blockIdx.z - sum_slice));
     if (ntiles % 8 == 0) tile = (tile % 8) * (ntiles / 8) + tile / 8;
     const int tile_x = tile % ntx, tile_y = (tile / ntx) % nty, tile_zr = tile / (ntx * nty);
     const int rep = ONE ? 0 : tile_zr / ntz, tile_z = tile_zr - rep * ntz;
@@ -838,93 +852,12 @@ __global__ void __launch_bounds__(kThreads) k_stencil_records(const RepDesc<T>* 
     }
 }
 
-// The distinct tiles (runs of `span` nodes, the last run possibly shorter)
-// of an axis of n nodes that the P-node stencil runs from wrapped base nodes
-// b0 and b1 meet. The two runs overlap or touch (b1 is b0 or b0 - 1 modulo
-// n), so together they cover at most P + 1 <= 5 consecutive nodes, which
-// cross at most two tile starts: at most three tiles, and three only when a
-// short last tile lies between them. Unused slots are -1.
-template <int P>
-__device__ __forceinline__ void axis_tiles(int b0, int b1, int n, int span, int& c0, int& c1, int& c2) {
-    c0 = b0 / span;
-    c1 = -1;
-    c2 = -1;
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-#pragma unroll
-        for (int t = 0; t < P; ++t) {
-            int node = (r == 0 ? b0 : b1) + t;
-            if (node >= n) node -= n;
-            const int c = node / span;
-            if (c != c0 && c != c1 && c != c2) {
-                if (c1 < 0)
-                    c1 = c;
-                else
-                    c2 = c;
-            }
-        }
-    }
-}
-
-// Bins of the spread inside the RHS kernel, one per RHS workgroup (tile and
-// z-chunk), one thread per blob: the blob is listed in every bin whose tile
-// and chunk meet the nodes of its stencils, read from the records that
-// k_gather_step1 wrote (per axis, the base node of the component grid
-// offset by 0 along it and that of the two offset by h/2); a bin's entries
-// beyond kRhsTileCap go to the overflow list. The counts start at zero: the
-// previous step's k_gather_final (or the host) cleared them.
+// The RHS bins of a batch's replicas, one thread per blob (a batch with
+// cell-list pair forces bins them in that launch instead; the autotuner's
+// RHS timing uses this one).
 template <typename T, int P>
 __global__ void __launch_bounds__(kThreads) k_bins(const RepDesc<T>* __restrict__ rd) {
-    if (rd[blockIdx.y].g.k0 && blockIdx.x == gridDim.x - 1) {
-        // the extra last block: the replica's total blob force, for the
-        // FP64-carried mean velocity (fixed summation order)
-        block_sum3<false>(rd[blockIdx.y].bp.nb, rd[blockIdx.y].bb.F, nullptr, nullptr, rd[blockIdx.y].g.k0 + 3);
-        return;
-    }
-    const RhsBlobs rb = rd[blockIdx.y].rb;
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= rb.nb) return;
-    const int nx = rd[blockIdx.y].g.nx, ny = rd[blockIdx.y].g.ny, nz = rd[blockIdx.y].g.nz;
-    const int zc = rd[blockIdx.y].g.zc;
-    const int tiles_x = rhs_tiles_x(nx), tiles_y = rhs_tiles_y(ny);
-    // record of component a: o + a kStcPerComp, base node along axis ax at
-    // [ax]; a record the step has not written yet (the autotuner's timing
-    // before a first step) may hold anything, and a value outside the axis
-    // reads as node 0, so that every bin index stays in range
-    const gptr<const double> o = as_global(rb.stc) + (long long)b * 3 * kStcPerComp;
-    auto node = [](double d, int n) { return (d >= 0.0 && d < (double)n) ? (int)d : 0; };
-    int x0, x1, x2, y0, y1, y2, z0, z1, z2;
-    axis_tiles<P>(node(o[0], nx), node(o[kStcPerComp], nx), nx, kRhsTileX, x0, x1, x2);
-    axis_tiles<P>(node(o[kStcPerComp + 1], ny), node(o[2 * kStcPerComp + 1], ny), ny, kRhsTileY, y0, y1, y2);
-    axis_tiles<P>(node(o[2 * kStcPerComp + 2], nz), node(o[2], nz), nz, zc, z0, z1, z2);
-    const gptr<int> count = as_global(rb.bin_count), list = as_global(rb.bin_list);
-#pragma unroll
-    for (int iz = 0; iz < 3; ++iz) {
-        const int cz = iz == 0 ? z0 : (iz == 1 ? z1 : z2);
-        if (cz < 0) continue;
-#pragma unroll
-        for (int iy = 0; iy < 3; ++iy) {
-            const int cy = iy == 0 ? y0 : (iy == 1 ? y1 : y2);
-            if (cy < 0) continue;
-#pragma unroll
-            for (int ix = 0; ix < 3; ++ix) {
-                const int cx = ix == 0 ? x0 : (ix == 1 ? x1 : x2);
-                if (cx < 0) continue;
-                const int bin = (cz * tiles_y + cy) * tiles_x + cx;
-                const int slot = __hip_atomic_fetch_add(&count[bin], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (slot < kRhsTileCap) {
-                    list[(long long)bin * kRhsTileCap + slot] = b;
-                } else {
-                    const int os = __hip_atomic_fetch_add(as_global(rb.ovf_count), 1, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT);
-                    if (os < rb.ovf_cap) {
-                        as_global(rb.ovf_list)[2 * os] = b;
-                        as_global(rb.ovf_list)[2 * os + 1] = bin;
-                    }
-                }
-            }
-        }
-    }
+    bin_blob_from_records<T, P>(rd[blockIdx.y], blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Step 9 fused: Jhvnew = J(q^{n+1/2}) v^{n+1}; q^{n+1} = q^n + dt/2
@@ -1108,11 +1041,13 @@ template <typename T>
 void launch_rhs(const Batch<T>& B, hipStream_t s) {
     const GridDesc<T>& g = B.g;
     const int ntz = (g.nz + g.zc - 1) / g.zc;
-    const dim3 grid((unsigned)((g.nx + RTX - 1) / RTX), (unsigned)((g.ny + RTY - 1) / RTY), (unsigned)(ntz * B.nrep));
+    const int sum_slice = (B.g.k0 && B.max_nb > 0) ? 1 : 0;
+    const dim3 grid((unsigned)((g.nx + RTX - 1) / RTX), (unsigned)((g.ny + RTY - 1) / RTY),
+                    (unsigned)(ntz * B.nrep + sum_slice));
     if (B.nrep == 1 && B.one)
-        hipLaunchKernelGGL((k_rhs_march<T, true>), grid, dim3(RTX * RTY), 0, s, B.d, *B.one, ntz);
+        hipLaunchKernelGGL((k_rhs_march<T, true>), grid, dim3(RTX * RTY), 0, s, B.d, *B.one, ntz, sum_slice);
     else
-        hipLaunchKernelGGL((k_rhs_march<T, false>), grid, dim3(RTX * RTY), 0, s, B.d, RepDesc<T>{}, ntz);
+        hipLaunchKernelGGL((k_rhs_march<T, false>), grid, dim3(RTX * RTY), 0, s, B.d, RepDesc<T>{}, ntz, sum_slice);
 }
 
 template <typename T>
@@ -1197,8 +1132,7 @@ void launch_stencil_records(const Batch<T>& B, hipStream_t s) {
 template <typename T>
 void launch_bins(const Batch<T>& B, hipStream_t s) {
     if (B.max_nb <= 0) return;
-    // one more block when the mean velocity is carried (the force sum)
-    const dim3 grid((unsigned)((B.max_nb + kThreads - 1) / kThreads + (B.g.k0 ? 1 : 0)), B.nrep);
+    const dim3 grid((unsigned)((B.max_nb + kThreads - 1) / kThreads), B.nrep);
     if (B.kernel == 3)
         hipLaunchKernelGGL((k_bins<T, 3>), grid, dim3(kThreads), 0, s, B.d);
     else

@@ -262,10 +262,9 @@ struct RepDesc {
 // in that order, U per pass with all of a pass's loads issued before the
 // first is added (at clamped indices, so that no branch stands between
 // them).
-template <bool DIFF>
+template <bool DIFF, int U = DIFF ? 4 : 16>  // 7 or 3 loads per blob
 __device__ inline void block_sum3(int nb, const double* a, const double* m, const double* b, double* out) {
     constexpr int NT = 256;
-    constexpr int U = DIFF ? 4 : 16;  // 7 or 3 loads per blob in flight
     __shared__ double red[3][NT];
     const int tid = (int)threadIdx.x;
     double s[3] = {0.0, 0.0, 0.0};
@@ -296,6 +295,85 @@ __device__ inline void block_sum3(int nb, const double* a, const double* m, cons
     }
     if (tid == 0)
         for (int c = 0; c < 3; ++c) out[c] = red[c][0];
+}
+
+// The distinct tiles (runs of `span` nodes, the last run possibly shorter)
+// of an axis of n nodes that the P-node stencil runs from wrapped base nodes
+// b0 and b1 meet. The two runs overlap or touch (b1 is b0 or b0 - 1 modulo
+// n), so together they cover at most P + 1 <= 5 consecutive nodes, which
+// cross at most two tile starts: at most three tiles, and three only when a
+// short last tile lies between them. Unused slots are -1.
+template <int P>
+__device__ __forceinline__ void axis_tiles(int b0, int b1, int n, int span, int& c0, int& c1, int& c2) {
+    c0 = b0 / span;
+    c1 = -1;
+    c2 = -1;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            int node = (r == 0 ? b0 : b1) + t;
+            if (node >= n) node -= n;
+            const int c = node / span;
+            if (c != c0 && c != c1 && c != c2) {
+                if (c1 < 0)
+                    c1 = c;
+                else
+                    c2 = c;
+            }
+        }
+    }
+}
+
+// Lists blob b of replica R (no-op for b >= nb) in every RHS bin (tile and
+// z-chunk) its stencils meet, from the stencil records of the step-1 gather
+// (per axis, the base node of the component grid offset by 0 along it and
+// that of the two offset by h/2); a bin's entries beyond kRhsTileCap go to
+// the overflow list. The counts start at zero: the previous step's final
+// gather (or the host) cleared them. A record the step has not written yet
+// (the autotuner's timing before a first step) may hold anything: a value
+// outside the axis reads as node 0, so that every bin index stays in range.
+template <typename T, int P>
+__device__ inline void bin_blob_from_records(const RepDesc<T>& R, int b) {
+    const RhsBlobs& rb = R.rb;
+    if (b >= rb.nb) return;
+    const int nx = R.g.nx, ny = R.g.ny, nz = R.g.nz, zc = R.g.zc;
+    const int tiles_x = rhs_tiles_x(nx), tiles_y = rhs_tiles_y(ny);
+    // record of component a: o + a kStcPerComp, base node along axis ax at [ax]
+    const gptr<const double> o = as_global(rb.stc) + (long long)b * 3 * kStcPerComp;
+    auto node = [](double d, int n) { return (d >= 0.0 && d < (double)n) ? (int)d : 0; };
+    int x0, x1, x2, y0, y1, y2, z0, z1, z2;
+    axis_tiles<P>(node(o[0], nx), node(o[kStcPerComp], nx), nx, kRhsTileX, x0, x1, x2);
+    axis_tiles<P>(node(o[kStcPerComp + 1], ny), node(o[2 * kStcPerComp + 1], ny), ny, kRhsTileY, y0, y1, y2);
+    axis_tiles<P>(node(o[2 * kStcPerComp + 2], nz), node(o[2], nz), nz, zc, z0, z1, z2);
+    const gptr<int> count = as_global(rb.bin_count), list = as_global(rb.bin_list);
+#pragma unroll
+    for (int iz = 0; iz < 3; ++iz) {
+        const int cz = iz == 0 ? z0 : (iz == 1 ? z1 : z2);
+        if (cz < 0) continue;
+#pragma unroll
+        for (int iy = 0; iy < 3; ++iy) {
+            const int cy = iy == 0 ? y0 : (iy == 1 ? y1 : y2);
+            if (cy < 0) continue;
+#pragma unroll
+            for (int ix = 0; ix < 3; ++ix) {
+                const int cx = ix == 0 ? x0 : (ix == 1 ? x1 : x2);
+                if (cx < 0) continue;
+                const int bin = (cz * tiles_y + cy) * tiles_x + cx;
+                const int slot = __hip_atomic_fetch_add(&count[bin], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (slot < kRhsTileCap) {
+                    list[(long long)bin * kRhsTileCap + slot] = b;
+                } else {
+                    const int os = __hip_atomic_fetch_add(as_global(rb.ovf_count), 1, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                    if (os < rb.ovf_cap) {
+                        as_global(rb.ovf_list)[2 * os] = b;
+                        as_global(rb.ovf_list)[2 * os + 1] = bin;
+                    }
+                }
+            }
+        }
+    }
 }
 
 // The k = 0 mode of a step's solve when the replica carries its mean
@@ -419,7 +497,8 @@ template <typename T>
 void launch_gather_step1(const Batch<T>& B, hipStream_t s);
 template <typename T>
 void launch_gather_final(const Batch<T>& B, int n_me, bool lag_from_v, hipStream_t s);
-// Bins of the RHS spread, one per RHS workgroup, from the stencil records;
+// Bins of the RHS spread, one per RHS workgroup, from the stencil records
+// (the step bins with the cell-list pair forces when the batch has them);
 // counters must start at zero.
 template <typename T>
 void launch_bins(const Batch<T>& B, hipStream_t s);
