@@ -870,6 +870,75 @@ def cpu_baseline(wl, seed_positions, steps=2):
                 cpu_model=cpu_model(), one_core=runs["one_core"], all_cores=a)
 
 
+def cpu_samples():
+    """The FP64 oracle, untuned, on bounded samples of the other workloads,
+    with scipy.fft on every host core the process may use, in cell-steps/s
+    (the initial fields are built outside the timed region):
+    plain_fp64_32 all 10 steps; single_blob_128 two steps for each of its
+    three excess masses; batched_ensemble one step of each of its 96
+    replicas. scale_512 is not sampled: the oracle's WCA forces are all
+    pairs (10^10 at 10^5 blobs, minutes per step) and its FP64 512^3 step
+    holds about 25 GB of fields."""
+    import scipy.fft as sfft
+    import icm_inputs
+    from oracle import icm as O
+    cores = len(os.sched_getaffinity(0))
+    W = icm_inputs.WORKLOADS
+
+    def params(wl, n, replica=0):
+        return O.Params(n=tuple(n), h=wl["h"], rho=wl["rho"], eta=wl["eta"], kT=wl["kT"], dt=wl["dt"],
+                        kernel=wl["kernel"], seed=wl["seed"], replica=replica)
+
+    def run(p, st, steps):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st = O.step(p, st)
+        return time.perf_counter() - t0
+
+    res = {}
+    with sfft.set_workers(cores):
+        wl = W["plain_fp64_32"]
+        p = params(wl, wl["n"])
+        q = icm_inputs.uniform_positions(1, wl["n"], wl["h"], seed=wl["seed"] + 1)
+        u0 = np.array([wl["kick"]], dtype=np.float64)
+        st = O.new_state(p, q, u=u0, f_const=np.array([wl["f_const"]], dtype=np.float64))
+        st.v = O.kick_field(p, q, u0, st.m_e)
+        sec = run(p, st, wl["steps"])
+        res["plain_fp64_32"] = dict(value=int(np.prod(wl["n"])) * wl["steps"] / sec, seconds=sec,
+                                    sample="all %d steps" % wl["steps"])
+
+        wl = W["single_blob_128"]
+        q = icm_inputs.uniform_positions(1, wl["n"], wl["h"], seed=wl["seed"] + 1)
+        sec = 0.0
+        for r, ratio in enumerate(wl["me_over_mf"]):
+            p = params(wl, wl["n"], r)
+            st = O.new_state(p, q, m_e=np.array([ratio * p.m_f]))
+            st.v = O.equilibrium_field(p)
+            st.u = O.interp(p, st.v, q)
+            sec += run(p, st, 2)
+        steps = 2 * len(wl["me_over_mf"])
+        res["single_blob_128"] = dict(value=int(np.prod(wl["n"])) * steps / sec, seconds=sec,
+                                      sample="2 steps for each of m_e/m_f = %s" % (wl["me_over_mf"],))
+
+        wl = W["batched_ensemble"]
+        ratios = icm_inputs.excess_mass_ratios(len(wl["grids"]), wl["me_over_mf"], seed=wl["seed"])
+        sec, cells = 0.0, 0
+        for r, n in enumerate(wl["grids"]):
+            p = params(wl, n, r)
+            q = icm_inputs.uniform_positions(1, n, wl["h"], seed=wl["seed"] + 1 + r)
+            st = O.new_state(p, q, m_e=np.array([ratios[r] * p.m_f]))
+            st.v = O.equilibrium_field(p)
+            sec += run(p, st, 1)
+            cells += int(np.prod(n))
+        res["batched_ensemble"] = dict(value=cells / sec, seconds=sec,
+                                       sample="one step of each of the %d replicas" % len(wl["grids"]))
+    for k, v in res.items():
+        v.update(unit="cell-steps/s", cores=cores, kind="oracle")
+    res["scale_512"] = dict(value=None, sample="not sampled: all-pairs WCA over 10^5 blobs and ~25 GB of "
+                                               "FP64 fields per step in the oracle")
+    return res
+
+
 def compact_record(out):
     """The headline keys plus one-line summaries of the other legs: the last
     stdout line, a few KB."""
@@ -884,6 +953,8 @@ def compact_record(out):
         cb = out["cpu_baseline"]
         c["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "cpu_model")}
         c["cpu_baseline"]["one_core_value"] = cb["one_core"]["value"]
+    if "cpu_samples" in out:
+        c["cpu_samples"] = {k: v["value"] for k, v in out["cpu_samples"].items()}
     c["phases_us"] = {k: round(v["avg_launch_us"], 1) for k, v in out.get("phases", {}).items()}
     if "fp64" in out:
         f = out["fp64"]
@@ -1088,6 +1159,10 @@ def main():
         log("CPU oracle: two steps of the same workload, all host cores and one core")
         out["cpu_baseline"] = cpu_baseline(wl, q)
         log("CPU oracle: %s" % out["cpu_baseline"]["sample"])
+        log("CPU oracle: samples of the other workloads")
+        out["cpu_samples"] = cpu_samples()
+        log("CPU oracle samples: %s" % {k: (None if v["value"] is None else "%.3g" % v["value"])
+                                        for k, v in out["cpu_samples"].items()})
     path = os.path.abspath(args.full_record)
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as fh:
