@@ -26,11 +26,11 @@ def I():
     return lib
 
 
-def run_parity(I, p, st, steps, precision, tol, name):
+def run_parity(I, p, st, steps, precision, tol, name, slots=None):
     banner("%s n=%s kernel=%d kT=%g nb=%d steps=%d prec=%d" % (name, p.n, p.kernel, p.kT, st.q.shape[0], steps,
                                                                precision))
     dtype = np.float64 if precision == I.FP64 else np.float32
-    sim = I.Sim([gpu_params(I, p)], [max(st.q.shape[0], 1)], precision)
+    sim = I.Sim([gpu_params(I, p)], [max(st.q.shape[0], 1) if slots is None else slots], precision)
     try:
         if precision == I.FP32_GRID:
             st = st.copy()
@@ -119,6 +119,18 @@ def test_no_blobs_fp64(I):
     run_parity(I, p, st, 2, I.FP64, TOL64, "no blobs")
 
 
+@pytest.mark.parametrize("slots", [0, 1])
+@pytest.mark.parametrize("n", [(12, 24, 18), (32, 16, 64)])
+def test_no_blobs_fp32(I, n, slots):
+    """FP32 grid without blobs (generic and fast transforms), in a context
+    with no blob slots (no force-sum workgroups) or one empty slot (they sum
+    no blobs): the mean mode carried in FP64 advances by the body force
+    alone."""
+    p = oracle_params(n, kT=2e-3, dt=0.4, seed=18, body=(1e-3, 2e-3, -5e-4))
+    st = initial_state(p, 0, seed=3)
+    run_parity(I, p, st, 2, I.FP32_GRID, TOL32, "no blobs fp32 %s slots %d" % (n, slots), slots=slots)
+
+
 def test_max_size_axis_fp64(I):
     """N = 512 along x (the largest supported transform) and radix-3 sizes."""
     p = oracle_params((512, 6, 12), kernel=3, kT=1e-3, dt=0.2, seed=19)
@@ -180,6 +192,18 @@ def test_stencils_across_short_last_tiles_fp64(I, kernel):
                      [7.5, 161.5, 15.5]])
     st.u = O.interp(p, st.v, st.q)
     run_parity(I, p, st, 2, I.FP64, TOL64, "short last tiles")
+
+
+@pytest.mark.parametrize("kernel", [3, 4])
+def test_stencils_across_short_last_tiles_fp32(I, kernel):
+    """The same stencils across short last tiles and chunks with an FP32
+    grid (the float instance of the RHS kernel), one step."""
+    p = oracle_params((16, 162, 18), kernel=kernel, kT=1e-3, dt=0.2, seed=152)
+    st = initial_state(p, 5, (0.0, 1.0), seed=44, min_sep=3.0)
+    st.q = np.array([[5.3, 160.6, 16.6], [10.7, 40.2, 17.4], [2.2, 0.6, 1.1], [12.0, 20.0, 8.0],
+                     [7.5, 161.5, 15.5]])
+    st.u = O.interp(p, st.v, st.q)
+    run_parity(I, p, st, 1, I.FP32_GRID, TOL32, "short last tiles fp32")
 
 
 def test_wca_small_box_all_pairs_fp64(I):
