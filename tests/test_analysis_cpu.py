@@ -86,6 +86,8 @@ def test_compact_record_is_small_and_carries_the_headline():
                phases=ph,
                cpu_baseline=dict(value=3e6, unit="cell-steps/s", cores=16, kind="oracle", sample="two steps",
                                  cpu_model="x", one_core=dict(value=2e6), all_cores=dict(value=3e6)),
+               cpu_samples=dict(plain_fp64_32=dict(value=1.5e7, seconds=0.1, sample="all 10 steps"),
+                                scale_512=dict(value=None, sample="not sampled")),
                fp64=dict(value=1e10, ms_per_step=1.4, steps=50, step_hbm_fraction=0.14),
                ensemble=dict(replicas=96, cells=12976128, batched=dict(ms_per_step=1.0, value=1.3e10),
                              single=dict(ms_per_step=12.0), speedup_batched_vs_single=12.0),
@@ -102,3 +104,4 @@ def test_compact_record_is_small_and_carries_the_headline():
     assert c["config"]["workload"] == "many_blobs_256"
     assert c["cpu_baseline"]["cores"] == 16 and c["cpu_baseline"]["kind"] == "oracle"
     assert c["ensemble"]["batched_ms_per_step"] == 1.0 and c["scale_512"]["max_rel_err_v"] == 3e-5
+    assert c["cpu_samples"] == {"plain_fp64_32": 1.5e7, "scale_512": None}
