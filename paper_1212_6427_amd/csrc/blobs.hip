@@ -248,8 +248,12 @@ __global__ void __launch_bounds__(kTabThreads) k_jps_table(const RepDesc<T>* __r
             T kv[Q];
 #pragma unroll
             for (int tx = 0; tx < Q; ++tx) {
-                const int x = dx0 + tx;
-                kv[tx] = row[x >= nx ? x - nx : x];
+                // dx0 + tx < nx + 2P - 2 <= 3 nx: an axis narrower than the
+                // 2P - 1 offsets (four nodes with P = 4) wraps twice
+                int x = dx0 + tx;
+                if (x >= nx) x -= nx;
+                if (x >= nx) x -= nx;
+                kv[tx] = row[x];
             }
             double sx = 0.0;
 #pragma unroll

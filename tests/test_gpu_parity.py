@@ -138,6 +138,16 @@ def test_max_size_axis_fp64(I):
     run_parity(I, p, st, 2, I.FP64, TOL64, "max axis")
 
 
+@pytest.mark.parametrize("kernel", [3, 4])
+def test_smallest_grid_fp64_and_fp32(I, kernel):
+    """(4, 6, 8), the smallest axis allowed: a 4-point stencil covers the
+    whole x axis, every RHS tile and transform is a ragged one."""
+    p = oracle_params((4, 6, 8), kernel=kernel, kT=1e-3, dt=0.2, seed=29 + kernel)
+    st = initial_state(p, 2, (0.0, 1.0), seed=47, min_sep=1.5)
+    run_parity(I, p, st, 2, I.FP64, TOL64, "smallest grid")
+    run_parity(I, p, st, 1, I.FP32_GRID, TOL32, "smallest grid fp32")
+
+
 def test_no_thermal_drift_and_nonunit_constants_fp64(I):
     p = oracle_params((18, 16, 24), kernel=4, kT=5e-3, dt=0.17, drift=False, h=0.8, rho=1.3, eta=0.6, seed=23)
     st = initial_state(p, 3, (0.0, 0.5), seed=25, min_sep=2.5)
