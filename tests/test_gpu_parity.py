@@ -483,6 +483,25 @@ def test_unwrapped_positions_far_from_the_box(I, kernel):
     run_parity(I, p, st, 3, I.FP64, TOL64, "unwrapped kernel=%d" % kernel)
 
 
+@pytest.mark.parametrize("kernel", [3, 4])
+def test_positions_on_nodes_and_faces(I, kernel):
+    """Blobs exactly on grid nodes, on half nodes, on the box faces and
+    within rounding of them (above and below): where the stencil's first
+    node changes and the coordinate folds to 0 or to the box length."""
+    p = oracle_params((24, 18, 12), kernel=kernel, kT=1e-3, dt=0.2, seed=132)
+    st = initial_state(p, 6, (0.0, 1.0, 0.0, -0.5, 0.0, 1.0), seed=133, min_sep=3.0)
+    e = 1e-12
+    st.q = np.array([[0.0, 0.0, 0.0],
+                     [24.0, 9.0, 6.0],
+                     [12.5, 4.5, 3.5],
+                     [24.0 - e, 18.0 - e, 12.0 - e],
+                     [-e, 13.0, 0.5 + e],
+                     [5.0, 17.5, 11.5 - e]])
+    st.u = O.interp(p, st.v, st.q)
+    run_parity(I, p, st, 3, I.FP64, TOL64, "nodes and faces kernel=%d" % kernel)
+    run_parity(I, p, st, 1, I.FP32_GRID, TOL32, "nodes and faces fp32 kernel=%d" % kernel)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_every_fft_launch_shape_keeps_parity(I, precision):
     """icm_set_fft_shapes installs launch shapes without measuring; every
