@@ -150,6 +150,18 @@ def test_smallest_grid_fp64_and_fp32(I, kernel, n):
     run_parity(I, p, st, 1, I.FP32_GRID, TOL32, "smallest grid fp32")
 
 
+@pytest.mark.parametrize("n", [(16, 32, 24), (32, 32, 32)])
+def test_inviscid_fp64_and_fp32(I, n):
+    """eta = 0 (allowed by the boundary): no stochastic stress, no viscous
+    term or viscous slip, H_1 = rho/dt and H_2 = rho; mixed excess masses,
+    on the generic transforms and on the fast ones (with the spectral form
+    of the inertial correction for few blobs)."""
+    p = oracle_params(n, kernel=4, kT=1e-3, dt=0.3, eta=0.0, seed=37, body=(2e-4, 0.0, -1e-4))
+    st = initial_state(p, 3, (0.0, 1.0, -0.5), seed=49, min_sep=3.0, velocity_field_scale=1e-2)
+    run_parity(I, p, st, 3, I.FP64, TOL64, "inviscid")
+    run_parity(I, p, st, 1, I.FP32_GRID, TOL32, "inviscid fp32")
+
+
 def test_no_thermal_drift_and_nonunit_constants_fp64(I):
     p = oracle_params((18, 16, 24), kernel=4, kT=5e-3, dt=0.17, drift=False, h=0.8, rho=1.3, eta=0.6, seed=23)
     st = initial_state(p, 3, (0.0, 0.5), seed=25, min_sep=2.5)
