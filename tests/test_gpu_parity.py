@@ -162,6 +162,18 @@ def test_inviscid_fp64_and_fp32(I, n):
     run_parity(I, p, st, 1, I.FP32_GRID, TOL32, "inviscid fp32")
 
 
+def test_step_counter_crosses_32_bits(I):
+    """Steps 2^32 - 2 to 2^32 + 1: the Philox counter's step words (low word
+    wrapping, high word carried) and the cell-list stamps across the carry,
+    with WCA pairs through the cell list, FP64 and FP32."""
+    p = oracle_params((24, 18, 12), kernel=4, kT=1e-3, dt=0.2, seed=53, wca_eps=1e-2,
+                      wca_sigma=2.0 / 2 ** (1 / 6))
+    st = initial_state(p, 5, (0.0, 1.0), seed=55, min_sep=2.2)
+    st.step = 2 ** 32 - 2
+    run_parity(I, p, st, 3, I.FP64, TOL64, "step 2^32")
+    run_parity(I, p, st, 1, I.FP32_GRID, TOL32, "step 2^32 fp32")
+
+
 def test_no_thermal_drift_and_nonunit_constants_fp64(I):
     p = oracle_params((18, 16, 24), kernel=4, kT=5e-3, dt=0.17, drift=False, h=0.8, rho=1.3, eta=0.6, seed=23)
     st = initial_state(p, 3, (0.0, 0.5), seed=25, min_sep=2.5)
