@@ -174,6 +174,16 @@ def test_step_counter_crosses_32_bits(I):
     run_parity(I, p, st, 1, I.FP32_GRID, TOL32, "step 2^32 fp32")
 
 
+def test_high_seed_and_replica_id(I):
+    """A seed above 2^32 (both key words) and a replica id whose tag fills
+    the counter word's top bits: the Philox key and counter layouts of the
+    noise, the equilibrium sample and the thermal drift, FP64 and FP32."""
+    p = oracle_params((16, 24, 18), kernel=3, kT=2e-3, dt=0.25, seed=2 ** 40 + 12345, replica=2 ** 27 + 3)
+    st = initial_state(p, 3, (0.0, 1.0, -0.5), seed=57, min_sep=3.0)
+    run_parity(I, p, st, 2, I.FP64, TOL64, "high seed and replica id")
+    run_parity(I, p, st, 1, I.FP32_GRID, TOL32, "high seed and replica id fp32")
+
+
 def test_no_thermal_drift_and_nonunit_constants_fp64(I):
     p = oracle_params((18, 16, 24), kernel=4, kT=5e-3, dt=0.17, drift=False, h=0.8, rho=1.3, eta=0.6, seed=23)
     st = initial_state(p, 3, (0.0, 0.5), seed=25, min_sep=2.5)
