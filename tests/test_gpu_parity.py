@@ -588,14 +588,14 @@ def test_set_fft_shapes_rejects_bad_values(I):
         sim.close()
 
 
-@pytest.mark.parametrize("grid", [(32, 24, 36), (32, 48, 64)])
+@pytest.mark.parametrize("grid", [(32, 24, 36), (32, 48, 64), (16, 16, 16)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_step5_table_and_field_paths_match_the_oracle(I, precision, grid):
     """Step 5's g = J P S (c5 dp) for replicas of at most 8 blobs comes from
     the tabulated projection kernel; with a capacity above 8 blobs (or 12
     blobs) it is formed as a field and interpolated. Both paths against the
     oracle, same state, mixed excess masses and both kernels. On the grid
-    with register-resident FFT plans (32 x 48 x 64) the table cases also
+    with register-resident FFT plans (32 x 48 x 64, 16^3) the table cases also
     take step 6's source transform from the blobs inside the z pass; on
     the other (generic FFT) they spread it into a field."""
     prec = I.FP64 if precision == "fp64" else I.FP32_GRID
