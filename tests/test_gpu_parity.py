@@ -139,12 +139,13 @@ def test_max_size_axis_fp64(I):
 
 
 @pytest.mark.parametrize("n", [(4, 6, 8), (8, 4, 6), (6, 8, 4)])
-@pytest.mark.parametrize("kernel", [3, 4])
-def test_smallest_grid_fp64_and_fp32(I, kernel, n):
-    """The smallest axis allowed (4) along x, y or z: a 4-point stencil
-    covers the whole axis, every RHS tile and transform is a ragged one, and
-    the projection table's 2P - 1 offsets wrap around it more than once."""
-    p = oracle_params(n, kernel=kernel, kT=1e-3, dt=0.2, seed=29 + kernel)
+@pytest.mark.parametrize("kernel,shift", [(3, 0.0), (4, 0.0), (3, 1.0)])
+def test_smallest_grid_fp64_and_fp32(I, kernel, shift, n):
+    """The smallest axis allowed (4) along x, y or z: a 4-point stencil (or
+    the split three-point kernel's four nodes) covers the whole axis, every
+    RHS tile and transform is a ragged one, and the projection table's
+    2P - 1 offsets wrap around it more than once."""
+    p = oracle_params(n, kernel=kernel, kT=1e-3, dt=0.2, seed=29 + kernel, kernel_shift=shift)
     st = initial_state(p, 2, (0.0, 1.0), seed=47, min_sep=1.5)
     run_parity(I, p, st, 2, I.FP64, TOL64, "smallest grid")
     run_parity(I, p, st, 1, I.FP32_GRID, TOL32, "smallest grid fp32")
