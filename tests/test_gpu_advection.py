@@ -56,7 +56,7 @@ def _check(got, p, st, steps, tol):
 
 
 @pytest.mark.parametrize("kernel", [3, 4])
-@pytest.mark.parametrize("n", [(16, 16, 16), (24, 18, 12), (32, 48, 32)])
+@pytest.mark.parametrize("n", [(16, 16, 16), (24, 18, 12), (32, 48, 32), (4, 6, 8)])
 def test_advection_deterministic_fp64(I, kernel, n):
     """kT = 0, a projected random flow of amplitude 0.3, blobs with mixed
     excess masses; four steps (Euler start, then three AB2 steps)."""
