@@ -341,6 +341,49 @@ def test_same_shape_batches_match_oracle(I, precision, graph):
         sim.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_pair_modes_mixed_in_one_batch(I, precision):
+    """Replicas of one shape in one batch with different pair forces: WCA
+    through the cell list, WCA through the all-pairs kernel (a cutoff above
+    a third of the box) and none; both force launches run over the batch
+    and each replica takes only its own."""
+    prec = I.FP64 if precision == "fp64" else I.FP32_GRID
+    tol = TOL64 if precision == "fp64" else TOL32
+    steps = 3 if precision == "fp64" else 1
+    dtype = np.float64 if prec == I.FP64 else np.float32
+    n = (24, 24, 24)
+    cases = [
+        (oracle_params(n, kernel=4, kT=1e-3, dt=0.2, seed=171, replica=0, wca_eps=1e-2,
+                       wca_sigma=2.0 / 2 ** (1 / 6)), (0.0, 1.0), 6, 2.2),
+        (oracle_params(n, kernel=4, kT=1e-3, dt=0.2, seed=171, replica=1, wca_eps=1e-7,
+                       wca_sigma=9.0 / 2 ** (1 / 6)), (0.0, -0.5), 4, 6.0),
+        (oracle_params(n, kernel=4, kT=1e-3, dt=0.2, seed=171, replica=2), (1.0,), 3, 3.0),
+    ]
+    states = [initial_state(p, nb, me, seed=180 + i, min_sep=ms) for i, (p, me, nb, ms) in enumerate(cases)]
+    # one pair within each cutoff (2 and 9), so that both force paths act
+    for st, dx in ((states[0], 1.9), (states[1], 7.0)):
+        st.q[1] = st.q[0] + np.array([dx, 0.0, 0.0])
+        st.u = O.interp(cases[0][0], st.v, st.q)
+    for (p, _, _, _), st in zip(cases[:2], states[:2]):
+        assert np.abs(O.wca_forces(p, st.q)).max() > 0
+    if prec == I.FP32_GRID:
+        for st in states:
+            st.v = st.v.astype(np.float32).astype(np.float64)
+    banner("pair modes in one batch %s" % precision)
+    sim = I.Sim([gpu_params(I, p) for p, _, _, _ in cases], [nb for _, _, nb, _ in cases], prec)
+    try:
+        for r, st in enumerate(states):
+            load_into_gpu(I, sim, r, st, dtype)
+        sim.step(steps, I.STEP_GRAPH)
+        for r, ((p, _, _, _), st) in enumerate(zip(cases, states)):
+            ref = O.run(p, st, steps)
+            errs, bad = compare(sim.get_state(r), ref, st.q, tol)
+            print("replica", r, {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+            assert not bad, (r, bad)
+    finally:
+        sim.close()
+
+
 def test_graph_replay_after_set_blobs(I):
     """A recorded step is dropped and recorded again when the blobs change;
     replays continue the Philox stream from the device step counter."""
