@@ -107,6 +107,18 @@ def test_inertial_mixed_masses_fp64(I, slip):
     run_parity(I, p, st, 3, I.FP64, TOL64, "inertial slip=%d" % slip)
 
 
+@pytest.mark.parametrize("slip", [O.SLIP_NONE, O.SLIP_VISCOUS, O.SLIP_FULL])
+def test_inertial_mixed_masses_fp32(I, slip):
+    """The same physics with an FP32 grid (FP64 blob state), one step."""
+    p = oracle_params((24, 24, 32), kernel=4, kT=1e-3, dt=0.3, slip=slip, seed=42, body=(1e-4, 0.0, -2e-4),
+                      wca_eps=1e-2, wca_sigma=2.0 / 2 ** (1 / 6), spring_k=0.01, spring_c=(12, 12, 16))
+    st = initial_state(p, 6, (0.0, 1.0, -0.5, 3.0), seed=10, min_sep=2.2)
+    # a lagged term from an earlier step, so that the viscous slip acts in
+    # this one step
+    st.lag_c = icm_inputs.random_forces(6, seed=11, scale=1e-3) * (st.m_e != 0)[:, None]
+    run_parity(I, p, st, 1, I.FP32_GRID, TOL32, "inertial fp32 slip=%d" % slip)
+
+
 def test_single_blob_me_fp64_3pt_deterministic(I):
     p = oracle_params((32, 32, 32), kernel=3, kT=0.0, dt=0.5, slip=O.SLIP_VISCOUS, seed=3)
     st = initial_state(p, 1, (2.0,), seed=13, force_scale=0.05, velocity_field_scale=1e-2)
@@ -189,6 +201,7 @@ def test_no_thermal_drift_and_nonunit_constants_fp64(I):
     p = oracle_params((18, 16, 24), kernel=4, kT=5e-3, dt=0.17, drift=False, h=0.8, rho=1.3, eta=0.6, seed=23)
     st = initial_state(p, 3, (0.0, 0.5), seed=25, min_sep=2.5)
     run_parity(I, p, st, 2, I.FP64, TOL64, "no drift")
+    run_parity(I, p, st, 1, I.FP32_GRID, TOL32, "no drift fp32")
 
 
 # ------------------------------------------------------------- FP32 parity
