@@ -45,10 +45,24 @@ def run_parity(I, p, st, steps, precision, tol, name, slots=None):
         errs, bad = compare(got, ref, q0, tol)
         print("errors:", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
         assert not bad, bad
-        assert got["diag"]["step"] == st.step + steps
-        # the advective CFL number of the new state, reduced on the device
+        d = got["diag"]
+        assert d["step"] == st.step + steps
+        # the FP64 reductions of the new state on the device: the advective
+        # CFL number, momentum (to the scale rho h^3 sum |v| + sum |m_e u|),
+        # kinetic energies and the discrete divergence
         alpha = O.advective_cfl(p, ref)
-        assert abs(got["diag"]["max_alpha"] - alpha) <= tol * alpha
+        assert abs(d["max_alpha"] - alpha) <= tol * alpha
+        scale = p.rho * p.cell_volume * float(np.sum(np.abs(ref.v)))
+        if ref.q.shape[0]:
+            scale += float(np.sum(np.abs(ref.m_e[:, None] * ref.u)))
+        assert np.max(np.abs(np.asarray(d["momentum"]) - O.momentum(p, ref))) <= tol * scale
+        ke_f, ke_b = O.kinetic_energy(p, ref)
+        assert abs(d["ke_fluid"] - ke_f) <= tol * ke_f
+        # (m_e of either sign: the blob energy can cancel, so its scale is
+        # sum |m_e| u^2 / 2)
+        kb_scale = 0.5 * float(np.sum(np.abs(ref.m_e[:, None]) * ref.u ** 2)) if ref.q.shape[0] else 0.0
+        assert abs(d["ke_blob"] - ke_b) <= tol * kb_scale
+        assert d["max_div"] <= (1e-12 if precision == I.FP64 else 1e-5)
         return got, ref
     finally:
         sim.close()
