@@ -1,6 +1,6 @@
 """Context set-up through the C ABI: a caller-provided workspace (no
-allocation by the library), the refusal of one too small, and the per-phase
-timers.
+allocation by the library), the refusal of one too small, a caller's HIP
+stream, and the per-phase timers.
 """
 import ctypes
 
@@ -108,11 +108,37 @@ def test_workspace_too_small_is_refused(I):
         ws.free()
 
 
+def test_caller_stream(I):
+    """A context created on a caller's HIP stream (default priority) enqueues
+    its work there, recorded graph included; the results match the oracle."""
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipStreamCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    hip.hipStreamDestroy.argtypes = [ctypes.c_void_p]
+    stream = ctypes.c_void_p()
+    assert hip.hipStreamCreate(ctypes.byref(stream)) == 0
+    p, me, nb = _cases()[0]
+    st = initial_state(p, nb, me, seed=241, min_sep=3.0)
+    banner("caller stream")
+    try:
+        sim = I.Sim([gpu_params(I, p)], [nb], I.FP64, stream=stream.value)
+        try:
+            load_into_gpu(I, sim, 0, st, np.float64)
+            sim.step(1)
+            sim.step(2, I.STEP_GRAPH)
+            errs, bad = compare(sim.get_state(0), O.run(p, st, 3), st.q, 1e-11)
+            print({k: "%.2e" % v for k, v in errs.items()}, flush=True)
+            assert not bad, bad
+        finally:
+            sim.close()
+    finally:
+        hip.hipStreamDestroy(stream)
+
+
 def test_phase_timers(I):
     """icm_set_timing brackets each phase's launches with events: after three
     eager steps every phase the plain step runs has three or more launches
-    and a positive time, the inertial-only phases none for an m_e = 0
-    replica, and a reset clears the counts."""
+    and a positive time, the advection phase none with advection off; a
+    reset clears the counts, and with the timers off nothing is counted."""
     p = oracle_params((32, 32, 32), kernel=4, kT=1e-3, dt=0.25, seed=231, wca_eps=1e-2,
                       wca_sigma=2.0 / 2 ** (1 / 6))
     st = initial_state(p, 6, (0.0,), seed=232, min_sep=2.5)
