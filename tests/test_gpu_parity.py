@@ -411,6 +411,45 @@ def test_pair_modes_mixed_in_one_batch(I, precision):
         sim.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_many_small_replicas_in_one_context(I, precision):
+    """40 replicas of two tiny shapes (4 x 6 x 8 and 8^3), one or two blobs
+    each with mixed excess masses, stepped from one recorded graph: the
+    per-replica loops of the batch kernels (the FP32 force sums of many
+    replicas in one workgroup, the projection table per replica) and the
+    parallel batch branches; every replica against its own oracle run."""
+    prec = I.FP64 if precision == "fp64" else I.FP32_GRID
+    tol = TOL64 if precision == "fp64" else TOL32
+    steps = 2 if precision == "fp64" else 1
+    dtype = np.float64 if prec == I.FP64 else np.float32
+    ratios = icm_inputs.excess_mass_ratios(40, (0.0, 1.0, -0.5), seed=250)
+    cases = []
+    for r in range(40):
+        n = (4, 6, 8) if r % 2 == 0 else (8, 8, 8)
+        p = oracle_params(n, kernel=4 if r % 4 < 2 else 3, kT=1e-3, dt=0.2, seed=251, replica=r)
+        nb = 1 + r % 2
+        cases.append((p, (float(ratios[r]), 0.0), nb))
+    states = [initial_state(p, nb, me, seed=260 + i, min_sep=1.5) for i, (p, me, nb) in enumerate(cases)]
+    if prec == I.FP32_GRID:
+        for st in states:
+            st.v = st.v.astype(np.float32).astype(np.float64)
+    banner("many small replicas %s" % precision)
+    sim = I.Sim([gpu_params(I, p) for p, _, _ in cases], [nb for _, _, nb in cases], prec)
+    try:
+        for r, st in enumerate(states):
+            load_into_gpu(I, sim, r, st, dtype)
+        sim.step(steps, I.STEP_GRAPH)
+        worst = {}
+        for r, ((p, _, _), st) in enumerate(zip(cases, states)):
+            errs, bad = compare(sim.get_state(r), O.run(p, st, steps), st.q, tol)
+            for k, v in errs.items():
+                worst[k] = max(worst.get(k, 0.0), v)
+            assert not bad, (r, bad)
+        print("worst over replicas", {k: "%.2e" % v for k, v in worst.items()}, flush=True)
+    finally:
+        sim.close()
+
+
 def test_graph_replay_after_set_blobs(I):
     """A recorded step is dropped and recorded again when the blobs change;
     replays continue the Philox stream from the device step counter."""
