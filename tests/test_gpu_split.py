@@ -60,16 +60,24 @@ def test_split_kernel_fp32_one_step(I):
     _run(I, [p], [st], 1, I.FP32_GRID, TOL32, "split fp32")
 
 
-def test_mixed_shifts_and_kernels_in_one_context(I):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mixed_shifts_and_kernels_in_one_context(I, precision):
     """Shifts 0.3 and 1.0, the plain three-point and the four-point kernel on
-    one grid shape: each replica matches its own oracle run."""
+    one grid shape (16^3: the spectral form of the inertial correction):
+    each replica matches its own oracle run."""
     specs = [(3, 0.3), (3, 1.0), (3, 0.0), (4, 0.0)]
     cases, states = [], []
     for r, (k, s) in enumerate(specs):
         p = oracle_params((16, 16, 16), kernel=k, kT=2e-3, dt=0.2, seed=221, replica=r, kernel_shift=s)
         cases.append(p)
-        states.append(initial_state(p, 3, (0.0, 1.0), seed=230 + r, min_sep=3.0))
-    _run(I, cases, states, 2, I.FP64, TOL64, "mixed shifts")
+        st = initial_state(p, 3, (0.0, 1.0), seed=230 + r, min_sep=3.0)
+        if precision == "fp32":
+            st.v = st.v.astype(np.float32).astype(np.float64)
+        states.append(st)
+    if precision == "fp64":
+        _run(I, cases, states, 2, I.FP64, TOL64, "mixed shifts")
+    else:
+        _run(I, cases, states, 1, I.FP32_GRID, TOL32, "mixed shifts fp32")
 
 
 def test_split_steady_mobility_matches_oracle(I):
