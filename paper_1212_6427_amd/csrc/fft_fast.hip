@@ -614,10 +614,14 @@ __global__ void __launch_bounds__(512) k_xinv_fast(const RepDesc<T>* __restrict_
     const bool ok = p < npairs;
     load_tw(tws, g.twx, N);
     const long long rp = g.Wp;
-    const gptr<const cplx<T>> s0 = as_global((const cplx<T>*)g.spec) + (long long)c * g.nspec + 2 * p * rp;
+    // a line past the last row pair reads the first one (never stored), so
+    // that no load sits behind a branch
+    const long long pc = ok ? p : 0;
+    const gptr<const cplx<T>> s0 = as_global((const cplx<T>*)g.spec) + (long long)c * g.nspec + 2 * pc * rp;
     constexpr int LS = xline<N>();
     // modes kx < N/2, two consecutive per thread (16-byte loads for FP32):
-    // pairs k = 2t + 2 TL m, m < E/4, all loads issued before the first is
+    // pairs k = 2t + 2 TL m, m < E/4, and the Nyquist mode of both rows
+    // (from nyq, real parts only), all loads issued before the first is
     // consumed
     static_assert(E % 4 == 0 && 2 * TL * (E / 4) == H, "mode pairs per thread");
     constexpr int NP = E / 4;
@@ -625,13 +629,11 @@ __global__ void __launch_bounds__(512) k_xinv_fast(const RepDesc<T>* __restrict_
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
         const int k = 2 * t + 2 * TL * m;
-        ea[m] = CPair<T>{};
-        eb[m] = CPair<T>{};
-        if (ok) {
-            ea[m] = *(gptr<const CPair<T>>)(s0 + k);
-            eb[m] = *(gptr<const CPair<T>>)(s0 + rp + k);
-        }
+        ea[m] = *(gptr<const CPair<T>>)(s0 + k);
+        eb[m] = *(gptr<const CPair<T>>)(s0 + rp + k);
     }
+    const gptr<const cplx<T>> nq = as_global((const cplx<T>*)g.nyq) + (long long)c * g.nz * g.ny + 2 * pc;
+    const cplx<T> nyA = nq[0], nyB = nq[1];
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
         const int k = 2 * t + 2 * TL * m;
@@ -647,16 +649,7 @@ __global__ void __launch_bounds__(512) k_xinv_fast(const RepDesc<T>* __restrict_
             if (kk > 0) lds[l * LS + skew<4>(N - kk)] = {A.x + Bv.y, -A.y + Bv.x};
         }
     }
-    // the Nyquist mode of both rows, from nyq (real parts only)
-    if (t == 0) {
-        cplx<T> A{0, 0}, Bv{0, 0};
-        if (ok) {
-            const gptr<const cplx<T>> nq = as_global((const cplx<T>*)g.nyq) + (long long)c * g.nz * g.ny + 2 * p;
-            A = nq[0];
-            Bv = nq[1];
-        }
-        lds[l * LS + skew<4>(H)] = {A.x, Bv.x};
-    }
+    if (t == 0) lds[l * LS + skew<4>(H)] = {nyA.x, nyB.x};
     __syncthreads();  // twiddles
     // each line is transformed by its own TL lanes, which lie in one wave
     cplx<T> a[E];
