@@ -409,15 +409,44 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
     const int kx = tail ? H : (int)blockIdx.x * B + b;
     const int y = tail ? (int)blockIdx.y * B + b : (int)blockIdx.y;
     const bool ok = tail ? y < g.ny : kx < H;
-    load_tw(tws, g.twz, N);
-    {
-        const gptr<const T> glz = as_global(g.lz);
-        const gptr<const cplx<T>> gdz = as_global(g.dz_hat);
+    // The twiddle and solve tables. FP32: each thread's first entry is
+    // loaded into registers before the column loads and written to LDS after
+    // them, so that the table round trip overlaps the column loads (loads in
+    // flight retire in order: the writes wait for the tables only); blocks
+    // narrower than N load the rest afterwards. FP64 (whose pencils leave no
+    // registers for that) stages them first.
+    constexpr bool kLate = sizeof(T) == 4;
+    const gptr<const cplx<T>> gtw = as_global(g.twz), gdz = as_global(g.dz_hat);
+    const gptr<const T> glz = as_global(g.lz);
+    if constexpr (!kLate) {
         for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            tws[i] = gtw[i];
             sdz[i] = gdz[i];
             slz[i] = glz[i];
         }
     }
+    const int ti = min((int)threadIdx.x, N - 1);
+    cplx<T> tw0{}, dz0{};
+    T lz0 = 0;
+    if constexpr (kLate) {
+        tw0 = gtw[ti];
+        dz0 = gdz[ti];
+        lz0 = glz[ti];
+    }
+    auto stage_tables = [&]() {
+        if constexpr (kLate) {
+            if ((int)threadIdx.x < N) {
+                tws[threadIdx.x] = tw0;
+                sdz[threadIdx.x] = dz0;
+                slz[threadIdx.x] = lz0;
+            }
+            for (int i = threadIdx.x + blockDim.x; i < N; i += blockDim.x) {
+                tws[i] = gtw[i];
+                sdz[i] = gdz[i];
+                slz[i] = glz[i];
+            }
+        }
+    };
     constexpr int TL = N / E;
     // Buffer accesses: one 32-bit per-thread offset (column, first plane); the
     // plane and component offsets are uniform and go in the scalar offset, so
@@ -438,6 +467,7 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
     cplx<T> a0[E], a1[E], a2[E];
     if constexpr (SRC > 0) {
         // the transform in (x, y, z) of the spread field, formed directly
+        stage_tables();
         __syncthreads();  // twiddles in LDS
         spectral_source<T, N, E>(rd[blockIdx.z], kx, y, t, tws, a0, a1, a2);
     } else {
@@ -447,6 +477,7 @@ __global__ void __launch_bounds__(512) k_z_fast(const RepDesc<T>* __restrict__ r
         for (int i = 0; i < E; ++i) a1[i] = sb.load(vo, (uint32_t)(TL * i) * zb + cb);
 #pragma unroll
         for (int i = 0; i < E; ++i) a2[i] = sb.load(vo, (uint32_t)(TL * i) * zb + 2 * cb);
+        stage_tables();
         __syncthreads();
         reg_fft<T, N, E, R0, R1, R2, -1>(a0, t, lds, B, b, tws);
         reg_fft<T, N, E, R0, R1, R2, -1>(a1, t, lds, B, b, tws);
